@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the predicted composite distance field on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: the
+per-slice composite fields of a 256x256x128 grid at 0.02 m (40 static
+boxes, 3 constant-velocity humans, 20 slices at dt = 0.1 s; the static
+field is built once beforehand, as the paper's environment field is) and
+10k exact sphere queries on those fields.
+
+Prints one JSON line.  `value` is voxel-slices/s of whole steps with the
+inputs resident in HBM.  `roofline` covers the dominant kernel (the
+streaming composite), timed with HIP events on its own launch stream.
+`cpu_baseline` times the CPU oracle on the same workload (rank 0, N=1).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("composite-EDT voxel-slices/s (% HBM peak); "
+          "sphere queries/s surrogate vs exact")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_config2_traffic.json")
+COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
+                             "composite.hip")
+
+
+def source_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(V: int, n: int):
+    """Measured HBM bytes per composite launch (rocprofv3 PMC FETCH_SIZE +
+    WRITE_SIZE, scaled by a copy-kernel calibration), or None when absent
+    or taken on a different version of the kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("composite_hip_sha256_16") != source_hash(COMPOSITE_SRC):
+        return None
+    if t.get("V") != V or t.get("n_slices") != n:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(sc, max_slices: int):
+    import numpy as np
+    import oracle
+    n = min(max_slices, sc.n_slices)
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    t0 = time.perf_counter()
+    oracle.predicted_composite(sc.grid, rs, sc.human_xy[:n], sc.radius,
+                               sc.height)
+    dt = time.perf_counter() - t0
+    return {"value": sc.grid.nvox * n / dt, "unit": "voxel-slices/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{n} of {sc.n_slices} slices of the same workload "
+                      f"(single-threaded C oracle, {dt:.1f} s)"}
+
+
+def calibrate_copy(mib: int, reps: int):
+    """A plain device copy of known size, for scaling PMC byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 4, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slices", type=int, default=20)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus "
+              f"{args.gpus} is not supported (slices shard across GPUs by "
+              f"design, but no multi-GPU path is built).", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib, max(1, args.steps))
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_2201_05058_amd as pc
+    import scenegen
+    from paper_2201_05058_amd import _native
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sc = scenegen.config2()
+    g = sc.grid
+    V, n, K = g.nvox, sc.n_slices, sc.n_humans
+    q = sc.queries
+    Q = len(q.radius)
+
+    h = pc.Handle()
+    occ = torch.from_numpy(sc.occ).to(dev)
+    centre = torch.from_numpy(q.centre).to(dev)
+    radius = torch.from_numpy(q.radius).to(dev)
+    slices = torch.from_numpy(q.slice).to(dev)
+    out_ssq = torch.empty((n,) + g.shape_zyx, dtype=torch.int32, device=dev)
+    out_sdf = torch.empty((n,) + g.shape_zyx, dtype=torch.float32, device=dev)
+
+    # static field, built once (not part of a step)
+    h.profile(True)
+    ssq_s, _ = pc.build_static_sdf(g, occ, handle=h)
+    pc.build_static_sdf(g, occ, ssq=ssq_s, want_sdf=False, handle=h)
+    torch.cuda.synchronize()
+    st_ms, st_n = h.profile_read(_native.KERNEL_STATIC)
+    static_ms = st_ms / max(st_n, 1)
+
+    def step():
+        pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
+                                   sc.height, out_ssq=out_ssq,
+                                   out_sdf=out_sdf, handle=h)
+        return pc.query_spheres(g, out_sdf, centre, radius, slices,
+                                handle=h)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    comp_ms, comp_n = h.profile_read(_native.KERNEL_COMPOSITE)
+    pl_ms, pl_n = h.profile_read(_native.KERNEL_PLANES)
+    qy_ms, qy_n = h.profile_read(_native.KERNEL_QUERY)
+    comp_avg_s = comp_ms / comp_n / 1e3
+    # compulsory bytes of one composite launch: read the static field once
+    # (4 B/voxel) and write both outputs (8 B/voxel-slice)
+    alg_bytes = (8.0 + 4.0 / n) * V * n
+    achieved = alg_bytes / comp_avg_s / 1e9
+    traffic = load_traffic(V, n)
+
+    line = {
+        "metric": METRIC,
+        "value": V * n / (ms_per_step / 1e3),
+        "unit": "voxel-slices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "config2: 256x256x128 grid at 0.02 m, 40 seeded "
+                        "boxes, 3 constant-velocity cylinder humans, 20 "
+                        "slices at dt=0.1 s, 10k exact sphere queries",
+            "grid": [g.nx, g.ny, g.nz], "voxel_m": g.h, "n_slices": n,
+            "n_humans": K, "n_queries": Q, "seed": sc.seed},
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_composite",
+            "kernel_ms": comp_avg_s * 1e3,
+            "bytes_per_voxel_slice": 8.0 + 4.0 / n,
+            "frac_12B_basis": 12.0 * V * n / comp_avg_s / 1e9 / HBM_PEAK_GBS,
+        },
+        "kernels_ms": {"composite": comp_avg_s * 1e3,
+                       "planes": pl_ms / max(pl_n, 1),
+                       "query": qy_ms / max(qy_n, 1),
+                       "static_build_once": static_ms},
+        "queries_per_s_exact_kernel": Q / (qy_ms / max(qy_n, 1) / 1e3)
+        if qy_ms > 0 else None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_slices)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * pcsdf — predicted composite signed distance fields on MI355X (gfx950).
+ *
+ * C-ABI of the GPU library.  The operations follow the mapping section of
+ * Finean et al., "Motion Planning in Dynamic Environments Using
+ * Context-Aware Human Trajectory Prediction" (2022), section "Mapping -
+ * Predicted Composite Distance Fields", and its RHAP-GPMP2 section:
+ *   - an environment distance field, computed once for the static map;
+ *   - one composite field per predicted time slice, the elementwise min of
+ *     the environment field and the field of the humans (vertical
+ *     cylinders) at their predicted positions;
+ *   - the fields sampled, distance and gradient, at collision spheres for
+ *     GPMP2's hinge-loss obstacle factors, with every time index past the
+ *     last slice mapped to the last slice.
+ *
+ * Conventions shared by every call:
+ *   - Grids are x fastest: idx = (k*ny + j)*nx + i, no padding; voxel
+ *     (i,j,k) has its centre at origin + h*(i+1/2, j+1/2, k+1/2).
+ *   - Fields come in two forms.  SSQ (int32) is the signed squared distance
+ *     in voxel units: E_O(v) = min_{u in O} |v-u|^2 for a free voxel,
+ *     -E_{G\O}(v) for an occupied one, +INT32_MAX / -INT32_MAX when the
+ *     other set is empty.  SDF (fp32, metres) is
+ *     F(x) = sign(x) * ((float)h * sqrtf(|x|)), +-inf for +-INT32_MAX.
+ *   - Per-slice outputs are slice-major: [n_slices][nz][ny][nx].
+ *   - Every device buffer is owned by the caller; the library never frees
+ *     it.  The library owns only its handle's workspace.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream; no call waits for the device except
+ *     where stated.  A handle is not reentrant: use one per host thread.
+ *   - Every call returns PCSDF_OK (0) or an error code.  On error nothing
+ *     has been enqueued unless the code is PCSDF_ERR_HIP, and output
+ *     buffers are unspecified.  pcsdf_last_error() describes the failure.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef PCSDF_H_
+#define PCSDF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pcsdf_status_code {
+  PCSDF_OK = 0,
+  PCSDF_ERR_INVALID_ARG = 1, /* null pointer, bad count or parameter */
+  PCSDF_ERR_DIMS = 2,        /* grid dimension out of [1, 1024] etc. */
+  PCSDF_ERR_ALIGN = 3,       /* device pointer not 4-byte aligned */
+  PCSDF_ERR_OOM = 4,         /* workspace allocation failed */
+  PCSDF_ERR_HIP = 5,         /* a HIP runtime call failed */
+  PCSDF_ERR_NUMERIC = 6      /* NaN/Inf or out-of-range real input */
+};
+
+/* Status bits of a sphere query (pcsdf_query_spheres). */
+#define PCSDF_Q_OOR_X 1u         /* centre outside the span of voxel centres in x; clamped */
+#define PCSDF_Q_OOR_Y 2u
+#define PCSDF_Q_OOR_Z 4u
+#define PCSDF_Q_SLICE_CLAMPED 8u /* slice >= n_slices, slice n_slices-1 used */
+#define PCSDF_Q_INF_CORNER 16u   /* a corner is +-inf: dist = +-inf, grad = 0 */
+#define PCSDF_Q_SLICE_NEG 32u    /* slice < 0: dist, grad, cost are NaN */
+
+/* Timed regions of pcsdf_profile_read. */
+#define PCSDF_KERNEL_COMPOSITE 0 /* streaming composite epilogue kernel */
+#define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (two kernels) */
+#define PCSDF_KERNEL_QUERY 2     /* sphere query kernel */
+#define PCSDF_KERNEL_STATIC 3    /* the three passes of the static build */
+#define PCSDF_KERNEL_COUNT 4
+
+typedef struct pcsdf_handle pcsdf_handle;
+
+/* Regular grid.  nx, ny, nz in [1, 1024]; voxel_m > 0 and finite; origin
+ * finite (the world position of the grid's minimum corner). */
+typedef struct pcsdf_grid {
+  int32_t nx, ny, nz;
+  int32_t reserved; /* must be 0 */
+  double voxel_m;
+  double origin_m[3];
+} pcsdf_grid;
+
+/* Creates a handle.  Touches no device; the workspace is allocated on the
+ * device current at the first call that needs it, and that device is used
+ * by the handle from then on.  Returns PCSDF_ERR_INVALID_ARG if out is
+ * NULL, PCSDF_ERR_OOM if the host allocation fails. */
+int pcsdf_create(pcsdf_handle **out);
+
+/* Waits for the handle's pending uploads, frees its workspace and the
+ * handle.  NULL is ignored.  Device buffers passed to earlier calls are
+ * not touched. */
+void pcsdf_destroy(pcsdf_handle *h);
+
+/* Message of the last failed call on this handle ("" if none).  The
+ * pointer stays valid until the next call on the handle. */
+const char *pcsdf_last_error(const pcsdf_handle *h);
+
+/* Name of a status code. */
+const char *pcsdf_status_string(int status);
+
+/* Environment distance field (mapping section: the environment field is
+ * computed once, or maintained; here one exact signed EDT of the caller's
+ * voxel map).
+ *   occ_dev  [V] uint8, nonzero = occupied.             (device, read)
+ *   ssq_dev  [V] int32 SSQ of the occupied set.         (device, written)
+ *   sdf_dev  [V] fp32 F(SSQ), may be NULL.              (device, written)
+ * Uses a workspace of 4*V bytes.  Exact: the int32 result is unique. */
+int pcsdf_build_static_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
+                           const uint8_t *occ_dev, int32_t *ssq_dev,
+                           float *sdf_dev, void *stream);
+
+/* The sequence of predicted composite fields (mapping section: the
+ * composite is a parallel min of the environment field and the fields of
+ * the humans, modelled as cylinder primitives, at their predicted
+ * positions; RHAP-GPMP2 section: one composite field per time slice).
+ *   static_ssq_dev [V] int32 from pcsdf_build_static_sdf.   (device, read)
+ *   n_slices >= 1, n_humans in [0, 256].
+ *   human_xy_host  [n_slices][n_humans][2] fp64 metres, the predicted
+ *                  (x, y) of each human in each slice.      (host, read
+ *                  before the call returns)
+ *   radius_m, height_m: the cylinder (base at z = origin_m[2]).
+ *   out_ssq_dev    [n_slices][V] int32, may be NULL.        (device, written)
+ *   out_sdf_dev    [n_slices][V] fp32, may be NULL.         (device, written)
+ * At least one output must be non-NULL.  Per slice s the humans' voxels
+ * are the closed integer voxelisation on a 2^-16 voxel lattice:
+ *   X = rint(((x - o_x)/h)*2^16), Y likewise, R = rint((r/h)*2^16),
+ *   Hq = rint((H/h)*2^16); voxel (i,j,k) is in a cylinder iff
+ *   (2^15(2i+1) - X)^2 + (2^15(2j+1) - Y)^2 <= R^2 and 2^15(2k+1) <= Hq.
+ * Voxels outside the grid do not exist (humans are clipped).  The result
+ * is min(static SSQ, SSQ of the humans' voxels), both signed, and its F.
+ * Errors: PCSDF_ERR_NUMERIC for non-finite inputs or when a fixed-point
+ * value reaches 2^62 in magnitude or R reaches 2^31.
+ * Uses a workspace of 8*n_slices*nx*ny + 16*n_slices*n_humans bytes. */
+int pcsdf_predicted_composite_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
+                                  const int32_t *static_ssq_dev,
+                                  int32_t n_slices, int32_t n_humans,
+                                  const double *human_xy_host,
+                                  double radius_m, double height_m,
+                                  int32_t *out_ssq_dev, float *out_sdf_dev,
+                                  void *stream);
+
+/* Sphere queries on a sequence of fp32 fields (GPMP2 obstacle factors
+ * sample distance and gradient; RHAP-GPMP2 assigns the last field to every
+ * time index past the horizon).
+ *   sdf_dev    [n_slices][V] fp32 fields.                   (device, read)
+ *   centre_dev [Q][3] fp32 metres, radius_dev [Q] fp32,
+ *   slice_dev  [Q] int32.                                   (device, read)
+ *   dist_dev   [Q] fp32: trilinear distance at the centre minus radius.
+ *   grad_dev   [Q][3] fp32: gradient of the trilinear field (m/m).
+ *   status_dev [Q] uint8 PCSDF_Q_* bits, may be NULL.
+ *   cost_dev   [Q] fp32 hinge max(0, hinge_eps_m - dist), may be NULL.
+ * Interpolation is in fp64: g_a = (c_a - o_a)/h - 1/2 clamped to
+ * [0, n_a - 1], cell i_a = min(floor(g_a), n_a - 2).  Requires every
+ * n_a >= 2 (else PCSDF_ERR_DIMS).  n_queries = 0 is a no-op. */
+int pcsdf_query_spheres(pcsdf_handle *h, const pcsdf_grid *grid,
+                        const float *sdf_dev, int32_t n_slices,
+                        int32_t n_queries, const float *centre_dev,
+                        const float *radius_dev, const int32_t *slice_dev,
+                        double hinge_eps_m, float *dist_dev, float *grad_dev,
+                        uint8_t *status_dev, float *cost_dev, void *stream);
+
+/* Kernel timing for measurement.  When on, each timed region (the
+ * PCSDF_KERNEL_* ids) is bracketed by two hipEventRecord calls on the
+ * launch stream.  pcsdf_profile_read waits for the recorded events and
+ * returns the accumulated milliseconds and region count of one id.
+ * pcsdf_profile_enable(h, 0) stops recording; pcsdf_profile_reset clears
+ * the totals (waiting for pending events first). */
+int pcsdf_profile_enable(pcsdf_handle *h, int on);
+int pcsdf_profile_read(pcsdf_handle *h, int kernel_id, double *total_ms,
+                       int64_t *count);
+int pcsdf_profile_reset(pcsdf_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCSDF_H_ */

@@ -1,0 +1,137 @@
+"""Predicted composite signed distance fields on MI355X (gfx950).
+
+Python face of libpcsdf.so.  Each function has the name of its C-ABI
+entry point (without the ``pcsdf_`` prefix), takes torch tensors that live
+on the GPU, and enqueues the library's HIP kernels on torch's current
+stream.  Nothing here computes any part of the method.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._native import (Grid, Handle, PcsdfError, Q_INF_CORNER, Q_OOR_X,
+                      Q_OOR_Y, Q_OOR_Z, Q_SLICE_CLAMPED, Q_SLICE_NEG,
+                      as_grid, default_handle, load_library)
+
+__all__ = [
+    "Grid", "Handle", "PcsdfError", "build_static_sdf",
+    "predicted_composite_sdf", "query_spheres", "load_library",
+    "Q_OOR_X", "Q_OOR_Y", "Q_OOR_Z", "Q_SLICE_CLAMPED", "Q_INF_CORNER",
+    "Q_SLICE_NEG",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, name, numel=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, "
+                         f"got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def build_static_sdf(grid, occ, ssq=None, sdf=None, want_sdf=True,
+                     handle: Handle | None = None):
+    """Exact signed squared EDT of a uint8 occupancy grid [nz, ny, nx]
+    (pcsdf_build_static_sdf).  Returns (ssq int32, sdf float32 or None)."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    V = g.nvox
+    dev = occ.device
+    if ssq is None:
+        ssq = torch.empty(g.shape_zyx, dtype=torch.int32, device=dev)
+    if sdf is None and want_sdf:
+        sdf = torch.empty(g.shape_zyx, dtype=torch.float32, device=dev)
+    rc = h.lib.pcsdf_build_static_sdf(
+        h.ptr, C.byref(g), _dev_ptr(occ, torch.uint8, "occ", V),
+        _dev_ptr(ssq, torch.int32, "ssq", V),
+        _dev_ptr(sdf, torch.float32, "sdf", V), _stream(dev))
+    h.check(rc)
+    return ssq, sdf
+
+
+def predicted_composite_sdf(grid, static_ssq, human_xy, radius, height,
+                            out_ssq=None, out_sdf=None, want_ssq=True,
+                            want_sdf=True, handle: Handle | None = None):
+    """Per-slice composite fields (pcsdf_predicted_composite_sdf).
+
+    human_xy: host array [n_slices, n_humans, 2] of predicted positions in
+    metres.  Returns (ssq int32 [n, nz, ny, nx] or None, sdf float32 or
+    None)."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n, K = xy.shape[0], xy.shape[1]
+    V = g.nvox
+    dev = static_ssq.device
+    shp = (n,) + g.shape_zyx
+    if out_ssq is None and want_ssq:
+        out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
+    if out_sdf is None and want_sdf:
+        out_sdf = torch.empty(shp, dtype=torch.float32, device=dev)
+    rc = h.lib.pcsdf_predicted_composite_sdf(
+        h.ptr, C.byref(g), _dev_ptr(static_ssq, torch.int32, "static_ssq", V),
+        n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
+        float(radius), float(height),
+        _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
+        _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev))
+    h.check(rc)
+    return out_ssq, out_sdf
+
+
+def query_spheres(grid, sdf, centre, radius, slices, hinge_eps=0.0,
+                  want_status=True, want_cost=False,
+                  handle: Handle | None = None):
+    """Trilinear distance and gradient at collision spheres
+    (pcsdf_query_spheres).  sdf: float32 [n_slices, nz, ny, nx] (or a
+    single field [nz, ny, nx]).  Returns (dist [Q], grad [Q, 3],
+    status uint8 [Q] or None, cost [Q] or None)."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    V = g.nvox
+    n_slices = sdf.numel() // V
+    if n_slices * V != sdf.numel():
+        raise ValueError("sdf size is not a whole number of fields")
+    Q = centre.shape[0] if centre.ndim > 1 else centre.numel() // 3
+    dev = sdf.device
+    dist = torch.empty(Q, dtype=torch.float32, device=dev)
+    grad = torch.empty((Q, 3), dtype=torch.float32, device=dev)
+    status = (torch.empty(Q, dtype=torch.uint8, device=dev)
+              if want_status else None)
+    cost = torch.empty(Q, dtype=torch.float32, device=dev) if want_cost \
+        else None
+    rc = h.lib.pcsdf_query_spheres(
+        h.ptr, C.byref(g), _dev_ptr(sdf, torch.float32, "sdf"), n_slices, Q,
+        _dev_ptr(centre, torch.float32, "centre", 3 * Q),
+        _dev_ptr(radius, torch.float32, "radius", Q),
+        _dev_ptr(slices, torch.int32, "slices", Q), float(hinge_eps),
+        _dev_ptr(dist, torch.float32, "dist"),
+        _dev_ptr(grad, torch.float32, "grad"),
+        _dev_ptr(status, torch.uint8, "status"),
+        _dev_ptr(cost, torch.float32, "cost"), _stream(dev))
+    h.check(rc)
+    return dist, grad, status, cost

@@ -1,0 +1,254 @@
+// Handle, error reporting, device binding and workspace management of the
+// C-ABI.  No kernels here.
+#include <cmath>
+#include <new>
+
+#include "internal.h"
+
+namespace pcsdf {
+
+int fail(Handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int bind_device(Handle *h) {
+  int d = -1;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP,
+                std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (h->device < 0) {
+    int lds = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              d);
+    if (e != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("hipDeviceGetAttribute: ") +
+                      hipGetErrorString(e));
+    e = hipEventCreateWithFlags(&h->staging_done, hipEventDisableTiming);
+    if (e != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("hipEventCreate: ") + hipGetErrorString(e));
+    h->max_lds = lds;
+    h->device = d;
+  } else if (d != h->device) {
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "handle is bound to device " + std::to_string(h->device) +
+                    " but device " + std::to_string(d) + " is current");
+  }
+  return PCSDF_OK;
+}
+
+int ensure_buffer(Handle *h, DevBuf &b, size_t bytes, hipStream_t stream) {
+  if (b.bytes >= bytes && b.ptr) return PCSDF_OK;
+  if (b.ptr) {
+    // Work queued earlier (on any stream) may still read the old buffer.
+    (void)stream;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("hipDeviceSynchronize: ") +
+                      hipGetErrorString(e));
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  const size_t want = align_up(bytes > 0 ? bytes : 256, 1 << 21);
+  hipError_t e = hipMalloc(&b.ptr, want);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(h, PCSDF_ERR_OOM,
+                "workspace allocation of " + std::to_string(want) +
+                    " bytes failed: " + hipGetErrorString(e));
+  }
+  b.bytes = want;
+  return PCSDF_OK;
+}
+
+int acquire_staging(Handle *h, size_t bytes) {
+  if (h->staging_pending) {
+    hipError_t e = hipEventSynchronize(h->staging_done);
+    if (e != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("hipEventSynchronize: ") +
+                      hipGetErrorString(e));
+    h->staging_pending = false;
+  }
+  if (h->pinned_bytes >= bytes && h->pinned) return PCSDF_OK;
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  h->pinned = nullptr;
+  h->pinned_bytes = 0;
+  const size_t want = align_up(bytes > 0 ? bytes : 64, 4096);
+  hipError_t e = hipHostMalloc(&h->pinned, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    h->pinned = nullptr;
+    (void)hipGetLastError();
+    return fail(h, PCSDF_ERR_OOM, "pinned staging allocation failed");
+  }
+  h->pinned_bytes = want;
+  return PCSDF_OK;
+}
+
+int release_staging(Handle *h, hipStream_t stream) {
+  hipError_t e = hipEventRecord(h->staging_done, stream);
+  if (e != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP,
+                std::string("hipEventRecord: ") + hipGetErrorString(e));
+  h->staging_pending = true;
+  return PCSDF_OK;
+}
+
+int check_launch(Handle *h, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+  return PCSDF_OK;
+}
+
+int check_grid(Handle *h, const pcsdf_grid *g) {
+  if (!g) return fail(h, PCSDF_ERR_INVALID_ARG, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nx > kMaxDim ||
+      g->ny > kMaxDim || g->nz > kMaxDim)
+    return fail(h, PCSDF_ERR_DIMS,
+                "grid dimensions must be in [1, 1024], got " +
+                    std::to_string(g->nx) + "x" + std::to_string(g->ny) +
+                    "x" + std::to_string(g->nz));
+  if (g->reserved != 0)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "grid.reserved must be 0");
+  if (!std::isfinite(g->voxel_m) || !(g->voxel_m > 0))
+    return fail(h, PCSDF_ERR_NUMERIC, "voxel_m must be finite and > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(g->origin_m[a]))
+      return fail(h, PCSDF_ERR_NUMERIC, "origin_m must be finite");
+  h->err.clear();
+  return PCSDF_OK;
+}
+
+static hipEvent_t take_event(Handle *h) {
+  if (!h->prof_pool.empty()) {
+    hipEvent_t e = h->prof_pool.back();
+    h->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(Handle *h, int id, hipStream_t s)
+    : h_(h), id_(id), s_(s) {
+  if (!h_->prof_on) return;
+  a_ = take_event(h_);
+  b_ = take_event(h_);
+  if (a_ && b_) (void)hipEventRecord(a_, s_);
+}
+
+void ProfScope::stop() {
+  if (!a_ || !b_) return;
+  (void)hipEventRecord(b_, s_);
+  h_->prof_pending.push_back({id_, a_, b_});
+  a_ = b_ = nullptr;
+}
+
+static int drain_profile(Handle *h) {
+  for (auto &p : h->prof_pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e != hipSuccess) {
+      h->prof_pending.clear();
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("profile events: ") + hipGetErrorString(e));
+    }
+    h->prof_ms[p.id] += ms;
+    h->prof_n[p.id] += 1;
+    h->prof_pool.push_back(p.a);
+    h->prof_pool.push_back(p.b);
+  }
+  h->prof_pending.clear();
+  return PCSDF_OK;
+}
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+extern "C" int pcsdf_profile_enable(pcsdf_handle *hp, int on) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  h->prof_on = on != 0;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_profile_read(pcsdf_handle *hp, int id, double *total_ms,
+                                  int64_t *count) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (id < 0 || id >= PCSDF_KERNEL_COUNT || !total_ms || !count)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "bad profile id or output pointer");
+  int rc = drain_profile(h);
+  if (rc) return rc;
+  *total_ms = h->prof_ms[id];
+  *count = h->prof_n[id];
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_profile_reset(pcsdf_handle *hp) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  int rc = drain_profile(h);
+  for (int i = 0; i < PCSDF_KERNEL_COUNT; ++i) {
+    h->prof_ms[i] = 0.0;
+    h->prof_n[i] = 0;
+  }
+  return rc;
+}
+
+extern "C" int pcsdf_create(pcsdf_handle **out) {
+  if (!out) return PCSDF_ERR_INVALID_ARG;
+  Handle *h = new (std::nothrow) Handle();
+  *out = reinterpret_cast<pcsdf_handle *>(h);
+  return h ? PCSDF_OK : PCSDF_ERR_OOM;
+}
+
+extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return;
+  if (h->staging_pending) (void)hipEventSynchronize(h->staging_done);
+  DevBuf *bufs[] = {&h->tmp_buf, &h->plane_buf, &h->param_buf, &h->stack_buf};
+  bool any = false;
+  for (DevBuf *b : bufs) any = any || b->ptr;
+  if (any) (void)hipDeviceSynchronize();
+  for (DevBuf *b : bufs)
+    if (b->ptr) (void)hipFree(b->ptr);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->staging_done) (void)hipEventDestroy(h->staging_done);
+  for (auto &p : h->prof_pending) {
+    (void)hipEventSynchronize(p.b);
+    h->prof_pool.push_back(p.a);
+    h->prof_pool.push_back(p.b);
+  }
+  for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+  delete h;
+}
+
+extern "C" const char *pcsdf_last_error(const pcsdf_handle *hp) {
+  const Handle *h = reinterpret_cast<const Handle *>(hp);
+  return h ? h->err.c_str() : "null handle";
+}
+
+extern "C" const char *pcsdf_status_string(int status) {
+  switch (status) {
+    case PCSDF_OK: return "PCSDF_OK";
+    case PCSDF_ERR_INVALID_ARG: return "PCSDF_ERR_INVALID_ARG";
+    case PCSDF_ERR_DIMS: return "PCSDF_ERR_DIMS";
+    case PCSDF_ERR_ALIGN: return "PCSDF_ERR_ALIGN";
+    case PCSDF_ERR_OOM: return "PCSDF_ERR_OOM";
+    case PCSDF_ERR_HIP: return "PCSDF_ERR_HIP";
+    case PCSDF_ERR_NUMERIC: return "PCSDF_ERR_NUMERIC";
+    default: return "PCSDF_ERR_UNKNOWN";
+  }
+}

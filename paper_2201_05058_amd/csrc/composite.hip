@@ -1,0 +1,228 @@
+// Predicted composite fields: one exact signed field of the humans per
+// time slice, min-composited with the environment field (mapping section:
+// a parallel min between the environment field and the humans' fields at
+// their predicted positions; RHAP-GPMP2 section: a sequence of n such
+// fields, one per slice).
+//
+// The humans are vertical cylinders sharing one radius and height, all
+// standing on the grid's floor, so a slice's human voxels form a product
+// set O_h = D x Z: D is the union of voxelised disks in the xy plane and
+// Z = {0..Kt} the voxel layers whose centres lie under the cylinder top.
+// The squared distance to a product set splits into one term per factor,
+// so for every voxel (i, j, k):
+//   outside:  E_{O_h}(i,j,k)    = E_D(i,j) + max(0, k - Kt)^2
+//   inside:   E_{G\O_h}(i,j,k)  = min(E_{Gxy\D}(i,j), (Kt + 1 - k)^2)
+// (the complement of D x Z in the grid is (Gxy\D) x Gz  union  Gxy x (Gz\Z),
+// and the second term is absent when Z reaches the grid top).  This is
+// the z pass of the separable EDT done in closed form: the column input
+// is constant on 0..Kt and empty elsewhere, and its lower envelope is that
+// constant plus the squared distance to the interval.  So the exact 3-D
+// field of the humans needs only a 2-D signed EDT per slice (x pass by
+// wave ballot over the disk predicate, y pass by lower envelope, both in
+// edt.hip), and the per-voxel work is a streaming epilogue:
+//   read the static field once, then for every slice compute the humans'
+//   value from the slice's plane, take the signed min, convert to metres
+//   and write both outputs.
+// The epilogue moves the compulsory bytes only: 4 B of static field per
+// voxel (read once for all slices) and 8 B per voxel-slice of output; the
+// planes (nx*ny*4 B per slice) stay in cache.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace pcsdf {
+
+// Value of the humans' signed field at a voxel of layer k whose planar
+// signed value is p (E_D outside D, -E_{Gxy\D} inside, +-kInf if the other
+// set is empty).  dz2o = max(0, k-Kt)^2; zin = (k <= Kt); dz2i =
+// (Kt+1-k)^2 when layer Kt+1 exists, else kInf.
+__device__ __forceinline__ int32_t human_value(int32_t p, int dz2o, bool zin,
+                                               int32_t dz2i) {
+  if (p == kInf) return kInf;  // no human voxel in this slice
+  if (p > 0) return p + dz2o;  // column outside the disks
+  if (!zin) return dz2o;       // above the cylinders: nearest is the top
+  const int32_t din = -p;      // kInf when the disks cover the plane
+  return -(din < dz2i ? din : dz2i);
+}
+
+template <int VEC, bool kSsq, bool kSdf>
+__global__ __launch_bounds__(256) void k_composite(
+    const int32_t *__restrict__ S, const int32_t *__restrict__ P,
+    int32_t *__restrict__ oc, float *__restrict__ of, uint32_t nx,
+    uint32_t ny, int n_slices, int Kt, int has_above, float hf, uint32_t V) {
+  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t v0 = g * VEC;
+  if (v0 >= V) return;
+  const uint32_t row = v0 / nx;
+  const uint32_t i = v0 - row * nx;
+  const uint32_t k = row / ny;
+  const uint32_t j = row - k * ny;
+  const int kk = (int)k;
+  const int dzo = kk > Kt ? kk - Kt : 0;
+  const int dz2o = dzo * dzo;
+  const bool zin = kk <= Kt;
+  const int32_t dz2i =
+      has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : kInf;
+  const size_t plane = (size_t)nx * ny;
+  const int32_t *prow = P + (size_t)j * nx + i;
+
+  if constexpr (VEC == 4) {
+    const int4 s4 = *reinterpret_cast<const int4 *>(S + v0);
+    for (int sl = 0; sl < n_slices; ++sl) {
+      const int4 p4 = *reinterpret_cast<const int4 *>(prow + sl * plane);
+      int4 c;
+      c.x = min(s4.x, human_value(p4.x, dz2o, zin, dz2i));
+      c.y = min(s4.y, human_value(p4.y, dz2o, zin, dz2i));
+      c.z = min(s4.z, human_value(p4.z, dz2o, zin, dz2i));
+      c.w = min(s4.w, human_value(p4.w, dz2o, zin, dz2i));
+      const size_t o = (size_t)sl * V + v0;
+      if (kSsq) *reinterpret_cast<int4 *>(oc + o) = c;
+      if (kSdf) {
+        float4 f;
+        f.x = ssq_to_metres(c.x, hf);
+        f.y = ssq_to_metres(c.y, hf);
+        f.z = ssq_to_metres(c.z, hf);
+        f.w = ssq_to_metres(c.w, hf);
+        *reinterpret_cast<float4 *>(of + o) = f;
+      }
+    }
+  } else {
+    const int32_t s = S[v0];
+    for (int sl = 0; sl < n_slices; ++sl) {
+      const int32_t c = min(s, human_value(prow[sl * plane], dz2o, zin, dz2i));
+      const size_t o = (size_t)sl * V + v0;
+      if (kSsq) oc[o] = c;
+      if (kSdf) of[o] = ssq_to_metres(c, hf);
+    }
+  }
+}
+
+template <int VEC>
+static void launch_comp(const int32_t *S, const int32_t *P, int32_t *oc,
+                        float *of, uint32_t nx, uint32_t ny, int n, int Kt,
+                        int has_above, float hf, uint32_t V, hipStream_t s) {
+  const uint32_t nthreads = (V + VEC - 1) / VEC;
+  const dim3 grid((nthreads + 255) / 256), block(256);
+  if (oc && of)
+    hipLaunchKernelGGL((k_composite<VEC, true, true>), grid, block, 0, s, S,
+                       P, oc, of, nx, ny, n, Kt, has_above, hf, V);
+  else if (oc)
+    hipLaunchKernelGGL((k_composite<VEC, true, false>), grid, block, 0, s, S,
+                       P, oc, of, nx, ny, n, Kt, has_above, hf, V);
+  else
+    hipLaunchKernelGGL((k_composite<VEC, false, true>), grid, block, 0, s, S,
+                       P, oc, of, nx, ny, n, Kt, has_above, hf, V);
+}
+
+// Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
+// rint(((p - o)/h) * 2^16), each step an IEEE fp64 operation.
+static bool to_fixed(double p, double o, double h, int64_t *out) {
+  double t = p - o;
+  t = t / h;
+  t = t * 65536.0;
+  if (!std::isfinite(t) || std::fabs(t) >= 4611686018427387904.0) return false;
+  *out = (int64_t)std::nearbyint(t);
+  return true;
+}
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+extern "C" int pcsdf_predicted_composite_sdf(
+    pcsdf_handle *hp, const pcsdf_grid *g, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, int32_t *out_ssq_dev,
+    float *out_sdf_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_grid(h, g);
+  if (rc) return rc;
+  if (!static_ssq_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "static_ssq_dev is required");
+  if (!out_ssq_dev && !out_sdf_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "at least one of out_ssq_dev / out_sdf_dev is required");
+  if (n_slices < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
+  if (n_humans < 0 || n_humans > kMaxHumans)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_humans must be in [0, 256]");
+  if (n_humans > 0 && !human_xy_host)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "human_xy_host is required");
+  if (((uintptr_t)static_ssq_dev & 3) || ((uintptr_t)out_ssq_dev & 3) ||
+      ((uintptr_t)out_sdf_dev & 3))
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  const double hv = g->voxel_m;
+  if (!std::isfinite(radius_m) || radius_m < 0 || !std::isfinite(height_m) ||
+      height_m < 0)
+    return fail(h, PCSDF_ERR_NUMERIC, "radius_m/height_m must be finite, >= 0");
+  int64_t R, Hq;
+  if (!to_fixed(radius_m, 0.0, hv, &R) || !to_fixed(height_m, 0.0, hv, &Hq))
+    return fail(h, PCSDF_ERR_NUMERIC, "radius/height out of range");
+  if (R >= (1LL << 31))
+    return fail(h, PCSDF_ERR_NUMERIC, "radius_m/voxel_m must be < 32768");
+
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int64_t V = (int64_t)nx * ny * nz;
+  // Highest layer whose centre lies at or under the cylinder top.
+  int Kt = Hq >= 32768 ? (int)std::min<int64_t>((Hq - 32768) / 65536, nz - 1)
+                       : -1;
+  const bool empty = Kt < 0 || n_humans == 0;
+  const int has_above = Kt + 1 <= nz - 1;
+
+  // Fixed-point centres, validated on the host before anything is queued.
+  const size_t ncent = (size_t)n_slices * n_humans;
+  std::vector<int64_t> &xy = h->host_xy;
+  xy.resize(2 * (ncent > 0 ? ncent : 1));
+  for (size_t t = 0; t < ncent; ++t) {
+    if (!to_fixed(human_xy_host[2 * t], g->origin_m[0], hv, &xy[2 * t]) ||
+        !to_fixed(human_xy_host[2 * t + 1], g->origin_m[1], hv,
+                  &xy[2 * t + 1]))
+      return fail(h, PCSDF_ERR_NUMERIC,
+                  "human position non-finite or out of range at index " +
+                      std::to_string(t));
+  }
+  if ((rc = bind_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
+  const size_t xy_bytes = xy.size() * sizeof(int64_t);
+  if ((rc = ensure_buffer(h, h->plane_buf, 2 * plane_bytes, s))) return rc;
+  if ((rc = ensure_buffer(h, h->param_buf, xy_bytes, s))) return rc;
+  int64_t *xy_dev = reinterpret_cast<int64_t *>(h->param_buf.ptr);
+  if (ncent > 0) {
+    if ((rc = acquire_staging(h, xy_bytes))) return rc;
+    std::memcpy(h->pinned, xy.data(), xy_bytes);
+    if (hipMemcpyAsync(xy_dev, h->pinned, xy_bytes, hipMemcpyHostToDevice,
+                       s) != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP, "upload of human positions failed");
+    if ((rc = release_staging(h, s))) return rc;
+  }
+
+  int32_t *p1 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
+  int32_t *p2 = p1 + (size_t)n_slices * nx * ny;
+  // Planar signed field of the disk union, per slice.
+  ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
+  if ((rc = launch_pass_x_disks(h, xy_dev, n_humans, R, empty, p1, nx, ny,
+                                n_slices, s)))
+    return rc;
+  if ((rc = launch_pass_col(h, p1, p2, nullptr, 0.f, nx, n_slices, ny, nx,
+                            (int64_t)nx * ny, s)))
+    return rc;
+  pp.stop();
+  // Streaming epilogue over all voxels and slices.
+  const float hf = (float)hv;
+  const bool vec4 = (nx % 4 == 0) && !((uintptr_t)static_ssq_dev & 15) &&
+                    !((uintptr_t)out_ssq_dev & 15) &&
+                    !((uintptr_t)out_sdf_dev & 15);
+  ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
+  if (vec4)
+    launch_comp<4>(static_ssq_dev, p2, out_ssq_dev, out_sdf_dev, nx, ny,
+                   n_slices, Kt, has_above, hf, (uint32_t)V, s);
+  else
+    launch_comp<1>(static_ssq_dev, p2, out_ssq_dev, out_sdf_dev, nx, ny,
+                   n_slices, Kt, has_above, hf, (uint32_t)V, s);
+  return check_launch(h, "composite");
+}

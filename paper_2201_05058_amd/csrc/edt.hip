@@ -1,0 +1,383 @@
+// Exact separable squared Euclidean distance transform on gfx950.
+//
+// The environment field of the mapping section (computed once for the
+// static map) and the humans' planar fields are both exact signed squared
+// EDTs.  Squared distance is a sum of per-axis terms, so the transform is
+// three 1-D passes; the x pass finds the nearest voxel of the other type
+// along each row, and every later pass takes the lower envelope of
+// parabolas g(q) = min_p f(p) + (q - p)^2 along its axis.
+//
+// Both channels travel in one signed int32 array.  Between passes a free
+// voxel holds +f_O (partial squared distance to the occupied set, >= 1)
+// and an occupied voxel holds -f_F (partial squared distance to the free
+// set, <= -1); +-kInf mean "no such voxel yet".  For the occupied-set
+// channel an occupied voxel is a site of value 0, and for the free-set
+// channel a free voxel is; so each channel's sites are recoverable from
+// the one array and the sign of every voxel never changes.
+//
+// Layout and mapping (CDNA4, wave64):
+//   - x pass: one wave per row; occupancy of 64 voxels at a time is a
+//     wave ballot, and nearest-left / nearest-right indices come from
+//     count-leading / trailing-zeros of the masked ballot with a carry
+//     across chunks.  No LDS.
+//   - y and z passes: lanes run along x, so every step of a column sweep is
+//     one coalesced 128-byte load shared by both halves of the wave:
+//     lanes 0..31 run the occupied-set channel of 32 adjacent columns and
+//     lanes 32..63 the free-set channel of the same columns.  No transpose
+//     is needed because x is the contiguous axis.  Each lane keeps its
+//     envelope stack in LDS, one packed 32-bit entry per site (site index
+//     in 10 bits, value in 22 bits: values stay below 2*1023^2 < 2^22
+//     before the last pass), laid out [depth][lane] so a wave's accesses
+//     spread over all banks.  Intersections are compared by
+//     cross-multiplication in int64, so the envelope has no division.
+#include "device_common.h"
+#include "internal.h"
+
+namespace pcsdf {
+
+// ------------------------------------------------------------------ x pass
+
+struct OccU8 {
+  const uint8_t *p;
+  int nx;
+  __device__ __forceinline__ void row_begin(int64_t) const {}
+  __device__ __forceinline__ bool at(int64_t row, int i) const {
+    return p[row * nx + i] != 0;
+  }
+};
+
+// Union of voxelised disks of one slice: rows are (slice, j).
+struct OccDisks {
+  const int64_t *xy;  // [n_slices][K][2] fixed point
+  int K;
+  int ny;
+  int64_t R;
+  bool empty;
+  __device__ __forceinline__ void row_begin(int64_t) const {}
+  __device__ __forceinline__ bool at(int64_t row, int i) const {
+    if (empty) return false;
+    const int64_t s = row / ny;
+    const int j = (int)(row - s * ny);
+    const int64_t A = 32768LL * (2LL * i + 1);
+    const int64_t B = 32768LL * (2LL * j + 1);
+    const int64_t *c = xy + s * (int64_t)K * 2;
+    const int64_t R2 = R * R;
+    for (int k = 0; k < K; ++k) {
+      const int64_t dx = A - c[2 * k];
+      const int64_t dy = B - c[2 * k + 1];
+      // |dx|, |dy| <= R < 2^31 keeps the sum of squares below 2^63
+      if (dx > R || dx < -R || dy > R || dy < -R) continue;
+      if (dx * dx + dy * dy <= R2) return true;
+    }
+    return false;
+  }
+};
+
+template <int MAXCH, class Occ>
+__global__ __launch_bounds__(256) void k_pass_x(Occ occ, int32_t *out,
+                                                int nx, int64_t rows) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;  // uniform across the wave
+  int32_t *dst = out + row * nx;
+  const int nch = (nx + 63) >> 6;
+  constexpr int kNone = 0x40000000;
+  const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const uint64_t ge = ~0ull << lane;
+
+  int left[MAXCH];
+  bool isocc[MAXCH];
+  int lastO = -kNone, lastF = -kNone;
+#pragma unroll
+  for (int c = 0; c < MAXCH; ++c) {
+    if (c < nch) {
+      const int i = c * 64 + lane;
+      const bool valid = i < nx;
+      const bool o = valid && occ.at(row, i);
+      const uint64_t mO = __ballot(o);
+      const uint64_t mF = __ballot(valid && !o);
+      const uint64_t tO = mO & le, tF = mF & le;
+      const int lo = tO ? c * 64 + 63 - __builtin_clzll(tO) : lastO;
+      const int lf = tF ? c * 64 + 63 - __builtin_clzll(tF) : lastF;
+      left[c] = o ? lf : lo;
+      isocc[c] = o;
+      if (mO) lastO = c * 64 + 63 - __builtin_clzll(mO);
+      if (mF) lastF = c * 64 + 63 - __builtin_clzll(mF);
+    }
+  }
+  int nextO = kNone, nextF = kNone;
+#pragma unroll
+  for (int c = MAXCH - 1; c >= 0; --c) {
+    if (c < nch) {
+      const int i = c * 64 + lane;
+      const bool valid = i < nx;
+      const bool o = isocc[c];
+      const uint64_t mO = __ballot(o);
+      const uint64_t mF = __ballot(valid && !o);
+      const uint64_t tO = mO & ge, tF = mF & ge;
+      const int ro = tO ? c * 64 + __builtin_ctzll(tO) : nextO;
+      const int rf = tF ? c * 64 + __builtin_ctzll(tF) : nextF;
+      const int r = o ? rf : ro;
+      const int l = left[c];
+      if (mO) nextO = c * 64 + __builtin_ctzll(mO);
+      if (mF) nextF = c * 64 + __builtin_ctzll(mF);
+      if (valid) {
+        const bool none_l = l < 0, none_r = r >= nx;
+        int32_t v;
+        if (none_l && none_r) {
+          v = kInf;
+        } else {
+          const int dl = none_l ? kNone : i - l;
+          const int dr = none_r ? kNone : r - i;
+          const int d = dl < dr ? dl : dr;
+          v = d * d;
+        }
+        dst[i] = o ? -v : v;
+      }
+    }
+  }
+}
+
+template <class Occ>
+static int launch_x(Handle *h, const Occ &occ, int32_t *out, int nx,
+                    int64_t rows, hipStream_t s, const char *what) {
+  if (rows <= 0) return PCSDF_OK;
+  const int nch = (nx + 63) / 64;
+  const dim3 grid((unsigned)((rows + 3) / 4)), block(256);
+  if (nch <= 1)
+    hipLaunchKernelGGL((k_pass_x<1, Occ>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  else if (nch <= 2)
+    hipLaunchKernelGGL((k_pass_x<2, Occ>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  else if (nch <= 4)
+    hipLaunchKernelGGL((k_pass_x<4, Occ>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  else if (nch <= 8)
+    hipLaunchKernelGGL((k_pass_x<8, Occ>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  else
+    hipLaunchKernelGGL((k_pass_x<16, Occ>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  return check_launch(h, what);
+}
+
+int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
+                     int64_t rows, hipStream_t s) {
+  return launch_x(h, OccU8{occ, nx}, out, nx, rows, s, "pass_x_u8");
+}
+
+int launch_pass_x_disks(Handle *h, const int64_t *xy, int n_humans,
+                        int64_t R, bool empty, int32_t *out, int nx, int ny,
+                        int n_slices, hipStream_t s) {
+  OccDisks d{xy, n_humans, ny, R, empty || n_humans == 0};
+  return launch_x(h, d, out, nx, (int64_t)n_slices * ny, s, "pass_x_disks");
+}
+
+// ------------------------------------------------------- y / z column pass
+
+__device__ __forceinline__ int site_of(uint32_t e) { return (int)(e >> 22); }
+__device__ __forceinline__ int val_of(uint32_t e) {
+  return (int)(e & 0x3FFFFFu);
+}
+
+template <bool kGlobalStack, bool kWriteSdf>
+__global__ __launch_bounds__(64) void k_pass_col(
+    const int32_t *__restrict__ in, int32_t *__restrict__ out,
+    float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
+    int64_t outer_stride, int64_t nblocks, int tiles, uint32_t *gstack) {
+  extern __shared__ uint32_t lds_stack[];
+  const int lane = threadIdx.x;
+  const int col = lane & 31;
+  const bool inside_ch = lane >= 32;  // channel of the free set
+  uint32_t *stk = kGlobalStack
+                      ? gstack + (int64_t)blockIdx.x * (int64_t)m * 64
+                      : lds_stack;
+
+  for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const int64_t o = b / tiles;
+    const int tile = (int)(b - o * tiles);
+    const int i = tile * 32 + col;
+    const bool active = i < nfast;
+    const int32_t *src = in + o * outer_stride + (active ? i : 0);
+    int32_t *dst = out + o * outer_stride + (active ? i : 0);
+    float *dsdf = kWriteSdf ? sdf + o * outer_stride + (active ? i : 0)
+                            : nullptr;
+
+    // Forward sweep: build the lower envelope of this lane's channel.
+    int top = -1;
+    uint32_t etop = 0;  // stk[top] cached in a register
+    for (int q0 = 0; q0 < m; q0 += 8) {
+      int32_t xb[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = q0 + t;
+        xb[t] = (active && q < m) ? src[(int64_t)q * stride] : 0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = q0 + t;
+        const int32_t x = xb[t];
+        bool site;
+        int f;
+        if (!inside_ch) {  // sites: occupied voxels (0), free with f_O
+          site = x != kInf;
+          f = x > 0 ? x : 0;
+        } else {           // sites: free voxels (0), occupied with f_F
+          site = x != -kInf;
+          f = x < 0 ? -x : 0;
+        }
+        site = site && active && q < m;
+        if (site) {
+          const int fq = f + q * q;
+          while (top >= 1) {
+            const uint32_t eb = stk[(top - 1) * 64 + lane];
+            const int sa = site_of(etop), fa = val_of(etop);
+            const int sb = site_of(eb), fb = val_of(eb);
+            const int64_t lhs = (int64_t)(fq - fa - sa * sa) * (sa - sb);
+            const int64_t rhs =
+                (int64_t)(fa + sa * sa - fb - sb * sb) * (q - sa);
+            if (lhs <= rhs) {
+              --top;
+              etop = eb;
+            } else {
+              break;
+            }
+          }
+          ++top;
+          etop = ((uint32_t)q << 22) | (uint32_t)f;
+          stk[top * 64 + lane] = etop;
+        }
+      }
+    }
+
+    // Fill sweep: walk the envelope and write this channel's voxels.
+    int k = 0;
+    uint32_t ek = top >= 0 ? stk[lane] : 0;
+    uint32_t ek1 = top >= 1 ? stk[64 + lane] : 0;
+    for (int q0 = 0; q0 < m; q0 += 8) {
+      int32_t xb[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = q0 + t;
+        xb[t] = (active && q < m) ? src[(int64_t)q * stride] : 0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = q0 + t;
+        const int32_t x = xb[t];
+        const bool mine = inside_ch ? (x < 0) : (x > 0);
+        int32_t val = kInf;
+        if (top >= 0) {
+          while (k < top) {
+            const int dk = q - site_of(ek), dk1 = q - site_of(ek1);
+            const int vk = dk * dk + val_of(ek);
+            const int vk1 = dk1 * dk1 + val_of(ek1);
+            if (vk1 <= vk) {
+              ++k;
+              ek = ek1;
+              ek1 = k < top ? stk[(k + 1) * 64 + lane] : 0;
+            } else {
+              break;
+            }
+          }
+          const int d = q - site_of(ek);
+          val = d * d + val_of(ek);
+        }
+        if (mine && active && q < m) {
+          const int32_t v = inside_ch ? -val : val;
+          dst[(int64_t)q * stride] = v;
+          if (kWriteSdf) dsdf[(int64_t)q * stride] = ssq_to_metres(v, hf);
+        }
+      }
+    }
+  }
+}
+
+template <bool G, bool W>
+static void set_lds_attr(size_t bytes) {
+  static size_t done = 0;
+  if (bytes > 65536 && bytes > done) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass_col<G, W>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+    done = bytes;
+  }
+}
+
+int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
+                    float *sdf_out, float h_f, int nfast, int nouter, int m,
+                    int64_t stride, int64_t outer_stride, hipStream_t s) {
+  if (nfast <= 0 || nouter <= 0 || m <= 0) return PCSDF_OK;
+  const int tiles = (nfast + 31) / 32;
+  const int64_t nblocks = (int64_t)tiles * nouter;
+  const size_t lds = (size_t)m * 64 * sizeof(uint32_t);
+  const dim3 block(64);
+  if ((int64_t)lds <= h->max_lds) {
+    const unsigned grid = (unsigned)(nblocks < (1LL << 30) ? nblocks
+                                                           : (1LL << 30));
+    if (sdf_out) {
+      set_lds_attr<false, true>(lds);
+      hipLaunchKernelGGL((k_pass_col<false, true>), dim3(grid), block, lds,
+                         s, in, out, sdf_out, h_f, nfast, m, stride,
+                         outer_stride, nblocks, tiles, nullptr);
+    } else {
+      set_lds_attr<false, false>(lds);
+      hipLaunchKernelGGL((k_pass_col<false, false>), dim3(grid), block, lds,
+                         s, in, out, sdf_out, h_f, nfast, m, stride,
+                         outer_stride, nblocks, tiles, nullptr);
+    }
+    return check_launch(h, "pass_col");
+  }
+  // Columns too long for LDS: stacks in a workspace slab, a bounded
+  // number of resident blocks striding over all columns.
+  const int64_t gblocks = nblocks < 4096 ? nblocks : 4096;
+  int rc = ensure_buffer(h, h->stack_buf, (size_t)gblocks * lds, s);
+  if (rc) return rc;
+  uint32_t *gstack = reinterpret_cast<uint32_t *>(h->stack_buf.ptr);
+  if (sdf_out)
+    hipLaunchKernelGGL((k_pass_col<true, true>), dim3((unsigned)gblocks),
+                       block, 0, s, in, out, sdf_out, h_f, nfast, m, stride,
+                       outer_stride, nblocks, tiles, gstack);
+  else
+    hipLaunchKernelGGL((k_pass_col<true, false>), dim3((unsigned)gblocks),
+                       block, 0, s, in, out, sdf_out, h_f, nfast, m, stride,
+                       outer_stride, nblocks, tiles, gstack);
+  return check_launch(h, "pass_col_global_stack");
+}
+
+// --------------------------------------------------------- static build
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+extern "C" int pcsdf_build_static_sdf(pcsdf_handle *hp, const pcsdf_grid *g,
+                                      const uint8_t *occ_dev,
+                                      int32_t *ssq_dev, float *sdf_dev,
+                                      void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_grid(h, g);
+  if (rc) return rc;
+  if (!occ_dev || !ssq_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "occ_dev and ssq_dev are required");
+  if (((uintptr_t)ssq_dev & 3) || ((uintptr_t)sdf_dev & 3))
+    return fail(h, PCSDF_ERR_ALIGN, "ssq_dev/sdf_dev must be 4-byte aligned");
+  if ((rc = bind_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int64_t V = (int64_t)nx * ny * nz;
+  if ((rc = ensure_buffer(h, h->tmp_buf, (size_t)V * 4, s))) return rc;
+  int32_t *tmp = reinterpret_cast<int32_t *>(h->tmp_buf.ptr);
+  const float hf = (float)g->voxel_m;
+  // x: occ -> ssq (as scratch); y: ssq -> tmp; z: tmp -> ssq (+ sdf)
+  ProfScope ps(h, PCSDF_KERNEL_STATIC, s);
+  if ((rc = launch_pass_x_u8(h, occ_dev, ssq_dev, nx, (int64_t)ny * nz, s)))
+    return rc;
+  if ((rc = launch_pass_col(h, ssq_dev, tmp, nullptr, hf, nx, nz, ny, nx,
+                            (int64_t)nx * ny, s)))
+    return rc;
+  return launch_pass_col(h, tmp, ssq_dev, sdf_dev, hf, nx, ny, nz,
+                         (int64_t)nx * ny, nx, s);
+}

@@ -1,0 +1,116 @@
+// Library-internal declarations shared by the translation units of
+// libpcsdf.so: the handle, error reporting, workspace management and the
+// kernel launchers each unit exports to the others.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pcsdf.h"
+
+namespace pcsdf {
+
+constexpr int32_t kInf = INT32_MAX;  // "no site" / empty set
+constexpr int kMaxDim = 1024;
+constexpr int kMaxHumans = 256;
+
+// A device buffer owned by the handle, grown on demand.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Handle {
+  std::string err;
+  int device = -1;
+  int max_lds = 65536;  // bytes of LDS a workgroup may use on `device`
+  DevBuf tmp_buf;       // int32 [V] intermediate of the 3-D EDT
+  DevBuf plane_buf;     // int32 planar fields of the humans
+  DevBuf param_buf;     // per-call parameter blocks (fixed-point centres)
+  DevBuf stack_buf;     // envelope stacks when a column exceeds LDS
+  // pinned host staging for small per-call parameter blocks
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t staging_done = nullptr;
+  bool staging_pending = false;
+  std::vector<int64_t> host_xy;  // fixed-point centres before upload
+  // kernel timing with HIP events on the launch stream (off by default)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_pool;
+  struct Pending {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> prof_pending;
+  double prof_ms[PCSDF_KERNEL_COUNT] = {};
+  int64_t prof_n[PCSDF_KERNEL_COUNT] = {};
+};
+
+// Brackets the launches of one timed region with HIP events when the
+// handle's profiling is on; a no-op otherwise.
+class ProfScope {
+ public:
+  ProfScope(Handle *h, int id, hipStream_t s);
+  ~ProfScope() { stop(); }
+  void stop();
+
+ private:
+  Handle *h_;
+  int id_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+// Records `msg` as the handle's last error and returns `code`.
+int fail(Handle *h, int code, const std::string &msg);
+
+// Binds the handle to the current device on first use, checks later calls
+// use the same device, and reads device limits.
+int bind_device(Handle *h);
+
+// Ensures `b` holds `bytes`; waits for `stream` before freeing a smaller
+// allocation that work already enqueued may still use.
+int ensure_buffer(Handle *h, DevBuf &b, size_t bytes, hipStream_t stream);
+
+// Pinned staging buffer for an H2D parameter upload: waits until the
+// previous upload from it has completed, then guarantees `bytes`.
+int acquire_staging(Handle *h, size_t bytes);
+// Marks the staging buffer as in use by work enqueued on `stream`.
+int release_staging(Handle *h, hipStream_t stream);
+
+// Checks the last launch; on failure records the HIP error.
+int check_launch(Handle *h, const char *what);
+
+int check_grid(Handle *h, const pcsdf_grid *g);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- launchers implemented in edt.hip ----------------------------------
+
+// Row pass along x of a uint8 occupancy grid of `rows` rows of nx voxels:
+// out = +d^2 (free voxel, d = distance along the row to the nearest
+// occupied voxel), -d^2 (occupied, nearest free), +-kInf if none.
+int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
+                     int64_t rows, hipStream_t s);
+
+// Row pass along x of the humans' disk union, per slice: rows are
+// (slice, j) of `n_slices` planes of ny rows; xy holds fixed-point centres
+// [n_slices][n_humans][2]; no human voxel at all when `empty` is set.
+int launch_pass_x_disks(Handle *h, const int64_t *xy, int n_humans,
+                        int64_t R, bool empty, int32_t *out, int nx, int ny,
+                        int n_slices, hipStream_t s);
+
+// Column pass of the separable EDT along a strided axis.  Columns are
+// indexed by (fast index i in [0, nfast), outer index o in [0, nouter)):
+// element q of column (i, o) is at o*outer_stride + i + q*stride, q < m.
+// Input and output are signed-squared partial fields (see edt.hip).
+// When sdf_out is non-null the pass also writes F(out) with voxel size h.
+int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
+                    float *sdf_out, float h_f, int nfast, int nouter, int m,
+                    int64_t stride, int64_t outer_stride, hipStream_t s);
+
+}  // namespace pcsdf

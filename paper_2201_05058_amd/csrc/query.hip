@@ -1,0 +1,177 @@
+// Sphere queries on the per-slice fields.  GPMP2's obstacle factors apply
+// a hinge loss to the distance field sampled at the robot's collision
+// spheres, and RHAP-GPMP2 hands every time index past the prediction
+// horizon the last composite field.  Each lane answers one sphere: the
+// slice is clamped, the centre mapped to fp64 grid coordinates, the eight
+// fp32 corners of its cell gathered, and the trilinear value and its
+// analytic gradient formed in fp64 from weighted corner differences (so no
+// large interpolated values are subtracted).  This unit is built with
+// -ffp-contract=off so every fp64 operation is rounded as written.
+#include <cmath>
+
+#include "internal.h"
+
+namespace pcsdf {
+
+__global__ __launch_bounds__(256) void k_query(
+    const float *__restrict__ sdf, int n_slices, int nx, int ny, int nz,
+    double h, double ox, double oy, double oz, int n_queries,
+    const float *__restrict__ centre, const float *__restrict__ radius,
+    const int32_t *__restrict__ slice, double eps, float *__restrict__ dist,
+    float *__restrict__ grad, uint8_t *__restrict__ status,
+    float *__restrict__ cost) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_queries) return;
+  uint32_t st = 0;
+  int s = slice[q];
+  if (s < 0) {
+    const float nan = __builtin_nanf("");
+    dist[q] = nan;
+    grad[3 * q] = nan;
+    grad[3 * q + 1] = nan;
+    grad[3 * q + 2] = nan;
+    if (cost) cost[q] = nan;
+    if (status) status[q] = (uint8_t)PCSDF_Q_SLICE_NEG;
+    return;
+  }
+  if (s > n_slices - 1) {
+    s = n_slices - 1;
+    st |= PCSDF_Q_SLICE_CLAMPED;
+  }
+  const int64_t V = (int64_t)nx * ny * nz;
+  const float *field = sdf + (int64_t)s * V;
+  const int n[3] = {nx, ny, nz};
+  const double o[3] = {ox, oy, oz};
+  int idx[3];
+  double fr[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double gc = ((double)centre[3 * q + a] - o[a]) / h - 0.5;
+    if (gc < 0.0) {
+      gc = 0.0;
+      st |= 1u << a;
+    } else if (gc > (double)(n[a] - 1)) {
+      gc = (double)(n[a] - 1);
+      st |= 1u << a;
+    }
+    int i = (int)floor(gc);
+    if (i > n[a] - 2) i = n[a] - 2;
+    idx[a] = i;
+    fr[a] = gc - (double)i;
+  }
+  const int64_t base = ((int64_t)idx[2] * ny + idx[1]) * nx + idx[0];
+  const int64_t sy = nx, sz = (int64_t)nx * ny;
+  double c[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        c[a][b][e] = (double)field[base + a + b * sy + e * sz];
+  bool infc = false;
+  double infval = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        if (!infc && isinf(c[a][b][e])) {
+          infc = true;
+          infval = c[a][b][e];
+        }
+  if (infc) {
+    dist[q] = (float)infval;
+    grad[3 * q] = 0.f;
+    grad[3 * q + 1] = 0.f;
+    grad[3 * q + 2] = 0.f;
+    if (cost) cost[q] = infval > 0 ? 0.f : __builtin_inff();
+    if (status) status[q] = (uint8_t)(st | PCSDF_Q_INF_CORNER);
+    return;
+  }
+  double w[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w[a][0] = 1.0 - fr[a];
+    w[a][1] = fr[a];
+  }
+  double D = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) D += w[0][a] * w[1][b] * w[2][e] * c[a][b][e];
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      gx += w[1][b] * w[2][e] * (c[1][b][e] - c[0][b][e]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      gy += w[0][a] * w[2][e] * (c[a][1][e] - c[a][0][e]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      gz += w[0][a] * w[1][b] * (c[a][b][1] - c[a][b][0]);
+  const double dsph = D - (double)radius[q];
+  dist[q] = (float)dsph;
+  grad[3 * q] = (float)(gx / h);
+  grad[3 * q + 1] = (float)(gy / h);
+  grad[3 * q + 2] = (float)(gz / h);
+  if (cost) {
+    const double hc = eps - dsph;
+    cost[q] = (float)(hc > 0.0 ? hc : 0.0);
+  }
+  if (status) status[q] = (uint8_t)st;
+}
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+extern "C" int pcsdf_query_spheres(pcsdf_handle *hp, const pcsdf_grid *g,
+                                   const float *sdf_dev, int32_t n_slices,
+                                   int32_t n_queries, const float *centre_dev,
+                                   const float *radius_dev,
+                                   const int32_t *slice_dev,
+                                   double hinge_eps_m, float *dist_dev,
+                                   float *grad_dev, uint8_t *status_dev,
+                                   float *cost_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_grid(h, g);
+  if (rc) return rc;
+  if (g->nx < 2 || g->ny < 2 || g->nz < 2)
+    return fail(h, PCSDF_ERR_DIMS, "queries need at least 2 voxels per axis");
+  if (n_slices < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
+  if (n_queries < 0)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_queries must be >= 0");
+  if (!std::isfinite(hinge_eps_m))
+    return fail(h, PCSDF_ERR_NUMERIC, "hinge_eps_m must be finite");
+  if (n_queries == 0) return PCSDF_OK;
+  if (!sdf_dev || !centre_dev || !radius_dev || !slice_dev || !dist_dev ||
+      !grad_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "sdf, centre, radius, slice, dist and grad are required");
+  if (((uintptr_t)sdf_dev | (uintptr_t)centre_dev | (uintptr_t)radius_dev |
+       (uintptr_t)slice_dev | (uintptr_t)dist_dev | (uintptr_t)grad_dev |
+       (uintptr_t)cost_dev) & 3)
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  if ((rc = bind_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)((n_queries + 255) / 256)), block(256);
+  ProfScope ps(h, PCSDF_KERNEL_QUERY, s);
+  hipLaunchKernelGGL(k_query, grid, block, 0, s, sdf_dev, n_slices, g->nx,
+                     g->ny, g->nz, g->voxel_m, g->origin_m[0], g->origin_m[1],
+                     g->origin_m[2], n_queries, centre_dev, radius_dev,
+                     slice_dev, hinge_eps_m, dist_dev, grad_dev, status_dev,
+                     cost_dev);
+  return check_launch(h, "query_spheres");
+}

@@ -1,0 +1,176 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point its header declares, and rejects bad arguments on the host before
+touching any device (fake device addresses are passed only to calls that
+must fail validation)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import paper_2201_05058_amd as pc
+from paper_2201_05058_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcsdf.h")
+
+# Addresses never dereferenced: every call using them fails validation.
+FAKE = C.c_void_p(0x10000)
+FAKE_MIS = C.c_void_p(0x10002)
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcsdf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("pcsdf_create", "pcsdf_destroy", "pcsdf_last_error",
+              "pcsdf_build_static_sdf", "pcsdf_predicted_composite_sdf",
+              "pcsdf_query_spheres"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(_native.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    lib = _native.load_library()
+    assert lib.pcsdf_status_string(0) == b"PCSDF_OK"
+    assert lib.pcsdf_status_string(6) == b"PCSDF_ERR_NUMERIC"
+    assert lib.pcsdf_status_string(99) == b"PCSDF_ERR_UNKNOWN"
+
+
+@pytest.fixture()
+def h():
+    hd = pc.Handle()
+    yield hd
+    hd.close()
+
+
+def grid(nx=8, ny=8, nz=8, vox=0.05, origin=(0, 0, 0)):
+    return _native.Grid.make(nx, ny, nz, vox, origin)
+
+
+def comp(h, g, n=2, K=1, xy=None, r=0.25, H=1.8, static=FAKE, out=FAKE,
+         outf=None):
+    import numpy as np
+    if xy is None:
+        xy = np.zeros((n, K, 2))
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    p = xy.ctypes.data_as(C.c_void_p) if xy.size else None
+    return h.lib.pcsdf_predicted_composite_sdf(
+        h.ptr, C.byref(g), static, n, K, p, r, H, out, outf, None)
+
+
+def test_create_destroy_without_device():
+    lib = _native.load_library()
+    hp = C.c_void_p()
+    assert lib.pcsdf_create(C.byref(hp)) == 0
+    assert lib.pcsdf_last_error(hp) == b""
+    lib.pcsdf_destroy(hp)
+    lib.pcsdf_destroy(None)
+    assert lib.pcsdf_create(None) == 1
+
+
+@pytest.mark.parametrize("dims,code", [((0, 4, 4), 2), ((4, 1025, 4), 2),
+                                       ((4, 4, -1), 2)])
+def test_bad_dims(h, dims, code):
+    g = grid(*dims)
+    rc = h.lib.pcsdf_build_static_sdf(h.ptr, C.byref(g), FAKE, FAKE, None,
+                                      None)
+    assert rc == code
+    assert "grid dimensions" in h.lib.pcsdf_last_error(h.ptr).decode()
+
+
+def test_bad_voxel_and_origin(h):
+    for vox in (0.0, -1.0, math.nan, math.inf):
+        g = grid(vox=vox)
+        assert h.lib.pcsdf_build_static_sdf(h.ptr, C.byref(g), FAKE, FAKE,
+                                            None, None) == 6
+    g = grid(origin=(0, math.nan, 0))
+    assert h.lib.pcsdf_build_static_sdf(h.ptr, C.byref(g), FAKE, FAKE, None,
+                                        None) == 6
+    g = grid()
+    g.reserved = 3
+    assert h.lib.pcsdf_build_static_sdf(h.ptr, C.byref(g), FAKE, FAKE, None,
+                                        None) == 1
+
+
+def test_null_and_misaligned(h):
+    g = grid()
+    assert h.lib.pcsdf_build_static_sdf(h.ptr, C.byref(g), None, FAKE, None,
+                                        None) == 1
+    assert h.lib.pcsdf_build_static_sdf(h.ptr, C.byref(g), FAKE, FAKE_MIS,
+                                        None, None) == 3
+    assert h.lib.pcsdf_build_static_sdf(h.ptr, None, FAKE, FAKE, None,
+                                        None) == 1
+    assert comp(h, g, static=None) == 1
+    assert comp(h, g, out=None, outf=None) == 1
+    assert comp(h, g, out=FAKE_MIS) == 3
+
+
+def test_composite_counts(h):
+    import numpy as np
+    g = grid()
+    assert comp(h, g, n=0, xy=np.zeros((0, 1, 2))) == 1
+    assert comp(h, g, K=300, xy=np.zeros((2, 300, 2))) == 1
+    assert comp(h, g, K=-1, xy=np.zeros((0, 0, 2))) == 1
+    rc = h.lib.pcsdf_predicted_composite_sdf(h.ptr, C.byref(g), FAKE, 2, 3,
+                                             None, 0.25, 1.8, FAKE, None,
+                                             None)
+    assert rc == 1
+
+
+def test_composite_numeric_inputs(h):
+    import numpy as np
+    g = grid()
+    for bad in (math.nan, math.inf, -math.inf, 1e300):
+        xy = np.zeros((3, 2, 2))
+        xy[2, 1, 0] = bad
+        assert comp(h, g, n=3, K=2, xy=xy) == 6
+        assert "index 5" in h.lib.pcsdf_last_error(h.ptr).decode()
+    for r, H in ((math.nan, 1.0), (0.25, math.inf), (-0.1, 1.0),
+                 (0.25, -1.0), (1e6, 1.0)):
+        assert comp(h, g, r=r, H=H) == 6
+
+
+def test_query_validation(h):
+    g = grid(nx=1)
+    args = [FAKE, 1, 10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, None, None, None]
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *args) == 2
+    g = grid()
+    a = list(args)
+    a[1] = 0
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *a) == 1
+    a = list(args)
+    a[2] = -5
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *a) == 1
+    a = list(args)
+    a[6] = math.nan
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *a) == 6
+    a = list(args)
+    a[3] = None
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *a) == 1
+    a = list(args)
+    a[7] = FAKE_MIS
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *a) == 3
+    # zero queries is a no-op that touches nothing
+    a = list(args)
+    a[2] = 0
+    assert h.lib.pcsdf_query_spheres(h.ptr, C.byref(g), *a) == 0
+
+
+def test_profile_calls_without_device(h):
+    h.profile(True)
+    ms, n = h.profile_read(_native.KERNEL_COMPOSITE)
+    assert ms == 0.0 and n == 0
+    h.profile_reset()
+    with pytest.raises(pc.PcsdfError):
+        h.profile_read(17)

@@ -1,0 +1,251 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Squared distances must be bit-exact; fp32 fields and query outputs within
+1e-6 relative (with the floors of the query contract).  Inputs are seeded
+synthetic scenes; expected values come only from the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pc(dev):
+    import paper_2201_05058_amd as m
+    m.load_library()
+    return m
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def assert_f32_close(got, want, rel=1e-6):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    fin = np.isfinite(want)
+    assert (np.isfinite(got) == fin).all()
+    np.testing.assert_array_equal(got[~fin], want[~fin])
+    err = np.abs(got[fin].astype(np.float64) - want[fin].astype(np.float64))
+    assert (err <= rel * np.abs(want[fin].astype(np.float64))).all(), \
+        float(err.max())
+
+
+def gpu_static(pc, grid, occ, dev):
+    occ_d = to_dev(occ.astype(np.uint8), dev)
+    ssq, sdf = pc.build_static_sdf(grid, occ_d)
+    torch.cuda.synchronize()
+    return ssq, sdf
+
+
+# ------------------------------------------------------------ static build
+
+STATIC_SHAPES = [  # (nz, ny, nx)
+    (1, 1, 1), (1, 1, 9), (1, 7, 1), (5, 1, 1), (4, 5, 6), (12, 12, 12),
+    (29, 131, 67), (33, 70, 130), (3, 2, 200), (7, 64, 64), (2, 3, 1024),
+]
+
+
+@pytest.mark.parametrize("shape", STATIC_SHAPES)
+def test_static_build_matches_oracle(pc, dev, shape):
+    rng = np.random.default_rng(sum(shape))
+    grid = scenegen.Grid(shape[2], shape[1], shape[0], 0.05)
+    for p in (0.0, 0.003, 0.05, 0.5, 0.97, 1.0):
+        occ = (rng.random(shape) < p).astype(np.uint8)
+        say(f"static shape={shape} p={p}")
+        ssq, sdf = gpu_static(pc, grid, occ, dev)
+        rs, rf = oracle.build_static(grid, occ)
+        np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
+        assert_f32_close(sdf.cpu().numpy(), rf)
+
+
+@pytest.mark.parametrize("shape", [(4, 1024, 3), (700, 5, 40)])
+def test_static_build_long_columns(pc, dev, shape):
+    # Columns longer than one workgroup's LDS can hold take the path with
+    # stacks in workspace memory.
+    rng = np.random.default_rng(7)
+    grid = scenegen.Grid(shape[2], shape[1], shape[0], 0.05)
+    occ = (rng.random(shape) < 0.01).astype(np.uint8)
+    say(f"static long columns shape={shape}")
+    ssq, sdf = gpu_static(pc, grid, occ, dev)
+    rs, rf = oracle.build_static(grid, occ)
+    np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
+
+
+def test_static_build_config1_and_fp32_exact(pc, dev):
+    sc = scenegen.config1()
+    ssq, sdf = gpu_static(pc, sc.grid, sc.occ, dev)
+    rs, rf = oracle.build_static(sc.grid, sc.occ)
+    np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
+    # correctly rounded sqrt on both sides: the fp32 field is bit-identical
+    np.testing.assert_array_equal(sdf.cpu().numpy(), rf)
+
+
+# --------------------------------------------------------------- composite
+
+def run_composite(pc, sc, dev, want_ssq=True, want_sdf=True):
+    ssq_s, _ = gpu_static(pc, sc.grid, sc.occ, dev)
+    c, cf = pc.predicted_composite_sdf(sc.grid, ssq_s, sc.human_xy,
+                                       sc.radius, sc.height,
+                                       want_ssq=want_ssq, want_sdf=want_sdf)
+    torch.cuda.synchronize()
+    return ssq_s, c, cf
+
+
+def check_composite(pc, sc, dev):
+    say(f"composite {sc.name} grid={sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} "
+        f"n={sc.n_slices} K={sc.n_humans} r={sc.radius} H={sc.height}")
+    _, c, cf = run_composite(pc, sc, dev)
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                        sc.height)
+    np.testing.assert_array_equal(c.cpu().numpy(), wc)
+    assert_f32_close(cf.cpu().numpy(), wf)
+
+
+@pytest.mark.parametrize("seed,dims,K,n", [
+    (1, (33, 27, 21), 3, 4), (2, (67, 131, 29), 2, 3), (3, (64, 64, 40), 8, 2),
+    (4, (5, 7, 3), 1, 2), (5, (130, 70, 33), 4, 5), (6, (1, 40, 40), 2, 2),
+    (7, (40, 1, 40), 2, 2), (8, (257, 65, 9), 3, 2)])
+def test_composite_small_scenes(pc, dev, seed, dims, K, n):
+    sc = scenegen.small_scene(seed, *dims, h=0.05, n_boxes=5, n_humans=K,
+                              n_slices=n)
+    check_composite(pc, sc, dev)
+
+
+@pytest.mark.parametrize("r,H", [(0.25, 1.8), (0.0, 1.8), (0.25, 0.01),
+                                 (0.25, 0.0249), (0.25, 0.025), (0.6, 100.0),
+                                 (5.0, 0.5), (5.0, 100.0), (0.07, 0.3)])
+def test_composite_cylinder_edge_cases(pc, dev, r, H):
+    # radius 0, no layer under the top, one layer, the whole column, a disk
+    # covering the whole plane (no free voxel in the plane), both at once.
+    sc = scenegen.small_scene(11, 37, 29, 23, h=0.05, n_boxes=4, n_humans=3,
+                              n_slices=3, radius=r, height=H)
+    check_composite(pc, sc, dev)
+
+
+def test_composite_no_humans_and_empty_static(pc, dev):
+    sc = scenegen.small_scene(12, 20, 18, 16, n_boxes=3, n_humans=2,
+                              n_slices=2)
+    sc.human_xy = np.zeros((2, 0, 2))
+    check_composite(pc, sc, dev)
+    sc2 = scenegen.small_scene(13, 20, 18, 16, n_boxes=3, n_humans=2,
+                               n_slices=2)
+    sc2.occ[:] = 0
+    check_composite(pc, sc2, dev)
+    sc2.human_xy[:] = -100.0  # everyone outside: the whole field is +inf
+    check_composite(pc, sc2, dev)
+    sc3 = scenegen.small_scene(14, 20, 18, 16, n_boxes=3, n_humans=1,
+                               n_slices=1)
+    sc3.occ[:] = 1            # full static grid: -inf everywhere
+    check_composite(pc, sc3, dev)
+
+
+def test_composite_single_output_modes(pc, dev):
+    sc = scenegen.small_scene(15, 36, 30, 20, n_humans=2, n_slices=3)
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                        sc.height)
+    _, c, cf = run_composite(pc, sc, dev, want_sdf=False)
+    assert cf is None
+    np.testing.assert_array_equal(c.cpu().numpy(), wc)
+    _, c, cf = run_composite(pc, sc, dev, want_ssq=False)
+    assert c is None
+    assert_f32_close(cf.cpu().numpy(), wf)
+
+
+def test_composite_config1(pc, dev):
+    check_composite(pc, scenegen.config1(), dev)
+
+
+@pytest.mark.slow
+def test_composite_config2_full(pc, dev):
+    """The full 256x256x128 x 20-slice workload, element by element."""
+    check_composite(pc, scenegen.config2(), dev)
+
+
+def test_composite_deterministic_and_on_side_stream(pc, dev):
+    sc = scenegen.small_scene(16, 96, 64, 48, n_humans=3, n_slices=4)
+    _, c1, f1 = run_composite(pc, sc, dev)
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        _, c2, f2 = run_composite(pc, sc, dev)
+    s.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(f1, f2)
+
+
+# ------------------------------------------------------------------ queries
+
+def check_queries(pc, sc, dev, centre, radius, slices, eps=0.3):
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    _, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                       sc.height)
+    wd, wg, wst, wc = oracle.query(sc.grid, wf, centre, radius, slices,
+                                   hinge_eps=eps)
+    _, _, cf = run_composite(pc, sc, dev, want_ssq=False)
+    d, g, st, cost = pc.query_spheres(sc.grid, cf, to_dev(centre, dev),
+                                      to_dev(radius, dev),
+                                      to_dev(slices, dev), hinge_eps=eps,
+                                      want_cost=True)
+    torch.cuda.synchronize()
+    d, g, st, cost = (x.cpu().numpy() for x in (d, g, st, cost))
+    np.testing.assert_array_equal(st, wst)
+    h = sc.grid.h
+    for got, want, floor in ((d, wd, h), (cost, wc, h)):
+        nanw = np.isnan(want)
+        assert (np.isnan(got) == nanw).all()
+        fin = np.isfinite(want)
+        np.testing.assert_array_equal(got[~fin & ~nanw], want[~fin & ~nanw])
+        err = np.abs(got[fin].astype(np.float64) - want[fin])
+        assert (err <= 1e-6 * np.maximum(np.abs(want[fin]), floor)).all()
+    nanw = np.isnan(wg)
+    assert (np.isnan(g) == nanw).all()
+    err = np.abs(g[~nanw].astype(np.float64) - wg[~nanw])
+    assert (err <= 1e-6 * np.maximum(np.abs(wg[~nanw]), 1.0)).all()
+
+
+def test_queries_config2(pc, dev):
+    sc = scenegen.config2()
+    q = sc.queries
+    say("queries config2 Q=", len(q.radius))
+    check_queries(pc, sc, dev, q.centre, q.radius, q.slice)
+
+
+def test_queries_edge_cases(pc, dev):
+    sc = scenegen.small_scene(21, 40, 36, 30, h=0.05, n_humans=2, n_slices=3)
+    rng = np.random.default_rng(5)
+    Q = 3000
+    L = np.array(sc.grid.extent)
+    centre = (rng.uniform(-0.2, 1.2, size=(Q, 3)) * L).astype(np.float32)
+    # exact voxel centres and the last cell face
+    centre[:50] = ((rng.integers(0, 30, size=(50, 3)) + 0.5) *
+                   sc.grid.h).astype(np.float32)
+    centre[50] = (L - sc.grid.h / 2).astype(np.float32)
+    radius = rng.uniform(0.05, 0.15, Q).astype(np.float32)
+    slices = rng.integers(-2, 6, Q).astype(np.int32)
+    check_queries(pc, sc, dev, centre, radius, slices)
+
+
+def test_queries_infinite_fields(pc, dev):
+    sc = scenegen.small_scene(22, 10, 9, 8, n_humans=1, n_slices=1)
+    sc.occ[:] = 0
+    sc.human_xy[:] = -50.0
+    c = np.array([[0.2, 0.2, 0.2], [0.1, 0.3, 0.2]], np.float32)
+    check_queries(pc, sc, dev, c, np.zeros(2, np.float32),
+                  np.zeros(2, np.int32))
+    sc.occ[:] = 1
+    check_queries(pc, sc, dev, c, np.zeros(2, np.float32),
+                  np.zeros(2, np.int32))
