@@ -127,7 +127,7 @@ int pcsdf_build_static_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
  * is min(static SSQ, SSQ of the humans' voxels), both signed, and its F.
  * Errors: PCSDF_ERR_NUMERIC for non-finite inputs or when a fixed-point
  * value reaches 2^62 in magnitude or R reaches 2^31.
- * Uses a workspace of 8*n_slices*nx*ny + 16*n_slices*n_humans bytes. */
+ * Uses a workspace of 8*n_slices*nx*ny + 24*n_slices*n_humans*ny bytes. */
 int pcsdf_predicted_composite_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                                   const int32_t *static_ssq_dev,
                                   int32_t n_slices, int32_t n_humans,

@@ -218,7 +218,8 @@ extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return;
   if (h->staging_pending) (void)hipEventSynchronize(h->staging_done);
-  DevBuf *bufs[] = {&h->tmp_buf, &h->plane_buf, &h->param_buf, &h->stack_buf};
+  DevBuf *bufs[] = {&h->tmp_buf, &h->plane_buf, &h->chord_buf,
+                    &h->param_buf, &h->stack_buf};
   bool any = false;
   for (DevBuf *b : bufs) any = any || b->ptr;
   if (any) (void)hipDeviceSynchronize();

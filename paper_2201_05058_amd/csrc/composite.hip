@@ -52,10 +52,13 @@ template <int VEC, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     int32_t *__restrict__ oc, float *__restrict__ of, uint32_t nx,
-    uint32_t ny, int n_slices, int Kt, int has_above, float hf, uint32_t V) {
+    uint32_t ny, int n_slices, int G, int Kt, int has_above, float hf,
+    uint32_t V) {
   const uint32_t g = blockIdx.x * 256u + threadIdx.x;
   const uint32_t v0 = g * VEC;
   if (v0 >= V) return;
+  const int s_begin = (int)blockIdx.y * G;
+  const int s_end = min(n_slices, s_begin + G);
   const uint32_t row = v0 / nx;
   const uint32_t i = v0 - row * nx;
   const uint32_t k = row / ny;
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(256) void k_composite(
 
   if constexpr (VEC == 4) {
     const int4 s4 = *reinterpret_cast<const int4 *>(S + v0);
-    for (int sl = 0; sl < n_slices; ++sl) {
+    for (int sl = s_begin; sl < s_end; ++sl) {
       const int4 p4 = *reinterpret_cast<const int4 *>(prow + sl * plane);
       int4 c;
       c.x = min(s4.x, human_value(p4.x, dz2o, zin, dz2i));
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(256) void k_composite(
     }
   } else {
     const int32_t s = S[v0];
-    for (int sl = 0; sl < n_slices; ++sl) {
+    for (int sl = s_begin; sl < s_end; ++sl) {
       const int32_t c = min(s, human_value(prow[sl * plane], dz2o, zin, dz2i));
       const size_t o = (size_t)sl * V + v0;
       if (kSsq) oc[o] = c;
@@ -102,19 +105,20 @@ __global__ __launch_bounds__(256) void k_composite(
 
 template <int VEC>
 static void launch_comp(const int32_t *S, const int32_t *P, int32_t *oc,
-                        float *of, uint32_t nx, uint32_t ny, int n, int Kt,
-                        int has_above, float hf, uint32_t V, hipStream_t s) {
+                        float *of, uint32_t nx, uint32_t ny, int n, int G,
+                        int Kt, int has_above, float hf, uint32_t V,
+                        hipStream_t s) {
   const uint32_t nthreads = (V + VEC - 1) / VEC;
-  const dim3 grid((nthreads + 255) / 256), block(256);
+  const dim3 grid((nthreads + 255) / 256, (n + G - 1) / G), block(256);
   if (oc && of)
     hipLaunchKernelGGL((k_composite<VEC, true, true>), grid, block, 0, s, S,
-                       P, oc, of, nx, ny, n, Kt, has_above, hf, V);
+                       P, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
   else if (oc)
     hipLaunchKernelGGL((k_composite<VEC, true, false>), grid, block, 0, s, S,
-                       P, oc, of, nx, ny, n, Kt, has_above, hf, V);
+                       P, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
   else
     hipLaunchKernelGGL((k_composite<VEC, false, true>), grid, block, 0, s, S,
-                       P, oc, of, nx, ny, n, Kt, has_above, hf, V);
+                       P, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
 }
 
 // Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
@@ -189,7 +193,10 @@ extern "C" int pcsdf_predicted_composite_sdf(
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
   const size_t xy_bytes = xy.size() * sizeof(int64_t);
+  const size_t chord_bytes =
+      (size_t)n_slices * (n_humans > 0 ? n_humans : 1) * ny * sizeof(int2);
   if ((rc = ensure_buffer(h, h->plane_buf, 2 * plane_bytes, s))) return rc;
+  if ((rc = ensure_buffer(h, h->chord_buf, chord_bytes, s))) return rc;
   if ((rc = ensure_buffer(h, h->param_buf, xy_bytes, s))) return rc;
   int64_t *xy_dev = reinterpret_cast<int64_t *>(h->param_buf.ptr);
   if (ncent > 0) {
@@ -201,15 +208,12 @@ extern "C" int pcsdf_predicted_composite_sdf(
     if ((rc = release_staging(h, s))) return rc;
   }
 
-  int32_t *p1 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
-  int32_t *p2 = p1 + (size_t)n_slices * nx * ny;
+  int32_t *p2 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
   // Planar signed field of the disk union, per slice.
   ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
-  if ((rc = launch_pass_x_disks(h, xy_dev, n_humans, R, empty, p1, nx, ny,
-                                n_slices, s)))
-    return rc;
-  if ((rc = launch_pass_col(h, p1, p2, nullptr, 0.f, nx, n_slices, ny, nx,
-                            (int64_t)nx * ny, s)))
+  if ((rc = launch_planes(h, xy_dev, n_humans, R, empty,
+                          reinterpret_cast<int2 *>(h->chord_buf.ptr), p2, nx,
+                          ny, n_slices, s)))
     return rc;
   pp.stop();
   // Streaming epilogue over all voxels and slices.
@@ -217,12 +221,17 @@ extern "C" int pcsdf_predicted_composite_sdf(
   const bool vec4 = (nx % 4 == 0) && !((uintptr_t)static_ssq_dev & 15) &&
                     !((uintptr_t)out_ssq_dev & 15) &&
                     !((uintptr_t)out_sdf_dev & 15);
+  // Slices per block row: consecutive blocks write the same slices, which
+  // keeps the concurrent write streams few and contiguous.
+  int G = h->comp_slices_per_block > 0 ? h->comp_slices_per_block : 2;
+  if (G > n_slices) G = n_slices;
+  while ((n_slices + G - 1) / G > 65535) ++G;
   ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
   if (vec4)
     launch_comp<4>(static_ssq_dev, p2, out_ssq_dev, out_sdf_dev, nx, ny,
-                   n_slices, Kt, has_above, hf, (uint32_t)V, s);
+                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   else
     launch_comp<1>(static_ssq_dev, p2, out_ssq_dev, out_sdf_dev, nx, ny,
-                   n_slices, Kt, has_above, hf, (uint32_t)V, s);
+                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   return check_launch(h, "composite");
 }

@@ -46,33 +46,6 @@ struct OccU8 {
   }
 };
 
-// Union of voxelised disks of one slice: rows are (slice, j).
-struct OccDisks {
-  const int64_t *xy;  // [n_slices][K][2] fixed point
-  int K;
-  int ny;
-  int64_t R;
-  bool empty;
-  __device__ __forceinline__ void row_begin(int64_t) const {}
-  __device__ __forceinline__ bool at(int64_t row, int i) const {
-    if (empty) return false;
-    const int64_t s = row / ny;
-    const int j = (int)(row - s * ny);
-    const int64_t A = 32768LL * (2LL * i + 1);
-    const int64_t B = 32768LL * (2LL * j + 1);
-    const int64_t *c = xy + s * (int64_t)K * 2;
-    const int64_t R2 = R * R;
-    for (int k = 0; k < K; ++k) {
-      const int64_t dx = A - c[2 * k];
-      const int64_t dy = B - c[2 * k + 1];
-      // |dx|, |dy| <= R < 2^31 keeps the sum of squares below 2^63
-      if (dx > R || dx < -R || dy > R || dy < -R) continue;
-      if (dx * dx + dy * dy <= R2) return true;
-    }
-    return false;
-  }
-};
-
 template <int MAXCH, class Occ>
 __global__ __launch_bounds__(256) void k_pass_x(Occ occ, int32_t *out,
                                                 int nx, int64_t rows) {
@@ -165,13 +138,6 @@ static int launch_x(Handle *h, const Occ &occ, int32_t *out, int nx,
 int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
                      int64_t rows, hipStream_t s) {
   return launch_x(h, OccU8{occ, nx}, out, nx, rows, s, "pass_x_u8");
-}
-
-int launch_pass_x_disks(Handle *h, const int64_t *xy, int n_humans,
-                        int64_t R, bool empty, int32_t *out, int nx, int ny,
-                        int n_slices, hipStream_t s) {
-  OccDisks d{xy, n_humans, ny, R, empty || n_humans == 0};
-  return launch_x(h, d, out, nx, (int64_t)n_slices * ny, s, "pass_x_disks");
 }
 
 // ------------------------------------------------------- y / z column pass

@@ -30,6 +30,7 @@ struct Handle {
   int max_lds = 65536;  // bytes of LDS a workgroup may use on `device`
   DevBuf tmp_buf;       // int32 [V] intermediate of the 3-D EDT
   DevBuf plane_buf;     // int32 planar fields of the humans
+  DevBuf chord_buf;     // int2 chords of the humans' disks per row
   DevBuf param_buf;     // per-call parameter blocks (fixed-point centres)
   DevBuf stack_buf;     // envelope stacks when a column exceeds LDS
   // pinned host staging for small per-call parameter blocks
@@ -38,6 +39,7 @@ struct Handle {
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
   std::vector<int64_t> host_xy;  // fixed-point centres before upload
+  int comp_slices_per_block = 0;  // composite launch shape; 0 = default
   // kernel timing with HIP events on the launch stream (off by default)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_pool;
@@ -97,12 +99,13 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
                      int64_t rows, hipStream_t s);
 
-// Row pass along x of the humans' disk union, per slice: rows are
-// (slice, j) of `n_slices` planes of ny rows; xy holds fixed-point centres
-// [n_slices][n_humans][2]; no human voxel at all when `empty` is set.
-int launch_pass_x_disks(Handle *h, const int64_t *xy, int n_humans,
-                        int64_t R, bool empty, int32_t *out, int nx, int ny,
-                        int n_slices, hipStream_t s);
+// Planar signed field of the humans' disk union for every slice, into
+// P [n_slices][ny][nx]: chords per (slice, human, row) into `chords`, then
+// one lane per pixel.  xy holds fixed-point centres [n_slices][K][2]; no
+// human voxel at all when `empty` is set.
+int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
+                  int2 *chords, int32_t *P, int nx, int ny, int n_slices,
+                  hipStream_t s);
 
 // Column pass of the separable EDT along a strided axis.  Columns are
 // indexed by (fast index i in [0, nfast), outer index o in [0, nouter)):
