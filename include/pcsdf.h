@@ -64,7 +64,8 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (two kernels) */
 #define PCSDF_KERNEL_QUERY 2     /* sphere query kernel */
 #define PCSDF_KERNEL_STATIC 3    /* the three passes of the static build */
-#define PCSDF_KERNEL_COUNT 4
+#define PCSDF_KERNEL_BATCH 4     /* a batch: both persistent launches */
+#define PCSDF_KERNEL_COUNT 5
 
 typedef struct pcsdf_handle pcsdf_handle;
 
@@ -155,6 +156,73 @@ int pcsdf_query_spheres(pcsdf_handle *h, const pcsdf_grid *grid,
                         const float *radius_dev, const int32_t *slice_dev,
                         double hinge_eps_m, float *dist_dev, float *grad_dev,
                         uint8_t *status_dev, float *cost_dev, void *stream);
+
+/* ---- Batches of scenes ------------------------------------------------
+ * One scene: the arguments of pcsdf_predicted_composite_sdf.  Scenes of a
+ * batch may differ in grid size, voxel size, slice count and humans. */
+typedef struct pcsdf_scene {
+  pcsdf_grid grid;
+  const int32_t *static_ssq_dev; /* [V] device, read */
+  int32_t n_slices, n_humans;
+  const double *human_xy_host; /* [n_slices][n_humans][2] host, read */
+  double radius_m, height_m;
+  int32_t *out_ssq_dev; /* [n_slices][V] device, may be NULL */
+  float *out_sdf_dev;   /* [n_slices][V] device, may be NULL */
+} pcsdf_scene;
+
+/* Launch shapes (0 = library default).  Chosen by the autotuner
+ * (pcsdf_autotune_*) or set directly. */
+typedef struct pcsdf_tuning {
+  int32_t composite_slices_per_block; /* composite: slices per block row */
+  int32_t batch_slices_per_item;      /* batch: slices per composite item */
+  int32_t batch_chunk_quads;          /* batch: voxel quads per composite
+                                         item, a multiple of 256 */
+  int32_t batch_blocks_per_cu;        /* batch: persistent workgroups per CU,
+                                         at most 32 */
+} pcsdf_tuning;
+
+int pcsdf_set_tuning(pcsdf_handle *h, const pcsdf_tuning *t);
+int pcsdf_get_tuning(const pcsdf_handle *h, pcsdf_tuning *t);
+
+/* All scenes' composite fields in two persistent launches: the same
+ * outputs, byte for byte, as one pcsdf_predicted_composite_sdf call per
+ * scene.  A fixed grid strides over the (scene, slice) planar-field items
+ * of all scenes, then a second over the (scene, slice group, voxel chunk)
+ * composite items; no workgroup waits on another.  Host arrays are read
+ * before the call returns.  Workspace: per scene
+ * 8*n_slices*nx*ny + 8*n_slices*max(n_humans,1)*ny bytes, plus the work
+ * list.  Errors as pcsdf_predicted_composite_sdf, prefixed with the scene
+ * index. */
+int pcsdf_predicted_composite_sdf_batch(pcsdf_handle *h, int32_t n_scenes,
+                                        const pcsdf_scene *scenes,
+                                        void *stream);
+
+/* The same batch captured once in a hipGraph (parameter upload from pinned
+ * memory owned by the graph, then the two persistent launches) and
+ * replayed with one hipGraphLaunch.  The graph owns its workspace; the
+ * scenes' device buffers must outlive it.  set_positions replaces one
+ * scene's predicted positions for later launches (waiting for a launch
+ * still reading them).  Errors of graph calls are reported through the
+ * creating handle. */
+typedef struct pcsdf_batch_graph pcsdf_batch_graph;
+int pcsdf_batch_graph_create(pcsdf_handle *h, int32_t n_scenes,
+                             const pcsdf_scene *scenes, void *stream,
+                             pcsdf_batch_graph **out);
+int pcsdf_batch_graph_set_positions(pcsdf_batch_graph *g, int32_t scene,
+                                    const double *human_xy_host);
+int pcsdf_batch_graph_launch(pcsdf_batch_graph *g, void *stream);
+void pcsdf_batch_graph_destroy(pcsdf_batch_graph *g);
+
+/* Autotuners: time candidate launch shapes (`reps` runs each, HIP events
+ * on `stream`) on the caller's real inputs, store the fastest in the
+ * handle's tuning and return it with its time in milliseconds.  Outputs
+ * are written as by the tuned call.  They synchronise with the device. */
+int pcsdf_autotune_batch(pcsdf_handle *h, int32_t n_scenes,
+                         const pcsdf_scene *scenes, void *stream,
+                         int32_t reps, pcsdf_tuning *best, double *best_ms);
+int pcsdf_autotune_composite(pcsdf_handle *h, const pcsdf_scene *scene,
+                             void *stream, int32_t reps, pcsdf_tuning *best,
+                             double *best_ms);
 
 /* Kernel timing for measurement.  When on, each timed region (the
  * PCSDF_KERNEL_* ids) is bracketed by two hipEventRecord calls on the

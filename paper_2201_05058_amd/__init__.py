@@ -11,13 +11,16 @@ import ctypes as C
 
 import numpy as np
 
+from . import _native
 from ._native import (Grid, Handle, PcsdfError, Q_INF_CORNER, Q_OOR_X,
                       Q_OOR_Y, Q_OOR_Z, Q_SLICE_CLAMPED, Q_SLICE_NEG,
-                      as_grid, default_handle, load_library)
+                      Scene, Tuning, as_grid, default_handle, load_library)
 
 __all__ = [
     "Grid", "Handle", "PcsdfError", "build_static_sdf",
     "predicted_composite_sdf", "query_spheres", "load_library",
+    "predicted_composite_sdf_batch", "BatchGraph",
+    "autotune_batch", "autotune_composite", "Scene", "Tuning",
     "Q_OOR_X", "Q_OOR_Y", "Q_OOR_Z", "Q_SLICE_CLAMPED", "Q_INF_CORNER",
     "Q_SLICE_NEG",
 ]
@@ -100,6 +103,118 @@ def predicted_composite_sdf(grid, static_ssq, human_xy, radius, height,
         _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev))
     h.check(rc)
     return out_ssq, out_sdf
+
+
+class _BatchScenes:
+    """pcsdf_scene array for a list of scene dicts, with outputs allocated
+    where not given, and the arrays it points to kept alive."""
+
+    def __init__(self, scenes):
+        torch = _torch()
+        self.keep = []
+        self.outputs = []
+        arr = (_native.Scene * len(scenes))()
+        for q, d in enumerate(scenes):
+            g = as_grid(d["grid"])
+            s = d["static_ssq"]
+            xy = np.ascontiguousarray(np.asarray(d["human_xy"],
+                                                 dtype=np.float64))
+            if xy.ndim != 3 or xy.shape[2] != 2:
+                raise ValueError(f"scene {q}: human_xy must be [n, K, 2]")
+            n, K = xy.shape[0], xy.shape[1]
+            V = g.nvox
+            shp = (n,) + g.shape_zyx
+            oc = d.get("out_ssq")
+            of = d.get("out_sdf")
+            if oc is None and d.get("want_ssq", True):
+                oc = torch.empty(shp, dtype=torch.int32, device=s.device)
+            if of is None and d.get("want_sdf", True):
+                of = torch.empty(shp, dtype=torch.float32, device=s.device)
+            e = arr[q]
+            e.grid = g
+            e.static_ssq_dev = _dev_ptr(s, torch.int32, "static_ssq", V)
+            e.n_slices, e.n_humans = n, K
+            e.human_xy_host = xy.ctypes.data_as(C.c_void_p) if K else None
+            e.radius_m = float(d["radius"])
+            e.height_m = float(d["height"])
+            e.out_ssq_dev = _dev_ptr(oc, torch.int32, "out_ssq", n * V)
+            e.out_sdf_dev = _dev_ptr(of, torch.float32, "out_sdf", n * V)
+            self.keep.append(xy)
+            self.outputs.append((oc, of))
+        self.arr = arr
+        self.n = len(scenes)
+        self.device = scenes[0]["static_ssq"].device
+
+
+def predicted_composite_sdf_batch(scenes, handle: Handle | None = None):
+    """All scenes in two persistent launches
+    (pcsdf_predicted_composite_sdf_batch).  `scenes` is a list of dicts
+    with keys grid, static_ssq, human_xy, radius, height and optionally
+    out_ssq / out_sdf / want_ssq / want_sdf.  Returns [(ssq, sdf), ...]."""
+    h = handle or default_handle()
+    b = _BatchScenes(scenes)
+    h.check(h.lib.pcsdf_predicted_composite_sdf_batch(
+        h.ptr, b.n, b.arr, _stream(b.device)))
+    return b.outputs
+
+
+class BatchGraph:
+    """A batch captured in a hipGraph (pcsdf_batch_graph_*)."""
+
+    def __init__(self, scenes, handle: Handle | None = None):
+        self.h = handle or default_handle()
+        self.b = _BatchScenes(scenes)
+        g = C.c_void_p()
+        self.h.check(self.h.lib.pcsdf_batch_graph_create(
+            self.h.ptr, self.b.n, self.b.arr, _stream(self.b.device),
+            C.byref(g)))
+        self.ptr = g
+        self.outputs = self.b.outputs
+
+    def launch(self):
+        self.h.check(self.h.lib.pcsdf_batch_graph_launch(
+            self.ptr, _stream(self.b.device)))
+
+    def set_positions(self, scene: int, human_xy):
+        xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+        self.h.check(self.h.lib.pcsdf_batch_graph_set_positions(
+            self.ptr, int(scene), xy.ctypes.data_as(C.c_void_p)))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.h.lib.pcsdf_batch_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_batch(scenes, reps: int = 2, handle: Handle | None = None):
+    """Times the batch launch shapes on these scenes and keeps the fastest
+    in the handle (pcsdf_autotune_batch).  Returns (tuning dict, ms)."""
+    h = handle or default_handle()
+    b = _BatchScenes(scenes)
+    t = _native.Tuning()
+    ms = C.c_double()
+    h.check(h.lib.pcsdf_autotune_batch(h.ptr, b.n, b.arr, _stream(b.device),
+                                       int(reps), C.byref(t), C.byref(ms)))
+    return t.as_dict(), ms.value
+
+
+def autotune_composite(scene, reps: int = 3, handle: Handle | None = None):
+    """Times the composite launch shapes for one scene and keeps the
+    fastest in the handle (pcsdf_autotune_composite)."""
+    h = handle or default_handle()
+    b = _BatchScenes([scene])
+    t = _native.Tuning()
+    ms = C.c_double()
+    h.check(h.lib.pcsdf_autotune_composite(h.ptr, b.arr, _stream(b.device),
+                                           int(reps), C.byref(t),
+                                           C.byref(ms)))
+    return t.as_dict(), ms.value, b.outputs[0]
 
 
 def query_spheres(grid, sdf, centre, radius, slices, hinge_eps=0.0,

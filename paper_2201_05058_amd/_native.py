@@ -23,6 +23,7 @@ STATUS_NAMES = {
 Q_OOR_X, Q_OOR_Y, Q_OOR_Z = 1, 2, 4
 Q_SLICE_CLAMPED, Q_INF_CORNER, Q_SLICE_NEG = 8, 16, 32
 KERNEL_COMPOSITE, KERNEL_PLANES, KERNEL_QUERY, KERNEL_STATIC = 0, 1, 2, 3
+KERNEL_BATCH = 4
 
 
 class PcsdfError(RuntimeError):
@@ -54,6 +55,33 @@ class Grid(C.Structure):
     @property
     def shape_zyx(self):
         return (self.nz, self.ny, self.nx)
+
+
+class Scene(C.Structure):
+    """pcsdf_scene: one scene of a batch."""
+    _fields_ = [("grid", Grid), ("static_ssq_dev", C.c_void_p),
+                ("n_slices", C.c_int32), ("n_humans", C.c_int32),
+                ("human_xy_host", C.c_void_p), ("radius_m", C.c_double),
+                ("height_m", C.c_double), ("out_ssq_dev", C.c_void_p),
+                ("out_sdf_dev", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    """pcsdf_tuning: launch shapes (0 = library default)."""
+    _fields_ = [("composite_slices_per_block", C.c_int32),
+                ("batch_slices_per_item", C.c_int32),
+                ("batch_chunk_quads", C.c_int32),
+                ("batch_blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for f, _ in cls._fields_:
+            setattr(t, f, int(d.get(f, 0)))
+        return t
 
 
 def as_grid(g) -> Grid:
@@ -105,6 +133,29 @@ def load_library():
         lib.pcsdf_profile_read.restype = C.c_int
         lib.pcsdf_profile_reset.argtypes = [P]
         lib.pcsdf_profile_reset.restype = C.c_int
+        SP = C.POINTER(Scene)
+        TP = C.POINTER(Tuning)
+        lib.pcsdf_set_tuning.argtypes = [P, TP]
+        lib.pcsdf_set_tuning.restype = C.c_int
+        lib.pcsdf_get_tuning.argtypes = [P, TP]
+        lib.pcsdf_get_tuning.restype = C.c_int
+        lib.pcsdf_predicted_composite_sdf_batch.argtypes = [P, i32, SP, P]
+        lib.pcsdf_predicted_composite_sdf_batch.restype = C.c_int
+        lib.pcsdf_batch_graph_create.argtypes = [P, i32, SP, P,
+                                                 C.POINTER(P)]
+        lib.pcsdf_batch_graph_create.restype = C.c_int
+        lib.pcsdf_batch_graph_set_positions.argtypes = [P, i32, P]
+        lib.pcsdf_batch_graph_set_positions.restype = C.c_int
+        lib.pcsdf_batch_graph_launch.argtypes = [P, P]
+        lib.pcsdf_batch_graph_launch.restype = C.c_int
+        lib.pcsdf_batch_graph_destroy.argtypes = [P]
+        lib.pcsdf_batch_graph_destroy.restype = None
+        lib.pcsdf_autotune_batch.argtypes = [P, i32, SP, P, i32, TP,
+                                             C.POINTER(C.c_double)]
+        lib.pcsdf_autotune_batch.restype = C.c_int
+        lib.pcsdf_autotune_composite.argtypes = [P, SP, P, i32, TP,
+                                                 C.POINTER(C.c_double)]
+        lib.pcsdf_autotune_composite.restype = C.c_int
         _lib = lib
         return lib
 
@@ -139,6 +190,16 @@ class Handle:
         self.check(self.lib.pcsdf_profile_read(self.ptr, int(kernel_id),
                                                C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_tuning(self, t):
+        if isinstance(t, dict):
+            t = Tuning.from_dict(t)
+        self.check(self.lib.pcsdf_set_tuning(self.ptr, C.byref(t)))
+
+    def get_tuning(self) -> "Tuning":
+        t = Tuning()
+        self.check(self.lib.pcsdf_get_tuning(self.ptr, C.byref(t)))
+        return t
 
     def close(self):
         if self.ptr:

@@ -218,8 +218,9 @@ extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return;
   if (h->staging_pending) (void)hipEventSynchronize(h->staging_done);
-  DevBuf *bufs[] = {&h->tmp_buf, &h->plane_buf, &h->chord_buf,
-                    &h->param_buf, &h->stack_buf};
+  DevBuf *bufs[] = {&h->tmp_buf,       &h->plane_buf,      &h->chord_buf,
+                    &h->param_buf,     &h->stack_buf,      &h->batch_params,
+                    &h->batch_scratch};
   bool any = false;
   for (DevBuf *b : bufs) any = any || b->ptr;
   if (any) (void)hipDeviceSynchronize();
@@ -239,6 +240,27 @@ extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
 extern "C" const char *pcsdf_last_error(const pcsdf_handle *hp) {
   const Handle *h = reinterpret_cast<const Handle *>(hp);
   return h ? h->err.c_str() : "null handle";
+}
+
+extern "C" int pcsdf_set_tuning(pcsdf_handle *hp, const pcsdf_tuning *t) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!t) return fail(h, PCSDF_ERR_INVALID_ARG, "tuning is NULL");
+  if (t->composite_slices_per_block < 0 || t->batch_slices_per_item < 0 ||
+      t->batch_chunk_quads < 0 || t->batch_blocks_per_cu < 0 ||
+      t->batch_blocks_per_cu > 32 || t->batch_chunk_quads % 256 != 0)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "tuning values must be >= 0, blocks per CU <= 32 and chunk "
+                "quads a multiple of 256");
+  h->tuning = *t;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_get_tuning(const pcsdf_handle *hp, pcsdf_tuning *t) {
+  const Handle *h = reinterpret_cast<const Handle *>(hp);
+  if (!h || !t) return PCSDF_ERR_INVALID_ARG;
+  *t = h->tuning;
+  return PCSDF_OK;
 }
 
 extern "C" const char *pcsdf_status_string(int status) {

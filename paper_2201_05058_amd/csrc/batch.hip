@@ -1,0 +1,382 @@
+// Batched predicted composite fields: many scenes of uneven grid sizes and
+// slice counts in two persistent launches, optionally captured in one
+// hipGraph with the upload of their parameters.
+//
+// Work list.  The planar-field items (scene, slice) and the composite items
+// (scene, slice group, voxel chunk) of all scenes, scene-major.  A fixed
+// persistent grid strides over the planar items, then a second over the
+// composite items; the only dependency (a composite item reads its
+// slices' planes) is the stream order of the two launches.  No workgroup
+// ever waits on another, so every workgroup runs a bounded number of
+// bounded items.  The launch shape (slices per composite item, voxels per
+// item, workgroups per CU) comes from the handle's tuning, which the
+// autotuner below fills by timing candidates on the caller's inputs.
+//
+// The device code lives in batch_device.h and the planning in
+// batch_plan.h, so that both can also be compiled for the host.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "batch_device.h"
+#include "batch_plan.h"
+#include "internal.h"
+
+namespace pcsdf {
+
+__global__ __launch_bounds__(256) void k_batch_planes(
+    const SceneDev *__restrict__ scenes, const int4 *__restrict__ items,
+    int n_items, int lds_cap) {
+  extern __shared__ int4 lds[];
+  batch_planes(scenes, items, n_items, lds_cap, lds);
+}
+
+__global__ __launch_bounds__(256) void k_batch_composites(
+    const SceneDev *__restrict__ scenes, const int4 *__restrict__ items,
+    int n_items, int G, uint32_t chunk_voxels) {
+  batch_composites(scenes, items, n_items, G, chunk_voxels);
+}
+
+// -------------------------------------------------------------- host side
+
+// Enqueues the two persistent launches (parameters already uploaded to
+// pbase).
+static int enqueue_batch(Handle *h, const BatchPlan &bp, char *pbase,
+                         hipStream_t s) {
+  const SceneDev *scenes = reinterpret_cast<const SceneDev *>(pbase);
+  const int4 *items =
+      reinterpret_cast<const int4 *>(pbase + param_layout(bp).items);
+  const int np = bp.n_plane_items;
+  const int nc = (int)bp.items.size() - np;
+  if (np > 0) {
+    hipLaunchKernelGGL(k_batch_planes, dim3(std::min(np, bp.blocks)),
+                       dim3(256), (size_t)bp.lds_cap, s, scenes, items, np,
+                       bp.lds_cap);
+    int rc = check_launch(h, "batch_planes");
+    if (rc) return rc;
+  }
+  if (nc > 0) {
+    hipLaunchKernelGGL(k_batch_composites, dim3(std::min(nc, bp.blocks)),
+                       dim3(256), 0, s, scenes, items + np, nc, bp.G,
+                       bp.chunk_voxels);
+    return check_launch(h, "batch_composites");
+  }
+  return PCSDF_OK;
+}
+
+static int device_cus(Handle *h, int *n_cu) {
+  int v = 0;
+  hipError_t e =
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount,
+                            h->device);
+  if (e != hipSuccess || v <= 0)
+    return fail(h, PCSDF_ERR_HIP, "cannot read the compute unit count");
+  *n_cu = v;
+  return PCSDF_OK;
+}
+
+// Plans, uploads and enqueues one batch through the handle's buffers.
+static int run_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
+                     const pcsdf_tuning &tu, hipStream_t s) {
+  int rc;
+  if ((rc = bind_device(h))) return rc;
+  int n_cu = 0;
+  if ((rc = device_cus(h, &n_cu))) return rc;
+  BatchPlan bp;
+  if ((rc = plan_batch(h, n_scenes, scenes, tu, n_cu, &bp))) return rc;
+  std::vector<char> &host = h->batch_host;
+  if ((rc = ensure_buffer(h, h->batch_params, param_layout(bp).total, s)))
+    return rc;
+  if ((rc = ensure_buffer(h, h->batch_scratch, plan_scratch(bp), s)))
+    return rc;
+  char *pbase = reinterpret_cast<char *>(h->batch_params.ptr);
+  bind_plan(&bp, scenes, pbase, reinterpret_cast<char *>(h->batch_scratch.ptr),
+            &host);
+  if ((rc = acquire_staging(h, host.size()))) return rc;
+  std::memcpy(h->pinned, host.data(), host.size());
+  if (hipMemcpyAsync(pbase, h->pinned, host.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP, "upload of the batch parameters failed");
+  if ((rc = release_staging(h, s))) return rc;
+  ProfScope ps(h, PCSDF_KERNEL_BATCH, s);
+  return enqueue_batch(h, bp, pbase, s);
+}
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+struct pcsdf_batch_graph {
+  Handle *h = nullptr;
+  BatchPlan plan;
+  std::vector<pcsdf_scene> scenes;
+  DevBuf params, scratch;
+  void *pinned = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+extern "C" int pcsdf_predicted_composite_sdf_batch(pcsdf_handle *hp,
+                                                   int32_t n_scenes,
+                                                   const pcsdf_scene *scenes,
+                                                   void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  h->err.clear();
+  return run_batch(h, n_scenes, scenes, h->tuning,
+                   reinterpret_cast<hipStream_t>(stream));
+}
+
+static int graph_fail(pcsdf_batch_graph *g, int code, const std::string &m) {
+  return fail(g->h, code, m);
+}
+
+extern "C" void pcsdf_batch_graph_destroy(pcsdf_batch_graph *g) {
+  if (!g) return;
+  if (g->pending && g->done) (void)hipEventSynchronize(g->done);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->done) (void)hipEventDestroy(g->done);
+  DevBuf *bufs[] = {&g->params, &g->scratch};
+  bool any = false;
+  for (DevBuf *b : bufs) any = any || b->ptr;
+  if (any) (void)hipDeviceSynchronize();
+  for (DevBuf *b : bufs)
+    if (b->ptr) (void)hipFree(b->ptr);
+  if (g->pinned) (void)hipHostFree(g->pinned);
+  delete g;
+}
+
+extern "C" int pcsdf_batch_graph_create(pcsdf_handle *hp, int32_t n_scenes,
+                                        const pcsdf_scene *scenes,
+                                        void *stream,
+                                        pcsdf_batch_graph **out) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!out) return fail(h, PCSDF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  h->err.clear();
+  (void)stream;  // capture runs on a private stream
+  int rc;
+  if ((rc = bind_device(h))) return rc;
+  int n_cu = 0;
+  if ((rc = device_cus(h, &n_cu))) return rc;
+  pcsdf_batch_graph *g = new (std::nothrow) pcsdf_batch_graph();
+  if (!g) return fail(h, PCSDF_ERR_OOM, "graph object allocation failed");
+  g->h = h;
+  if ((rc = plan_batch(h, n_scenes, scenes, h->tuning, n_cu, &g->plan))) {
+    delete g;
+    return rc;
+  }
+  g->scenes.assign(scenes, scenes + n_scenes);
+  std::vector<char> host;
+  hipStream_t cap = nullptr;
+  if ((rc = ensure_buffer(h, g->params, param_layout(g->plan).total,
+                          nullptr)) ||
+      (rc = ensure_buffer(h, g->scratch, plan_scratch(g->plan), nullptr))) {
+    pcsdf_batch_graph_destroy(g);
+    return rc;
+  }
+  char *pbase = reinterpret_cast<char *>(g->params.ptr);
+  bind_plan(&g->plan, scenes, pbase, reinterpret_cast<char *>(g->scratch.ptr),
+            &host);
+  if (hipHostMalloc(&g->pinned, host.size(), hipHostMallocDefault) !=
+      hipSuccess) {
+    g->pinned = nullptr;
+    pcsdf_batch_graph_destroy(g);
+    return fail(h, PCSDF_ERR_OOM, "pinned staging allocation failed");
+  }
+  std::memcpy(g->pinned, host.data(), host.size());
+  if (hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+    pcsdf_batch_graph_destroy(g);
+    return fail(h, PCSDF_ERR_HIP, "graph stream/event creation failed");
+  }
+  bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) ==
+            hipSuccess;
+  if (ok) {
+    ok = hipMemcpyAsync(pbase, g->pinned, host.size(), hipMemcpyHostToDevice,
+                        cap) == hipSuccess;
+    if (ok) ok = enqueue_batch(h, g->plan, pbase, cap) == PCSDF_OK;
+    hipGraph_t graph = nullptr;
+    const bool ended = hipStreamEndCapture(cap, &graph) == hipSuccess;
+    ok = ok && ended && graph;
+    g->graph = graph;
+  }
+  if (ok)
+    ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) ==
+         hipSuccess;
+  (void)hipStreamDestroy(cap);
+  if (!ok) {
+    (void)hipGetLastError();
+    pcsdf_batch_graph_destroy(g);
+    return fail(h, PCSDF_ERR_HIP, "capturing the batch graph failed");
+  }
+  *out = g;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_batch_graph_set_positions(pcsdf_batch_graph *g,
+                                               int32_t scene,
+                                               const double *human_xy_host) {
+  if (!g) return PCSDF_ERR_INVALID_ARG;
+  Handle *h = g->h;
+  if (scene < 0 || scene >= (int32_t)g->scenes.size())
+    return graph_fail(g, PCSDF_ERR_INVALID_ARG, "scene index out of range");
+  const pcsdf_scene &sc = g->scenes[scene];
+  const SceneDev &d = g->plan.scenes[scene];
+  if (d.K == 0) return PCSDF_OK;
+  if (!human_xy_host)
+    return graph_fail(g, PCSDF_ERR_INVALID_ARG, "human_xy_host is NULL");
+  std::vector<int64_t> tmp((size_t)d.n * d.K * 2);
+  for (int64_t t = 0; t < (int64_t)d.n * d.K; ++t) {
+    if (!fixed(human_xy_host[2 * t], sc.grid.origin_m[0], sc.grid.voxel_m,
+               &tmp[2 * t]) ||
+        !fixed(human_xy_host[2 * t + 1], sc.grid.origin_m[1], sc.grid.voxel_m,
+               &tmp[2 * t + 1]))
+      return graph_fail(g, PCSDF_ERR_NUMERIC,
+                        "human position non-finite or out of range");
+  }
+  if (g->pending) {
+    if (hipEventSynchronize(g->done) != hipSuccess)
+      return graph_fail(g, PCSDF_ERR_HIP, "waiting for the graph failed");
+    g->pending = false;
+  }
+  const size_t off_xy = param_layout(g->plan).xy;
+  std::memcpy(static_cast<char *>(g->pinned) + off_xy +
+                  g->plan.xy_off[scene] * 8,
+              tmp.data(), tmp.size() * 8);
+  (void)h;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_batch_graph_launch(pcsdf_batch_graph *g, void *stream) {
+  if (!g) return PCSDF_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ProfScope ps(g->h, PCSDF_KERNEL_BATCH, s);
+  if (hipGraphLaunch(g->exec, s) != hipSuccess)
+    return graph_fail(g, PCSDF_ERR_HIP, "hipGraphLaunch failed");
+  ps.stop();
+  if (hipEventRecord(g->done, s) != hipSuccess)
+    return graph_fail(g, PCSDF_ERR_HIP, "hipEventRecord failed");
+  g->pending = true;
+  return PCSDF_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+namespace {
+
+// Times `fn` (which enqueues on s) reps times with HIP events; -1 on error.
+template <class F>
+double time_ms(hipStream_t s, int reps, F fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return -1.0;
+  double out = -1.0;
+  if (fn() == PCSDF_OK && hipStreamSynchronize(s) == hipSuccess) {
+    (void)hipEventRecord(a, s);
+    int rc = PCSDF_OK;
+    for (int r = 0; r < reps && rc == PCSDF_OK; ++r) rc = fn();
+    (void)hipEventRecord(b, s);
+    float ms = 0.f;
+    if (rc == PCSDF_OK && hipEventSynchronize(b) == hipSuccess &&
+        hipEventElapsedTime(&ms, a, b) == hipSuccess)
+      out = ms / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return out;
+}
+
+}  // namespace
+
+extern "C" int pcsdf_autotune_batch(pcsdf_handle *hp, int32_t n_scenes,
+                                    const pcsdf_scene *scenes, void *stream,
+                                    int32_t reps, pcsdf_tuning *best,
+                                    double *best_ms) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!best || !best_ms || reps < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "best, best_ms and reps >= 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const pcsdf_tuning base = h->tuning;
+  pcsdf_tuning win = base;
+  double win_ms = -1.0;
+  const int Gs[] = {1, 2, 4};
+  const int Cs[] = {2048, 8192, 32768};
+  const int Bs[] = {2, 4, 8};
+  for (int G : Gs)
+    for (int C : Cs)
+      for (int B : Bs) {
+        pcsdf_tuning t = base;
+        t.batch_slices_per_item = G;
+        t.batch_chunk_quads = C;
+        t.batch_blocks_per_cu = B;
+        const double ms = time_ms(s, reps, [&] {
+          return run_batch(h, n_scenes, scenes, t, s);
+        });
+        if (ms < 0) {
+          h->tuning = base;
+          return h->err.empty() ? fail(h, PCSDF_ERR_HIP, "tuning run failed")
+                                : PCSDF_ERR_HIP;
+        }
+        if (win_ms < 0 || ms < win_ms) {
+          win_ms = ms;
+          win = t;
+        }
+      }
+  h->tuning = win;
+  // leave the outputs as the tuned configuration writes them
+  int rc = run_batch(h, n_scenes, scenes, win, s);
+  if (rc) return rc;
+  *best = win;
+  *best_ms = win_ms;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_autotune_composite(pcsdf_handle *hp,
+                                        const pcsdf_scene *sc, void *stream,
+                                        int32_t reps, pcsdf_tuning *best,
+                                        double *best_ms) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!sc || !best || !best_ms || reps < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "scene, best, best_ms, reps >= 1");
+  const pcsdf_tuning base = h->tuning;
+  pcsdf_tuning win = base;
+  double win_ms = -1.0;
+  const int n = sc->n_slices;
+  const int Gs[] = {1, 2, 3, 4, 5, 10, n};
+  for (int G : Gs) {
+    if (G < 1 || G > n) continue;
+    h->tuning = base;
+    h->tuning.composite_slices_per_block = G;
+    const double ms = time_ms(reinterpret_cast<hipStream_t>(stream), reps, [&] {
+      return pcsdf_predicted_composite_sdf(
+          hp, &sc->grid, sc->static_ssq_dev, sc->n_slices, sc->n_humans,
+          sc->human_xy_host, sc->radius_m, sc->height_m, sc->out_ssq_dev,
+          sc->out_sdf_dev, stream);
+    });
+    if (ms < 0) {
+      h->tuning = base;
+      return PCSDF_ERR_HIP;
+    }
+    if (win_ms < 0 || ms < win_ms) {
+      win_ms = ms;
+      win = h->tuning;
+    }
+  }
+  h->tuning = win;
+  int rc = pcsdf_predicted_composite_sdf(
+      hp, &sc->grid, sc->static_ssq_dev, sc->n_slices, sc->n_humans,
+      sc->human_xy_host, sc->radius_m, sc->height_m, sc->out_ssq_dev,
+      sc->out_sdf_dev, stream);
+  if (rc) return rc;
+  *best = win;
+  *best_ms = win_ms;
+  return PCSDF_OK;
+}

@@ -1,0 +1,176 @@
+// Host side of the batched composite: validation of the scenes, the work
+// list and the layout of the parameter block (see batch.hip).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "batch_device.h"
+#include "internal.h"
+
+namespace pcsdf {
+
+struct BatchPlan {
+  std::vector<SceneDev> scenes;
+  std::vector<int4> items;
+  std::vector<int64_t> xy;
+  std::vector<size_t> xy_off;  // per scene, in int64 units
+  int n_plane_items = 0;  // items[0 .. n_plane_items) are planar items
+  int lds_cap = 0;
+  int G = 2;
+  uint32_t chunk_voxels = 0;
+  int blocks = 0;
+};
+
+inline bool fixed(double p, double o, double h, int64_t *out) {
+  double t = p - o;
+  t = t / h;
+  t = t * 65536.0;
+  if (!std::isfinite(t) || std::fabs(t) >= 4611686018427387904.0) return false;
+  *out = (int64_t)std::nearbyint(t);
+  return true;
+}
+
+// Validates the scenes and fills everything but device addresses.
+inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
+                      const pcsdf_tuning &tu, int n_cu, BatchPlan *bp) {
+  if (n_scenes < 1 || !scenes)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "need at least one scene");
+  bp->G = tu.batch_slices_per_item > 0 ? tu.batch_slices_per_item : 2;
+  const int quads = tu.batch_chunk_quads > 0 ? tu.batch_chunk_quads : 8192;
+  bp->chunk_voxels = (uint32_t)quads * 4;
+  const int bpc = tu.batch_blocks_per_cu > 0 ? tu.batch_blocks_per_cu : 4;
+  bp->blocks = n_cu * bpc;
+  bp->scenes.resize(n_scenes);
+  bp->xy_off.resize(n_scenes);
+  bp->xy.clear();
+  int lds_need = 0;
+  for (int q = 0; q < n_scenes; ++q) {
+    const pcsdf_scene &in = scenes[q];
+    const std::string tag = "scene " + std::to_string(q) + ": ";
+    int rc = check_grid(h, &in.grid);
+    if (rc) return fail(h, rc, tag + h->err);
+    if (!in.static_ssq_dev || (!in.out_ssq_dev && !in.out_sdf_dev))
+      return fail(h, PCSDF_ERR_INVALID_ARG,
+                  tag + "inline field and one output are required");
+    if (in.n_slices < 1 || in.n_humans < 0 || in.n_humans > kMaxHumans ||
+        (in.n_humans > 0 && !in.human_xy_host))
+      return fail(h, PCSDF_ERR_INVALID_ARG, tag + "bad slice/human counts");
+    if (((uintptr_t)in.static_ssq_dev | (uintptr_t)in.out_ssq_dev |
+         (uintptr_t)in.out_sdf_dev) & 3)
+      return fail(h, PCSDF_ERR_ALIGN, tag + "buffers must be 4-byte aligned");
+    const double hv = in.grid.voxel_m;
+    int64_t R, Hq;
+    if (!std::isfinite(in.radius_m) || in.radius_m < 0 ||
+        !std::isfinite(in.height_m) || in.height_m < 0 ||
+        !fixed(in.radius_m, 0.0, hv, &R) || !fixed(in.height_m, 0.0, hv, &Hq) ||
+        R >= (1LL << 31))
+      return fail(h, PCSDF_ERR_NUMERIC, tag + "bad radius or height");
+    SceneDev &d = bp->scenes[q];
+    std::memset(&d, 0, sizeof(d));
+    d.nx = in.grid.nx;
+    d.ny = in.grid.ny;
+    d.nz = in.grid.nz;
+    d.n = in.n_slices;
+    d.V = (uint32_t)((int64_t)d.nx * d.ny * d.nz);
+    d.R = R;
+    d.Kt = Hq >= 32768 ? (int)std::min<int64_t>((Hq - 32768) / 65536, d.nz - 1)
+                       : -1;
+    d.has_above = d.Kt + 1 <= d.nz - 1;
+    d.K = (d.Kt < 0) ? 0 : in.n_humans;
+    d.hf = (float)hv;
+    d.vec4 = (d.nx % 4 == 0) &&
+             !(((uintptr_t)in.static_ssq_dev | (uintptr_t)in.out_ssq_dev |
+                (uintptr_t)in.out_sdf_dev) & 15);
+    bp->xy_off[q] = bp->xy.size();
+    for (int64_t t = 0; t < (int64_t)in.n_slices * in.n_humans; ++t) {
+      int64_t X, Y;
+      if (!fixed(in.human_xy_host[2 * t], in.grid.origin_m[0], hv, &X) ||
+          !fixed(in.human_xy_host[2 * t + 1], in.grid.origin_m[1], hv, &Y))
+        return fail(h, PCSDF_ERR_NUMERIC,
+                    tag + "human position non-finite or out of range at "
+                          "index " + std::to_string(t));
+      if (d.K > 0) {
+        bp->xy.push_back(X);
+        bp->xy.push_back(Y);
+      }
+    }
+    lds_need = std::max(lds_need, d.K * 16 + d.K * d.ny * 8);
+  }
+  bp->lds_cap = std::min(lds_need, 48 * 1024);
+  // items: all planar items, then all composite items, scene-major
+  bp->items.clear();
+  for (int q = 0; q < n_scenes; ++q)
+    for (int s = 0; s < bp->scenes[q].n; ++s)
+      bp->items.push_back(make_int4(kItemPlane, q, s, 0));
+  bp->n_plane_items = (int)bp->items.size();
+  for (int q = 0; q < n_scenes; ++q) {
+    const SceneDev &d = bp->scenes[q];
+    for (int s0 = 0; s0 < d.n; s0 += bp->G)
+      for (uint32_t v = 0; v < d.V; v += bp->chunk_voxels)
+        bp->items.push_back(make_int4(kItemComposite, q, s0, (int)v));
+  }
+  return PCSDF_OK;
+}
+
+inline size_t scratch_of(const SceneDev &d) {
+  const size_t plane = (size_t)d.n * d.nx * d.ny;
+  return align_up((size_t)d.n * std::max(d.K, 1) * d.ny * sizeof(int2), 256) +
+         2 * align_up(plane * sizeof(int32_t), 256);
+}
+
+// Byte offsets of the parameter block: scene table, items, centres.
+struct ParamLayout {
+  size_t items, xy, total;
+};
+inline ParamLayout param_layout(const BatchPlan &bp) {
+  ParamLayout L;
+  L.items = align_up(bp.scenes.size() * sizeof(SceneDev), 256);
+  L.xy = align_up(L.items + bp.items.size() * 16, 256);
+  L.total = L.xy + bp.xy.size() * 8;
+  return L;
+}
+
+// Assigns device addresses and serialises the parameter block into
+// `host` (scene table, items, centres).
+inline void bind_plan(BatchPlan *bp, const pcsdf_scene *scenes, char *pbase,
+                      char *sbase, std::vector<char> *host) {
+  const size_t n_sc = bp->scenes.size();
+  const ParamLayout L = param_layout(*bp);
+  const size_t off_items = L.items, off_xy = L.xy, total = L.total;
+  size_t soff = 0;
+  for (size_t q = 0; q < n_sc; ++q) {
+    SceneDev &d = bp->scenes[q];
+    d.S = scenes[q].static_ssq_dev;
+    d.oc = scenes[q].out_ssq_dev;
+    d.of = scenes[q].out_sdf_dev;
+    d.xy = reinterpret_cast<const int64_t *>(pbase + off_xy) + bp->xy_off[q];
+    const size_t plane = (size_t)d.n * d.nx * d.ny;
+    d.chords = reinterpret_cast<int2 *>(sbase + soff);
+    soff += align_up((size_t)d.n * std::max(d.K, 1) * d.ny * sizeof(int2), 256);
+    d.P = reinterpret_cast<int32_t *>(sbase + soff);
+    soff += align_up(plane * sizeof(int32_t), 256);
+    d.F1 = reinterpret_cast<int32_t *>(sbase + soff);
+    soff += align_up(plane * sizeof(int32_t), 256);
+  }
+  host->assign(total, 0);
+  std::memcpy(host->data(), bp->scenes.data(), n_sc * sizeof(SceneDev));
+  std::memcpy(host->data() + off_items, bp->items.data(),
+              bp->items.size() * 16);
+  if (!bp->xy.empty())
+    std::memcpy(host->data() + off_xy, bp->xy.data(), bp->xy.size() * 8);
+}
+
+inline size_t plan_scratch(const BatchPlan &bp) {
+  size_t t = 0;
+  for (const SceneDev &d : bp.scenes) t += scratch_of(d);
+  return t;
+}
+
+// Enqueues counter reset and the persistent kernel (parameters already
+// uploaded to bufs.params).
+
+}  // namespace pcsdf

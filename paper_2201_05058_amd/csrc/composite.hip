@@ -35,19 +35,6 @@
 
 namespace pcsdf {
 
-// Value of the humans' signed field at a voxel of layer k whose planar
-// signed value is p (E_D outside D, -E_{Gxy\D} inside, +-kInf if the other
-// set is empty).  dz2o = max(0, k-Kt)^2; zin = (k <= Kt); dz2i =
-// (Kt+1-k)^2 when layer Kt+1 exists, else kInf.
-__device__ __forceinline__ int32_t human_value(int32_t p, int dz2o, bool zin,
-                                               int32_t dz2i) {
-  if (p == kInf) return kInf;  // no human voxel in this slice
-  if (p > 0) return p + dz2o;  // column outside the disks
-  if (!zin) return dz2o;       // above the cylinders: nearest is the top
-  const int32_t din = -p;      // kInf when the disks cover the plane
-  return -(din < dz2i ? din : dz2i);
-}
-
 template <int VEC, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
@@ -223,7 +210,9 @@ extern "C" int pcsdf_predicted_composite_sdf(
                     !((uintptr_t)out_sdf_dev & 15);
   // Slices per block row: consecutive blocks write the same slices, which
   // keeps the concurrent write streams few and contiguous.
-  int G = h->comp_slices_per_block > 0 ? h->comp_slices_per_block : 2;
+  int G = h->tuning.composite_slices_per_block > 0
+              ? h->tuning.composite_slices_per_block
+              : 2;
   if (G > n_slices) G = n_slices;
   while ((n_slices + G - 1) / G > 65535) ++G;
   ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);

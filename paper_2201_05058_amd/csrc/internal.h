@@ -33,13 +33,16 @@ struct Handle {
   DevBuf chord_buf;     // int2 chords of the humans' disks per row
   DevBuf param_buf;     // per-call parameter blocks (fixed-point centres)
   DevBuf stack_buf;     // envelope stacks when a column exceeds LDS
+  DevBuf batch_params;  // batch: scene table, work items, centres
+  DevBuf batch_scratch; // batch: chords, planes and row passes per scene
+  std::vector<char> batch_host;  // batch parameter block before upload
+  pcsdf_tuning tuning = {0, 0, 0, 0};  // launch shapes; 0 = default
   // pinned host staging for small per-call parameter blocks
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
   std::vector<int64_t> host_xy;  // fixed-point centres before upload
-  int comp_slices_per_block = 0;  // composite launch shape; 0 = default
   // kernel timing with HIP events on the launch stream (off by default)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_pool;
