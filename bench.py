@@ -33,8 +33,47 @@ COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
 
 
 def source_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the composite kernel's own source text (the k_composite
+    template), so host-side edits of the file keep a measurement valid."""
+    with open(path) as f:
+        src = f.read()
+    a = src.find("template <int VEC, bool kSsq, bool kSdf>")
+    b = src.find("template <int VEC>", a)
+    text = src[a:b] if a >= 0 and b > a else src
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def traffic_from(prof_dir: str, V: int, n: int) -> dict:
+    """HBM bytes per composite launch from two rocprofv3 --pmc runs
+    (FETCH_SIZE and WRITE_SIZE, KiB per dispatch) of this benchmark and of
+    a 1 GiB device copy (--calibrate-copy-mib 1024), each counter scaled
+    by copy bytes / what it reads for the copy."""
+    import csv
+    import statistics
+
+    def load(sub):
+        d = {}
+        path = None
+        for root, _, files in os.walk(os.path.join(prof_dir, sub)):
+            for fn in files:
+                if fn.endswith("counter_collection.csv"):
+                    path = os.path.join(root, fn)
+        for r in csv.DictReader(open(path)):
+            d.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return d
+    f, w = load("prof_fetch"), load("prof_write")
+    cf, cw = load("prof_cfetch"), load("prof_cwrite")
+    ck = [k for k in cf if "copyBuffer" in k][0]
+    copy = 1024 * 2 ** 20
+    fs = copy / (statistics.mean(cf[ck]) * 1024)
+    ws = copy / (statistics.mean(cw[ck]) * 1024)
+    fb = statistics.mean(f["k_composite"]) * 1024 * fs
+    wb = statistics.mean(w["k_composite"]) * 1024 * ws
+    return {"kernel": "k_composite", "V": V, "n_slices": n,
+            "fetch_bytes": fb, "write_bytes": wb,
+            "bytes_per_launch": fb + wb, "fetch_scale": fs,
+            "write_scale": ws,
+            "composite_hip_sha256_16": source_hash(COMPOSITE_SRC)}
 
 
 def load_traffic(V: int, n: int):
@@ -68,6 +107,61 @@ def cpu_baseline(sc, max_slices: int):
                       f"(single-threaded C oracle, {dt:.1f} s)"}
 
 
+def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
+    """64 uneven scenes (5-30 slices, 1-4 humans, grids 64..256 x 64..256 x
+    64..128 at 0.02-0.05 m): one captured hipGraph replay of the batch
+    against 64 plain calls on one stream, same outputs.  Static fields are
+    built before timing."""
+    scs = scenegen.config3()
+    h = pc.Handle()
+    scenes = []
+    for sc in scs:
+        occ = torch.from_numpy(sc.occ).to(dev)
+        ssq, _ = pc.build_static_sdf(sc.grid, occ, want_sdf=False, handle=h)
+        del occ
+        shp = (sc.n_slices,) + sc.grid.shape_zyx
+        scenes.append({"grid": sc.grid, "static_ssq": ssq,
+                       "human_xy": sc.human_xy, "radius": sc.radius,
+                       "height": sc.height,
+                       "out_ssq": torch.empty(shp, dtype=torch.int32,
+                                              device=dev),
+                       "out_sdf": torch.empty(shp, dtype=torch.float32,
+                                              device=dev)})
+    vs = sum(sc.grid.nvox * sc.n_slices for sc in scs)
+    tuning, _, _ = autotune.tuned(
+        h, autotune.batch_signature(scenes),
+        lambda: pc.autotune_batch(scenes, reps=2, handle=h))
+    graph = pc.BatchGraph(scenes, handle=h)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    def plain_all():
+        for d in scenes:
+            pc.predicted_composite_sdf(d["grid"], d["static_ssq"],
+                                       d["human_xy"], d["radius"],
+                                       d["height"], out_ssq=d["out_ssq"],
+                                       out_sdf=d["out_sdf"], handle=h)
+
+    g_ms = timed(graph.launch)
+    p_ms = timed(plain_all)
+    graph.close()
+    h.close()
+    return {"scenes": len(scs), "voxel_slices": vs,
+            "graph_ms": g_ms, "plain_64_calls_ms": p_ms,
+            "graph_voxel_slices_per_s": vs / (g_ms / 1e3),
+            "plain_voxel_slices_per_s": vs / (p_ms / 1e3),
+            "speedup_vs_plain": p_ms / g_ms,
+            "graph_gbs_8B_basis": 8.0 * vs / (g_ms / 1e3) / 1e9,
+            "tuning": tuning}
+
+
 def calibrate_copy(mib: int, reps: int):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -88,6 +182,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=20)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-scene batch measurement")
+    ap.add_argument("--traffic-from", default="",
+                    help="write the composite's measured HBM traffic from "
+                         "rocprofv3 PMC output under this directory")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -98,13 +197,19 @@ def main():
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib, max(1, args.steps))
         return
+    if args.traffic_from:
+        t = traffic_from(args.traffic_from, 256 * 256 * 128, 20)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(t, fh, indent=1)
+        print(json.dumps(t))
+        return
 
     import numpy as np
     import torch
 
     import paper_2201_05058_amd as pc
     import scenegen
-    from paper_2201_05058_amd import _native
+    from paper_2201_05058_amd import _native, autotune
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -129,6 +234,14 @@ def main():
     torch.cuda.synchronize()
     st_ms, st_n = h.profile_read(_native.KERNEL_STATIC)
     static_ms = st_ms / max(st_n, 1)
+
+    # launch shape of the composite, tuned on this workload (cached)
+    scene = {"grid": g, "static_ssq": ssq_s, "human_xy": sc.human_xy,
+             "radius": sc.radius, "height": sc.height, "out_ssq": out_ssq,
+             "out_sdf": out_sdf}
+    tuning, _, _ = autotune.tuned(
+        h, autotune.composite_signature(g, n, K),
+        lambda: pc.autotune_composite(scene, reps=3, handle=h)[:2])
 
     def step():
         pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
@@ -189,7 +302,12 @@ def main():
                        "static_build_once": static_ms},
         "queries_per_s_exact_kernel": Q / (qy_ms / max(qy_n, 1) / 1e3)
         if qy_ms > 0 else None,
+        "tuning": tuning,
     }
+    del out_ssq, out_sdf
+    if not args.no_batch:
+        line["config3_batch"] = batch_section(pc, autotune, scenegen, torch,
+                                              dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_slices)
     print(json.dumps(line), flush=True)

@@ -65,7 +65,9 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_QUERY 2     /* sphere query kernel */
 #define PCSDF_KERNEL_STATIC 3    /* the three passes of the static build */
 #define PCSDF_KERNEL_BATCH 4     /* a batch: both persistent launches */
-#define PCSDF_KERNEL_COUNT 5
+#define PCSDF_KERNEL_MLP 5       /* surrogate forward (+ input gradient) */
+#define PCSDF_KERNEL_MLP_TRAIN 6 /* one surrogate training step */
+#define PCSDF_KERNEL_COUNT 7
 
 typedef struct pcsdf_handle pcsdf_handle;
 
@@ -223,6 +225,47 @@ int pcsdf_autotune_batch(pcsdf_handle *h, int32_t n_scenes,
 int pcsdf_autotune_composite(pcsdf_handle *h, const pcsdf_scene *scene,
                              void *stream, int32_t reps, pcsdf_tuning *best,
                              double *best_ms);
+
+/* ---- Learned surrogate for sphere queries (not in the paper) ----------
+ * A multilayer perceptron mapping 22 features (sphere centre x, y, z in
+ * metres, slice time t in seconds, and for each of three humans its
+ * position x, y, z and velocity x, y, z at t = 0) to the composite distance
+ * at the centre in metres:  u = (x - offset) * scale;  4 hidden layers of
+ * 128 SiLU units;  y = out_scale * (W4 a4 + b4).  Weights are fp32 masters
+ * used as BF16 on the matrix cores with FP32 accumulation; activations,
+ * SiLU derivatives and backward pre-activation gradients are rounded to
+ * BF16 before each product.  Parameter vector (fp32, PCSDF_MLP_NPARAM):
+ * W0[128][22] b0[128] W1[128][128] b1 W2[128][128] b2 W3[128][128] b3
+ * W4[1][128] b4[1].  The network object owns its weights, optimiser state
+ * and workspace on the handle's device; calls on one network must not
+ * overlap.  Batches are padded internally to a multiple of 1024 rows. */
+#define PCSDF_MLP_IN 22
+#define PCSDF_MLP_NPARAM 52609
+typedef struct pcsdf_mlp pcsdf_mlp;
+int pcsdf_mlp_create(pcsdf_handle *h, pcsdf_mlp **out);
+void pcsdf_mlp_destroy(pcsdf_mlp *m);
+/* Uploads parameters and the input/output normalisation, and resets the
+ * optimiser (waits for the device).  PCSDF_ERR_NUMERIC on non-finite
+ * values. */
+int pcsdf_mlp_set_params(pcsdf_mlp *m, const float *params_host,
+                         const float *in_offset_host,
+                         const float *in_scale_host, float out_scale);
+int pcsdf_mlp_get_params(pcsdf_mlp *m, float *params_host);
+/* y[n] = network(x[n][22]) and, if grad_x_dev is given, dy/dx [n][22]. */
+int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
+                      float *y_dev, float *grad_x_dev, void *stream);
+/* Gradient of sum_m dy[m] * y[m] w.r.t. every parameter (grad_params_dev,
+ * fp32 [PCSDF_MLP_NPARAM]) and, if given, w.r.t. the inputs. */
+int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n, const float *x_dev,
+                        const float *dy_dev, float *grad_params_dev,
+                        float *grad_x_dev, void *stream);
+/* One Adam step (bias-corrected) on the mean squared error between y(x)
+ * and target [n] (metres); loss_dev [1] receives the loss before the
+ * step, if given. */
+int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n, const float *x_dev,
+                         const float *target_dev, float lr, float beta1,
+                         float beta2, float eps, float *loss_dev,
+                         void *stream);
 
 /* Kernel timing for measurement.  When on, each timed region (the
  * PCSDF_KERNEL_* ids) is bracketed by two hipEventRecord calls on the

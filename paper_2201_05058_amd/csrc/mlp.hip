@@ -1,0 +1,362 @@
+// C-ABI of the surrogate MLP: parameters, forward with input gradient,
+// full gradients and the Adam training step.  Kernels in mlp_kernels.h.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "mlp_kernels.h"
+
+namespace pcsdf {
+
+constexpr int kChunk = 1024;  // rows per weight-gradient chunk
+constexpr int kWofs[5] = {0, 4096, 20480, 36864, 53248};
+constexpr int kWbfTotal = 53376;
+
+struct Mlp {
+  Handle *h = nullptr;
+  DevBuf params, grad, m1, m2, wbf, wtbf, norm, wofs;
+  float out_scale = 1.f;
+  int step = 0;
+  // workspace, grown with the batch
+  int cap = 0;
+  DevBuf a0, act, dact, dz, seed, y, wpart, bpart, lpart;
+};
+
+static int ws(Mlp *m, int npad, hipStream_t s) {
+  Handle *h = m->h;
+  if (npad <= m->cap) return PCSDF_OK;
+  const size_t r = (size_t)npad;
+  int rc;
+  if ((rc = ensure_buffer(h, m->a0, r * kInPad * 2, s)) ||
+      (rc = ensure_buffer(h, m->act, 4 * r * kHid * 2, s)) ||
+      (rc = ensure_buffer(h, m->dact, 4 * r * kHid * 2, s)) ||
+      (rc = ensure_buffer(h, m->dz, 4 * r * kHid * 2, s)) ||
+      (rc = ensure_buffer(h, m->seed, r * 4, s)) ||
+      (rc = ensure_buffer(h, m->y, r * 4, s)) ||
+      (rc = ensure_buffer(h, m->wpart, (r / kChunk) * kHid * kHid * 4, s)) ||
+      (rc = ensure_buffer(h, m->bpart, (r / kChunk) * (kHid + 1) * 4, s)) ||
+      (rc = ensure_buffer(h, m->lpart, (r / 256 + 1) * 4, s)))
+    return rc;
+  m->cap = npad;
+  return PCSDF_OK;
+}
+
+static uint16_t *actp(Mlp *m, int l) {  // A_l, l = 1..4, [cap][128]
+  return reinterpret_cast<uint16_t *>(m->act.ptr) + (size_t)(l - 1) * m->cap * kHid;
+}
+static uint16_t *dp(Mlp *m, int l) {  // D_l, l = 0..3
+  return reinterpret_cast<uint16_t *>(m->dact.ptr) + (size_t)l * m->cap * kHid;
+}
+static uint16_t *dzp(Mlp *m, int l) {  // dZ_l, l = 0..3
+  return reinterpret_cast<uint16_t *>(m->dz.ptr) + (size_t)l * m->cap * kHid;
+}
+static const uint16_t *wb(Mlp *m, int l) {
+  return reinterpret_cast<const uint16_t *>(m->wbf.ptr) + kWofs[l];
+}
+static const uint16_t *wtb(Mlp *m, int l) {
+  return reinterpret_cast<const uint16_t *>(m->wtbf.ptr) + kWofs[l];
+}
+static const float *pf(Mlp *m) {
+  return reinterpret_cast<const float *>(m->params.ptr);
+}
+
+static unsigned blocks(int64_t n, int per) {
+  return (unsigned)((n + per - 1) / per);
+}
+
+// Sums the chunk partials of one layer's weight gradient into the flat
+// gradient vector: W [out][in] from part [chunks][out][in_pad].
+__global__ __launch_bounds__(256) void k_sum_w(const float *__restrict__ part,
+                                               int chunks, int out, int in,
+                                               int in_pad,
+                                               float *__restrict__ g) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= out * in) return;
+  const int o = t / in, i = t - o * in;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c)
+    s += part[((int64_t)c * out + o) * in_pad + i];
+  g[t] = s;
+}
+
+__global__ void k_fill(float *p, float v, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+__global__ void k_copy_pad(const float *__restrict__ src, int n, int npad,
+                           float *__restrict__ dst) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < npad) dst[t] = t < n ? src[t] : 0.f;
+}
+
+__global__ void k_loss_final(const float *__restrict__ part, int nparts,
+                             float inv_n, float *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < nparts; ++i) s += part[i];
+    out[0] = s * inv_n;
+  }
+}
+
+// Forward pass over rows [0, npad): activations and SiLU derivatives of
+// every hidden layer in the workspace; y [n] if given.
+static int forward(Mlp *m, int n, int npad, const float *x, float *y,
+                   hipStream_t s) {
+  const float *norm = reinterpret_cast<const float *>(m->norm.ptr);
+  uint16_t *a0 = reinterpret_cast<uint16_t *>(m->a0.ptr);
+  hipLaunchKernelGGL(k_mlp_input, dim3(blocks((int64_t)npad * kInPad, 256)),
+                     dim3(256), 0, s, x, n, npad, norm, norm + kIn, a0);
+  const float *p = pf(m);
+  const unsigned g = (unsigned)(npad / 128);
+  hipLaunchKernelGGL(k_mlp_fwd<kInPad>, dim3(g), dim3(256), 0, s, a0,
+                     wb(m, 0), p + layer_desc(0).b_off, actp(m, 1), dp(m, 0));
+  for (int l = 1; l < kLayers; ++l)
+    hipLaunchKernelGGL(k_mlp_fwd<kHid>, dim3(g), dim3(256), 0, s, actp(m, l),
+                       wb(m, l), p + layer_desc(l).b_off, actp(m, l + 1),
+                       dp(m, l));
+  if (y)
+    hipLaunchKernelGGL(k_mlp_out, dim3(blocks(n, 256)), dim3(256), 0, s,
+                       actp(m, 4), wb(m, 4), p + layer_desc(4).b_off,
+                       m->out_scale, n, y);
+  return check_launch(m->h, "mlp forward");
+}
+
+// Backward pass from seed [npad] (dLoss/dy, zero on padded rows).  With
+// gp, writes the parameter gradient; with grad_x, the input gradient.
+static int backward(Mlp *m, int n, int npad, float *gp, float *grad_x,
+                    hipStream_t s) {
+  const float *norm = reinterpret_cast<const float *>(m->norm.ptr);
+  const float *seed = reinterpret_cast<const float *>(m->seed.ptr);
+  float *wpart = reinterpret_cast<float *>(m->wpart.ptr);
+  float *bpart = reinterpret_cast<float *>(m->bpart.ptr);
+  const int chunks = npad / kChunk;
+  const unsigned g = (unsigned)(npad / 128);
+  if (gp) {
+    hipLaunchKernelGGL(k_mlp_wgrad_out, dim3(chunks), dim3(256), 0, s, seed,
+                       m->out_scale, actp(m, 4), n, bpart);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, bpart, chunks,
+                       kHid + 1, gp + layer_desc(4).w_off);
+  }
+  hipLaunchKernelGGL(k_mlp_bwd_out, dim3(blocks((int64_t)npad * kHid, 256)),
+                     dim3(256), 0, s, seed, m->out_scale, wb(m, 4), dp(m, 3),
+                     npad, dzp(m, 3));
+  for (int l = kLayers - 1; l >= 0; --l) {
+    const LayerDesc d = layer_desc(l);
+    if (gp) {
+      const uint16_t *A = l == 0 ? reinterpret_cast<const uint16_t *>(m->a0.ptr)
+                                 : actp(m, l);
+      if (l == 0)
+        hipLaunchKernelGGL(k_mlp_wgrad<kInPad>, dim3(chunks), dim3(256), 0, s,
+                           dzp(m, 0), A, wpart, bpart);
+      else
+        hipLaunchKernelGGL(k_mlp_wgrad<kHid>, dim3(chunks), dim3(256), 0, s,
+                           dzp(m, l), A, wpart, bpart);
+      hipLaunchKernelGGL(k_sum_w, dim3(blocks(kHid * d.in, 256)), dim3(256), 0,
+                         s, wpart, chunks, kHid, d.in, d.in_pad,
+                         gp + d.w_off);
+      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, bpart, chunks,
+                         kHid, gp + d.b_off);
+    }
+    if (l > 0)
+      hipLaunchKernelGGL(k_mlp_bwd<kHid>, dim3(g), dim3(256), 0, s, dzp(m, l),
+                         wtb(m, l), dp(m, l - 1), dzp(m, l - 1), norm + kIn, n,
+                         nullptr);
+    else if (grad_x)
+      hipLaunchKernelGGL(k_mlp_bwd<kInPad>, dim3(g), dim3(256), 0, s,
+                         dzp(m, 0), wtb(m, 0), nullptr, nullptr, norm + kIn, n,
+                         grad_x);
+  }
+  return check_launch(m->h, "mlp backward");
+}
+
+static int check_rows(Mlp *m, int n, const void *x) {
+  if (n < 0 || n > (1 << 28))
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "n must be in [0, 2^28]");
+  if (n > 0 && !x) return fail(m->h, PCSDF_ERR_INVALID_ARG, "x is NULL");
+  return PCSDF_OK;
+}
+
+static int pad_rows(int n) { return ((n + kChunk - 1) / kChunk) * kChunk; }
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+struct pcsdf_mlp : Mlp {};
+
+extern "C" int pcsdf_mlp_create(pcsdf_handle *hp, pcsdf_mlp **out) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!out) return fail(h, PCSDF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc;
+  if ((rc = bind_device(h))) return rc;
+  pcsdf_mlp *m = new (std::nothrow) pcsdf_mlp();
+  if (!m) return fail(h, PCSDF_ERR_OOM, "mlp allocation failed");
+  m->h = h;
+  const size_t P = (size_t)kNParam * 4;
+  if ((rc = ensure_buffer(h, m->params, P, nullptr)) ||
+      (rc = ensure_buffer(h, m->grad, P, nullptr)) ||
+      (rc = ensure_buffer(h, m->m1, P, nullptr)) ||
+      (rc = ensure_buffer(h, m->m2, P, nullptr)) ||
+      (rc = ensure_buffer(h, m->wbf, kWbfTotal * 2, nullptr)) ||
+      (rc = ensure_buffer(h, m->wtbf, kWbfTotal * 2, nullptr)) ||
+      (rc = ensure_buffer(h, m->norm, 2 * kIn * 4, nullptr)) ||
+      (rc = ensure_buffer(h, m->wofs, 5 * 4, nullptr))) {
+    pcsdf_mlp_destroy(m);
+    return rc;
+  }
+  if (hipMemset(m->wbf.ptr, 0, m->wbf.bytes) != hipSuccess ||
+      hipMemset(m->wtbf.ptr, 0, m->wtbf.bytes) != hipSuccess ||
+      hipMemcpy(m->wofs.ptr, kWofs, sizeof(kWofs), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    pcsdf_mlp_destroy(m);
+    return fail(h, PCSDF_ERR_HIP, "mlp initialisation failed");
+  }
+  *out = m;
+  return PCSDF_OK;
+}
+
+extern "C" void pcsdf_mlp_destroy(pcsdf_mlp *m) {
+  if (!m) return;
+  DevBuf *bufs[] = {&m->params, &m->grad, &m->m1,   &m->m2,    &m->wbf,
+                    &m->wtbf,   &m->norm, &m->wofs, &m->a0,    &m->act,
+                    &m->dact,   &m->dz,   &m->seed, &m->y,     &m->wpart,
+                    &m->bpart,  &m->lpart};
+  bool any = false;
+  for (DevBuf *b : bufs) any = any || b->ptr;
+  if (any) (void)hipDeviceSynchronize();
+  for (DevBuf *b : bufs)
+    if (b->ptr) (void)hipFree(b->ptr);
+  delete m;
+}
+
+extern "C" int pcsdf_mlp_set_params(pcsdf_mlp *m, const float *params_host,
+                                    const float *in_offset_host,
+                                    const float *in_scale_host,
+                                    float out_scale) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  Handle *h = m->h;
+  if (!params_host || !in_offset_host || !in_scale_host)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "params, offset and scale required");
+  for (int i = 0; i < kNParam; ++i)
+    if (!std::isfinite(params_host[i]))
+      return fail(h, PCSDF_ERR_NUMERIC,
+                  "non-finite parameter at index " + std::to_string(i));
+  for (int i = 0; i < kIn; ++i)
+    if (!std::isfinite(in_offset_host[i]) || !std::isfinite(in_scale_host[i]))
+      return fail(h, PCSDF_ERR_NUMERIC, "non-finite normalisation");
+  if (!std::isfinite(out_scale))
+    return fail(h, PCSDF_ERR_NUMERIC, "non-finite output scale");
+  std::vector<float> norm(2 * kIn);
+  std::memcpy(norm.data(), in_offset_host, kIn * 4);
+  std::memcpy(norm.data() + kIn, in_scale_host, kIn * 4);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(m->params.ptr, params_host, (size_t)kNParam * 4,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->norm.ptr, norm.data(), norm.size() * 4,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(m->m1.ptr, 0, (size_t)kNParam * 4) != hipSuccess ||
+      hipMemset(m->m2.ptr, 0, (size_t)kNParam * 4) != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP, "uploading the parameters failed");
+  m->out_scale = out_scale;
+  m->step = 0;
+  hipLaunchKernelGGL(k_cast_weights, dim3(blocks(kNParam, 256)), dim3(256), 0,
+                     nullptr, reinterpret_cast<const float *>(m->params.ptr),
+                     reinterpret_cast<uint16_t *>(m->wbf.ptr),
+                     reinterpret_cast<uint16_t *>(m->wtbf.ptr),
+                     reinterpret_cast<const int *>(m->wofs.ptr));
+  if (hipDeviceSynchronize() != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP, "casting the weights failed");
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_mlp_get_params(pcsdf_mlp *m, float *params_host) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  if (!params_host) return fail(m->h, PCSDF_ERR_INVALID_ARG, "params NULL");
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(params_host, m->params.ptr, (size_t)kNParam * 4,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(m->h, PCSDF_ERR_HIP, "reading the parameters failed");
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
+                                 float *y_dev, float *grad_x_dev,
+                                 void *stream) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_rows(m, n, x_dev);
+  if (rc || n == 0) return rc;
+  if (!y_dev) return fail(m->h, PCSDF_ERR_INVALID_ARG, "y_dev is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int npad = pad_rows(n);
+  if ((rc = ws(m, npad, s))) return rc;
+  ProfScope ps(m->h, PCSDF_KERNEL_MLP, s);
+  if ((rc = forward(m, n, npad, x_dev, y_dev, s))) return rc;
+  if (!grad_x_dev) return PCSDF_OK;
+  hipLaunchKernelGGL(k_fill, dim3(blocks(npad, 256)), dim3(256), 0, s,
+                     reinterpret_cast<float *>(m->seed.ptr), 1.f,
+                     (int64_t)npad);
+  return backward(m, n, npad, nullptr, grad_x_dev, s);
+}
+
+extern "C" int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n,
+                                   const float *x_dev, const float *dy_dev,
+                                   float *grad_params_dev, float *grad_x_dev,
+                                   void *stream) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_rows(m, n, x_dev);
+  if (rc) return rc;
+  if (n == 0 || !dy_dev || !grad_params_dev)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "need n > 0, dy and grad");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int npad = pad_rows(n);
+  if ((rc = ws(m, npad, s))) return rc;
+  if ((rc = forward(m, n, npad, x_dev, nullptr, s))) return rc;
+  hipLaunchKernelGGL(k_copy_pad, dim3(blocks(npad, 256)), dim3(256), 0, s,
+                     dy_dev, n, npad, reinterpret_cast<float *>(m->seed.ptr));
+  return backward(m, n, npad, grad_params_dev, grad_x_dev, s);
+}
+
+extern "C" int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n,
+                                    const float *x_dev,
+                                    const float *target_dev, float lr,
+                                    float beta1, float beta2, float eps,
+                                    float *loss_dev, void *stream) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_rows(m, n, x_dev);
+  if (rc) return rc;
+  if (n == 0 || !target_dev)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "need n > 0 and targets");
+  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+      !(eps > 0))
+    return fail(m->h, PCSDF_ERR_NUMERIC, "bad optimiser hyper-parameters");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int npad = pad_rows(n);
+  if ((rc = ws(m, npad, s))) return rc;
+  ProfScope ps(m->h, PCSDF_KERNEL_MLP_TRAIN, s);
+  float *y = reinterpret_cast<float *>(m->y.ptr);
+  if ((rc = forward(m, n, npad, x_dev, y, s))) return rc;
+  float *lpart = reinterpret_cast<float *>(m->lpart.ptr);
+  hipLaunchKernelGGL(k_mse, dim3(blocks(npad, 256)), dim3(256), 0, s, y,
+                     target_dev, n, npad,
+                     reinterpret_cast<float *>(m->seed.ptr), lpart);
+  if (loss_dev)
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, lpart,
+                       (int)blocks(npad, 256), 1.f / (float)n, loss_dev);
+  float *gp = reinterpret_cast<float *>(m->grad.ptr);
+  if ((rc = backward(m, n, npad, gp, nullptr, s))) return rc;
+  m->step += 1;
+  const float c1 = 1.f - std::pow(beta1, (float)m->step);
+  const float c2 = 1.f - std::pow(beta2, (float)m->step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam, 256)), dim3(256), 0, s,
+                     reinterpret_cast<float *>(m->params.ptr), gp,
+                     reinterpret_cast<float *>(m->m1.ptr),
+                     reinterpret_cast<float *>(m->m2.ptr), lr, beta1, beta2,
+                     eps, c1, c2, reinterpret_cast<uint16_t *>(m->wbf.ptr),
+                     reinterpret_cast<uint16_t *>(m->wtbf.ptr),
+                     reinterpret_cast<const int *>(m->wofs.ptr));
+  return check_launch(m->h, "mlp train step");
+}
