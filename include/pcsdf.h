@@ -67,7 +67,8 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_BATCH 4     /* a batch: both persistent launches */
 #define PCSDF_KERNEL_MLP 5       /* surrogate forward (+ input gradient) */
 #define PCSDF_KERNEL_MLP_TRAIN 6 /* one surrogate training step */
-#define PCSDF_KERNEL_COUNT 7
+#define PCSDF_KERNEL_SURROGATE_DECIDE 7 /* surrogate accept / fallback split */
+#define PCSDF_KERNEL_COUNT 8
 
 typedef struct pcsdf_handle pcsdf_handle;
 
@@ -266,6 +267,45 @@ int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n, const float *x_dev,
                          const float *target_dev, float lr, float beta1,
                          float beta2, float eps, float *loss_dev,
                          void *stream);
+
+/* Network input for sphere queries: x[q] = [c_x, c_y, c_z, t, state[0..17]]
+ * with t = dt_s * clamp(slice[q], 0, n_slices - 1).  state_host holds the
+ * 18 state features (three humans' position x, y, z and velocity x, y, z
+ * in metres and metres per second, at t = 0).  centre_dev [n][3],
+ * slice_dev [n], x_dev [n][22] (fp32, caller-owned). */
+int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
+                             const float *centre_dev,
+                             const int32_t *slice_dev, int32_t n_slices,
+                             double dt_s, const float *state_host,
+                             float *x_dev, void *stream);
+
+/* Sphere queries answered by the network, with the exact path as fallback.
+ * Same outputs and status bits as pcsdf_query_spheres, for the composite
+ * fields that pcsdf_predicted_composite_sdf would build from the same
+ * static field, human positions and cylinder (arguments as there).
+ * A query falls back to the exact path when
+ *   - its predicted sphere distance y(c, t) - r is below fallback_margin_m,
+ *   - the network's value or gradient is not finite, or
+ *   - its centre lies outside the span of voxel centres (the exact path then
+ *     clamps and flags it);
+ * other queries get dist = y - r, grad = dy/dc, status = SLICE_CLAMPED or 0,
+ * cost = max(0, hinge_eps_m - dist).  Queries with slice < 0 get NaN and
+ * SLICE_NEG.  used_fallback_dev [n] (nullable) is 1 for exact answers.
+ * Only the slices that some fallback query reads are built, into
+ * field_work_dev [n_slices][V] (fp32, caller-owned; the other slices are
+ * left untouched).  No host synchronisation: the fallback list and the
+ * slice marks live on the device.  The network must belong to handle `h`.
+ * The net takes the features of pcsdf_surrogate_features; its state
+ * (state_host) and the human positions must describe the same humans. */
+int pcsdf_query_spheres_surrogate(
+    pcsdf_handle *h, pcsdf_mlp *m, const pcsdf_grid *grid,
+    const int32_t *static_ssq_dev, int32_t n_slices, int32_t n_humans,
+    const double *human_xy_host, double radius_m, double height_m,
+    const float *state_host, double dt_s, double fallback_margin_m,
+    int32_t n_queries, const float *centre_dev, const float *radius_dev,
+    const int32_t *slice_dev, double hinge_eps_m, float *field_work_dev,
+    float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,
+    uint8_t *used_fallback_dev, void *stream);
 
 /* Kernel timing for measurement.  When on, each timed region (the
  * PCSDF_KERNEL_* ids) is bracketed by two hipEventRecord calls on the

@@ -23,7 +23,7 @@ STATUS_NAMES = {
 Q_OOR_X, Q_OOR_Y, Q_OOR_Z = 1, 2, 4
 Q_SLICE_CLAMPED, Q_INF_CORNER, Q_SLICE_NEG = 8, 16, 32
 KERNEL_COMPOSITE, KERNEL_PLANES, KERNEL_QUERY, KERNEL_STATIC = 0, 1, 2, 3
-KERNEL_BATCH = 4
+KERNEL_BATCH, KERNEL_MLP, KERNEL_MLP_TRAIN, KERNEL_SURROGATE_DECIDE = 4, 5, 6, 7
 
 
 class PcsdfError(RuntimeError):

@@ -35,9 +35,11 @@
 
 namespace pcsdf {
 
+// Slices with need[sl] == 0 are skipped when `need` is non-null.
 template <int VEC, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
+    const int32_t *__restrict__ need,
     int32_t *__restrict__ oc, float *__restrict__ of, uint32_t nx,
     uint32_t ny, int n_slices, int G, int Kt, int has_above, float hf,
     uint32_t V) {
@@ -46,6 +48,11 @@ __global__ __launch_bounds__(256) void k_composite(
   if (v0 >= V) return;
   const int s_begin = (int)blockIdx.y * G;
   const int s_end = min(n_slices, s_begin + G);
+  if (need) {  // skip the static read when none of the block's slices is due
+    bool any = false;
+    for (int sl = s_begin; sl < s_end; ++sl) any = any || need[sl] != 0;
+    if (!any) return;
+  }
   const uint32_t row = v0 / nx;
   const uint32_t i = v0 - row * nx;
   const uint32_t k = row / ny;
@@ -62,6 +69,7 @@ __global__ __launch_bounds__(256) void k_composite(
   if constexpr (VEC == 4) {
     const int4 s4 = *reinterpret_cast<const int4 *>(S + v0);
     for (int sl = s_begin; sl < s_end; ++sl) {
+      if (need && need[sl] == 0) continue;
       const int4 p4 = *reinterpret_cast<const int4 *>(prow + sl * plane);
       int4 c;
       c.x = min(s4.x, human_value(p4.x, dz2o, zin, dz2i));
@@ -82,6 +90,7 @@ __global__ __launch_bounds__(256) void k_composite(
   } else {
     const int32_t s = S[v0];
     for (int sl = s_begin; sl < s_end; ++sl) {
+      if (need && need[sl] == 0) continue;
       const int32_t c = min(s, human_value(prow[sl * plane], dz2o, zin, dz2i));
       const size_t o = (size_t)sl * V + v0;
       if (kSsq) oc[o] = c;
@@ -91,21 +100,21 @@ __global__ __launch_bounds__(256) void k_composite(
 }
 
 template <int VEC>
-static void launch_comp(const int32_t *S, const int32_t *P, int32_t *oc,
-                        float *of, uint32_t nx, uint32_t ny, int n, int G,
-                        int Kt, int has_above, float hf, uint32_t V,
-                        hipStream_t s) {
+static void launch_comp(const int32_t *S, const int32_t *P,
+                        const int32_t *need, int32_t *oc, float *of,
+                        uint32_t nx, uint32_t ny, int n, int G, int Kt,
+                        int has_above, float hf, uint32_t V, hipStream_t s) {
   const uint32_t nthreads = (V + VEC - 1) / VEC;
   const dim3 grid((nthreads + 255) / 256, (n + G - 1) / G), block(256);
   if (oc && of)
     hipLaunchKernelGGL((k_composite<VEC, true, true>), grid, block, 0, s, S,
-                       P, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
+                       P, need, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
   else if (oc)
     hipLaunchKernelGGL((k_composite<VEC, true, false>), grid, block, 0, s, S,
-                       P, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
+                       P, need, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
   else
     hipLaunchKernelGGL((k_composite<VEC, false, true>), grid, block, 0, s, S,
-                       P, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
+                       P, need, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
 }
 
 // Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
@@ -119,17 +128,11 @@ static bool to_fixed(double p, double o, double h, int64_t *out) {
   return true;
 }
 
-}  // namespace pcsdf
-
-using namespace pcsdf;
-
-extern "C" int pcsdf_predicted_composite_sdf(
-    pcsdf_handle *hp, const pcsdf_grid *g, const int32_t *static_ssq_dev,
-    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
-    double radius_m, double height_m, int32_t *out_ssq_dev,
-    float *out_sdf_dev, void *stream) {
-  Handle *h = reinterpret_cast<Handle *>(hp);
-  if (!h) return PCSDF_ERR_INVALID_ARG;
+int composite_run(Handle *h, const pcsdf_grid *g,
+                  const int32_t *static_ssq_dev, int32_t n_slices,
+                  int32_t n_humans, const double *human_xy_host,
+                  double radius_m, double height_m, int32_t *out_ssq_dev,
+                  float *out_sdf_dev, const int32_t *need, hipStream_t s) {
   int rc = check_grid(h, g);
   if (rc) return rc;
   if (!static_ssq_dev)
@@ -177,7 +180,6 @@ extern "C" int pcsdf_predicted_composite_sdf(
                       std::to_string(t));
   }
   if ((rc = bind_device(h))) return rc;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
   const size_t xy_bytes = xy.size() * sizeof(int64_t);
   const size_t chord_bytes =
@@ -200,7 +202,7 @@ extern "C" int pcsdf_predicted_composite_sdf(
   ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
   if ((rc = launch_planes(h, xy_dev, n_humans, R, empty,
                           reinterpret_cast<int2 *>(h->chord_buf.ptr), p2, nx,
-                          ny, n_slices, s)))
+                          ny, n_slices, need, s)))
     return rc;
   pp.stop();
   // Streaming epilogue over all voxels and slices.
@@ -217,10 +219,27 @@ extern "C" int pcsdf_predicted_composite_sdf(
   while ((n_slices + G - 1) / G > 65535) ++G;
   ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
   if (vec4)
-    launch_comp<4>(static_ssq_dev, p2, out_ssq_dev, out_sdf_dev, nx, ny,
-                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+    launch_comp<4>(static_ssq_dev, p2, need, out_ssq_dev, out_sdf_dev, nx,
+                   ny, n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   else
-    launch_comp<1>(static_ssq_dev, p2, out_ssq_dev, out_sdf_dev, nx, ny,
-                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+    launch_comp<1>(static_ssq_dev, p2, need, out_ssq_dev, out_sdf_dev, nx,
+                   ny, n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   return check_launch(h, "composite");
+}
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+extern "C" int pcsdf_predicted_composite_sdf(
+    pcsdf_handle *hp, const pcsdf_grid *g, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, int32_t *out_ssq_dev,
+    float *out_sdf_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  return composite_run(h, g, static_ssq_dev, n_slices, n_humans,
+                       human_xy_host, radius_m, height_m, out_ssq_dev,
+                       out_sdf_dev, nullptr,
+                       reinterpret_cast<hipStream_t>(stream));
 }

@@ -35,6 +35,7 @@ struct Handle {
   DevBuf stack_buf;     // envelope stacks when a column exceeds LDS
   DevBuf batch_params;  // batch: scene table, work items, centres
   DevBuf batch_scratch; // batch: chords, planes and row passes per scene
+  DevBuf sur_buf;       // surrogate queries: features, outputs, fallback list
   std::vector<char> batch_host;  // batch parameter block before upload
   pcsdf_tuning tuning = {0, 0, 0, 0};  // launch shapes; 0 = default
   // pinned host staging for small per-call parameter blocks
@@ -102,14 +103,6 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
                      int64_t rows, hipStream_t s);
 
-// Planar signed field of the humans' disk union for every slice, into
-// P [n_slices][ny][nx]: chords per (slice, human, row) into `chords`, then
-// one lane per pixel.  xy holds fixed-point centres [n_slices][K][2]; no
-// human voxel at all when `empty` is set.
-int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
-                  int2 *chords, int32_t *P, int nx, int ny, int n_slices,
-                  hipStream_t s);
-
 // Column pass of the separable EDT along a strided axis.  Columns are
 // indexed by (fast index i in [0, nfast), outer index o in [0, nouter)):
 // element q of column (i, o) is at o*outer_stride + i + q*stride, q < m.
@@ -118,5 +111,44 @@ int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
 int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                     float *sdf_out, float h_f, int nfast, int nouter, int m,
                     int64_t stride, int64_t outer_stride, hipStream_t s);
+
+// ---- implemented in planes.hip -----------------------------------------
+
+// Planar signed field of the humans' disk union for every slice, into
+// P [n_slices][ny][nx]: chords per (slice, human, row) into `chords`, then
+// one lane per pixel.  xy holds fixed-point centres [n_slices][K][2]; no
+// human voxel at all when `empty` is set.  With `need` (device int32
+// [n_slices]) only slices with a non-zero entry are computed.
+int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
+                  int2 *chords, int32_t *P, int nx, int ny, int n_slices,
+                  const int32_t *need, hipStream_t s);
+
+// ---- implemented in composite.hip --------------------------------------
+
+// The whole predicted-composite call (validation, fixed-point upload,
+// planes, streaming epilogue).  With `need` (device int32 [n_slices]) only
+// the slices whose entry is non-zero are computed and written; the other
+// slices of the outputs are left untouched.
+int composite_run(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
+                  int32_t n_slices, int32_t n_humans, const double *xy_host,
+                  double radius_m, double height_m, int32_t *out_ssq,
+                  float *out_sdf, const int32_t *need, hipStream_t s);
+
+// ---- implemented in query.hip ------------------------------------------
+
+// Sphere queries for the indices list[0 .. *count) only (count on the
+// device; the grid is sized for at most `max_count` entries).
+int launch_query_list(Handle *h, const pcsdf_grid *g, const float *sdf,
+                      int n_slices, const int32_t *list,
+                      const int32_t *count, int max_count,
+                      const float *centre, const float *radius,
+                      const int32_t *slice, double eps, float *dist,
+                      float *grad, uint8_t *status, float *cost,
+                      hipStream_t s);
+
+// ---- implemented in mlp.hip --------------------------------------------
+
+// The handle a network was created on.
+Handle *mlp_handle(pcsdf_mlp *m);
 
 }  // namespace pcsdf

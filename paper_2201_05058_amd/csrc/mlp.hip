@@ -186,6 +186,8 @@ using namespace pcsdf;
 
 struct pcsdf_mlp : Mlp {};
 
+Handle *pcsdf::mlp_handle(pcsdf_mlp *m) { return m ? m->h : nullptr; }
+
 extern "C" int pcsdf_mlp_create(pcsdf_handle *hp, pcsdf_mlp **out) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return PCSDF_ERR_INVALID_ARG;

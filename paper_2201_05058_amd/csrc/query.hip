@@ -13,15 +13,28 @@
 
 namespace pcsdf {
 
-__global__ __launch_bounds__(256) void k_query(
-    const float *__restrict__ sdf, int n_slices, int nx, int ny, int nz,
-    double h, double ox, double oy, double oz, int n_queries,
-    const float *__restrict__ centre, const float *__restrict__ radius,
-    const int32_t *__restrict__ slice, double eps, float *__restrict__ dist,
-    float *__restrict__ grad, uint8_t *__restrict__ status,
-    float *__restrict__ cost) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= n_queries) return;
+struct QueryArgs {
+  const float *sdf;  // [n_slices][V]
+  int n_slices, nx, ny, nz;
+  double h, ox, oy, oz, eps;
+  const float *centre, *radius;
+  const int32_t *slice;
+  float *dist, *grad, *cost;
+  uint8_t *status;
+};
+
+// Answers query q.
+__device__ __forceinline__ void answer(const QueryArgs &A, int q) {
+  const float *__restrict__ sdf = A.sdf;
+  const float *__restrict__ centre = A.centre;
+  const float *__restrict__ radius = A.radius;
+  const int32_t *__restrict__ slice = A.slice;
+  float *__restrict__ dist = A.dist;
+  float *__restrict__ grad = A.grad;
+  float *__restrict__ cost = A.cost;
+  uint8_t *__restrict__ status = A.status;
+  const int n_slices = A.n_slices, nx = A.nx, ny = A.ny, nz = A.nz;
+  const double h = A.h, ox = A.ox, oy = A.oy, oz = A.oz, eps = A.eps;
   uint32_t st = 0;
   int s = slice[q];
   if (s < 0) {
@@ -131,6 +144,60 @@ __global__ __launch_bounds__(256) void k_query(
   if (status) status[q] = (uint8_t)st;
 }
 
+__global__ __launch_bounds__(256) void k_query(QueryArgs A, int n_queries) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q < n_queries) answer(A, q);
+}
+
+// Queries list[0 .. *count) only.
+__global__ __launch_bounds__(256) void k_query_list(
+    QueryArgs A, const int32_t *__restrict__ list,
+    const int32_t *__restrict__ count) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < *count) answer(A, list[t]);
+}
+
+static QueryArgs query_args(const pcsdf_grid *g, const float *sdf,
+                            int n_slices, const float *centre,
+                            const float *radius, const int32_t *slice,
+                            double eps, float *dist, float *grad,
+                            uint8_t *status, float *cost) {
+  QueryArgs A;
+  A.sdf = sdf;
+  A.n_slices = n_slices;
+  A.nx = g->nx;
+  A.ny = g->ny;
+  A.nz = g->nz;
+  A.h = g->voxel_m;
+  A.ox = g->origin_m[0];
+  A.oy = g->origin_m[1];
+  A.oz = g->origin_m[2];
+  A.eps = eps;
+  A.centre = centre;
+  A.radius = radius;
+  A.slice = slice;
+  A.dist = dist;
+  A.grad = grad;
+  A.cost = cost;
+  A.status = status;
+  return A;
+}
+
+int launch_query_list(Handle *h, const pcsdf_grid *g, const float *sdf,
+                      int n_slices, const int32_t *list,
+                      const int32_t *count, int max_count,
+                      const float *centre, const float *radius,
+                      const int32_t *slice, double eps, float *dist,
+                      float *grad, uint8_t *status, float *cost,
+                      hipStream_t s) {
+  if (max_count <= 0) return PCSDF_OK;
+  const QueryArgs A = query_args(g, sdf, n_slices, centre, radius, slice, eps,
+                                 dist, grad, status, cost);
+  hipLaunchKernelGGL(k_query_list, dim3((unsigned)((max_count + 255) / 256)),
+                     dim3(256), 0, s, A, list, count);
+  return check_launch(h, "query list");
+}
+
 }  // namespace pcsdf
 
 using namespace pcsdf;
@@ -168,10 +235,9 @@ extern "C" int pcsdf_query_spheres(pcsdf_handle *hp, const pcsdf_grid *g,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)((n_queries + 255) / 256)), block(256);
   ProfScope ps(h, PCSDF_KERNEL_QUERY, s);
-  hipLaunchKernelGGL(k_query, grid, block, 0, s, sdf_dev, n_slices, g->nx,
-                     g->ny, g->nz, g->voxel_m, g->origin_m[0], g->origin_m[1],
-                     g->origin_m[2], n_queries, centre_dev, radius_dev,
-                     slice_dev, hinge_eps_m, dist_dev, grad_dev, status_dev,
-                     cost_dev);
+  const QueryArgs A =
+      query_args(g, sdf_dev, n_slices, centre_dev, radius_dev, slice_dev,
+                 hinge_eps_m, dist_dev, grad_dev, status_dev, cost_dev);
+  hipLaunchKernelGGL(k_query, grid, block, 0, s, A, n_queries);
   return check_launch(h, "query_spheres");
 }

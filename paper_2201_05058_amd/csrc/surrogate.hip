@@ -1,0 +1,286 @@
+// Surrogate sphere queries with an exact fallback.
+//
+// The learned network answers a sphere query from the sphere's centre, the
+// slice time and the humans' current state (positions and velocities) --
+// without building any distance field.  Where its answer cannot be trusted
+// the exact path answers instead: a query falls back when the predicted
+// sphere distance d(c) - r is below a safety margin (near an obstacle the
+// planner needs exact values), when the network's value or gradient is not
+// finite, or when the centre lies outside the grid's interior (the network
+// was trained there only; the exact path clamps and flags such centres).
+//
+// One call runs, all on the caller's stream and without host round trips:
+//   1. features:  x = [c_x, c_y, c_z, t, state...] per query, t = dt * slice
+//                 (slice clamped to the horizon as for exact queries);
+//   2. network:   value and input gradient (mlp.hip);
+//   3. decide:    surrogate answers are written out; fallback queries are
+//                 appended to a compact list (wave ballot + one atomic per
+//                 wave) and their slices marked as needed;
+//   4. fields:    the exact composite of the marked slices only (the other
+//                 slices' kernels exit at once);
+//   5. exact:     the sphere query kernel over the compact list.
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace pcsdf {
+
+constexpr int kNetIn = PCSDF_MLP_IN;
+constexpr int kState = PCSDF_MLP_IN - 4;
+
+struct NetState {
+  float v[kState];
+};
+
+// x[q][0..21] for queries [0, n): one lane per query, constant indices only.
+__global__ __launch_bounds__(256) void k_features(
+    const float *__restrict__ centre, const int32_t *__restrict__ slice,
+    int n_slices, float dt, NetState st, int n, float *__restrict__ x) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  int s = slice[q];
+  s = s < 0 ? 0 : (s > n_slices - 1 ? n_slices - 1 : s);
+  float *row = x + (int64_t)q * kNetIn;
+  row[0] = centre[3 * q];
+  row[1] = centre[3 * q + 1];
+  row[2] = centre[3 * q + 2];
+  row[3] = (float)s * dt;
+#pragma unroll
+  for (int c = 0; c < kState; ++c) row[4 + c] = st.v[c];
+}
+
+__global__ void k_clear(int32_t *__restrict__ p, int n) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < n) p[t] = 0;
+}
+
+struct DecideArgs {
+  const float *y, *gx, *centre, *radius;
+  const int32_t *slice;
+  int n, n_slices, nx, ny, nz;
+  double h, ox, oy, oz, eps;
+  float margin;
+  float *dist, *grad, *cost;
+  uint8_t *status, *used;
+  int32_t *list, *count, *need;
+};
+
+__global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  bool fb = false;
+  if (q < A.n) {
+    const int s = A.slice[q];
+    if (s < 0) {  // same answer as the exact path
+      const float nan = __builtin_nanf("");
+      A.dist[q] = nan;
+      A.grad[3 * q] = nan;
+      A.grad[3 * q + 1] = nan;
+      A.grad[3 * q + 2] = nan;
+      if (A.cost) A.cost[q] = nan;
+      if (A.status) A.status[q] = (uint8_t)PCSDF_Q_SLICE_NEG;
+      if (A.used) A.used[q] = 0;
+    } else {
+      const int sc = s > A.n_slices - 1 ? A.n_slices - 1 : s;
+      const int n3[3] = {A.nx, A.ny, A.nz};
+      const double o3[3] = {A.ox, A.oy, A.oz};
+      bool inside = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double g = ((double)A.centre[3 * q + a] - o3[a]) / A.h - 0.5;
+        inside = inside && g >= 0.0 && g <= (double)(n3[a] - 1);
+      }
+      const float ds = A.y[q] - A.radius[q];
+      const float g0 = A.gx[(int64_t)q * kNetIn];
+      const float g1 = A.gx[(int64_t)q * kNetIn + 1];
+      const float g2 = A.gx[(int64_t)q * kNetIn + 2];
+      const bool ok = inside && isfinite(ds) && ds >= A.margin &&
+                      isfinite(g0) && isfinite(g1) && isfinite(g2);
+      if (ok) {
+        A.dist[q] = ds;
+        A.grad[3 * q] = g0;
+        A.grad[3 * q + 1] = g1;
+        A.grad[3 * q + 2] = g2;
+        if (A.cost) {
+          const double hc = A.eps - (double)ds;
+          A.cost[q] = (float)(hc > 0.0 ? hc : 0.0);
+        }
+        if (A.status)
+          A.status[q] = (uint8_t)(s != sc ? PCSDF_Q_SLICE_CLAMPED : 0);
+      } else {
+        fb = true;
+        A.need[sc] = 1;
+      }
+      if (A.used) A.used[q] = fb ? 1 : 0;
+    }
+  }
+  // Append the wave's fallback queries to the list with one atomic.
+  const uint64_t mask = __ballot(fb);
+  if (mask == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(A.count, __popcll(mask));
+  base = __shfl(base, leader);
+  if (fb) {
+    const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
+    A.list[base + __popcll(below)] = q;
+  }
+}
+
+static unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace pcsdf
+
+using namespace pcsdf;
+
+extern "C" int pcsdf_surrogate_features(pcsdf_handle *hp, int32_t n_queries,
+                                        const float *centre_dev,
+                                        const int32_t *slice_dev,
+                                        int32_t n_slices, double dt_s,
+                                        const float *state_host,
+                                        float *x_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (n_queries < 0)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_queries must be >= 0");
+  if (n_slices < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
+  if (!state_host)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "state_host is required");
+  if (!std::isfinite(dt_s) || dt_s < 0)
+    return fail(h, PCSDF_ERR_NUMERIC, "dt_s must be finite and >= 0");
+  NetState st;
+  for (int c = 0; c < kState; ++c) {
+    if (!std::isfinite(state_host[c]))
+      return fail(h, PCSDF_ERR_NUMERIC, "non-finite state entry");
+    st.v[c] = state_host[c];
+  }
+  if (n_queries == 0) return PCSDF_OK;
+  if (!centre_dev || !slice_dev || !x_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "centre, slice and x are required");
+  if (((uintptr_t)centre_dev | (uintptr_t)slice_dev | (uintptr_t)x_dev) & 3)
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  int rc;
+  if ((rc = bind_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_features, dim3(nblocks(n_queries)), dim3(256), 0, s,
+                     centre_dev, slice_dev, n_slices, (float)dt_s, st,
+                     n_queries, x_dev);
+  return check_launch(h, "surrogate features");
+}
+
+extern "C" int pcsdf_query_spheres_surrogate(
+    pcsdf_handle *hp, pcsdf_mlp *m, const pcsdf_grid *g,
+    const int32_t *static_ssq_dev, int32_t n_slices, int32_t n_humans,
+    const double *human_xy_host, double radius_m, double height_m,
+    const float *state_host, double dt_s, double fallback_margin_m,
+    int32_t n_queries, const float *centre_dev, const float *radius_dev,
+    const int32_t *slice_dev, double hinge_eps_m, float *field_work_dev,
+    float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,
+    uint8_t *used_fallback_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!m) return fail(h, PCSDF_ERR_INVALID_ARG, "network is NULL");
+  if (mlp_handle(m) != h)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "the network was created on another handle");
+  int rc = check_grid(h, g);
+  if (rc) return rc;
+  if (g->nx < 2 || g->ny < 2 || g->nz < 2)
+    return fail(h, PCSDF_ERR_DIMS, "queries need at least 2 voxels per axis");
+  if (n_slices < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
+  if (n_queries < 0)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_queries must be >= 0");
+  if (n_humans < 0 || n_humans > kMaxHumans)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_humans must be in [0, 256]");
+  if (n_humans > 0 && !human_xy_host)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "human_xy_host is required");
+  if (!static_ssq_dev || !state_host)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "static_ssq_dev and state_host are required");
+  if (!std::isfinite(fallback_margin_m) || !std::isfinite(hinge_eps_m) ||
+      !std::isfinite(dt_s) || dt_s < 0 || !std::isfinite(radius_m) ||
+      !std::isfinite(height_m))
+    return fail(h, PCSDF_ERR_NUMERIC,
+                "margin, hinge, dt, radius and height must be finite");
+  for (int c = 0; c < kState; ++c)
+    if (!std::isfinite(state_host[c]))
+      return fail(h, PCSDF_ERR_NUMERIC, "non-finite state entry");
+  if (n_queries == 0) return PCSDF_OK;
+  if (!centre_dev || !radius_dev || !slice_dev || !dist_dev || !grad_dev ||
+      !field_work_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "centre, radius, slice, field_work, dist and grad are "
+                "required");
+  if (((uintptr_t)centre_dev | (uintptr_t)radius_dev |
+       (uintptr_t)slice_dev | (uintptr_t)dist_dev | (uintptr_t)grad_dev |
+       (uintptr_t)cost_dev | (uintptr_t)field_work_dev) & 3)
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  if ((rc = bind_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  // workspace: x [n][22], gx [n][22], y [n], list [n], count, need [n_slices]
+  const size_t n = (size_t)n_queries;
+  const size_t bx = align_up(n * kNetIn * 4, 256);
+  const size_t by = align_up(n * 4, 256);
+  const size_t bctl = align_up((1 + (size_t)n_slices) * 4, 256);
+  if ((rc = ensure_buffer(h, h->sur_buf, 2 * bx + 2 * by + bctl, s)))
+    return rc;
+  char *base = reinterpret_cast<char *>(h->sur_buf.ptr);
+  float *x = reinterpret_cast<float *>(base);
+  float *gx = reinterpret_cast<float *>(base + bx);
+  float *y = reinterpret_cast<float *>(base + 2 * bx);
+  int32_t *list = reinterpret_cast<int32_t *>(base + 2 * bx + by);
+  int32_t *ctl = reinterpret_cast<int32_t *>(base + 2 * bx + 2 * by);
+  int32_t *count = ctl, *need = ctl + 1;
+
+  if ((rc = pcsdf_surrogate_features(hp, n_queries, centre_dev, slice_dev,
+                                     n_slices, dt_s, state_host, x, stream)))
+    return rc;
+  if ((rc = pcsdf_mlp_forward(m, n_queries, x, y, gx, stream))) return rc;
+  hipLaunchKernelGGL(k_clear, dim3(nblocks(1 + n_slices)), dim3(256), 0, s,
+                     ctl, 1 + n_slices);
+  DecideArgs A;
+  A.y = y;
+  A.gx = gx;
+  A.centre = centre_dev;
+  A.radius = radius_dev;
+  A.slice = slice_dev;
+  A.n = n_queries;
+  A.n_slices = n_slices;
+  A.nx = g->nx;
+  A.ny = g->ny;
+  A.nz = g->nz;
+  A.h = g->voxel_m;
+  A.ox = g->origin_m[0];
+  A.oy = g->origin_m[1];
+  A.oz = g->origin_m[2];
+  A.eps = hinge_eps_m;
+  A.margin = (float)fallback_margin_m;
+  A.dist = dist_dev;
+  A.grad = grad_dev;
+  A.cost = cost_dev;
+  A.status = status_dev;
+  A.used = used_fallback_dev;
+  A.list = list;
+  A.count = count;
+  A.need = need;
+  {
+    ProfScope ps(h, PCSDF_KERNEL_SURROGATE_DECIDE, s);
+    hipLaunchKernelGGL(k_decide, dim3(nblocks(n_queries)), dim3(256), 0, s, A);
+    if ((rc = check_launch(h, "surrogate decide"))) return rc;
+  }
+  // Exact fields of the slices some fallback query reads, then the exact
+  // queries of the fallback list.
+  if ((rc = composite_run(h, g, static_ssq_dev, n_slices, n_humans,
+                          human_xy_host, radius_m, height_m, nullptr,
+                          field_work_dev, need, s)))
+    return rc;
+  ProfScope pq(h, PCSDF_KERNEL_QUERY, s);
+  return launch_query_list(h, g, field_work_dev, n_slices, list, count,
+                           n_queries, centre_dev, radius_dev, slice_dev,
+                           hinge_eps_m, dist_dev, grad_dev, status_dev,
+                           cost_dev, s);
+}

@@ -9,7 +9,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._native import Handle, default_handle, load_library
+from ._native import Handle, as_grid, default_handle, load_library
 
 NPARAM = 52609
 NIN = 22
@@ -37,6 +37,14 @@ def _declare(lib):
     lib.pcsdf_mlp_train_step.argtypes = [P, i32, P, P, f32, f32, f32, f32, P,
                                          P]
     lib.pcsdf_mlp_train_step.restype = C.c_int
+    lib.pcsdf_surrogate_features.argtypes = [P, i32, P, P, i32, C.c_double,
+                                             P, P, P]
+    lib.pcsdf_surrogate_features.restype = C.c_int
+    d = C.c_double
+    lib.pcsdf_query_spheres_surrogate.argtypes = [
+        P, P, P, P, i32, i32, P, d, d, P, d, d, i32, P, P, P, d, P, P, P, P,
+        P, P, P]
+    lib.pcsdf_query_spheres_surrogate.restype = C.c_int
     lib._mlp_declared = True
 
 
@@ -139,3 +147,81 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def _state(state):
+    st = np.ascontiguousarray(np.asarray(state, np.float32).reshape(-1))
+    if st.size != NIN - 4:
+        raise ValueError(f"state must hold {NIN - 4} values")
+    return st
+
+
+def surrogate_features(centre, slice_, n_slices, dt, state,
+                       handle: Handle | None = None):
+    """Network input [n, 22] for sphere queries (pcsdf_surrogate_features):
+    centre [n, 3] float32 and slice [n] int32 on the GPU; state: 18 host
+    floats (three humans' position and velocity at t = 0)."""
+    import torch
+    from . import _dev_ptr, _stream
+    h = handle or default_handle()
+    lib = load_library()
+    _declare(lib)
+    n = slice_.numel()
+    x = torch.empty((n, NIN), dtype=torch.float32, device=centre.device)
+    st = _state(state)
+    h.check(lib.pcsdf_surrogate_features(
+        h.ptr, n, _dev_ptr(centre, torch.float32, "centre", 3 * n),
+        _dev_ptr(slice_, torch.int32, "slice", n), int(n_slices), float(dt),
+        st.ctypes.data_as(C.c_void_p), _dev_ptr(x, torch.float32, "x"),
+        _stream(centre.device)))
+    return x
+
+
+def query_spheres_surrogate(net: Mlp, grid, static_ssq, human_xy, radius,
+                            height, state, dt, centre, sphere_radius, slice_,
+                            fallback_margin=0.10, hinge_eps=0.0,
+                            field_work=None, want_status=True,
+                            want_cost=False):
+    """Sphere queries by the network with exact fallback
+    (pcsdf_query_spheres_surrogate).  Returns a dict with dist, grad,
+    status, cost (or None), used_fallback and the field work buffer
+    (exact fields of the slices some fallback query read)."""
+    import torch
+    from . import _dev_ptr, _stream
+    g = as_grid(grid)
+    h = net.h
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n_slices, K = xy.shape[0], xy.shape[1]
+    V = g.nvox
+    dev = centre.device
+    n = slice_.numel()
+    if field_work is None:
+        field_work = torch.empty((n_slices,) + g.shape_zyx,
+                                 dtype=torch.float32, device=dev)
+    dist = torch.empty(n, dtype=torch.float32, device=dev)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    status = torch.empty(n, dtype=torch.uint8, device=dev) \
+        if want_status else None
+    cost = torch.empty(n, dtype=torch.float32, device=dev) \
+        if want_cost else None
+    used = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = _state(state)
+    h.check(net.lib.pcsdf_query_spheres_surrogate(
+        h.ptr, net.ptr, C.byref(g),
+        _dev_ptr(static_ssq, torch.int32, "static_ssq", V), n_slices, K,
+        xy.ctypes.data_as(C.c_void_p) if K > 0 else None, float(radius),
+        float(height), st.ctypes.data_as(C.c_void_p), float(dt),
+        float(fallback_margin), n,
+        _dev_ptr(centre, torch.float32, "centre", 3 * n),
+        _dev_ptr(sphere_radius, torch.float32, "radius", n),
+        _dev_ptr(slice_, torch.int32, "slice", n), float(hinge_eps),
+        _dev_ptr(field_work, torch.float32, "field_work", n_slices * V),
+        _dev_ptr(dist, torch.float32, "dist"),
+        _dev_ptr(grad, torch.float32, "grad"),
+        _dev_ptr(status, torch.uint8, "status"),
+        _dev_ptr(cost, torch.float32, "cost"),
+        _dev_ptr(used, torch.uint8, "used"), _stream(dev)))
+    return {"dist": dist, "grad": grad, "status": status, "cost": cost,
+            "used_fallback": used, "field_work": field_work}

@@ -1,0 +1,288 @@
+"""Trainer of the sphere-query surrogate for one static room.
+
+Each step of the data pipeline and of the optimisation runs in the
+library's kernels: for every fresh draw of three constant-velocity humans
+the exact composite fields of all slices are built
+(pcsdf_predicted_composite_sdf); uniformly drawn sphere centres and slices
+are labelled with the exact distance at the centre (pcsdf_query_spheres
+with zero radius); the network input is assembled on the device
+(pcsdf_surrogate_features); and one Adam step is taken on the squared
+error (pcsdf_mlp_train_step).  This module only draws the random inputs
+(human starts and velocities on the host, centres and slices with a seeded
+torch generator on the device) and sequences the calls.
+
+The network sees the room only through its training data, so one network
+serves one static room.  Labels below -0.1 m are raised to -0.1 m: deep
+inside obstacles the surrogate is never trusted (the fallback rule sends
+every predicted distance under the margin to the exact path), and the
+clamp keeps the regression target bounded.
+
+Usage:  python -m paper_2201_05058_amd.train --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+import scenegen
+
+from . import (build_static_sdf, default_handle, predicted_composite_sdf,
+               query_spheres)
+from .surrogate import NIN, Mlp, init_params, surrogate_features
+
+LABEL_FLOOR = -0.1
+
+
+def normalisation(grid):
+    """Input offset/scale mapping the room to [-1, 1], the slice time and
+    speeds to about unit range.  Feature order: centre x y z, t, then per
+    human position x y z and velocity x y z."""
+    L = np.array(grid.extent, np.float64)
+    o = np.array(grid.origin, np.float64)
+    off = np.zeros(NIN, np.float64)
+    scl = np.ones(NIN, np.float64)
+    off[0:3] = o + L / 2
+    scl[0:3] = 2.0 / L
+    off[3], scl[3] = 1.0, 1.0
+    for k in range(3):
+        b = 4 + 6 * k
+        off[b:b + 2] = o[:2] + L[:2] / 2
+        scl[b:b + 2] = 2.0 / L[:2]
+        scl[b + 3:b + 5] = 1.0 / 1.5
+    return off.astype(np.float32), scl.astype(np.float32)
+
+
+class Room:
+    """A static room (occupancy, static field) and the slice schedule."""
+
+    def __init__(self, scene, dev):
+        import torch
+        self.sc = scene
+        self.grid = scene.grid
+        self.dev = dev
+        occ = torch.from_numpy(scene.occ.astype(np.uint8)).to(dev)
+        self.static_ssq, _ = build_static_sdf(self.grid, occ, want_sdf=False)
+        self.n_slices = scene.n_slices
+        self.dt = scene.dt
+        self.fields = torch.empty((self.n_slices,) + self.grid.shape_zyx,
+                                  dtype=torch.float32, device=dev)
+
+    def draw_humans(self, rng):
+        start, vel = scenegen._cv_humans(rng, self.grid, 3,
+                                         scenegen.HUMAN_RADIUS)
+        xy = scenegen.cv_positions(start, vel, self.n_slices, self.dt)
+        return xy, scenegen.human_state(start, vel)
+
+    def build(self, xy):
+        predicted_composite_sdf(self.grid, self.static_ssq, xy,
+                                scenegen.HUMAN_RADIUS, scenegen.HUMAN_HEIGHT,
+                                out_sdf=self.fields, want_ssq=False)
+
+    def draw_queries(self, gen, n):
+        """Centres uniform over the span of voxel centres, slices uniform."""
+        import torch
+        g = self.grid
+        lo = torch.tensor(np.array(g.origin) + g.h / 2, dtype=torch.float32,
+                          device=self.dev)
+        span = torch.tensor(np.array(g.extent) - g.h, dtype=torch.float32,
+                            device=self.dev)
+        c = torch.rand((n, 3), generator=gen, device=self.dev) * span + lo
+        s = torch.randint(0, self.n_slices, (n,), generator=gen,
+                          device=self.dev, dtype=torch.int32)
+        return c.contiguous(), s
+
+    def label(self, c, s):
+        import torch
+        zero = torch.zeros(s.numel(), dtype=torch.float32, device=self.dev)
+        d, _, _, _ = query_spheres(self.grid, self.fields, c, zero, s,
+                                   want_status=False)
+        return d.clamp_(min=LABEL_FLOOR)
+
+
+def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
+          lr=2e-3, lr_min=2e-5, seed=0, log_every=200, log=print):
+    import torch
+    room = Room(scene, dev)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    net = Mlp()
+    off, scl = normalisation(room.grid)
+    net.set_params(init_params(rng), off, scl, 1.0)
+    steps = max(1, samples // batch)
+    per_draw = max(batch, per_draw // batch * batch)
+    loss = torch.zeros(1, device=dev)
+    hist = []
+    t0 = time.time()
+    step = 0
+    while step < steps:
+        xy, state = room.draw_humans(rng)
+        room.build(xy)
+        c, s = room.draw_queries(gen, per_draw)
+        y = room.label(c, s)
+        x = surrogate_features(c, s, room.n_slices, room.dt, state)
+        for b in range(0, per_draw, batch):
+            if step >= steps:
+                break
+            a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step
+                                                             / steps))
+            net.train_step(x[b:b + batch], y[b:b + batch], a, loss=loss)
+            step += 1
+            if step % log_every == 0 or step == steps:
+                l = float(loss.cpu()[0])
+                hist.append((step, l))
+                log(json.dumps({"step": step, "loss": l, "lr": a,
+                                "s": round(time.time() - t0, 1)}))
+    torch.cuda.synchronize()
+    return net, {"steps": steps, "batch": batch, "samples": steps * batch,
+                 "seconds": time.time() - t0, "loss": hist,
+                 "in_offset": off, "in_scale": scl}
+
+
+def save(path, net, info, scene):
+    np.savez(path, params=net.get_params(), in_offset=info["in_offset"],
+             in_scale=info["in_scale"], out_scale=np.float32(1.0),
+             meta=json.dumps({"room": scene.name, "seed": scene.seed,
+                              "grid": [scene.grid.nx, scene.grid.ny,
+                                       scene.grid.nz],
+                              "voxel_m": scene.grid.h,
+                              "n_slices": scene.n_slices, "dt": scene.dt,
+                              "samples": info["samples"],
+                              "steps": info["steps"],
+                              "final_loss": info["loss"][-1][1]
+                              if info["loss"] else None}))
+
+
+def load(path, handle=None) -> Mlp:
+    d = np.load(path, allow_pickle=False)
+    net = Mlp(handle or default_handle())
+    net.set_params(d["params"], d["in_offset"], d["in_scale"],
+                   float(d["out_scale"]))
+    return net
+
+
+def _time_ms(fn, reps=5, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
+             time_queries=None):
+    """Surrogate vs exact sphere queries on a fresh draw of the humans.
+
+    Errors are measured on the queries the surrogate answers (exact
+    answers have no error): max, p99 and mean absolute distance error in
+    metres, and the fallback fraction.  Timings: the 1M-query call of each
+    path on fields already built, and the end-to-end cost per new human
+    state at the room's own query load (time_queries, default: the scene's
+    query count), where the exact path builds every slice and the surrogate
+    path only the slices its fallback queries read."""
+    import torch
+
+    from .surrogate import query_spheres_surrogate
+    room = Room(scene, dev)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    xy, state = room.draw_humans(rng)
+    room.build(xy)
+    c, s = room.draw_queries(gen, n_queries)
+    r = (torch.rand(n_queries, generator=gen, device=dev) * 0.10 + 0.05)
+    d_ex, g_ex, _, _ = query_spheres(room.grid, room.fields, c, r, s,
+                                     want_status=False)
+    work = torch.empty_like(room.fields)
+
+    def sur(cc=c, rr=r, ss=s):
+        return query_spheres_surrogate(
+            net, room.grid, room.static_ssq, xy, scenegen.HUMAN_RADIUS,
+            scenegen.HUMAN_HEIGHT, state, room.dt, cc, rr, ss,
+            fallback_margin=margin, field_work=work, want_status=False)
+    out = sur()
+    torch.cuda.synchronize()
+    used = out["used_fallback"].bool()
+    acc = ~used
+    err = (out["dist"] - d_ex).abs()[acc]
+    gerr = (out["grad"] - g_ex).norm(dim=1)[acc]
+    e = err.double().cpu().numpy()
+    ge = gerr.double().cpu().numpy()
+    res = {
+        "queries": n_queries, "margin_m": margin,
+        "rule": "fallback when predicted sphere distance y - r < margin",
+        "fallback_fraction": float(used.float().mean()),
+        "err_max_m": float(e.max()) if e.size else None,
+        "err_p99_m": float(np.percentile(e, 99)) if e.size else None,
+        "err_mean_m": float(e.mean()) if e.size else None,
+        "grad_err_mean": float(ge.mean()) if ge.size else None,
+        "grad_err_p99": float(np.percentile(ge, 99)) if ge.size else None,
+    }
+    # kernels at 1M queries on fields already resident
+    x = surrogate_features(c, s, room.n_slices, room.dt, state)
+    res["mlp_forward_grad_ms_1M"] = _time_ms(lambda: net.forward(x))
+    res["exact_query_ms_1M"] = _time_ms(
+        lambda: query_spheres(room.grid, room.fields, c, r, s,
+                              want_status=False))
+    res["surrogate_path_ms_1M"] = _time_ms(sur)
+    # end-to-end per new human state at the room's query load
+    nq = time_queries or (len(scene.queries.radius) if scene.queries
+                          else 10_000)
+    cq, sq = c[:nq].contiguous(), (torch.arange(nq, device=dev,
+                                                dtype=torch.int32)
+                                   % room.n_slices)
+    rq = r[:nq].contiguous()
+
+    def exact_e2e():
+        room.build(xy)
+        query_spheres(room.grid, room.fields, cq, rq, sq, want_status=False)
+    res["e2e_queries"] = nq
+    res["e2e_exact_ms"] = _time_ms(exact_e2e)
+    res["e2e_surrogate_ms"] = _time_ms(lambda: sur(cq, rq, sq))
+    o2 = sur(cq, rq, sq)
+    used_q = o2["used_fallback"].bool().cpu().numpy()
+    res["e2e_fallback_fraction"] = float(used_q.mean())
+    res["e2e_slices_built"] = int(len(np.unique(sq.cpu().numpy()[used_q])))
+    res["n_slices"] = room.n_slices
+    return res
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--samples", type=float, default=50e6)
+    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--per-draw", type=int, default=32768)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--eval", action="store_true",
+                    help="evaluate the trained network on 1M queries")
+    a = ap.parse_args(argv)
+    dev = torch.device("cuda:0")
+    scene = scenegen.config2()
+    net, info = train(scene, dev, samples=int(a.samples), batch=a.batch,
+                      per_draw=a.per_draw, lr=a.lr, seed=a.seed,
+                      log=lambda s: print(s, flush=True))
+    save(a.out, net, info, scene)
+    print(json.dumps({"saved": a.out, "samples": info["samples"],
+                      "seconds": round(info["seconds"], 1)}), flush=True)
+    if a.eval:
+        print(json.dumps({"eval": evaluate(net, scene, dev)}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

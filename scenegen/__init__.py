@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Grid", "Scene", "Queries", "draw_boxes", "voxelise_boxes",
     "cv_positions", "piecewise_positions", "draw_queries",
-    "config1", "config2", "config3", "config5", "small_scene",
+    "config1", "config2", "config3", "config5", "small_scene", "human_state",
     "HUMAN_RADIUS", "HUMAN_HEIGHT",
 ]
 
@@ -303,4 +303,18 @@ def small_scene(seed: int, nx: int, ny: int, nz: int, h: float = 0.05,
     xy = cv_positions(start, vel, n_slices, dt)
     q = draw_queries(rng, g, n_queries, n_slices) if n_queries else None
     return Scene(f"small_{seed}", g, idx, occ, xy, radius=radius,
-                 height=height, dt=dt, queries=q, seed=seed)
+                 height=height, dt=dt, queries=q, seed=seed,
+                 meta={"start": start, "vel": vel})
+
+
+def human_state(start_xy: np.ndarray, vel_xy: np.ndarray) -> np.ndarray:
+    """The 18 state features of three constant-velocity humans at t = 0:
+    per human its position (x, y, 0) and velocity (vx, vy, 0), float32."""
+    start_xy = np.asarray(start_xy, np.float64)
+    vel_xy = np.asarray(vel_xy, np.float64)
+    if start_xy.shape != (3, 2) or vel_xy.shape != (3, 2):
+        raise ValueError("the state describes exactly three humans")
+    out = np.zeros((3, 6), np.float64)
+    out[:, 0:2] = start_xy
+    out[:, 3:5] = vel_xy
+    return out.reshape(-1).astype(np.float32)

@@ -174,3 +174,30 @@ def test_profile_calls_without_device(h):
     h.profile_reset()
     with pytest.raises(pc.PcsdfError):
         h.profile_read(17)
+
+
+def test_surrogate_validation(h):
+    from paper_2201_05058_amd import surrogate as sg
+    sg._declare(h.lib)
+    g = grid()
+    st = (C.c_float * 18)()
+    # no network
+    assert h.lib.pcsdf_query_spheres_surrogate(
+        h.ptr, None, C.byref(g), FAKE, 2, 0, None, 0.25, 1.8, st, 0.1, 0.1,
+        10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, FAKE, None, None, None,
+        None) == 1
+
+    def feat(n=5, centre=FAKE, slices=FAKE, n_slices=2, dt=0.1, state=st,
+             x=FAKE):
+        return h.lib.pcsdf_surrogate_features(h.ptr, n, centre, slices,
+                                              n_slices, dt, state, x, None)
+    assert feat(n=-1) == 1
+    assert feat(n_slices=0) == 1
+    assert feat(state=None) == 1
+    assert feat(dt=math.nan) == 6
+    assert feat(dt=-0.1) == 6
+    bad = (C.c_float * 18)(*([0.0] * 17 + [math.inf]))
+    assert feat(state=bad) == 6
+    assert feat(centre=None) == 1
+    assert feat(x=FAKE_MIS) == 3
+    assert feat(n=0) == 0  # no work, nothing touched

@@ -19,8 +19,11 @@ n u = 1.2e-4 of the sum's RMS at n = 2048 (u = 2^-24); the GPU's median
 there was 7e-5.  So the maximum error is bounded at 1% (outputs) and 5%
 (gradients) of the reference's RMS, the median at 5e-5 (5e-4 for weight
 gradients), and the share of elements off by more than 1e-3 at 2% (15% for
-input gradients): a systematic mistake (a wrong index, sign or dropped
-term) moves the median by orders of magnitude more.
+input gradients, whose flips move whole rows, and 10% for weight
+gradients, where a unit's bias and weight gradients collect the flips of
+every sample in the batch: 4.7% of one 128-element bias gradient in a
+measured run): a systematic mistake (a wrong index, sign or dropped term)
+moves the median by orders of magnitude more.
 """
 import sys
 
@@ -102,7 +105,7 @@ def test_parameter_gradients(sg, dev, seed, n):
     wg, wgx = omlp.backward(p.astype(np.float64), x, dy, off, sc, osc)
     gp = gp.cpu().numpy()
     for name, a, b in zip(range(10), omlp.unpack(gp), omlp.unpack(wg)):
-        close(a, b, rtol_rms=5e-2, med=5e-4)
+        close(a, b, rtol_rms=5e-2, med=5e-4, frac=0.10)
     close(gx.cpu().numpy(), wgx, rtol_rms=5e-2, frac=0.15)
     net.close()
 

@@ -1,0 +1,247 @@
+"""Surrogate sphere queries with exact fallback (through the C-ABI) against
+the oracle of the accept / fallback rule.
+
+Exact answers (fallback queries) are held to the exact-query contract
+(1e-6 relative with floors; status bits equal).  Network answers are held
+to the network's parity bounds (see the MLP parity tests for their
+derivation from BF16 rounding flips), widened for the larger weights used
+here (gain 2.5 instead of 1.5, so that outputs spread across the margin),
+which amplify a flip more on its way to the output: outputs within 3% of
+the output RMS (1.03% measured), gradients within 5%, medians within 5e-5,
+and at most 5% of the answers off by more than 1e-3 of RMS.  The decision
+itself depends on the network's value, which the GPU computes with FP32
+accumulation: the two sides may only disagree for queries whose oracle
+value lies within the output bound of the margin.  Fields are built only
+for the slices that some fallback query reads, bit-identical to the
+oracle's composite; the other slices of the work buffer stay untouched.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from oracle import mlp as omlp
+from oracle import surrogate as osur
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SENTINEL = 12345.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg(dev):
+    import paper_2201_05058_amd.surrogate as m
+    return m
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def rand_net(seed, gain=1.5):
+    r = np.random.default_rng(seed)
+    out = []
+    for s in omlp.SHAPES:
+        fan = s[-1] if len(s) == 2 else 16
+        out.append(r.uniform(-1, 1, size=s) * gain / np.sqrt(fan))
+    return omlp.pack(out).astype(np.float32)
+
+
+def make_case(seed, Q=4000, nx=40, ny=36, nz=30, n_slices=4):
+    sc = scenegen.small_scene(seed, nx, ny, nz, h=0.05, n_humans=3,
+                              n_slices=n_slices)
+    rng = np.random.default_rng(seed + 1)
+    L = np.array(sc.grid.extent)
+    c = (rng.uniform(-0.05, 1.05, size=(Q, 3)) * L).astype(np.float32)
+    r = rng.uniform(0, 0.15, size=Q).astype(np.float32)
+    s = rng.integers(-1, n_slices + 2, size=Q).astype(np.int32)
+    st = scenegen.human_state(sc.meta["start"], sc.meta["vel"])
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    _, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                       sc.height)
+    return sc, c, r, s, st, rs, wf
+
+
+def run_gpu(sg, dev, sc, rs, c, r, s, st, params, off, scl, osc, margin,
+            eps):
+    net = sg.Mlp()
+    net.set_params(params, off, scl, osc)
+    fw = torch.full((sc.n_slices,) + sc.grid.shape_zyx, SENTINEL,
+                    dtype=torch.float32, device=dev)
+    out = sg.query_spheres_surrogate(
+        net, sc.grid, to_dev(rs, dev), sc.human_xy, sc.radius, sc.height, st,
+        sc.dt, to_dev(c, dev), to_dev(r, dev), to_dev(s, dev),
+        fallback_margin=margin, hinge_eps=eps, field_work=fw, want_cost=True)
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if v is not None else None)
+           for k, v in out.items()}
+    net.close()
+    return res
+
+
+def check_exact(got_d, got_g, got_st, got_c, wd, wg, wst, wc, h):
+    np.testing.assert_array_equal(got_st, wst)
+    for got, want, floor in ((got_d, wd, h), (got_c, wc, h)):
+        nanw = np.isnan(want)
+        assert (np.isnan(got) == nanw).all()
+        fin = np.isfinite(want)
+        np.testing.assert_array_equal(got[~fin & ~nanw], want[~fin & ~nanw])
+        err = np.abs(got[fin].astype(np.float64) - want[fin])
+        assert (err <= 1e-6 * np.maximum(np.abs(want[fin]), floor)).all()
+    nanw = np.isnan(wg)
+    assert (np.isnan(got_g) == nanw).all()
+    err = np.abs(got_g[~nanw].astype(np.float64) - wg[~nanw])
+    assert (err <= 1e-6 * np.maximum(np.abs(wg[~nanw]), 1.0)).all()
+
+
+def check_fields(res, wf, used, s, n_slices):
+    fw = res["field_work"]
+    need = np.zeros(n_slices, bool)
+    need[np.clip(s[used == 1], 0, n_slices - 1)] = True
+    for j in range(n_slices):
+        if need[j]:
+            np.testing.assert_array_equal(fw[j], wf[j])
+        else:
+            assert (fw[j] == SENTINEL).all(), j
+    return need
+
+
+@pytest.mark.parametrize("seed", [61, 62])
+def test_surrogate_matches_oracle(sg, dev, seed):
+    sc, c, r, s, st, rs, wf = make_case(seed)
+    rng = np.random.default_rng(seed + 7)
+    p = rand_net(seed, gain=2.5)  # outputs spread across the margin
+    off = (rng.normal(size=22) * 0.1).astype(np.float32)
+    scl = (0.5 + rng.random(22)).astype(np.float32)
+    osc, margin, eps = 0.4, 0.10, 0.3
+    say(f"surrogate parity seed={seed} Q={len(r)}")
+    res = run_gpu(sg, dev, sc, rs, c, r, s, st, p, off, scl, osc, margin,
+                  eps)
+    wd, wg, wst, wc, wused, wy = osur.query(
+        sc.grid, wf, p, off, scl, osc, st, sc.dt, c, r, s, margin, eps)
+    used = res["used_fallback"]
+    neg = s < 0
+    assert (used[neg] == 0).all()
+    assert np.isnan(res["dist"][neg]).all() and (res["status"][neg] == 32).all()
+    # decisions agree except within the network's parity bound of the margin
+    rms = np.sqrt(np.mean(wy[~neg] ** 2))
+    dis = (used != wused) & ~neg
+    band = np.abs(wy - r - margin) <= 3e-2 * rms
+    assert (band[dis]).all(), np.nonzero(dis & ~band)
+    assert dis.mean() < 0.01
+    assert 0.05 < used[~neg].mean() < 0.95  # both branches exercised
+    # exact answers
+    ex = (used == 1) & (wused == 1)
+    xd, xg, xst, xc = oracle.query(sc.grid, wf, c, r, s, hinge_eps=eps)
+    check_exact(res["dist"][ex], res["grad"][ex], res["status"][ex],
+                res["cost"][ex], xd[ex], xg[ex], xst[ex], xc[ex], sc.grid.h)
+    # network answers
+    ok = (used == 0) & ~neg
+    x = osur.features(c, s, sc.n_slices, sc.dt, st)
+    wgx = omlp.input_gradient(p.astype(np.float64), x, off, scl, osc)[:, :3]
+    d_err = np.abs(res["dist"][ok] - (wy[ok] - r[ok])) / rms
+    assert d_err.max() <= 3e-2 and np.median(d_err) <= 5e-5
+    assert np.mean(d_err > 1e-3) <= 0.05
+    grms = np.sqrt(np.mean(wgx ** 2))
+    g_err = np.abs(res["grad"][ok] - wgx[ok]) / grms
+    assert g_err.max() <= 5e-2 and np.median(g_err) <= 5e-5
+    assert (res["dist"][ok] >= np.float32(margin)).all()
+    np.testing.assert_array_equal(
+        res["status"][ok], np.where(s[ok] > sc.n_slices - 1, 8, 0))
+    wcost = np.maximum(eps - res["dist"][ok].astype(np.float64), 0)
+    np.testing.assert_array_equal(res["cost"][ok], wcost.astype(np.float32))
+    check_fields(res, wf, used, s, sc.n_slices)
+
+
+def test_all_fallback_equals_exact_query(sg, dev):
+    sc, c, r, s, st, rs, wf = make_case(63, Q=3000)
+    p = rand_net(63)
+    one, zero = np.ones(22, np.float32), np.zeros(22, np.float32)
+    say("surrogate all-fallback")
+    res = run_gpu(sg, dev, sc, rs, c, r, s, st, p, zero, one, 1.0, 1e30, 0.2)
+    xd, xg, xst, xc = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.2)
+    assert (res["used_fallback"] == (s >= 0)).all()
+    check_exact(res["dist"], res["grad"], res["status"], res["cost"], xd, xg,
+                xst, xc, sc.grid.h)
+    need = check_fields(res, wf, res["used_fallback"], s, sc.n_slices)
+    assert need.all()
+
+
+def test_no_fallback_builds_no_field(sg, dev):
+    sc, c, r, s, st, rs, wf = make_case(64, Q=2000)
+    L = np.array(sc.grid.extent)
+    rng = np.random.default_rng(3)
+    c = (rng.uniform(0.1, 0.9, size=(len(r), 3)) * L).astype(np.float32)
+    s = np.abs(s).astype(np.int32)
+    p = rand_net(64)
+    one, zero = np.ones(22, np.float32), np.zeros(22, np.float32)
+    say("surrogate no-fallback")
+    res = run_gpu(sg, dev, sc, rs, c, r, s, st, p, zero, one, 1.0, -1e30, 0.0)
+    assert (res["used_fallback"] == 0).all()
+    assert (res["field_work"] == SENTINEL).all()
+
+
+def test_nonfinite_network_routes_everything_to_exact(sg, dev):
+    sc, c, r, s, st, rs, wf = make_case(65, Q=2000, n_slices=3)
+    p = np.zeros(omlp.NPARAM, np.float32)
+    p[-1] = 1e30  # a constant output bias of 1e30 times an output scale of
+    one, zero = np.ones(22, np.float32), np.zeros(22, np.float32)
+    say("surrogate non-finite network")  # 1e30 overflows fp32 to +inf
+    res = run_gpu(sg, dev, sc, rs, c, r, s, st, p, zero, one, 1e30, 0.1, 0.0)
+    xd, xg, xst, xc = oracle.query(sc.grid, wf, c, r, s)
+    assert (res["used_fallback"] == (s >= 0)).all()
+    check_exact(res["dist"], res["grad"], res["status"], res["cost"], xd, xg,
+                xst, xc, sc.grid.h)
+
+
+def test_features_layout(sg, dev):
+    rng = np.random.default_rng(8)
+    c = rng.normal(size=(777, 3)).astype(np.float32)
+    s = rng.integers(-3, 9, size=777).astype(np.int32)
+    st = rng.normal(size=18).astype(np.float32)
+    say("surrogate features")
+    x = sg.surrogate_features(to_dev(c, dev), to_dev(s, dev), 5, 0.1, st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(x.cpu().numpy(),
+                                  osur.features(c, s, 5, 0.1, st))
+
+
+def test_network_of_another_handle_is_rejected(sg, dev):
+    import paper_2201_05058_amd as pc
+    other = pc.Handle()
+    net = sg.Mlp(other)
+    sc, c, r, s, st, rs, wf = make_case(66, Q=10)
+    say("surrogate network of another handle")
+    with pytest.raises(pc.PcsdfError):
+        _call_with_handle(net, pc.default_handle(), sc, rs, c, r, s, st, dev)
+    net.close()
+    other.close()
+
+
+def _call_with_handle(net, handle, sc, rs, c, r, s, st, dev):
+    import ctypes as C
+    from paper_2201_05058_amd._native import as_grid
+    g = as_grid(sc.grid)
+    n = len(r)
+    xy = np.ascontiguousarray(sc.human_xy, np.float64)
+    buf = torch.empty(sc.n_slices * sc.grid.nvox, device=dev)
+    outs = [torch.empty(n, device=dev), torch.empty(3 * n, device=dev)]
+    stt = np.ascontiguousarray(st, np.float32)
+    rd, cd, sd = to_dev(rs, dev), to_dev(c, dev), to_dev(r, dev)
+    sl = to_dev(s, dev)
+    P = C.c_void_p
+    handle.check(net.lib.pcsdf_query_spheres_surrogate(
+        handle.ptr, net.ptr, C.byref(g), P(rd.data_ptr()), sc.n_slices,
+        sc.n_humans, xy.ctypes.data_as(P), sc.radius, sc.height,
+        stt.ctypes.data_as(P), sc.dt, 0.1, n, P(cd.data_ptr()),
+        P(sd.data_ptr()), P(sl.data_ptr()), 0.0, P(buf.data_ptr()),
+        P(outs[0].data_ptr()), P(outs[1].data_ptr()), None, None, None,
+        None))

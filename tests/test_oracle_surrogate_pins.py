@@ -1,0 +1,105 @@
+"""Pins of the surrogate-query oracle (accept / fallback rule) by cases
+whose answer is known without it: a constant network (closed form), an
+infinite margin (reduces to the exact query), a non-finite network, the
+input layout, and the boundary of the span of voxel centres."""
+import numpy as np
+
+import oracle
+import scenegen
+from oracle import mlp as omlp
+from oracle import surrogate as osur
+
+
+def scene():
+    sc = scenegen.small_scene(41, 14, 12, 10, h=0.1, n_humans=3, n_slices=3)
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    _, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                       sc.height)
+    st = scenegen.human_state(sc.meta["start"], sc.meta["vel"])
+    return sc, wf, st
+
+
+def queries(sc, Q=400, seed=0):
+    rng = np.random.default_rng(seed)
+    L = np.array(sc.grid.extent)
+    c = (rng.uniform(-0.1, 1.1, size=(Q, 3)) * L).astype(np.float32)
+    r = rng.uniform(0, 0.3, size=Q).astype(np.float32)
+    s = rng.integers(-1, sc.n_slices + 2, size=Q).astype(np.int32)
+    return c, r, s
+
+
+def const_net(value):
+    p = np.zeros(omlp.NPARAM)
+    p[-1] = value  # output bias: y = value * out_scale everywhere
+    return p
+
+
+def test_constant_network_closed_form():
+    sc, wf, st = scene()
+    c, r, s = queries(sc)
+    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
+    d, g, status, cost, used, _ = osur.query(
+        sc.grid, wf, const_net(0.5), zeros, ones, 1.0, st, sc.dt, c, r, s,
+        margin=0.1, hinge_eps=0.4)
+    ed, eg, est, ecost = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.4)
+    inside = osur.in_span(sc.grid, c)
+    accept = inside & (s >= 0) & (np.float32(0.5) - r >= np.float32(0.1))
+    assert accept.any() and (~accept & (s >= 0)).any()
+    np.testing.assert_array_equal(d[accept], np.float32(0.5) - r[accept])
+    np.testing.assert_array_equal(g[accept], 0.0)
+    np.testing.assert_array_equal(
+        status[accept], np.where(s[accept] > sc.n_slices - 1, 8, 0))
+    np.testing.assert_array_equal(
+        cost[accept],
+        np.maximum(0.4 - (np.float32(0.5) - r[accept]).astype(np.float64),
+                   0).astype(np.float32))
+    rest = ~accept
+    np.testing.assert_array_equal(d[rest], ed[rest])
+    np.testing.assert_array_equal(status[rest], est[rest])
+    np.testing.assert_array_equal(used, (~accept & (s >= 0)).astype(np.uint8))
+    # slice < 0: NaN and the SLICE_NEG bit, never a fallback
+    neg = s < 0
+    assert np.isnan(d[neg]).all() and (status[neg] == 32).all()
+
+
+def test_infinite_margin_is_the_exact_query():
+    sc, wf, st = scene()
+    c, r, s = queries(sc, seed=1)
+    p = np.random.default_rng(3).normal(size=omlp.NPARAM) * 0.05
+    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
+    got = osur.query(sc.grid, wf, p, zeros, ones, 1.0, st, sc.dt, c, r, s,
+                     margin=np.inf, hinge_eps=0.2)
+    want = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.2)
+    for a, b in zip(got[:4], want):
+        np.testing.assert_array_equal(a, b)
+    assert (got[4] == (s >= 0)).all()
+
+
+def test_nonfinite_network_falls_back():
+    sc, wf, st = scene()
+    c, r, s = queries(sc, seed=2)
+    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
+    got = osur.query(sc.grid, wf, const_net(1.0), zeros, ones, np.inf, st,
+                     sc.dt, c, r, s, margin=0.1)
+    want = oracle.query(sc.grid, wf, c, r, s)
+    np.testing.assert_array_equal(got[0], want[0])
+    assert (got[4] == (s >= 0)).all()
+
+
+def test_feature_layout():
+    st = np.arange(18, dtype=np.float32)
+    x = osur.features(np.array([[1, 2, 3], [4, 5, 6]], np.float32),
+                      np.array([7, -2]), 5, 0.1, st)
+    np.testing.assert_array_equal(x[0, :3], [1, 2, 3])
+    assert x[0, 3] == np.float32(4) * np.float32(0.1)  # clamped to n-1 = 4
+    assert x[1, 3] == 0.0
+    np.testing.assert_array_equal(x[:, 4:], np.stack([st, st]))
+
+
+def test_span_boundary():
+    g = scenegen.Grid(4, 5, 6, 0.5)
+    first = np.array([[0.25, 0.25, 0.25]], np.float32)
+    last = np.array([[1.75, 2.25, 2.75]], np.float32)
+    assert osur.in_span(g, first)[0] and osur.in_span(g, last)[0]
+    assert not osur.in_span(g, first - np.float32(1e-3))[0]
+    assert not osur.in_span(g, last + np.float32(1e-3))[0]
