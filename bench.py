@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("composite-EDT voxel-slices/s (% HBM peak); "
           "sphere queries/s surrogate vs exact")
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_config2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_room256_traffic.json")
 COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
                              "composite.hip")
 
@@ -112,7 +112,7 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
     64..128 at 0.02-0.05 m): one captured hipGraph replay of the batch
     against 64 plain calls on one stream, same outputs.  Static fields are
     built before timing."""
-    scs = scenegen.config3()
+    scs = scenegen.batch64()
     h = pc.Handle()
     scenes = []
     for sc in scs:
@@ -213,7 +213,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    sc = scenegen.config2()
+    sc = scenegen.room256()
     g = sc.grid
     V, n, K = g.nvox, sc.n_slices, sc.n_humans
     q = sc.queries
@@ -282,7 +282,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": "config2: 256x256x128 grid at 0.02 m, 40 seeded "
+            "workload": "256x256x128 grid at 0.02 m, 40 seeded "
                         "boxes, 3 constant-velocity cylinder humans, 20 "
                         "slices at dt=0.1 s, 10k exact sphere queries",
             "grid": [g.nx, g.ny, g.nz], "voxel_m": g.h, "n_slices": n,
@@ -306,7 +306,7 @@ def main():
     }
     del out_ssq, out_sdf
     if not args.no_batch:
-        line["config3_batch"] = batch_section(pc, autotune, scenegen, torch,
+        line["batch64"] = batch_section(pc, autotune, scenegen, torch,
                                               dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_slices)

@@ -105,7 +105,7 @@ class Room:
 
 
 def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
-          lr=2e-3, lr_min=2e-5, seed=0, log_every=200, log=print):
+          lr=2e-3, lr_min=2e-5, seed=0, log_every=1000, log=print):
     import torch
     room = Room(scene, dev)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -272,7 +272,7 @@ def main(argv=None):
                     help="evaluate the trained network on 1M queries")
     a = ap.parse_args(argv)
     dev = torch.device("cuda:0")
-    scene = scenegen.config2()
+    scene = scenegen.room256()
     net, info = train(scene, dev, samples=int(a.samples), batch=a.batch,
                       per_draw=a.per_draw, lr=a.lr, seed=a.seed,
                       log=lambda s: print(s, flush=True))

@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Grid", "Scene", "Queries", "draw_boxes", "voxelise_boxes",
     "cv_positions", "piecewise_positions", "draw_queries",
-    "config1", "config2", "config3", "config5", "small_scene", "human_state",
+    "cube64", "room256", "batch64", "room512", "small_scene", "human_state",
     "HUMAN_RADIUS", "HUMAN_HEIGHT",
 ]
 
@@ -204,7 +204,7 @@ def _cv_humans(rng, grid: Grid, count: int, r: float):
     return start, vel
 
 
-def config1(seed: int = 1) -> Scene:
+def cube64(seed: int = 1) -> Scene:
     """64^3 at 0.05 m, 12 boxes, one cylinder at a seeded position, 1 slice."""
     rng = np.random.Generator(np.random.PCG64(seed))
     g = Grid(64, 64, 64, 0.05)
@@ -213,10 +213,10 @@ def config1(seed: int = 1) -> Scene:
     Lx, Ly, _ = g.extent
     r = HUMAN_RADIUS
     xy = np.array([[[rng.uniform(r, Lx - r), rng.uniform(r, Ly - r)]]])
-    return Scene("config1", g, idx, occ, xy, dt=0.0, seed=seed)
+    return Scene("cube64", g, idx, occ, xy, dt=0.0, seed=seed)
 
 
-def config2(seed: int = 2, n_queries: int = 10_000) -> Scene:
+def room256(seed: int = 2, n_queries: int = 10_000) -> Scene:
     """256x256x128 at 0.02 m, 40 boxes, 3 constant-velocity humans,
     20 slices at dt = 0.1 s, 10k sphere queries (slice = q mod 20)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -227,11 +227,11 @@ def config2(seed: int = 2, n_queries: int = 10_000) -> Scene:
     n, dt = 20, 0.1
     xy = cv_positions(start, vel, n, dt)
     q = draw_queries(rng, g, n_queries, n)
-    return Scene("config2", g, idx, occ, xy, dt=dt, queries=q, seed=seed,
+    return Scene("room256", g, idx, occ, xy, dt=dt, queries=q, seed=seed,
                  meta={"start": start, "vel": vel})
 
 
-def config3(seed: int = 3, n_scenes: int = 64) -> List[Scene]:
+def batch64(seed: int = 3, n_scenes: int = 64) -> List[Scene]:
     """64 independent scenes of uneven sizes: nx, ny ~ U{64..256},
     nz ~ U{64..128}, h ~ U(0.02, 0.05), boxes = max(4, round(40*vol/67.1)),
     n ~ U{5..30} slices, K ~ U{1..4} constant-velocity humans, dt = 0.1 s."""
@@ -251,11 +251,11 @@ def config3(seed: int = 3, n_scenes: int = 64) -> List[Scene]:
         K = int(rng.integers(1, 5))
         start, vel = _cv_humans(rng, g, K, HUMAN_RADIUS)
         xy = cv_positions(start, vel, n, 0.1)
-        out.append(Scene(f"config3_{s}", g, idx, occ, xy, dt=0.1, seed=seed))
+        out.append(Scene(f"batch64_{s}", g, idx, occ, xy, dt=0.1, seed=seed))
     return out
 
 
-def config5(seed: int = 5, queries_per_slice: int = 100_000,
+def room512(seed: int = 5, queries_per_slice: int = 100_000,
             with_queries: bool = True) -> Scene:
     """512x512x256 at 0.01 m, 200 boxes, 8 humans on 4-waypoint
     piecewise-linear paths (segment speed ~ U(0.5, 1.5) m/s, held at the
@@ -275,7 +275,7 @@ def config5(seed: int = 5, queries_per_slice: int = 100_000,
     q = None
     if with_queries:
         q = draw_queries(rng, g, queries_per_slice * n, n)
-    return Scene("config5", g, idx, occ, xy, dt=dt, queries=q, seed=seed,
+    return Scene("room512", g, idx, occ, xy, dt=dt, queries=q, seed=seed,
                  meta={"waypoints": wp, "speeds": sp})
 
 

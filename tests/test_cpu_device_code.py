@@ -52,7 +52,7 @@ def run_planes(exe, tmp, sc):
 
 
 def plane_scenes():
-    yield scenegen.config2()
+    yield scenegen.room256()
     for q, (nx, ny, K, r) in enumerate([(37, 29, 2, 0.25), (21, 60, 1, 0.25),
                                         (100, 36, 4, 0.25), (64, 64, 8, 0.4),
                                         (40, 40, 3, 3.0), (33, 27, 3, 0.0)]):

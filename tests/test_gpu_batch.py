@@ -164,10 +164,10 @@ def test_autotuners_pick_a_shape_with_identical_output(pc, dev):
 
 
 @pytest.mark.slow
-def test_config3_batch_equals_64_plain_calls(pc, dev):
-    scs = scenegen.config3()
+def test_batch64_equals_64_plain_calls(pc, dev):
+    scs = scenegen.batch64()
     ds = [scene_dict(pc, sc, dev) for sc in scs]
-    say("config3: 64 scenes, voxel-slices =",
+    say("batch64: 64 scenes, voxel-slices =",
         sum(sc.grid.nvox * sc.n_slices for sc in scs))
     outs = pc.predicted_composite_sdf_batch(ds)
     torch.cuda.synchronize()

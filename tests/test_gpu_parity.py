@@ -85,8 +85,8 @@ def test_static_build_long_columns(pc, dev, shape):
     np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
 
 
-def test_static_build_config1_and_fp32_exact(pc, dev):
-    sc = scenegen.config1()
+def test_static_build_cube64_and_fp32_exact(pc, dev):
+    sc = scenegen.cube64()
     ssq, sdf = gpu_static(pc, sc.grid, sc.occ, dev)
     rs, rf = oracle.build_static(sc.grid, sc.occ)
     np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
@@ -167,14 +167,14 @@ def test_composite_single_output_modes(pc, dev):
     assert_f32_close(cf.cpu().numpy(), wf)
 
 
-def test_composite_config1(pc, dev):
-    check_composite(pc, scenegen.config1(), dev)
+def test_composite_cube64(pc, dev):
+    check_composite(pc, scenegen.cube64(), dev)
 
 
 @pytest.mark.slow
-def test_composite_config2_full(pc, dev):
+def test_composite_room256_full(pc, dev):
     """The full 256x256x128 x 20-slice workload, element by element."""
-    check_composite(pc, scenegen.config2(), dev)
+    check_composite(pc, scenegen.room256(), dev)
 
 
 def test_composite_deterministic_and_on_side_stream(pc, dev):
@@ -217,10 +217,10 @@ def check_queries(pc, sc, dev, centre, radius, slices, eps=0.3):
     assert (err <= 1e-6 * np.maximum(np.abs(wg[~nanw]), 1.0)).all()
 
 
-def test_queries_config2(pc, dev):
-    sc = scenegen.config2()
+def test_queries_room256(pc, dev):
+    sc = scenegen.room256()
     q = sc.queries
-    say("queries config2 Q=", len(q.radius))
+    say("queries room256 Q=", len(q.radius))
     check_queries(pc, sc, dev, q.centre, q.radius, q.slice)
 
 

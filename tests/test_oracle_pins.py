@@ -145,10 +145,10 @@ def box_union_outside(boxes, shape):
     return best
 
 
-@pytest.mark.parametrize("maker", ["config1", "small"])
+@pytest.mark.parametrize("maker", ["cube64", "small"])
 def test_box_scenes_outside_closed_form(maker):
-    if maker == "config1":
-        sc = scenegen.config1()
+    if maker == "cube64":
+        sc = scenegen.cube64()
     else:
         sc = scenegen.small_scene(7, 37, 29, 23, h=0.05, n_boxes=9)
     ssq = oracle.signed_sq(sc.occ)
