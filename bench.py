@@ -162,6 +162,85 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
             "tuning": tuning}
 
 
+def recompute_section(pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h,
+                      reps: int = 3):
+    """The paper's composite benchmark (mapping section, Fig. 6) on this
+    workload: the composite call against recomputing every slice's field
+    from scratch (exact signed EDT of the environment and the humans' voxels
+    with this library's three-pass EDT), without and with copying the n
+    fp32 fields to pinned host memory afterwards."""
+    g = sc.grid
+    host = torch.empty(tuple(out_sdf.shape), dtype=torch.float32,
+                       pin_memory=True)
+
+    def comp():
+        pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
+                                   sc.height, out_ssq=out_ssq,
+                                   out_sdf=out_sdf, handle=h)
+
+    def reco():
+        pc.recompute_sdf(g, occ, sc.human_xy, sc.radius, sc.height,
+                         out_ssq=out_ssq, out_sdf=out_sdf, handle=h)
+
+    def copied(fn):
+        def run():
+            fn()
+            host.copy_(out_sdf, non_blocking=True)
+        return run
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    c_ms, r_ms = timed(comp), timed(reco)
+    cc_ms, rc_ms = timed(copied(comp)), timed(copied(reco))
+    del host
+    return {"slices": sc.n_slices, "composite_ms": c_ms,
+            "recompute_ms": r_ms, "speedup_excl_copy": r_ms / c_ms,
+            "composite_with_copy_ms": cc_ms,
+            "recompute_with_copy_ms": rc_ms,
+            "speedup_incl_copy": rc_ms / cc_ms,
+            "copy_bytes": out_sdf.numel() * 4,
+            "copy_gbs": out_sdf.numel() * 4 / ((cc_ms - c_ms) / 1e3) / 1e9
+            if cc_ms > c_ms else None,
+            "paper_context": "9.1-13.6x excluding and 1.7-2.1x including "
+                             "the device-to-host copy, against PBA on an "
+                             "RTX 2060 (grid sizes not recoverable)"}
+
+
+def surrogate_section(pc, torch, dev, weights: str):
+    """Sphere queries by the trained surrogate (with exact fallback)
+    against the exact path: error in metres on the queries it answers, the
+    fallback fraction, the kernels at 1M queries and the end-to-end cost
+    per new human state at this workload's 10k queries."""
+    import scenegen
+    from paper_2201_05058_amd import train
+    if not os.path.exists(weights):
+        return {"weights": None, "note": "no trained weights file"}
+    net, meta = train.load(weights)
+    sc = scenegen.room256()
+    res = train.evaluate(net, sc, dev, mode=meta.get("mode", "env"))
+    # matrix-core work of the network: forward + input gradient per query
+    flop = 2 * (22 * 128 + 3 * 128 * 128 + 128) * 2 - 2 * 22 * 128
+    ms = res["mlp_forward_grad_ms_1M"]
+    res["mlp_flop_per_query"] = flop
+    res["mlp_tflops"] = flop * res["queries"] / (ms / 1e3) / 1e12
+    res["mlp_frac_bf16_peak"] = res["mlp_tflops"] / 2500.0
+    res["queries_per_s_surrogate_path_1M"] = res["queries"] / (
+        res["surrogate_path_ms_1M"] / 1e3)
+    res["queries_per_s_exact_1M"] = res["queries"] / (
+        res["exact_query_ms_1M"] / 1e3)
+    res["weights"] = os.path.relpath(weights, ROOT)
+    res["trained_on"] = meta
+    net.close()
+    return res
+
+
 def calibrate_copy(mib: int, reps: int):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -184,6 +263,12 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-scene batch measurement")
+    ap.add_argument("--no-recompute", action="store_true",
+                    help="skip the composite vs full recompute measurement")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate query measurement")
+    ap.add_argument("--weights", default=os.path.join(
+        ROOT, "paper_2201_05058_amd", "weights", "surrogate_room256.npz"))
     ap.add_argument("--traffic-from", default="",
                     help="write the composite's measured HBM traffic from "
                          "rocprofv3 PMC output under this directory")
@@ -304,7 +389,12 @@ def main():
         if qy_ms > 0 else None,
         "tuning": tuning,
     }
+    if not args.no_recompute:
+        line["fig6_recompute"] = recompute_section(
+            pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h)
     del out_ssq, out_sdf
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_section(pc, torch, dev, args.weights)
     if not args.no_batch:
         line["batch64"] = batch_section(pc, autotune, scenegen, torch,
                                               dev)

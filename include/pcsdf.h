@@ -68,7 +68,8 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_MLP 5       /* surrogate forward (+ input gradient) */
 #define PCSDF_KERNEL_MLP_TRAIN 6 /* one surrogate training step */
 #define PCSDF_KERNEL_SURROGATE_DECIDE 7 /* surrogate accept / fallback split */
-#define PCSDF_KERNEL_COUNT 8
+#define PCSDF_KERNEL_RECOMPUTE 8 /* full recompute: every slice's union EDT */
+#define PCSDF_KERNEL_COUNT 9
 
 typedef struct pcsdf_handle pcsdf_handle;
 
@@ -139,6 +140,37 @@ int pcsdf_predicted_composite_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                                   double radius_m, double height_m,
                                   int32_t *out_ssq_dev, float *out_sdf_dev,
                                   void *stream);
+
+/* The same sequence with a radius per slice (discussion section: the
+ * cylinders could grow over the prediction horizon to account for the
+ * growing uncertainty of the predicted positions, e.g. r(t) = r0 + sigma*t).
+ * radius_per_slice_m [n_slices] fp64 metres (host, read before the call
+ * returns); every human of slice s has radius radius_per_slice_m[s].  All
+ * other arguments, the voxelisation and the result as for
+ * pcsdf_predicted_composite_sdf. */
+int pcsdf_predicted_composite_sdf_growing(
+    pcsdf_handle *h, const pcsdf_grid *grid, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    const double *radius_per_slice_m, double height_m, int32_t *out_ssq_dev,
+    float *out_sdf_dev, void *stream);
+
+/* Full recompute, the baseline of the mapping section's benchmark (Fig. 6:
+ * composite fields against computing every slice's distance field from
+ * scratch): for every slice, the exact signed squared EDT of the union of
+ * the environment's occupied voxels and the humans' voxels, by the same
+ * three passes as pcsdf_build_static_sdf.
+ *   static_occ_dev [V] uint8 environment map (nonzero = occupied). (device)
+ *   human arguments and voxelisation as pcsdf_predicted_composite_sdf.
+ *   out_ssq_dev [n_slices][V] int32, required (the x pass writes it first).
+ *   out_sdf_dev [n_slices][V] fp32, may be NULL.
+ * Outside both sets the result equals the composite; inside it is the
+ * depth in the union.  Uses the static build's workspace plus V bytes. */
+int pcsdf_recompute_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
+                        const uint8_t *static_occ_dev, int32_t n_slices,
+                        int32_t n_humans, const double *human_xy_host,
+                        double radius_m, double height_m,
+                        int32_t *out_ssq_dev, float *out_sdf_dev,
+                        void *stream);
 
 /* Sphere queries on a sequence of fp32 fields (GPMP2 obstacle factors
  * sample distance and gradient; RHAP-GPMP2 assigns the last field to every
@@ -283,6 +315,12 @@ int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
  * Same outputs and status bits as pcsdf_query_spheres, for the composite
  * fields that pcsdf_predicted_composite_sdf would build from the same
  * static field, human positions and cylinder (arguments as there).
+ * The prediction is y(c, t) = network(x) when static_sdf_dev is NULL.  With
+ * the environment's fp32 field static_sdf_dev [V] (as written by
+ * pcsdf_build_static_sdf), the network predicts the humans' part only and
+ * the prediction is min(s, network(x)), s the environment field sampled at
+ * c exactly as pcsdf_query_spheres samples (fp64 trilinear, rounded to
+ * fp32); where s wins (ties included) the gradient is the environment's.
  * A query falls back to the exact path when
  *   - its predicted sphere distance y(c, t) - r is below fallback_margin_m,
  *   - the network's value or gradient is not finite, or
@@ -299,9 +337,10 @@ int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
  * (state_host) and the human positions must describe the same humans. */
 int pcsdf_query_spheres_surrogate(
     pcsdf_handle *h, pcsdf_mlp *m, const pcsdf_grid *grid,
-    const int32_t *static_ssq_dev, int32_t n_slices, int32_t n_humans,
-    const double *human_xy_host, double radius_m, double height_m,
-    const float *state_host, double dt_s, double fallback_margin_m,
+    const int32_t *static_ssq_dev, const float *static_sdf_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, const float *state_host, double dt_s,
+    double fallback_margin_m,
     int32_t n_queries, const float *centre_dev, const float *radius_dev,
     const int32_t *slice_dev, double hinge_eps_m, float *field_work_dev,
     float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,

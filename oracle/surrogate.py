@@ -16,6 +16,12 @@ at the collision spheres, with a hinge cost).  Definition:
   predicted sphere distance, the conservative one of the two readings);
   otherwise dist = y - r (fp32 subtraction of the fp32 network output),
   grad = g, status = SLICE_CLAMPED when s > n-1, cost = max(0, eps - dist).
+
+With the environment's fp32 field given, the network predicts the humans'
+part only and y is replaced by min(e, y) before the rule is applied, e the
+environment field at the centre as the exact query samples it (fp64
+trilinear rounded to fp32, zero radius); where e <= y (ties included) the
+gradient is the environment's.
 """
 from __future__ import annotations
 
@@ -49,7 +55,7 @@ def in_span(grid, centre) -> np.ndarray:
 
 def query(grid, sdf, params, in_offset, in_scale, out_scale, state, dt,
           centre, radius, slices, margin: float, hinge_eps: float = 0.0,
-          y=None, gx=None):
+          y=None, gx=None, static_sdf=None):
     """Returns (dist, grad, status, cost, used, y).  y/gx may be given to
     decide with a network output computed elsewhere (same shapes as
     oracle/mlp.py returns); by default the fp64 oracle network is used."""
@@ -61,8 +67,17 @@ def query(grid, sdf, params, in_offset, in_scale, out_scale, state, dt,
         p = np.asarray(params, np.float64)
         y, _ = _mlp.forward(p, x, in_offset, in_scale, out_scale)
         gx = _mlp.input_gradient(p, x, in_offset, in_scale, out_scale)
-    y32 = np.asarray(y).astype(np.float32)
-    g32 = np.asarray(gx)[:, :3].astype(np.float32)
+    y32 = np.asarray(y).astype(np.float32).copy()
+    g32 = np.asarray(gx)[:, :3].astype(np.float32).copy()
+    if static_sdf is not None:
+        e, eg, _, _ = _exact_query(
+            grid, np.asarray(static_sdf, np.float32).reshape(
+                (1,) + tuple(sdf.shape[1:])), centre,
+            np.zeros(len(r), np.float32), np.zeros(len(r), np.int32))
+        with np.errstate(invalid="ignore"):
+            take = e <= y32
+        y32[take] = e[take]
+        g32[take] = eg[take]
     with np.errstate(invalid="ignore", over="ignore"):
         ds = y32 - r
         ok = (in_span(grid, centre) & np.isfinite(ds) & (ds >= margin) &

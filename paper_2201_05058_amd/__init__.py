@@ -19,6 +19,7 @@ from ._native import (Grid, Handle, PcsdfError, Q_INF_CORNER, Q_OOR_X,
 __all__ = [
     "Grid", "Handle", "PcsdfError", "build_static_sdf",
     "predicted_composite_sdf", "query_spheres", "load_library",
+    "predicted_composite_sdf_growing", "recompute_sdf",
     "predicted_composite_sdf_batch", "BatchGraph",
     "autotune_batch", "autotune_composite", "Scene", "Tuning",
     "Q_OOR_X", "Q_OOR_Y", "Q_OOR_Z", "Q_SLICE_CLAMPED", "Q_INF_CORNER",
@@ -102,6 +103,68 @@ def predicted_composite_sdf(grid, static_ssq, human_xy, radius, height,
         _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
         _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev))
     h.check(rc)
+    return out_ssq, out_sdf
+
+
+def predicted_composite_sdf_growing(grid, static_ssq, human_xy,
+                                    radius_per_slice, height, out_ssq=None,
+                                    out_sdf=None, want_ssq=True,
+                                    want_sdf=True,
+                                    handle: Handle | None = None):
+    """Composite fields with one cylinder radius per slice
+    (pcsdf_predicted_composite_sdf_growing), e.g. r0 + sigma * t_j."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n, K = xy.shape[0], xy.shape[1]
+    rad = np.ascontiguousarray(np.asarray(radius_per_slice, np.float64))
+    if rad.shape != (n,):
+        raise ValueError("radius_per_slice must have n_slices entries")
+    V = g.nvox
+    dev = static_ssq.device
+    shp = (n,) + g.shape_zyx
+    if out_ssq is None and want_ssq:
+        out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
+    if out_sdf is None and want_sdf:
+        out_sdf = torch.empty(shp, dtype=torch.float32, device=dev)
+    h.check(h.lib.pcsdf_predicted_composite_sdf_growing(
+        h.ptr, C.byref(g), _dev_ptr(static_ssq, torch.int32, "static_ssq", V),
+        n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
+        rad.ctypes.data_as(C.c_void_p), float(height),
+        _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
+        _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev)))
+    return out_ssq, out_sdf
+
+
+def recompute_sdf(grid, static_occ, human_xy, radius, height, out_ssq=None,
+                  out_sdf=None, want_sdf=True,
+                  handle: Handle | None = None):
+    """Full recompute (pcsdf_recompute_sdf): the exact signed EDT of the
+    environment and the humans' voxels, from scratch for every slice.
+    Returns (ssq int32 [n, nz, ny, nx], sdf float32 or None)."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n, K = xy.shape[0], xy.shape[1]
+    V = g.nvox
+    dev = static_occ.device
+    shp = (n,) + g.shape_zyx
+    if out_ssq is None:
+        out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
+    if out_sdf is None and want_sdf:
+        out_sdf = torch.empty(shp, dtype=torch.float32, device=dev)
+    h.check(h.lib.pcsdf_recompute_sdf(
+        h.ptr, C.byref(g), _dev_ptr(static_occ, torch.uint8, "static_occ", V),
+        n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
+        float(radius), float(height),
+        _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
+        _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev)))
     return out_ssq, out_sdf
 
 

@@ -26,6 +26,7 @@ COMMON = [
 PER_FILE = {
     # fp64 interpolation rounded as written (no FMA contraction)
     "query.hip": ["-ffp-contract=off"],
+    "surrogate.hip": ["-ffp-contract=off"],
 }
 
 

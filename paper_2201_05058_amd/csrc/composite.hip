@@ -128,49 +128,43 @@ static bool to_fixed(double p, double o, double h, int64_t *out) {
   return true;
 }
 
-int composite_run(Handle *h, const pcsdf_grid *g,
-                  const int32_t *static_ssq_dev, int32_t n_slices,
-                  int32_t n_humans, const double *human_xy_host,
-                  double radius_m, double height_m, int32_t *out_ssq_dev,
-                  float *out_sdf_dev, const int32_t *need, hipStream_t s) {
-  int rc = check_grid(h, g);
-  if (rc) return rc;
-  if (!static_ssq_dev)
-    return fail(h, PCSDF_ERR_INVALID_ARG, "static_ssq_dev is required");
-  if (!out_ssq_dev && !out_sdf_dev)
-    return fail(h, PCSDF_ERR_INVALID_ARG,
-                "at least one of out_ssq_dev / out_sdf_dev is required");
+int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+               int32_t n_humans, const double *human_xy_host, double radius_m,
+               const double *radius_per_slice, double height_m,
+               const int32_t *need, hipStream_t s, PlaneSet *out) {
   if (n_slices < 1)
     return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
   if (n_humans < 0 || n_humans > kMaxHumans)
     return fail(h, PCSDF_ERR_INVALID_ARG, "n_humans must be in [0, 256]");
   if (n_humans > 0 && !human_xy_host)
     return fail(h, PCSDF_ERR_INVALID_ARG, "human_xy_host is required");
-  if (((uintptr_t)static_ssq_dev & 3) || ((uintptr_t)out_ssq_dev & 3) ||
-      ((uintptr_t)out_sdf_dev & 3))
-    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
   const double hv = g->voxel_m;
-  if (!std::isfinite(radius_m) || radius_m < 0 || !std::isfinite(height_m) ||
-      height_m < 0)
-    return fail(h, PCSDF_ERR_NUMERIC, "radius_m/height_m must be finite, >= 0");
-  int64_t R, Hq;
-  if (!to_fixed(radius_m, 0.0, hv, &R) || !to_fixed(height_m, 0.0, hv, &Hq))
-    return fail(h, PCSDF_ERR_NUMERIC, "radius/height out of range");
-  if (R >= (1LL << 31))
-    return fail(h, PCSDF_ERR_NUMERIC, "radius_m/voxel_m must be < 32768");
-
+  if (!std::isfinite(height_m) || height_m < 0)
+    return fail(h, PCSDF_ERR_NUMERIC, "height_m must be finite, >= 0");
+  int64_t Hq;
+  if (!to_fixed(height_m, 0.0, hv, &Hq))
+    return fail(h, PCSDF_ERR_NUMERIC, "height out of range");
+  // Fixed-point radius of every slice.
+  std::vector<int64_t> Rs((size_t)n_slices);
+  for (int32_t j = 0; j < n_slices; ++j) {
+    const double r = radius_per_slice ? radius_per_slice[j] : radius_m;
+    if (!std::isfinite(r) || r < 0)
+      return fail(h, PCSDF_ERR_NUMERIC, "radius must be finite, >= 0");
+    if (!to_fixed(r, 0.0, hv, &Rs[j]))
+      return fail(h, PCSDF_ERR_NUMERIC, "radius out of range");
+    if (Rs[j] >= (1LL << 31))
+      return fail(h, PCSDF_ERR_NUMERIC, "radius/voxel_m must be < 32768");
+  }
   const int nx = g->nx, ny = g->ny, nz = g->nz;
-  const int64_t V = (int64_t)nx * ny * nz;
   // Highest layer whose centre lies at or under the cylinder top.
-  int Kt = Hq >= 32768 ? (int)std::min<int64_t>((Hq - 32768) / 65536, nz - 1)
-                       : -1;
+  const int Kt =
+      Hq >= 32768 ? (int)std::min<int64_t>((Hq - 32768) / 65536, nz - 1) : -1;
   const bool empty = Kt < 0 || n_humans == 0;
-  const int has_above = Kt + 1 <= nz - 1;
 
   // Fixed-point centres, validated on the host before anything is queued.
   const size_t ncent = (size_t)n_slices * n_humans;
   std::vector<int64_t> &xy = h->host_xy;
-  xy.resize(2 * (ncent > 0 ? ncent : 1));
+  xy.resize(2 * ncent + (size_t)n_slices);
   for (size_t t = 0; t < ncent; ++t) {
     if (!to_fixed(human_xy_host[2 * t], g->origin_m[0], hv, &xy[2 * t]) ||
         !to_fixed(human_xy_host[2 * t + 1], g->origin_m[1], hv,
@@ -179,6 +173,8 @@ int composite_run(Handle *h, const pcsdf_grid *g,
                   "human position non-finite or out of range at index " +
                       std::to_string(t));
   }
+  std::memcpy(xy.data() + 2 * ncent, Rs.data(), Rs.size() * sizeof(int64_t));
+  int rc;
   if ((rc = bind_device(h))) return rc;
   const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
   const size_t xy_bytes = xy.size() * sizeof(int64_t);
@@ -188,25 +184,50 @@ int composite_run(Handle *h, const pcsdf_grid *g,
   if ((rc = ensure_buffer(h, h->chord_buf, chord_bytes, s))) return rc;
   if ((rc = ensure_buffer(h, h->param_buf, xy_bytes, s))) return rc;
   int64_t *xy_dev = reinterpret_cast<int64_t *>(h->param_buf.ptr);
-  if (ncent > 0) {
-    if ((rc = acquire_staging(h, xy_bytes))) return rc;
-    std::memcpy(h->pinned, xy.data(), xy_bytes);
-    if (hipMemcpyAsync(xy_dev, h->pinned, xy_bytes, hipMemcpyHostToDevice,
-                       s) != hipSuccess)
-      return fail(h, PCSDF_ERR_HIP, "upload of human positions failed");
-    if ((rc = release_staging(h, s))) return rc;
-  }
+  if ((rc = acquire_staging(h, xy_bytes))) return rc;
+  std::memcpy(h->pinned, xy.data(), xy_bytes);
+  if (hipMemcpyAsync(xy_dev, h->pinned, xy_bytes, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return fail(h, PCSDF_ERR_HIP, "upload of human positions failed");
+  if ((rc = release_staging(h, s))) return rc;
 
   int32_t *p2 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
   // Planar signed field of the disk union, per slice.
   ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
-  if ((rc = launch_planes(h, xy_dev, n_humans, R, empty,
+  if ((rc = launch_planes(h, xy_dev, n_humans, xy_dev + 2 * ncent, empty,
                           reinterpret_cast<int2 *>(h->chord_buf.ptr), p2, nx,
                           ny, n_slices, need, s)))
     return rc;
-  pp.stop();
+  out->P = p2;
+  out->Kt = empty ? -1 : Kt;
+  out->has_above = out->Kt + 1 <= nz - 1;
+  return PCSDF_OK;
+}
+
+int composite_run(Handle *h, const pcsdf_grid *g,
+                  const int32_t *static_ssq_dev, int32_t n_slices,
+                  int32_t n_humans, const double *human_xy_host,
+                  double radius_m, const double *radius_per_slice,
+                  double height_m, int32_t *out_ssq_dev, float *out_sdf_dev,
+                  const int32_t *need, hipStream_t s) {
+  int rc = check_grid(h, g);
+  if (rc) return rc;
+  if (!static_ssq_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "static_ssq_dev is required");
+  if (!out_ssq_dev && !out_sdf_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "at least one of out_ssq_dev / out_sdf_dev is required");
+  if (((uintptr_t)static_ssq_dev & 3) || ((uintptr_t)out_ssq_dev & 3) ||
+      ((uintptr_t)out_sdf_dev & 3))
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  PlaneSet ps_;
+  if ((rc = planes_run(h, g, n_slices, n_humans, human_xy_host, radius_m,
+                       radius_per_slice, height_m, need, s, &ps_)))
+    return rc;
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int64_t V = (int64_t)nx * ny * nz;
   // Streaming epilogue over all voxels and slices.
-  const float hf = (float)hv;
+  const float hf = (float)g->voxel_m;
   const bool vec4 = (nx % 4 == 0) && !((uintptr_t)static_ssq_dev & 15) &&
                     !((uintptr_t)out_ssq_dev & 15) &&
                     !((uintptr_t)out_sdf_dev & 15);
@@ -219,11 +240,13 @@ int composite_run(Handle *h, const pcsdf_grid *g,
   while ((n_slices + G - 1) / G > 65535) ++G;
   ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
   if (vec4)
-    launch_comp<4>(static_ssq_dev, p2, need, out_ssq_dev, out_sdf_dev, nx,
-                   ny, n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+    launch_comp<4>(static_ssq_dev, ps_.P, need, out_ssq_dev, out_sdf_dev, nx,
+                   ny, n_slices, G, ps_.Kt, ps_.has_above, hf, (uint32_t)V,
+                   s);
   else
-    launch_comp<1>(static_ssq_dev, p2, need, out_ssq_dev, out_sdf_dev, nx,
-                   ny, n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+    launch_comp<1>(static_ssq_dev, ps_.P, need, out_ssq_dev, out_sdf_dev, nx,
+                   ny, n_slices, G, ps_.Kt, ps_.has_above, hf, (uint32_t)V,
+                   s);
   return check_launch(h, "composite");
 }
 
@@ -239,7 +262,22 @@ extern "C" int pcsdf_predicted_composite_sdf(
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return PCSDF_ERR_INVALID_ARG;
   return composite_run(h, g, static_ssq_dev, n_slices, n_humans,
-                       human_xy_host, radius_m, height_m, out_ssq_dev,
-                       out_sdf_dev, nullptr,
+                       human_xy_host, radius_m, nullptr, height_m,
+                       out_ssq_dev, out_sdf_dev, nullptr,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int pcsdf_predicted_composite_sdf_growing(
+    pcsdf_handle *hp, const pcsdf_grid *g, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    const double *radius_per_slice_m, double height_m, int32_t *out_ssq_dev,
+    float *out_sdf_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (!radius_per_slice_m)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "radius_per_slice_m is required");
+  return composite_run(h, g, static_ssq_dev, n_slices, n_humans,
+                       human_xy_host, 0.0, radius_per_slice_m, height_m,
+                       out_ssq_dev, out_sdf_dev, nullptr,
                        reinterpret_cast<hipStream_t>(stream));
 }

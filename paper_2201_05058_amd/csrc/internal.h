@@ -36,6 +36,7 @@ struct Handle {
   DevBuf batch_params;  // batch: scene table, work items, centres
   DevBuf batch_scratch; // batch: chords, planes and row passes per scene
   DevBuf sur_buf;       // surrogate queries: features, outputs, fallback list
+  DevBuf union_buf;     // full recompute: uint8 union map of one slice
   std::vector<char> batch_host;  // batch parameter block before upload
   pcsdf_tuning tuning = {0, 0, 0, 0};  // launch shapes; 0 = default
   // pinned host staging for small per-call parameter blocks
@@ -117,22 +118,37 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
 // Planar signed field of the humans' disk union for every slice, into
 // P [n_slices][ny][nx]: chords per (slice, human, row) into `chords`, then
 // one lane per pixel.  xy holds fixed-point centres [n_slices][K][2]; no
-// human voxel at all when `empty` is set.  With `need` (device int32
-// [n_slices]) only slices with a non-zero entry are computed.
-int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
-                  int2 *chords, int32_t *P, int nx, int ny, int n_slices,
-                  const int32_t *need, hipStream_t s);
+// human voxel at all when `empty` is set.  Rs [n_slices] holds each
+// slice's fixed-point disk radius.  With `need` (device int32 [n_slices])
+// only slices with a non-zero entry are computed.
+int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
+                  bool empty, int2 *chords, int32_t *P, int nx, int ny,
+                  int n_slices, const int32_t *need, hipStream_t s);
 
 // ---- implemented in composite.hip --------------------------------------
 
-// The whole predicted-composite call (validation, fixed-point upload,
-// planes, streaming epilogue).  With `need` (device int32 [n_slices]) only
-// the slices whose entry is non-zero are computed and written; the other
-// slices of the outputs are left untouched.
+// The humans' planes of every slice (validation of the human arguments,
+// fixed-point upload, chords, planar EDT) into the handle's plane buffer.
+// radius_per_slice (host, nullable) overrides radius_m slice by slice.
+struct PlaneSet {
+  int32_t *P;     // [n_slices][ny][nx] signed squared planar field
+  int Kt;         // highest voxel layer of the cylinders, -1 if none
+  int has_above;  // a free layer exists above Kt
+};
+int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+               int32_t n_humans, const double *xy_host, double radius_m,
+               const double *radius_per_slice, double height_m,
+               const int32_t *need, hipStream_t s, PlaneSet *out);
+
+// The whole predicted-composite call (validation, planes, streaming
+// epilogue).  With `need` (device int32 [n_slices]) only the slices whose
+// entry is non-zero are computed and written; the other slices of the
+// outputs are left untouched.
 int composite_run(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
                   int32_t n_slices, int32_t n_humans, const double *xy_host,
-                  double radius_m, double height_m, int32_t *out_ssq,
-                  float *out_sdf, const int32_t *need, hipStream_t s);
+                  double radius_m, const double *radius_per_slice,
+                  double height_m, int32_t *out_ssq, float *out_sdf,
+                  const int32_t *need, hipStream_t s);
 
 // ---- implemented in query.hip ------------------------------------------
 

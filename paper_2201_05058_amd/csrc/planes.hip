@@ -33,9 +33,11 @@ namespace pcsdf {
 // chords[s][k][j] = (a, b), empty when a > b.
 // Slices whose entry in `need` is zero are skipped (all slices when `need`
 // is null) by this kernel and the two below.
+// Rs[s] is slice s's fixed-point disk radius.
 __global__ __launch_bounds__(256) void k_chords(const int64_t *__restrict__ xy,
-                                                int K, int64_t R, int nx,
-                                                int ny, int64_t total,
+                                                int K,
+                                                const int64_t *__restrict__ Rs,
+                                                int nx, int ny, int64_t total,
                                                 const int32_t *__restrict__ need,
                                                 int2 *__restrict__ chords) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_chords(const int64_t *__restrict__ xy,
   const int64_t sk = t / ny;  // s*K + k
   if (need && need[sk / K] == 0) return;
   const int64_t X = xy[2 * sk], Y = xy[2 * sk + 1];
-  const int2 c = disk_chord(X, Y, R, nx, j);
+  const int2 c = disk_chord(X, Y, Rs[sk / K], nx, j);
   chords[t] = c;
 }
 
@@ -71,12 +73,14 @@ __global__ __launch_bounds__(256) void k_rowfree(
 template <bool kLds>
 __global__ __launch_bounds__(256) void k_planes(
     const int2 *__restrict__ chords, const int64_t *__restrict__ xy, int K,
-    int64_t R, int nx, int ny, int tiles, const int32_t *__restrict__ F1,
-    const int32_t *__restrict__ need, int32_t *__restrict__ P) {
+    const int64_t *__restrict__ Rs, int nx, int ny, int tiles,
+    const int32_t *__restrict__ F1, const int32_t *__restrict__ need,
+    int32_t *__restrict__ P) {
   extern __shared__ int4 sh4[];
   const int s = blockIdx.x / tiles;
   const int tile = blockIdx.x - s * tiles;
   if (need && need[s] == 0) return;  // uniform over the block
+  const int64_t R = Rs[s];
   const int2 *gch = chords + (int64_t)s * K * ny;
   int4 *box = sh4;                                   // K boxes
   int2 *lch = reinterpret_cast<int2 *>(sh4 + K);     // K*ny chords
@@ -102,14 +106,15 @@ __global__ __launch_bounds__(256) void k_planes(
   }
 }
 
-int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
+int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
+                  bool empty,
                   int2 *chords, int32_t *P, int nx, int ny, int n_slices,
                   const int32_t *need, hipStream_t s) {
   const int Keff = empty ? 0 : K;
   const int64_t total = (int64_t)n_slices * Keff * ny;
   if (total > 0) {
     hipLaunchKernelGGL(k_chords, dim3((unsigned)((total + 255) / 256)),
-                       dim3(256), 0, s, xy, Keff, R, nx, ny, total, need,
+                       dim3(256), 0, s, xy, Keff, Rs, nx, ny, total, need,
                        chords);
     int rc = check_launch(h, "chords");
     if (rc) return rc;
@@ -133,10 +138,10 @@ int launch_planes(Handle *h, const int64_t *xy, int K, int64_t R, bool empty,
   const dim3 grid((unsigned)((int64_t)tiles * n_slices)), block(256);
   if (use_lds)
     hipLaunchKernelGGL(k_planes<true>, grid, block, box_bytes + ch_bytes, s,
-                       chords, xy, Keff, R, nx, ny, tiles, F1, need, P);
+                       chords, xy, Keff, Rs, nx, ny, tiles, F1, need, P);
   else
     hipLaunchKernelGGL(k_planes<false>, grid, block, box_bytes, s, chords, xy,
-                       Keff, R, nx, ny, tiles, F1, need, P);
+                       Keff, Rs, nx, ny, tiles, F1, need, P);
   return check_launch(h, "planes");
 }
 

@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "query_device.h"
 
 namespace pcsdf {
 
@@ -52,86 +53,19 @@ __device__ __forceinline__ void answer(const QueryArgs &A, int q) {
     st |= PCSDF_Q_SLICE_CLAMPED;
   }
   const int64_t V = (int64_t)nx * ny * nz;
-  const float *field = sdf + (int64_t)s * V;
-  const int n[3] = {nx, ny, nz};
-  const double o[3] = {ox, oy, oz};
-  int idx[3];
-  double fr[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double gc = ((double)centre[3 * q + a] - o[a]) / h - 0.5;
-    if (gc < 0.0) {
-      gc = 0.0;
-      st |= 1u << a;
-    } else if (gc > (double)(n[a] - 1)) {
-      gc = (double)(n[a] - 1);
-      st |= 1u << a;
-    }
-    int i = (int)floor(gc);
-    if (i > n[a] - 2) i = n[a] - 2;
-    idx[a] = i;
-    fr[a] = gc - (double)i;
-  }
-  const int64_t base = ((int64_t)idx[2] * ny + idx[1]) * nx + idx[0];
-  const int64_t sy = nx, sz = (int64_t)nx * ny;
-  double c[2][2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-        c[a][b][e] = (double)field[base + a + b * sy + e * sz];
-  bool infc = false;
-  double infval = 0.0;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-        if (!infc && isinf(c[a][b][e])) {
-          infc = true;
-          infval = c[a][b][e];
-        }
-  if (infc) {
-    dist[q] = (float)infval;
+  const Trilinear T = trilinear(sdf + (int64_t)s * V, nx, ny, nz, h, ox, oy,
+                                oz, centre + 3 * q);
+  st |= T.status;
+  if (T.inf) {
+    dist[q] = (float)T.D;
     grad[3 * q] = 0.f;
     grad[3 * q + 1] = 0.f;
     grad[3 * q + 2] = 0.f;
-    if (cost) cost[q] = infval > 0 ? 0.f : __builtin_inff();
+    if (cost) cost[q] = T.D > 0 ? 0.f : __builtin_inff();
     if (status) status[q] = (uint8_t)(st | PCSDF_Q_INF_CORNER);
     return;
   }
-  double w[3][2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    w[a][0] = 1.0 - fr[a];
-    w[a][1] = fr[a];
-  }
-  double D = 0.0;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 2; ++e) D += w[0][a] * w[1][b] * w[2][e] * c[a][b][e];
-  double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-      gx += w[1][b] * w[2][e] * (c[1][b][e] - c[0][b][e]);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-      gy += w[0][a] * w[2][e] * (c[a][1][e] - c[a][0][e]);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-      gz += w[0][a] * w[1][b] * (c[a][b][1] - c[a][b][0]);
+  const double D = T.D, gx = T.g[0], gy = T.g[1], gz = T.g[2];
   const double dsph = D - (double)radius[q];
   dist[q] = (float)dsph;
   grad[3 * q] = (float)(gx / h);

@@ -2,12 +2,18 @@
 //
 // The learned network answers a sphere query from the sphere's centre, the
 // slice time and the humans' current state (positions and velocities) --
-// without building any distance field.  Where its answer cannot be trusted
-// the exact path answers instead: a query falls back when the predicted
-// sphere distance d(c) - r is below a safety margin (near an obstacle the
-// planner needs exact values), when the network's value or gradient is not
-// finite, or when the centre lies outside the grid's interior (the network
-// was trained there only; the exact path clamps and flags such centres).
+// without building any per-slice field.  It either predicts the composite
+// distance itself, or (when the environment's fp32 field is passed) only
+// the humans' part, the answer then being the smaller of the network's
+// value and the environment field sampled exactly at the centre: the
+// environment field is built once per room, not per slice, and a network
+// that need not memorise the room is far more accurate.  Where the answer
+// cannot be trusted the exact path answers instead: a query falls back when
+// the predicted sphere distance d(c) - r is below a safety margin (near an
+// obstacle the planner needs exact values), when the value or gradient is
+// not finite, or when the centre lies outside the span of voxel centres
+// (the network was trained there only; the exact path clamps and flags such
+// centres).
 //
 // One call runs, all on the caller's stream and without host round trips:
 //   1. features:  x = [c_x, c_y, c_z, t, state...] per query, t = dt * slice
@@ -23,6 +29,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "query_device.h"
 
 namespace pcsdf {
 
@@ -57,6 +64,7 @@ __global__ void k_clear(int32_t *__restrict__ p, int n) {
 
 struct DecideArgs {
   const float *y, *gx, *centre, *radius;
+  const float *static_sdf;  // [V] or null (network answers alone)
   const int32_t *slice;
   int n, n_slices, nx, ny, nz;
   double h, ox, oy, oz, eps;
@@ -90,10 +98,25 @@ __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
         const double g = ((double)A.centre[3 * q + a] - o3[a]) / A.h - 0.5;
         inside = inside && g >= 0.0 && g <= (double)(n3[a] - 1);
       }
-      const float ds = A.y[q] - A.radius[q];
-      const float g0 = A.gx[(int64_t)q * kNetIn];
-      const float g1 = A.gx[(int64_t)q * kNetIn + 1];
-      const float g2 = A.gx[(int64_t)q * kNetIn + 2];
+      float v = A.y[q];
+      float g0 = A.gx[(int64_t)q * kNetIn];
+      float g1 = A.gx[(int64_t)q * kNetIn + 1];
+      float g2 = A.gx[(int64_t)q * kNetIn + 2];
+      if (A.static_sdf && inside) {
+        // the network predicts the humans' part: the answer is the smaller
+        // of it and the environment field (exact, sampled as the exact
+        // query does; the environment wins ties)
+        const Trilinear T = trilinear(A.static_sdf, A.nx, A.ny, A.nz, A.h,
+                                      A.ox, A.oy, A.oz, A.centre + 3 * q);
+        const float sv = (float)T.D;
+        if (sv <= v) {
+          v = sv;
+          g0 = (float)(T.g[0] / A.h);
+          g1 = (float)(T.g[1] / A.h);
+          g2 = (float)(T.g[2] / A.h);
+        }
+      }
+      const float ds = v - A.radius[q];
       const bool ok = inside && isfinite(ds) && ds >= A.margin &&
                       isfinite(g0) && isfinite(g1) && isfinite(g2);
       if (ok) {
@@ -172,9 +195,10 @@ extern "C" int pcsdf_surrogate_features(pcsdf_handle *hp, int32_t n_queries,
 
 extern "C" int pcsdf_query_spheres_surrogate(
     pcsdf_handle *hp, pcsdf_mlp *m, const pcsdf_grid *g,
-    const int32_t *static_ssq_dev, int32_t n_slices, int32_t n_humans,
-    const double *human_xy_host, double radius_m, double height_m,
-    const float *state_host, double dt_s, double fallback_margin_m,
+    const int32_t *static_ssq_dev, const float *static_sdf_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, const float *state_host, double dt_s,
+    double fallback_margin_m,
     int32_t n_queries, const float *centre_dev, const float *radius_dev,
     const int32_t *slice_dev, double hinge_eps_m, float *field_work_dev,
     float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,
@@ -216,7 +240,8 @@ extern "C" int pcsdf_query_spheres_surrogate(
                 "required");
   if (((uintptr_t)centre_dev | (uintptr_t)radius_dev |
        (uintptr_t)slice_dev | (uintptr_t)dist_dev | (uintptr_t)grad_dev |
-       (uintptr_t)cost_dev | (uintptr_t)field_work_dev) & 3)
+       (uintptr_t)cost_dev | (uintptr_t)field_work_dev |
+       (uintptr_t)static_sdf_dev) & 3)
     return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
   if ((rc = bind_device(h))) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -247,6 +272,7 @@ extern "C" int pcsdf_query_spheres_surrogate(
   A.gx = gx;
   A.centre = centre_dev;
   A.radius = radius_dev;
+  A.static_sdf = static_sdf_dev;
   A.slice = slice_dev;
   A.n = n_queries;
   A.n_slices = n_slices;
@@ -275,7 +301,7 @@ extern "C" int pcsdf_query_spheres_surrogate(
   // Exact fields of the slices some fallback query reads, then the exact
   // queries of the fallback list.
   if ((rc = composite_run(h, g, static_ssq_dev, n_slices, n_humans,
-                          human_xy_host, radius_m, height_m, nullptr,
+                          human_xy_host, radius_m, nullptr, height_m, nullptr,
                           field_work_dev, need, s)))
     return rc;
   ProfScope pq(h, PCSDF_KERNEL_QUERY, s);

@@ -42,8 +42,8 @@ def _declare(lib):
     lib.pcsdf_surrogate_features.restype = C.c_int
     d = C.c_double
     lib.pcsdf_query_spheres_surrogate.argtypes = [
-        P, P, P, P, i32, i32, P, d, d, P, d, d, i32, P, P, P, d, P, P, P, P,
-        P, P, P]
+        P, P, P, P, P, i32, i32, P, d, d, P, d, d, i32, P, P, P, d, P, P, P,
+        P, P, P, P]
     lib.pcsdf_query_spheres_surrogate.restype = C.c_int
     lib._mlp_declared = True
 
@@ -181,10 +181,12 @@ def query_spheres_surrogate(net: Mlp, grid, static_ssq, human_xy, radius,
                             height, state, dt, centre, sphere_radius, slice_,
                             fallback_margin=0.10, hinge_eps=0.0,
                             field_work=None, want_status=True,
-                            want_cost=False):
+                            want_cost=False, static_sdf=None):
     """Sphere queries by the network with exact fallback
-    (pcsdf_query_spheres_surrogate).  Returns a dict with dist, grad,
-    status, cost (or None), used_fallback and the field work buffer
+    (pcsdf_query_spheres_surrogate).  With static_sdf (the environment's
+    fp32 field) the network predicts the humans' part and the prediction is
+    the smaller of it and the environment field.  Returns a dict with dist,
+    grad, status, cost (or None), used_fallback and the field work buffer
     (exact fields of the slices some fallback query read)."""
     import torch
     from . import _dev_ptr, _stream
@@ -210,7 +212,8 @@ def query_spheres_surrogate(net: Mlp, grid, static_ssq, human_xy, radius,
     st = _state(state)
     h.check(net.lib.pcsdf_query_spheres_surrogate(
         h.ptr, net.ptr, C.byref(g),
-        _dev_ptr(static_ssq, torch.int32, "static_ssq", V), n_slices, K,
+        _dev_ptr(static_ssq, torch.int32, "static_ssq", V),
+        _dev_ptr(static_sdf, torch.float32, "static_sdf", V), n_slices, K,
         xy.ctypes.data_as(C.c_void_p) if K > 0 else None, float(radius),
         float(height), st.ctypes.data_as(C.c_void_p), float(dt),
         float(fallback_margin), n,

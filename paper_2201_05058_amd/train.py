@@ -11,11 +11,18 @@ error (pcsdf_mlp_train_step).  This module only draws the random inputs
 (human starts and velocities on the host, centres and slices with a seeded
 torch generator on the device) and sequences the calls.
 
-The network sees the room only through its training data, so one network
-serves one static room.  Labels below -0.1 m are raised to -0.1 m: deep
-inside obstacles the surrogate is never trusted (the fallback rule sends
-every predicted distance under the margin to the exact path), and the
-clamp keeps the regression target bounded.
+Two modes.  "env" (the default) trains the network on the humans' part of
+the field only -- the exact per-slice field of the cylinders, built by the
+same composite call over an empty environment -- and answers queries with
+the smaller of the network's value and the environment field sampled
+exactly at the centre (the environment field is built once per room, not
+per slice).  "pure" trains the network on the full composite; it then has
+to memorise the room through its training data, and one network serves
+one static room.  Labels below -0.1 m are raised to -0.1 m: deep inside
+obstacles the surrogate is never trusted (the fallback rule sends every
+predicted distance under the margin to the exact path); labels above 3 m
+(the humans' part is +inf when all humans have left the grid) are capped
+at 3 m.
 
 Usage:  python -m paper_2201_05058_amd.train --out weights.npz
 """
@@ -36,6 +43,10 @@ from . import (build_static_sdf, default_handle, predicted_composite_sdf,
 from .surrogate import NIN, Mlp, init_params, surrogate_features
 
 LABEL_FLOOR = -0.1
+# The humans' part of the field is +inf where every human has left the
+# grid; labels are capped (far beyond any distance in a room) so that the
+# regression target stays finite.
+LABEL_CAP = 3.0
 
 
 def normalisation(grid):
@@ -57,20 +68,31 @@ def normalisation(grid):
     return off.astype(np.float32), scl.astype(np.float32)
 
 
+MODES = ("env", "pure")
+
+
 class Room:
     """A static room (occupancy, static field) and the slice schedule."""
 
-    def __init__(self, scene, dev):
+    def __init__(self, scene, dev, mode="env"):
         import torch
+        if mode not in MODES:
+            raise ValueError(f"mode must be one of {MODES}")
         self.sc = scene
         self.grid = scene.grid
         self.dev = dev
+        self.mode = mode
         occ = torch.from_numpy(scene.occ.astype(np.uint8)).to(dev)
-        self.static_ssq, _ = build_static_sdf(self.grid, occ, want_sdf=False)
+        self.static_ssq, self.static_sdf = build_static_sdf(self.grid, occ)
+        # labels of the env mode: the humans' field over an empty room
+        self.empty_ssq = torch.full(self.grid.shape_zyx, 2 ** 31 - 1,
+                                    dtype=torch.int32, device=dev)
         self.n_slices = scene.n_slices
         self.dt = scene.dt
         self.fields = torch.empty((self.n_slices,) + self.grid.shape_zyx,
                                   dtype=torch.float32, device=dev)
+        self.label_fields = (torch.empty_like(self.fields) if mode == "env"
+                             else self.fields)
 
     def draw_humans(self, rng):
         start, vel = scenegen._cv_humans(rng, self.grid, 3,
@@ -79,9 +101,23 @@ class Room:
         return xy, scenegen.human_state(start, vel)
 
     def build(self, xy):
+        """The exact composite fields of every slice."""
         predicted_composite_sdf(self.grid, self.static_ssq, xy,
                                 scenegen.HUMAN_RADIUS, scenegen.HUMAN_HEIGHT,
                                 out_sdf=self.fields, want_ssq=False)
+
+    def build_labels(self, xy):
+        """The fields the network is trained on (see the module note)."""
+        if self.mode == "pure":
+            self.build(xy)
+            return
+        predicted_composite_sdf(self.grid, self.empty_ssq, xy,
+                                scenegen.HUMAN_RADIUS, scenegen.HUMAN_HEIGHT,
+                                out_sdf=self.label_fields, want_ssq=False)
+
+    @property
+    def env_sdf(self):
+        return self.static_sdf if self.mode == "env" else None
 
     def draw_queries(self, gen, n):
         """Centres uniform over the span of voxel centres, slices uniform."""
@@ -99,15 +135,16 @@ class Room:
     def label(self, c, s):
         import torch
         zero = torch.zeros(s.numel(), dtype=torch.float32, device=self.dev)
-        d, _, _, _ = query_spheres(self.grid, self.fields, c, zero, s,
+        d, _, _, _ = query_spheres(self.grid, self.label_fields, c, zero, s,
                                    want_status=False)
-        return d.clamp_(min=LABEL_FLOOR)
+        return d.clamp_(min=LABEL_FLOOR, max=LABEL_CAP)
 
 
 def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
-          lr=2e-3, lr_min=2e-5, seed=0, log_every=1000, log=print):
+          lr=2e-3, lr_min=2e-5, seed=0, log_every=1000, log=print,
+          mode="env"):
     import torch
-    room = Room(scene, dev)
+    room = Room(scene, dev, mode)
     rng = np.random.Generator(np.random.PCG64(seed))
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
@@ -122,7 +159,7 @@ def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
     step = 0
     while step < steps:
         xy, state = room.draw_humans(rng)
-        room.build(xy)
+        room.build_labels(xy)
         c, s = room.draw_queries(gen, per_draw)
         y = room.label(c, s)
         x = surrogate_features(c, s, room.n_slices, room.dt, state)
@@ -135,13 +172,15 @@ def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
             step += 1
             if step % log_every == 0 or step == steps:
                 l = float(loss.cpu()[0])
+                if not math.isfinite(l):
+                    raise FloatingPointError(f"loss {l} at step {step}")
                 hist.append((step, l))
                 log(json.dumps({"step": step, "loss": l, "lr": a,
                                 "s": round(time.time() - t0, 1)}))
     torch.cuda.synchronize()
     return net, {"steps": steps, "batch": batch, "samples": steps * batch,
                  "seconds": time.time() - t0, "loss": hist,
-                 "in_offset": off, "in_scale": scl}
+                 "in_offset": off, "in_scale": scl, "mode": mode}
 
 
 def save(path, net, info, scene):
@@ -152,18 +191,20 @@ def save(path, net, info, scene):
                                        scene.grid.nz],
                               "voxel_m": scene.grid.h,
                               "n_slices": scene.n_slices, "dt": scene.dt,
+                              "mode": info["mode"],
                               "samples": info["samples"],
                               "steps": info["steps"],
                               "final_loss": info["loss"][-1][1]
                               if info["loss"] else None}))
 
 
-def load(path, handle=None) -> Mlp:
+def load(path, handle=None):
+    """(network, meta dict) from a file written by save()."""
     d = np.load(path, allow_pickle=False)
     net = Mlp(handle or default_handle())
     net.set_params(d["params"], d["in_offset"], d["in_scale"],
                    float(d["out_scale"]))
-    return net
+    return net, json.loads(str(d["meta"]))
 
 
 def _time_ms(fn, reps=5, warmup=2):
@@ -182,7 +223,7 @@ def _time_ms(fn, reps=5, warmup=2):
 
 
 def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
-             time_queries=None):
+             time_queries=None, mode="env"):
     """Surrogate vs exact sphere queries on a fresh draw of the humans.
 
     Errors are measured on the queries the surrogate answers (exact
@@ -195,7 +236,7 @@ def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
     import torch
 
     from .surrogate import query_spheres_surrogate
-    room = Room(scene, dev)
+    room = Room(scene, dev, mode)
     rng = np.random.Generator(np.random.PCG64(seed))
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
@@ -211,7 +252,8 @@ def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
         return query_spheres_surrogate(
             net, room.grid, room.static_ssq, xy, scenegen.HUMAN_RADIUS,
             scenegen.HUMAN_HEIGHT, state, room.dt, cc, rr, ss,
-            fallback_margin=margin, field_work=work, want_status=False)
+            fallback_margin=margin, field_work=work, want_status=False,
+            static_sdf=room.env_sdf)
     out = sur()
     torch.cuda.synchronize()
     used = out["used_fallback"].bool()
@@ -221,7 +263,7 @@ def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
     e = err.double().cpu().numpy()
     ge = gerr.double().cpu().numpy()
     res = {
-        "queries": n_queries, "margin_m": margin,
+        "mode": mode, "queries": n_queries, "margin_m": margin,
         "rule": "fallback when predicted sphere distance y - r < margin",
         "fallback_fraction": float(used.float().mean()),
         "err_max_m": float(e.max()) if e.size else None,
@@ -270,17 +312,19 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval", action="store_true",
                     help="evaluate the trained network on 1M queries")
+    ap.add_argument("--mode", choices=MODES, default="env")
     a = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     scene = scenegen.room256()
     net, info = train(scene, dev, samples=int(a.samples), batch=a.batch,
                       per_draw=a.per_draw, lr=a.lr, seed=a.seed,
-                      log=lambda s: print(s, flush=True))
+                      log=lambda s: print(s, flush=True), mode=a.mode)
     save(a.out, net, info, scene)
     print(json.dumps({"saved": a.out, "samples": info["samples"],
                       "seconds": round(info["seconds"], 1)}), flush=True)
     if a.eval:
-        print(json.dumps({"eval": evaluate(net, scene, dev)}), flush=True)
+        print(json.dumps({"eval": evaluate(net, scene, dev, mode=a.mode)}),
+              flush=True)
     return 0
 
 

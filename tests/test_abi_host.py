@@ -183,7 +183,8 @@ def test_surrogate_validation(h):
     st = (C.c_float * 18)()
     # no network
     assert h.lib.pcsdf_query_spheres_surrogate(
-        h.ptr, None, C.byref(g), FAKE, 2, 0, None, 0.25, 1.8, st, 0.1, 0.1,
+        h.ptr, None, C.byref(g), FAKE, None, 2, 0, None, 0.25, 1.8, st, 0.1,
+        0.1,
         10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, FAKE, None, None, None,
         None) == 1
 

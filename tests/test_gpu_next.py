@@ -1,0 +1,79 @@
+"""The rows after the hot path proper: the full recompute per slice (the
+baseline of the paper's composite benchmark) and cylinders whose radius
+grows with the prediction time (the discussion section's proposal), both
+against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pc(dev):
+    import paper_2201_05058_amd as m
+    return m
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+CASES = [(71, (37, 29, 23), 3, 2), (72, (64, 48, 40), 4, 3),
+         (73, (21, 60, 17), 1, 1), (74, (8, 8, 8), 2, 0)]
+
+
+@pytest.mark.parametrize("seed,dims,n,K", CASES)
+def test_recompute_matches_oracle(pc, dev, seed, dims, n, K):
+    sc = scenegen.small_scene(seed, *dims, h=0.05, n_humans=K, n_slices=n)
+    say(f"recompute seed={seed} dims={dims} n={n} K={K}")
+    occ = to_dev(sc.occ, dev)
+    ssq, sdf = pc.recompute_sdf(sc.grid, occ, sc.human_xy, sc.radius,
+                                sc.height)
+    s_ssq, _ = pc.build_static_sdf(sc.grid, occ)
+    c, _ = pc.predicted_composite_sdf(sc.grid, s_ssq, sc.human_xy, sc.radius,
+                                      sc.height)
+    torch.cuda.synchronize()
+    ssq, sdf, c = ssq.cpu().numpy(), sdf.cpu().numpy(), c.cpu().numpy()
+    for j in range(n):
+        hum = oracle.human_occupancy(sc.grid, sc.human_xy[j], sc.radius,
+                                     sc.height)
+        union = np.maximum(sc.occ, hum)
+        want = oracle.signed_sq(union)
+        np.testing.assert_array_equal(ssq[j], want)
+        np.testing.assert_array_equal(sdf[j], oracle.to_float(want,
+                                                              sc.grid.h))
+        # outside every obstacle the composite is the union's field
+        free = union == 0
+        np.testing.assert_array_equal(c[j][free], ssq[j][free])
+        assert ((c[j] < 0) == (union != 0)).all()
+
+
+@pytest.mark.parametrize("seed,dims,n,K", CASES[:3])
+def test_growing_radius_matches_oracle(pc, dev, seed, dims, n, K):
+    sc = scenegen.small_scene(seed, *dims, h=0.05, n_humans=K, n_slices=n)
+    # r(t) = r0 + sigma t with t = j dt; the first slice also at radius 0
+    rad = 0.25 + 0.3 * np.arange(n) * sc.dt
+    rad[0] = 0.0 if n > 1 else rad[0]
+    say(f"growing radius seed={seed} dims={dims} radii={rad}")
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    s_ssq, _ = pc.build_static_sdf(sc.grid, to_dev(sc.occ, dev))
+    c, cf = pc.predicted_composite_sdf_growing(sc.grid, s_ssq, sc.human_xy,
+                                               rad, sc.height)
+    torch.cuda.synchronize()
+    c, cf = c.cpu().numpy(), cf.cpu().numpy()
+    for j in range(n):
+        wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy[j:j + 1],
+                                            rad[j], sc.height)
+        np.testing.assert_array_equal(c[j], wc[0])
+        np.testing.assert_array_equal(cf[j], wf[0])

@@ -103,3 +103,26 @@ def test_span_boundary():
     assert osur.in_span(g, first)[0] and osur.in_span(g, last)[0]
     assert not osur.in_span(g, first - np.float32(1e-3))[0]
     assert not osur.in_span(g, last + np.float32(1e-3))[0]
+
+
+def test_environment_min_closed_form():
+    # Constant network 0.3 with the environment field: the prediction is
+    # min(e, 0.3) with e the exact environment value at the centre.
+    sc, wf, st = scene()
+    rs, rf = oracle.build_static(sc.grid, sc.occ)
+    c, r, s = queries(sc, seed=4)
+    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
+    d, g, status, cost, used, _ = osur.query(
+        sc.grid, wf, const_net(0.3), zeros, ones, 1.0, st, sc.dt, c, r, s,
+        margin=0.05, static_sdf=rf)
+    e, eg, _, _ = oracle.query(sc.grid, rf[None], c, np.zeros_like(r),
+                               np.zeros_like(s))
+    v = np.minimum(e, np.float32(0.3))
+    inside = osur.in_span(sc.grid, c)
+    accept = inside & (s >= 0) & (v - r >= np.float32(0.05))
+    assert accept.any() and (accept & (e < 0.3)).any()
+    np.testing.assert_array_equal(d[accept], (v - r)[accept])
+    env = accept & (e <= np.float32(0.3))
+    np.testing.assert_array_equal(g[env], eg[env])
+    np.testing.assert_array_equal(g[accept & ~env], 0.0)
+    np.testing.assert_array_equal(used, (~accept & (s >= 0)).astype(np.uint8))
