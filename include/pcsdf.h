@@ -69,7 +69,8 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_MLP_TRAIN 6 /* one surrogate training step */
 #define PCSDF_KERNEL_SURROGATE_DECIDE 7 /* surrogate accept / fallback split */
 #define PCSDF_KERNEL_RECOMPUTE 8 /* full recompute: every slice's union EDT */
-#define PCSDF_KERNEL_COUNT 9
+#define PCSDF_KERNEL_TEMPLATE 9  /* shifted-template composite epilogue */
+#define PCSDF_KERNEL_COUNT 10
 
 typedef struct pcsdf_handle pcsdf_handle;
 
@@ -171,6 +172,29 @@ int pcsdf_recompute_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                         double radius_m, double height_m,
                         int32_t *out_ssq_dev, float *out_sdf_dev,
                         void *stream);
+
+/* The mapping section's own placement of the humans: each human's cylinder
+ * field is computed once (at its first-slice position, sub-voxel phase
+ * included, in a window of (2(nx+m)+1) x (2(ny+m)+1) voxels around it,
+ * m = floor(R/2^16) + 2, unclipped by the grid) and every slice composites
+ * it shifted by the whole number of voxels nearest to the human's
+ * displacement since the first slice, d = floor((X_s - X_0 + 2^15)/2^16):
+ *   C_s = min(static SSQ, min over humans of the shifted templates),
+ * a human contributing nothing where its window does not reach.
+ * Arguments, layouts and outputs as pcsdf_predicted_composite_sdf.  Equal
+ * to that call's result when every displacement is a whole number of
+ * voxels, the humans do not overlap and their cylinders lie inside the
+ * grid; otherwise an approximation of it (sub-voxel shift, the first
+ * slice's voxelisation phase, unclipped windows at the grid's edge, the
+ * min of separate signed fields where humans overlap).
+ * Uses a workspace of 8*n_humans*(window pixels) bytes. */
+int pcsdf_template_composite_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
+                                 const int32_t *static_ssq_dev,
+                                 int32_t n_slices, int32_t n_humans,
+                                 const double *human_xy_host,
+                                 double radius_m, double height_m,
+                                 int32_t *out_ssq_dev, float *out_sdf_dev,
+                                 void *stream);
 
 /* Sphere queries on a sequence of fp32 fields (GPMP2 obstacle factors
  * sample distance and gradient; RHAP-GPMP2 assigns the last field to every

@@ -20,6 +20,7 @@ __all__ = [
     "Grid", "Handle", "PcsdfError", "build_static_sdf",
     "predicted_composite_sdf", "query_spheres", "load_library",
     "predicted_composite_sdf_growing", "recompute_sdf",
+    "template_composite_sdf",
     "predicted_composite_sdf_batch", "BatchGraph",
     "autotune_batch", "autotune_composite", "Scene", "Tuning",
     "Q_OOR_X", "Q_OOR_Y", "Q_OOR_Z", "Q_SLICE_CLAMPED", "Q_INF_CORNER",
@@ -134,6 +135,34 @@ def predicted_composite_sdf_growing(grid, static_ssq, human_xy,
         h.ptr, C.byref(g), _dev_ptr(static_ssq, torch.int32, "static_ssq", V),
         n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
         rad.ctypes.data_as(C.c_void_p), float(height),
+        _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
+        _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev)))
+    return out_ssq, out_sdf
+
+
+def template_composite_sdf(grid, static_ssq, human_xy, radius, height,
+                           out_ssq=None, out_sdf=None, want_ssq=True,
+                           want_sdf=True, handle: Handle | None = None):
+    """Compute-once-and-shift composite (pcsdf_template_composite_sdf):
+    arguments and outputs as predicted_composite_sdf."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n, K = xy.shape[0], xy.shape[1]
+    V = g.nvox
+    dev = static_ssq.device
+    shp = (n,) + g.shape_zyx
+    if out_ssq is None and want_ssq:
+        out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
+    if out_sdf is None and want_sdf:
+        out_sdf = torch.empty(shp, dtype=torch.float32, device=dev)
+    h.check(h.lib.pcsdf_template_composite_sdf(
+        h.ptr, C.byref(g), _dev_ptr(static_ssq, torch.int32, "static_ssq", V),
+        n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
+        float(radius), float(height),
         _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
         _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev)))
     return out_ssq, out_sdf

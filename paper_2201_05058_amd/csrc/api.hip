@@ -220,7 +220,8 @@ extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
   if (h->staging_pending) (void)hipEventSynchronize(h->staging_done);
   DevBuf *bufs[] = {&h->tmp_buf,       &h->plane_buf,      &h->chord_buf,
                     &h->param_buf,     &h->stack_buf,      &h->batch_params,
-                    &h->batch_scratch, &h->sur_buf,     &h->union_buf};
+                    &h->batch_scratch, &h->sur_buf,     &h->union_buf,
+                    &h->tmpl_buf};
   bool any = false;
   for (DevBuf *b : bufs) any = any || b->ptr;
   if (any) (void)hipDeviceSynchronize();

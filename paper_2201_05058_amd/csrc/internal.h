@@ -37,6 +37,7 @@ struct Handle {
   DevBuf batch_scratch; // batch: chords, planes and row passes per scene
   DevBuf sur_buf;       // surrogate queries: features, outputs, fallback list
   DevBuf union_buf;     // full recompute: uint8 union map of one slice
+  DevBuf tmpl_buf;      // shifted-template composite: per-human windows
   std::vector<char> batch_host;  // batch parameter block before upload
   pcsdf_tuning tuning = {0, 0, 0, 0};  // launch shapes; 0 = default
   // pinned host staging for small per-call parameter blocks

@@ -20,9 +20,12 @@ per slice).  "pure" trains the network on the full composite; it then has
 to memorise the room through its training data, and one network serves
 one static room.  Labels below -0.1 m are raised to -0.1 m: deep inside
 obstacles the surrogate is never trusted (the fallback rule sends every
-predicted distance under the margin to the exact path); labels above 3 m
-(the humans' part is +inf when all humans have left the grid) are capped
-at 3 m.
+predicted distance under the margin to the exact path).  In the env mode
+labels are capped 0.2 m above the room's largest environment distance
+(there the environment wins the min anyway; the humans' part is +inf when
+every human has left the grid).  A fraction of the training centres can be
+drawn near the humans (within 1 m of a human's predicted position in x, y),
+where the humans' part decides the answer.
 
 Usage:  python -m paper_2201_05058_amd.train --out weights.npz
 """
@@ -43,10 +46,10 @@ from . import (build_static_sdf, default_handle, predicted_composite_sdf,
 from .surrogate import NIN, Mlp, init_params, surrogate_features
 
 LABEL_FLOOR = -0.1
-# The humans' part of the field is +inf where every human has left the
-# grid; labels are capped (far beyond any distance in a room) so that the
-# regression target stays finite.
-LABEL_CAP = 3.0
+# Labels of the env mode are capped just above the room's largest
+# environment distance: beyond it the environment always wins the min, and
+# the humans' part (+inf where every human has left the grid) stays finite.
+CAP_ABOVE_ENV = 0.2
 
 
 def normalisation(grid):
@@ -93,6 +96,9 @@ class Room:
                                   dtype=torch.float32, device=dev)
         self.label_fields = (torch.empty_like(self.fields) if mode == "env"
                              else self.fields)
+        fin = self.static_sdf[torch.isfinite(self.static_sdf)]
+        self.cap = (float(fin.max()) + CAP_ABOVE_ENV if mode == "env"
+                    and fin.numel() else float("inf"))
 
     def draw_humans(self, rng):
         start, vel = scenegen._cv_humans(rng, self.grid, 3,
@@ -119,8 +125,10 @@ class Room:
     def env_sdf(self):
         return self.static_sdf if self.mode == "env" else None
 
-    def draw_queries(self, gen, n):
-        """Centres uniform over the span of voxel centres, slices uniform."""
+    def draw_queries(self, gen, n, xy=None, near=0.0):
+        """Centres uniform over the span of voxel centres, slices uniform;
+        with near > 0 that fraction of the centres is drawn within 1 m
+        (in x and y) of a random human's position in the sample's slice."""
         import torch
         g = self.grid
         lo = torch.tensor(np.array(g.origin) + g.h / 2, dtype=torch.float32,
@@ -130,6 +138,17 @@ class Room:
         c = torch.rand((n, 3), generator=gen, device=self.dev) * span + lo
         s = torch.randint(0, self.n_slices, (n,), generator=gen,
                           device=self.dev, dtype=torch.int32)
+        m = int(n * near)
+        if m > 0 and xy is not None and xy.shape[1] > 0:
+            pos = torch.tensor(xy, dtype=torch.float32, device=self.dev)
+            k = torch.randint(0, xy.shape[1], (m,), generator=gen,
+                              device=self.dev)
+            p = pos[s[:m].long(), k]
+            off = (torch.rand((m, 2), generator=gen, device=self.dev) * 2
+                   - 1)
+            near_xy = p + off
+            c[:m, :2] = torch.minimum(torch.maximum(near_xy, lo[:2]),
+                                      lo[:2] + span[:2])
         return c.contiguous(), s
 
     def label(self, c, s):
@@ -137,12 +156,12 @@ class Room:
         zero = torch.zeros(s.numel(), dtype=torch.float32, device=self.dev)
         d, _, _, _ = query_spheres(self.grid, self.label_fields, c, zero, s,
                                    want_status=False)
-        return d.clamp_(min=LABEL_FLOOR, max=LABEL_CAP)
+        return d.clamp_(min=LABEL_FLOOR, max=self.cap)
 
 
 def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
-          lr=2e-3, lr_min=2e-5, seed=0, log_every=1000, log=print,
-          mode="env"):
+          lr=1e-3, lr_min=1e-5, seed=0, log_every=1000, log=print,
+          mode="env", near=0.5):
     import torch
     room = Room(scene, dev, mode)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -160,7 +179,7 @@ def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
     while step < steps:
         xy, state = room.draw_humans(rng)
         room.build_labels(xy)
-        c, s = room.draw_queries(gen, per_draw)
+        c, s = room.draw_queries(gen, per_draw, xy, near)
         y = room.label(c, s)
         x = surrogate_features(c, s, room.n_slices, room.dt, state)
         for b in range(0, per_draw, batch):
@@ -180,7 +199,8 @@ def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
     torch.cuda.synchronize()
     return net, {"steps": steps, "batch": batch, "samples": steps * batch,
                  "seconds": time.time() - t0, "loss": hist,
-                 "in_offset": off, "in_scale": scl, "mode": mode}
+                 "in_offset": off, "in_scale": scl, "mode": mode,
+                 "near": near, "lr": lr, "label_cap": room.cap}
 
 
 def save(path, net, info, scene):
@@ -191,7 +211,9 @@ def save(path, net, info, scene):
                                        scene.grid.nz],
                               "voxel_m": scene.grid.h,
                               "n_slices": scene.n_slices, "dt": scene.dt,
-                              "mode": info["mode"],
+                              "mode": info["mode"], "near": info["near"],
+                              "lr": info["lr"],
+                              "label_cap": info["label_cap"],
                               "samples": info["samples"],
                               "steps": info["steps"],
                               "final_loss": info["loss"][-1][1]
@@ -308,7 +330,8 @@ def main(argv=None):
     ap.add_argument("--samples", type=float, default=50e6)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--per-draw", type=int, default=32768)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--near", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval", action="store_true",
                     help="evaluate the trained network on 1M queries")
@@ -318,7 +341,8 @@ def main(argv=None):
     scene = scenegen.room256()
     net, info = train(scene, dev, samples=int(a.samples), batch=a.batch,
                       per_draw=a.per_draw, lr=a.lr, seed=a.seed,
-                      log=lambda s: print(s, flush=True), mode=a.mode)
+                      log=lambda s: print(s, flush=True), mode=a.mode,
+                      near=a.near)
     save(a.out, net, info, scene)
     print(json.dumps({"saved": a.out, "samples": info["samples"],
                       "seconds": round(info["seconds"], 1)}), flush=True)

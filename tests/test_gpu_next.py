@@ -77,3 +77,38 @@ def test_growing_radius_matches_oracle(pc, dev, seed, dims, n, K):
                                             rad[j], sc.height)
         np.testing.assert_array_equal(c[j], wc[0])
         np.testing.assert_array_equal(cf[j], wf[0])
+
+
+@pytest.mark.parametrize("seed,dims,n,K", CASES)
+def test_template_matches_oracle(pc, dev, seed, dims, n, K):
+    from oracle.template import template_composite
+    sc = scenegen.small_scene(seed, *dims, h=0.05, n_humans=K, n_slices=n)
+    say(f"template seed={seed} dims={dims} n={n} K={K}")
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    s_ssq, _ = pc.build_static_sdf(sc.grid, to_dev(sc.occ, dev))
+    c, cf = pc.template_composite_sdf(sc.grid, s_ssq, sc.human_xy,
+                                      sc.radius, sc.height)
+    torch.cuda.synchronize()
+    wc, wf = template_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                sc.height)
+    np.testing.assert_array_equal(c.cpu().numpy(), wc)
+    np.testing.assert_array_equal(cf.cpu().numpy(), wf)
+
+
+def test_template_whole_voxel_motion_equals_exact(pc, dev):
+    sc = scenegen.small_scene(75, 48, 40, 30, h=0.05, n_boxes=5,
+                              n_humans=2, n_slices=6)
+    h = sc.grid.h
+    start = np.array([[10.3 * h, 12.6 * h], [33.1 * h, 24.4 * h]])
+    step = np.array([[2, 1], [-1, -2]]) * h
+    xy = start[None] + np.arange(6)[:, None, None] * step[None]
+    say("template whole-voxel motion")
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    s_ssq, _ = pc.build_static_sdf(sc.grid, to_dev(sc.occ, dev))
+    c, cf = pc.template_composite_sdf(sc.grid, s_ssq, xy, 0.2, 0.9)
+    e, ef = pc.predicted_composite_sdf(sc.grid, s_ssq, xy, 0.2, 0.9)
+    torch.cuda.synchronize()
+    wc, wf = oracle.predicted_composite(sc.grid, rs, xy, 0.2, 0.9)
+    np.testing.assert_array_equal(c.cpu().numpy(), wc)
+    np.testing.assert_array_equal(cf.cpu().numpy(), wf)
+    np.testing.assert_array_equal(e.cpu().numpy(), wc)
