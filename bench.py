@@ -213,6 +213,59 @@ def recompute_section(pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h,
                              "RTX 2060 (grid sizes not recoverable)"}
 
 
+def template_section(pc, torch, sc, ssq_s, out_ssq, out_sdf, h,
+                     reps: int = 5):
+    """The mapping section's own placement (each human's cylinder field
+    computed once and shifted by whole voxels per slice) against the exact
+    per-slice composite on this workload: time of each call and how far the
+    shifted templates are from the exact fields."""
+    g = sc.grid
+
+    def exact():
+        pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
+                                   sc.height, out_ssq=out_ssq,
+                                   out_sdf=out_sdf, handle=h)
+
+    def tmpl():
+        pc.template_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
+                                  sc.height, out_ssq=out_ssq,
+                                  out_sdf=out_sdf, handle=h)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    e_ms, t_ms = timed(exact), timed(tmpl)
+    h.profile_reset()
+    tmpl()
+    torch.cuda.synchronize()
+    from paper_2201_05058_amd import _native
+    k_ms, k_n = h.profile_read(_native.KERNEL_TEMPLATE)
+    k_ms /= max(k_n, 1)
+    exact()
+    ref = out_sdf.clone()
+    tmpl()
+    torch.cuda.synchronize()
+    fin = torch.isfinite(ref) & torch.isfinite(out_sdf)
+    d = (out_sdf - ref).abs()[fin]
+    differ = float((out_sdf != ref).float().mean())
+    V, n = g.nvox, sc.n_slices
+    res = {"exact_call_ms": e_ms, "template_call_ms": t_ms,
+           "template_kernel_ms": k_ms,
+           "template_kernel_gbs_8B_basis":
+               (8.0 + 4.0 / n) * V * n / (k_ms / 1e3) / 1e9,
+           "voxels_differing": differ,
+           "max_abs_diff_m": float(d.max()), "mean_abs_diff_m":
+               float(d.mean())}
+    del ref
+    return res
+
+
 def surrogate_section(pc, torch, dev, weights: str):
     """Sphere queries by the trained surrogate (with exact fallback)
     against the exact path: error in metres on the queries it answers, the
@@ -392,6 +445,8 @@ def main():
     if not args.no_recompute:
         line["fig6_recompute"] = recompute_section(
             pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h)
+        line["template_composite"] = template_section(
+            pc, torch, sc, ssq_s, out_ssq, out_sdf, h)
     del out_ssq, out_sdf
     if not args.no_surrogate:
         line["surrogate"] = surrogate_section(pc, torch, dev, args.weights)

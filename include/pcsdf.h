@@ -70,7 +70,8 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_SURROGATE_DECIDE 7 /* surrogate accept / fallback split */
 #define PCSDF_KERNEL_RECOMPUTE 8 /* full recompute: every slice's union EDT */
 #define PCSDF_KERNEL_TEMPLATE 9  /* shifted-template composite epilogue */
-#define PCSDF_KERNEL_COUNT 10
+#define PCSDF_KERNEL_FACTORS 10  /* obstacle factors of all support states */
+#define PCSDF_KERNEL_COUNT 11
 
 typedef struct pcsdf_handle pcsdf_handle;
 
@@ -111,6 +112,18 @@ const char *pcsdf_status_string(int status);
 int pcsdf_build_static_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                            const uint8_t *occ_dev, int32_t *ssq_dev,
                            float *sdf_dev, void *stream);
+
+/* The environment collapsed to the floor plane for the human-trajectory
+ * predictor (RHAP-GPMP2 section: the 3-D voxel grid is collapsed to 2-D and
+ * its EDT computed on the GPU): pixel (i, j) is occupied iff some voxel
+ * (i, j, k) with z_lo <= k <= z_hi is, and the result is that planar map's
+ * signed squared EDT and F, as pcsdf_build_static_sdf on an nx x ny x 1
+ * grid.  ssq_dev [ny][nx] int32 (required), sdf_dev [ny][nx] fp32
+ * (nullable).  Needs 0 <= z_lo <= z_hi < nz.  Uses 4*nx*ny + nx*ny bytes
+ * of workspace. */
+int pcsdf_build_floor_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
+                          const uint8_t *occ_dev, int32_t z_lo, int32_t z_hi,
+                          int32_t *ssq_dev, float *sdf_dev, void *stream);
 
 /* The sequence of predicted composite fields (mapping section: the
  * composite is a parallel min of the environment field and the fields of
@@ -215,6 +228,31 @@ int pcsdf_query_spheres(pcsdf_handle *h, const pcsdf_grid *grid,
                         const float *radius_dev, const int32_t *slice_dev,
                         double hinge_eps_m, float *dist_dev, float *grad_dev,
                         uint8_t *status_dev, float *cost_dev, void *stream);
+
+/* Obstacle factors of the planner (RHAP-GPMP2 section: the obstacle factor
+ * of time index i reads composite field i, the last field past the
+ * horizon; GPMP2's hinge loss on the distance field, as adopted in the
+ * human-trajectory section).  For support state i and sphere j:
+ *   e_ij = max(0, eps_m - (d_s(c_ij) - r_j)),  s = min(state_slice[i], n-1)
+ *   J_ij = -grad d_s(c_ij) where e_ij > 0, else 0
+ *   cost_i = sum_j 0.5 * (e_ij / sigma)^2   (fp64)
+ * with d and grad sampled exactly as pcsdf_query_spheres does.
+ *   sdf_dev          [n_slices][V] fp32 composite fields.     (device, read)
+ *   centre_dev       [n_states][n_spheres][3] fp32 metres.    (device, read)
+ *   radius_dev       [n_spheres] fp32 metres.                 (device, read)
+ *   state_slice_dev  [n_states] int32; < 0 gives NaN.         (device, read)
+ *   err_dev          [n_states][n_spheres] fp32.              (device, written)
+ *   jac_dev          [n_states][n_spheres][3] fp32.           (device, written)
+ *   cost_dev         [n_states] fp64 (8-byte aligned).        (device, written)
+ * An infinite corner gives e = 0 (+inf) or +inf (-inf) and J = 0.
+ * Errors: sigma must be > 0 and eps finite (PCSDF_ERR_NUMERIC). */
+int pcsdf_obstacle_factors(pcsdf_handle *h, const pcsdf_grid *grid,
+                           const float *sdf_dev, int32_t n_slices,
+                           int32_t n_states, int32_t n_spheres,
+                           const float *centre_dev, const float *radius_dev,
+                           const int32_t *state_slice_dev, double eps_m,
+                           double sigma, float *err_dev, float *jac_dev,
+                           double *cost_dev, void *stream);
 
 /* ---- Batches of scenes ------------------------------------------------
  * One scene: the arguments of pcsdf_predicted_composite_sdf.  Scenes of a

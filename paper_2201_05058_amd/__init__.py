@@ -20,7 +20,7 @@ __all__ = [
     "Grid", "Handle", "PcsdfError", "build_static_sdf",
     "predicted_composite_sdf", "query_spheres", "load_library",
     "predicted_composite_sdf_growing", "recompute_sdf",
-    "template_composite_sdf",
+    "template_composite_sdf", "obstacle_factors", "build_floor_sdf",
     "predicted_composite_sdf_batch", "BatchGraph",
     "autotune_batch", "autotune_composite", "Scene", "Tuning",
     "Q_OOR_X", "Q_OOR_Y", "Q_OOR_Z", "Q_SLICE_CLAMPED", "Q_INF_CORNER",
@@ -72,6 +72,26 @@ def build_static_sdf(grid, occ, ssq=None, sdf=None, want_sdf=True,
         _dev_ptr(ssq, torch.int32, "ssq", V),
         _dev_ptr(sdf, torch.float32, "sdf", V), _stream(dev))
     h.check(rc)
+    return ssq, sdf
+
+
+def build_floor_sdf(grid, occ, z_lo=0, z_hi=None, want_sdf=True,
+                    handle: Handle | None = None):
+    """Signed EDT of the map collapsed to the floor plane over layers
+    [z_lo, z_hi] (pcsdf_build_floor_sdf).  Returns (ssq int32 [ny, nx],
+    sdf float32 [ny, nx] or None)."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    z_hi = g.nz - 1 if z_hi is None else z_hi
+    dev = occ.device
+    ssq = torch.empty((g.ny, g.nx), dtype=torch.int32, device=dev)
+    sdf = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev) \
+        if want_sdf else None
+    h.check(h.lib.pcsdf_build_floor_sdf(
+        h.ptr, C.byref(g), _dev_ptr(occ, torch.uint8, "occ", g.nvox),
+        int(z_lo), int(z_hi), _dev_ptr(ssq, torch.int32, "ssq"),
+        _dev_ptr(sdf, torch.float32, "sdf"), _stream(dev)))
     return ssq, sdf
 
 
@@ -138,6 +158,35 @@ def predicted_composite_sdf_growing(grid, static_ssq, human_xy,
         _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
         _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev)))
     return out_ssq, out_sdf
+
+
+def obstacle_factors(grid, sdf, centre, radius, state_slice, eps, sigma,
+                     handle: Handle | None = None):
+    """GPMP2 obstacle factors of every support state
+    (pcsdf_obstacle_factors): centre [S, J, 3] float32, radius [J],
+    state_slice [S] int32, all on the GPU.  Returns (err [S, J],
+    jac [S, J, 3], cost [S] float64)."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    V = g.nvox
+    n_slices = sdf.numel() // V
+    if n_slices * V != sdf.numel():
+        raise ValueError("sdf size is not a whole number of fields")
+    S, J = centre.shape[0], centre.shape[1]
+    dev = sdf.device
+    err = torch.empty((S, J), dtype=torch.float32, device=dev)
+    jac = torch.empty((S, J, 3), dtype=torch.float32, device=dev)
+    cost = torch.empty(S, dtype=torch.float64, device=dev)
+    h.check(h.lib.pcsdf_obstacle_factors(
+        h.ptr, C.byref(g), _dev_ptr(sdf, torch.float32, "sdf"), n_slices, S,
+        J, _dev_ptr(centre, torch.float32, "centre", S * J * 3),
+        _dev_ptr(radius, torch.float32, "radius", J),
+        _dev_ptr(state_slice, torch.int32, "state_slice", S), float(eps),
+        float(sigma), _dev_ptr(err, torch.float32, "err"),
+        _dev_ptr(jac, torch.float32, "jac"),
+        _dev_ptr(cost, torch.float64, "cost"), _stream(dev)))
+    return err, jac, cost
 
 
 def template_composite_sdf(grid, static_ssq, human_xy, radius, height,

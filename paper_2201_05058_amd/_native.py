@@ -24,7 +24,7 @@ Q_OOR_X, Q_OOR_Y, Q_OOR_Z = 1, 2, 4
 Q_SLICE_CLAMPED, Q_INF_CORNER, Q_SLICE_NEG = 8, 16, 32
 KERNEL_COMPOSITE, KERNEL_PLANES, KERNEL_QUERY, KERNEL_STATIC = 0, 1, 2, 3
 KERNEL_BATCH, KERNEL_MLP, KERNEL_MLP_TRAIN, KERNEL_SURROGATE_DECIDE = 4, 5, 6, 7
-KERNEL_RECOMPUTE, KERNEL_TEMPLATE = 8, 9
+KERNEL_RECOMPUTE, KERNEL_TEMPLATE, KERNEL_FACTORS = 8, 9, 10
 
 
 class PcsdfError(RuntimeError):
@@ -132,6 +132,11 @@ def load_library():
         lib.pcsdf_template_composite_sdf.argtypes = [
             P, GP, P, i32, i32, P, f64, f64, P, P, P]
         lib.pcsdf_template_composite_sdf.restype = C.c_int
+        lib.pcsdf_obstacle_factors.argtypes = [
+            P, GP, P, i32, i32, i32, P, P, P, f64, f64, P, P, P, P]
+        lib.pcsdf_obstacle_factors.restype = C.c_int
+        lib.pcsdf_build_floor_sdf.argtypes = [P, GP, P, i32, i32, P, P, P]
+        lib.pcsdf_build_floor_sdf.restype = C.c_int
         lib.pcsdf_query_spheres.argtypes = [
             P, GP, P, i32, i32, P, P, P, f64, P, P, P, P, P]
         lib.pcsdf_query_spheres.restype = C.c_int

@@ -27,6 +27,7 @@ PER_FILE = {
     # fp64 interpolation rounded as written (no FMA contraction)
     "query.hip": ["-ffp-contract=off"],
     "surrogate.hip": ["-ffp-contract=off"],
+    "factors.hip": ["-ffp-contract=off"],
 }
 
 

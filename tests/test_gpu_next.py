@@ -112,3 +112,56 @@ def test_template_whole_voxel_motion_equals_exact(pc, dev):
     np.testing.assert_array_equal(c.cpu().numpy(), wc)
     np.testing.assert_array_equal(cf.cpu().numpy(), wf)
     np.testing.assert_array_equal(e.cpu().numpy(), wc)
+
+
+@pytest.mark.parametrize("seed,S,J", [(91, 20, 30), (92, 7, 1), (93, 45, 130)])
+def test_obstacle_factors_match_oracle(pc, dev, seed, S, J):
+    from oracle.factors import obstacle_factors
+    sc = scenegen.small_scene(seed, 40, 36, 30, h=0.05, n_humans=2,
+                              n_slices=5)
+    rng = np.random.default_rng(seed)
+    L = np.array(sc.grid.extent)
+    c = (rng.uniform(-0.05, 1.05, size=(S, J, 3)) * L).astype(np.float32)
+    r = rng.uniform(0.02, 0.15, size=J).astype(np.float32)
+    sl = rng.integers(-1, sc.n_slices + 3, size=S).astype(np.int32)
+    eps, sigma = 0.3, 0.08
+    say(f"obstacle factors seed={seed} S={S} J={J}")
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    _, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                       sc.height)
+    werr, wjac, wcost = obstacle_factors(sc.grid, wf, c, r, sl, eps, sigma)
+    s_ssq, _ = pc.build_static_sdf(sc.grid, to_dev(sc.occ, dev))
+    _, cf = pc.predicted_composite_sdf(sc.grid, s_ssq, sc.human_xy,
+                                       sc.radius, sc.height, want_ssq=False)
+    err, jac, cost = pc.obstacle_factors(sc.grid, cf, to_dev(c, dev),
+                                         to_dev(r, dev), to_dev(sl, dev), eps,
+                                         sigma)
+    torch.cuda.synchronize()
+    err, jac, cost = err.cpu().numpy(), jac.cpu().numpy(), cost.cpu().numpy()
+    nan = np.isnan(werr)
+    assert (np.isnan(err) == nan).all()
+    fin = ~nan & np.isfinite(werr)
+    e = np.abs(err[fin].astype(np.float64) - werr[fin])
+    assert (e <= 1e-6 * np.maximum(np.abs(werr[fin]), sc.grid.h)).all()
+    jn = np.isnan(wjac)
+    assert (np.isnan(jac) == jn).all()
+    e = np.abs(jac[~jn].astype(np.float64) - wjac[~jn])
+    assert (e <= 1e-6 * np.maximum(np.abs(wjac[~jn]), 1.0)).all()
+    cn = ~np.isfinite(wcost)
+    assert (np.isnan(cost) == np.isnan(wcost)).all()
+    np.testing.assert_allclose(cost[~cn], wcost[~cn], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed,dims,zr", [(95, (37, 29, 23), (0, 22)),
+                                          (96, (64, 48, 40), (3, 17)),
+                                          (97, (5, 70, 9), (8, 8))])
+def test_floor_sdf_matches_oracle(pc, dev, seed, dims, zr):
+    sc = scenegen.small_scene(seed, *dims, h=0.05, n_boxes=8)
+    say(f"floor sdf seed={seed} dims={dims} layers={zr}")
+    ssq, sdf = pc.build_floor_sdf(sc.grid, to_dev(sc.occ, dev), *zr)
+    torch.cuda.synchronize()
+    flat = sc.occ[zr[0]:zr[1] + 1].any(0).astype(np.uint8)
+    want = oracle.signed_sq(flat[None])[0]
+    np.testing.assert_array_equal(ssq.cpu().numpy(), want)
+    np.testing.assert_array_equal(sdf.cpu().numpy(),
+                                  oracle.to_float(want, sc.grid.h))
