@@ -229,6 +229,25 @@ int pcsdf_query_spheres(pcsdf_handle *h, const pcsdf_grid *grid,
                         double hinge_eps_m, float *dist_dev, float *grad_dev,
                         uint8_t *status_dev, float *cost_dev, void *stream);
 
+/* The same sphere queries on the composite fields that
+ * pcsdf_predicted_composite_sdf would build (its arguments), answered
+ * without building them: the humans' voxels of a slice are D x {0..Kt}
+ * (a disk union times the cylinders' layers), so the composite at voxel
+ * (i, j, k) is min(static SSQ, the humans' value from the planar signed
+ * field of D at pixel (i, j) and layer k), and the planar value of one
+ * pixel is a search over the slice's chords.  Each query evaluates the
+ * planar field at the four pixels of its cell and reads eight static
+ * values.  Outputs, status bits and layouts as pcsdf_query_spheres, and
+ * bit-identical to building the fields and sampling them.  Uses the
+ * chords' workspace only. */
+int pcsdf_query_spheres_direct(
+    pcsdf_handle *h, const pcsdf_grid *grid, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, int32_t n_queries,
+    const float *centre_dev, const float *radius_dev,
+    const int32_t *slice_dev, double hinge_eps_m, float *dist_dev,
+    float *grad_dev, uint8_t *status_dev, float *cost_dev, void *stream);
+
 /* Obstacle factors of the planner (RHAP-GPMP2 section: the obstacle factor
  * of time index i reads composite field i, the last field past the
  * horizon; GPMP2's hinge loss on the distance field, as adopted in the
@@ -373,6 +392,18 @@ int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
                              double dt_s, const float *state_host,
                              float *x_dev, void *stream);
 
+/* The same for queries drawn over a pool of human configurations (for
+ * training on many configurations per batch): slice_dev[q] = c*n_slices + s
+ * selects configuration c in [0, n_configs) with state states_dev[c][0..17]
+ * (device, fp32) and slice s (the global index is clamped to the pool);
+ * t = dt_s * s. */
+int pcsdf_surrogate_features_pool(pcsdf_handle *h, int32_t n_queries,
+                                  const float *centre_dev,
+                                  const int32_t *slice_dev, int32_t n_slices,
+                                  int32_t n_configs, double dt_s,
+                                  const float *states_dev, float *x_dev,
+                                  void *stream);
+
 /* Sphere queries answered by the network, with the exact path as fallback.
  * Same outputs and status bits as pcsdf_query_spheres, for the composite
  * fields that pcsdf_predicted_composite_sdf would build from the same
@@ -390,11 +421,11 @@ int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
  *     clamps and flags it);
  * other queries get dist = y - r, grad = dy/dc, status = SLICE_CLAMPED or 0,
  * cost = max(0, hinge_eps_m - dist).  Queries with slice < 0 get NaN and
- * SLICE_NEG.  used_fallback_dev [n] (nullable) is 1 for exact answers.
- * Only the slices that some fallback query reads are built, into
- * field_work_dev [n_slices][V] (fp32, caller-owned; the other slices are
- * left untouched).  No host synchronisation: the fallback list and the
- * slice marks live on the device.  The network must belong to handle `h`.
+ * SLICE_NEG.  used_fallback_dev [n] (nullable) is 1 for exact answers,
+ * which are computed as pcsdf_query_spheres_direct computes them: no field
+ * is built, only the chords of the slices that some fallback query reads.
+ * No host synchronisation: the fallback list and the slice marks live on
+ * the device.  The network must belong to handle `h`.
  * The net takes the features of pcsdf_surrogate_features; its state
  * (state_host) and the human positions must describe the same humans. */
 int pcsdf_query_spheres_surrogate(
@@ -404,8 +435,8 @@ int pcsdf_query_spheres_surrogate(
     double radius_m, double height_m, const float *state_host, double dt_s,
     double fallback_margin_m,
     int32_t n_queries, const float *centre_dev, const float *radius_dev,
-    const int32_t *slice_dev, double hinge_eps_m, float *field_work_dev,
-    float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,
+    const int32_t *slice_dev, double hinge_eps_m, float *dist_dev,
+    float *grad_dev, uint8_t *status_dev, float *cost_dev,
     uint8_t *used_fallback_dev, void *stream);
 
 /* Kernel timing for measurement.  When on, each timed region (the

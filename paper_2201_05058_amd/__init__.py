@@ -21,6 +21,7 @@ __all__ = [
     "predicted_composite_sdf", "query_spheres", "load_library",
     "predicted_composite_sdf_growing", "recompute_sdf",
     "template_composite_sdf", "obstacle_factors", "build_floor_sdf",
+    "query_spheres_direct",
     "predicted_composite_sdf_batch", "BatchGraph",
     "autotune_batch", "autotune_composite", "Scene", "Tuning",
     "Q_OOR_X", "Q_OOR_Y", "Q_OOR_Z", "Q_SLICE_CLAMPED", "Q_INF_CORNER",
@@ -158,6 +159,43 @@ def predicted_composite_sdf_growing(grid, static_ssq, human_xy,
         _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
         _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev)))
     return out_ssq, out_sdf
+
+
+def query_spheres_direct(grid, static_ssq, human_xy, radius, height, centre,
+                         sphere_radius, slices, hinge_eps=0.0,
+                         want_status=True, want_cost=False,
+                         handle: Handle | None = None):
+    """Sphere queries on the composite fields of (static_ssq, human_xy,
+    radius, height) without building them (pcsdf_query_spheres_direct).
+    Returns (dist, grad, status or None, cost or None) as query_spheres."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n, K = xy.shape[0], xy.shape[1]
+    Q = centre.shape[0] if centre.ndim > 1 else centre.numel() // 3
+    dev = static_ssq.device
+    dist = torch.empty(Q, dtype=torch.float32, device=dev)
+    grad = torch.empty((Q, 3), dtype=torch.float32, device=dev)
+    status = (torch.empty(Q, dtype=torch.uint8, device=dev)
+              if want_status else None)
+    cost = torch.empty(Q, dtype=torch.float32, device=dev) if want_cost \
+        else None
+    h.check(h.lib.pcsdf_query_spheres_direct(
+        h.ptr, C.byref(g), _dev_ptr(static_ssq, torch.int32, "static_ssq",
+                                    g.nvox),
+        n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
+        float(radius), float(height), Q,
+        _dev_ptr(centre, torch.float32, "centre", 3 * Q),
+        _dev_ptr(sphere_radius, torch.float32, "radius", Q),
+        _dev_ptr(slices, torch.int32, "slices", Q), float(hinge_eps),
+        _dev_ptr(dist, torch.float32, "dist"),
+        _dev_ptr(grad, torch.float32, "grad"),
+        _dev_ptr(status, torch.uint8, "status"),
+        _dev_ptr(cost, torch.float32, "cost"), _stream(dev)))
+    return dist, grad, status, cost
 
 
 def obstacle_factors(grid, sdf, centre, radius, state_slice, eps, sigma,

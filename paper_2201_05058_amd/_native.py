@@ -137,6 +137,9 @@ def load_library():
         lib.pcsdf_obstacle_factors.restype = C.c_int
         lib.pcsdf_build_floor_sdf.argtypes = [P, GP, P, i32, i32, P, P, P]
         lib.pcsdf_build_floor_sdf.restype = C.c_int
+        lib.pcsdf_query_spheres_direct.argtypes = [
+            P, GP, P, i32, i32, P, f64, f64, i32, P, P, P, f64, P, P, P, P, P]
+        lib.pcsdf_query_spheres_direct.restype = C.c_int
         lib.pcsdf_query_spheres.argtypes = [
             P, GP, P, i32, i32, P, P, P, f64, P, P, P, P, P]
         lib.pcsdf_query_spheres.restype = C.c_int

@@ -128,10 +128,10 @@ static bool to_fixed(double p, double o, double h, int64_t *out) {
   return true;
 }
 
-int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
-               int32_t n_humans, const double *human_xy_host, double radius_m,
-               const double *radius_per_slice, double height_m,
-               const int32_t *need, hipStream_t s, PlaneSet *out) {
+int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+                  int32_t n_humans, const double *human_xy_host,
+                  double radius_m, const double *radius_per_slice,
+                  double height_m, hipStream_t s, HumanSet *out) {
   if (n_slices < 1)
     return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
   if (n_humans < 0 || n_humans > kMaxHumans)
@@ -155,7 +155,7 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
     if (Rs[j] >= (1LL << 31))
       return fail(h, PCSDF_ERR_NUMERIC, "radius/voxel_m must be < 32768");
   }
-  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int ny = g->ny, nz = g->nz;
   // Highest layer whose centre lies at or under the cylinder top.
   const int Kt =
       Hq >= 32768 ? (int)std::min<int64_t>((Hq - 32768) / 65536, nz - 1) : -1;
@@ -176,11 +176,9 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   std::memcpy(xy.data() + 2 * ncent, Rs.data(), Rs.size() * sizeof(int64_t));
   int rc;
   if ((rc = bind_device(h))) return rc;
-  const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
   const size_t xy_bytes = xy.size() * sizeof(int64_t);
   const size_t chord_bytes =
       (size_t)n_slices * (n_humans > 0 ? n_humans : 1) * ny * sizeof(int2);
-  if ((rc = ensure_buffer(h, h->plane_buf, 2 * plane_bytes, s))) return rc;
   if ((rc = ensure_buffer(h, h->chord_buf, chord_bytes, s))) return rc;
   if ((rc = ensure_buffer(h, h->param_buf, xy_bytes, s))) return rc;
   int64_t *xy_dev = reinterpret_cast<int64_t *>(h->param_buf.ptr);
@@ -190,17 +188,35 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
       hipSuccess)
     return fail(h, PCSDF_ERR_HIP, "upload of human positions failed");
   if ((rc = release_staging(h, s))) return rc;
+  out->xy = xy_dev;
+  out->Rs = xy_dev + 2 * ncent;
+  out->chords = reinterpret_cast<int2 *>(h->chord_buf.ptr);
+  out->K = empty ? 0 : n_humans;
+  out->Kt = empty ? -1 : Kt;
+  out->has_above = out->Kt + 1 <= nz - 1;
+  return PCSDF_OK;
+}
 
+int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+               int32_t n_humans, const double *human_xy_host, double radius_m,
+               const double *radius_per_slice, double height_m,
+               const int32_t *need, hipStream_t s, PlaneSet *out) {
+  HumanSet hs;
+  int rc = humans_upload(h, g, n_slices, n_humans, human_xy_host, radius_m,
+                         radius_per_slice, height_m, s, &hs);
+  if (rc) return rc;
+  const int nx = g->nx, ny = g->ny;
+  const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
+  if ((rc = ensure_buffer(h, h->plane_buf, 2 * plane_bytes, s))) return rc;
   int32_t *p2 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
   // Planar signed field of the disk union, per slice.
   ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
-  if ((rc = launch_planes(h, xy_dev, n_humans, xy_dev + 2 * ncent, empty,
-                          reinterpret_cast<int2 *>(h->chord_buf.ptr), p2, nx,
-                          ny, n_slices, need, s)))
+  if ((rc = launch_planes(h, hs.xy, n_humans, hs.Rs, hs.K == 0, hs.chords, p2,
+                          nx, ny, n_slices, need, s)))
     return rc;
   out->P = p2;
-  out->Kt = empty ? -1 : Kt;
-  out->has_above = out->Kt + 1 <= nz - 1;
+  out->Kt = hs.Kt;
+  out->has_above = hs.has_above;
   return PCSDF_OK;
 }
 

@@ -126,7 +126,29 @@ int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
                   bool empty, int2 *chords, int32_t *P, int nx, int ny,
                   int n_slices, const int32_t *need, hipStream_t s);
 
+// Chords only (the first step of launch_planes): chords[s][k][j], K humans
+// per slice (0: nothing to do).
+int launch_chords(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
+                  int2 *chords, int nx, int ny, int n_slices,
+                  const int32_t *need, hipStream_t s);
+
 // ---- implemented in composite.hip --------------------------------------
+
+// The humans of every slice validated, converted to the fixed-point
+// lattice and uploaded (one pinned staging copy): xy [n_slices][K][2] and
+// Rs [n_slices] on the device, chords buffer sized for them.
+struct HumanSet {
+  const int64_t *xy;  // device
+  const int64_t *Rs;  // device
+  int2 *chords;       // device, [n_slices][K][ny] (K >= 1 rows reserved)
+  int K;              // humans per slice after dropping empty cylinders
+  int Kt;             // highest voxel layer of the cylinders, -1 if none
+  int has_above;      // a free layer exists above Kt
+};
+int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+                  int32_t n_humans, const double *xy_host, double radius_m,
+                  const double *radius_per_slice, double height_m,
+                  hipStream_t s, HumanSet *out);
 
 // The humans' planes of every slice (validation of the human arguments,
 // fixed-point upload, chords, planar EDT) into the handle's plane buffer.
@@ -150,6 +172,28 @@ int composite_run(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
                   double radius_m, const double *radius_per_slice,
                   double height_m, int32_t *out_ssq, float *out_sdf,
                   const int32_t *need, hipStream_t s);
+
+// ---- implemented in direct.hip -----------------------------------------
+
+// Exact queries straight from the chords and the static field (no field
+// is built): the humans uploaded and the chords of the slices with a
+// non-zero `need` entry (all when null) built.
+struct DirectSet {
+  HumanSet hs;
+  const int32_t *S;  // static SSQ
+};
+int direct_setup(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
+                 int32_t n_slices, int32_t n_humans, const double *xy_host,
+                 double radius_m, double height_m, const int32_t *need,
+                 hipStream_t s, DirectSet *out);
+// Exact queries for list[0 .. *count) (grid sized for max_count).
+int launch_direct_list(Handle *h, const pcsdf_grid *g, const DirectSet &d,
+                       int n_slices, const int32_t *list,
+                       const int32_t *count, int max_count,
+                       const float *centre, const float *radius,
+                       const int32_t *slice, double eps, float *dist,
+                       float *grad, uint8_t *status, float *cost,
+                       hipStream_t s);
 
 // ---- implemented in query.hip ------------------------------------------
 

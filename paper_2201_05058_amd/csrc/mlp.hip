@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "mlp_fused.h"
 #include "mlp_kernels.h"
 
 namespace pcsdf {
@@ -285,6 +286,9 @@ extern "C" int pcsdf_mlp_get_params(pcsdf_mlp *m, float *params_host) {
   return PCSDF_OK;
 }
 
+// Inference (value and input gradient) runs fused, one workgroup per tile
+// of 128 rows (mlp_fused.h); training keeps the layer-by-layer kernels,
+// whose stored activations the weight gradients need.
 extern "C" int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
                                  float *y_dev, float *grad_x_dev,
                                  void *stream) {
@@ -292,16 +296,19 @@ extern "C" int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
   int rc = check_rows(m, n, x_dev);
   if (rc || n == 0) return rc;
   if (!y_dev) return fail(m->h, PCSDF_ERR_INVALID_ARG, "y_dev is NULL");
+  if (((uintptr_t)x_dev | (uintptr_t)y_dev | (uintptr_t)grad_x_dev) & 3)
+    return fail(m->h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int npad = pad_rows(n);
-  if ((rc = ws(m, npad, s))) return rc;
+  NetWeights w;
+  for (int l = 0; l <= kLayers; ++l) w.W[l] = wb(m, l);
+  for (int l = 0; l < kLayers; ++l) w.Wt[l] = wtb(m, l);
+  const int tiles = (n + kTileRows - 1) / kTileRows;
+  const int grid = tiles < 1024 ? tiles : 1024;
   ProfScope ps(m->h, PCSDF_KERNEL_MLP, s);
-  if ((rc = forward(m, n, npad, x_dev, y_dev, s))) return rc;
-  if (!grad_x_dev) return PCSDF_OK;
-  hipLaunchKernelGGL(k_fill, dim3(blocks(npad, 256)), dim3(256), 0, s,
-                     reinterpret_cast<float *>(m->seed.ptr), 1.f,
-                     (int64_t)npad);
-  return backward(m, n, npad, nullptr, grad_x_dev, s);
+  hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, s, x_dev, n,
+                     reinterpret_cast<const float *>(m->norm.ptr), w, pf(m),
+                     m->out_scale, y_dev, grad_x_dev, tiles);
+  return check_launch(m->h, "mlp inference");
 }
 
 extern "C" int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n,

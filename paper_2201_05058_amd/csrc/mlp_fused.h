@@ -1,0 +1,188 @@
+// Fused inference of the surrogate MLP (included by mlp.hip): forward pass
+// and input gradient of a tile of 128 rows in one workgroup, with no
+// intermediate in HBM.
+//
+// Layout.  Four waves; wave w owns hidden units 32w..32w+31 of every layer
+// for all 128 rows of the tile (four 32-row blocks): in the forward pass as
+// its output columns, in the backward pass as the input units whose
+// gradient it forms.  The forward output block of layer l and the backward
+// output block of layer l+1 therefore cover the same rows and units in the
+// same accumulator layout, so each wave keeps its SiLU derivatives D_l
+// private from the forward to the backward pass: D_2 and D_3 in registers,
+// D_0 and D_1 in LDS (registers would spill).  Activations and
+// pre-activation gradients of the whole tile are exchanged through two LDS
+// tiles [128][136] (ping-pong).  The weight operand of a wave (its 32 rows
+// of W_l, or of W_l^T going backward) is read from the BF16 weight copies
+// in global memory: 8 KB per wave and layer, common to all workgroups and
+// served by the caches.
+//
+// The rounding points are those of the layered kernels and of the oracle:
+// A_{l+1} = bf16(SiLU(Z_l)), D_l = bf16(SiLU'(Z_l)), dZ_3 = bf16(out_scale
+// W4 (.) D_3), dZ_{l-1} = bf16((dZ_l W_l) (.) D_{l-1}); y and the input
+// gradient are FP32.
+#pragma once
+
+#include "mlp_kernels.h"
+
+namespace pcsdf {
+
+constexpr int kTileRows = 128;
+constexpr int kTS = kHid + 8;  // LDS row stride of a tile (bf16 elements)
+
+struct NetWeights {
+  const uint16_t *W[kLayers + 1];  // W_l [128][in_pad] (W4: [128])
+  const uint16_t *Wt[kLayers];     // W_l^T [in_pad][128]
+};
+
+__device__ __forceinline__ uint16_t lo16(uint32_t v) { return (uint16_t)v; }
+__device__ __forceinline__ uint16_t hi16(uint32_t v) {
+  return (uint16_t)(v >> 16);
+}
+
+// acc[rb] = A_tile[rb rows] x B^T for this wave's 32 units: A from LDS
+// ([128][kTS], K columns used), B [128][K] in global memory, row `unit`.
+template <int K>
+__device__ __forceinline__ void tile_gemm(const uint16_t *a_lds,
+                                          const uint16_t *__restrict__ B,
+                                          int unit, int lane, f32x16 acc[4]) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
+  const uint16_t *brow = B + (size_t)unit * K + 8 * (lane >> 5);
+  bf16x8 bv[K / 16];
+#pragma unroll
+  for (int ks = 0; ks < K / 16; ++ks) bv[ks] = load8(brow + ks * 16);
+  const uint16_t *arow = a_lds + (lane & 31) * kTS + 8 * (lane >> 5);
+#pragma unroll
+  for (int ks = 0; ks < K / 16; ++ks)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      acc[rb] = mfma(load8(arow + rb * 32 * kTS + ks * 16), bv[ks], acc[rb]);
+}
+
+// y [n] and, when gx is given, dy/dx [n][22] for rows [0, n).
+__global__ __launch_bounds__(256, 1) void k_mlp_infer(
+    const float *__restrict__ x, int n, const float *__restrict__ norm,
+    NetWeights w, const float *__restrict__ p, float out_scale,
+    float *__restrict__ y, float *__restrict__ gx, int tiles) {
+  __shared__ uint16_t tl[2][kTileRows * kTS];
+  __shared__ uint16_t dl[2][kTileRows * kTS];  // D_0, D_1
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int unit = wave * 32 + (lane & 31);
+  const float *off = norm, *scale = norm + kIn;
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t row0 = (int64_t)tile * kTileRows;
+    // A0 = bf16((x - offset) * scale), zero beyond 22 columns and n rows
+    for (int t = threadIdx.x; t < kTileRows * kInPad; t += 256) {
+      const int r = t / kInPad, c = t - r * kInPad;
+      const int64_t m = row0 + r;
+      tl[0][r * kTS + c] =
+          (c < kIn && m < n) ? to_bf16((x[m * kIn + c] - off[c]) * scale[c])
+                             : (uint16_t)0;
+    }
+    __syncthreads();
+    uint32_t D[2][4][8];  // bf16 SiLU' of layers 2, 3 for this wave, 2 a word
+    f32x16 acc[4];
+    // forward: layer l reads tile l&1 and writes tile (l+1)&1
+#pragma unroll
+    for (int l = 0; l < kLayers; ++l) {
+      if (l == 0)
+        tile_gemm<kInPad>(tl[0], w.W[0], unit, lane, acc);
+      else
+        tile_gemm<kHid>(tl[l & 1], w.W[l], unit, lane, acc);
+      uint16_t *aout = tl[(l + 1) & 1];
+      const float bias = p[layer_desc(l).b_off + unit];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int row = rb * 32 + acc_row(r, lane);  // r+1: row+1
+          const float z0 = acc[rb][r] + bias, z1 = acc[rb][r + 1] + bias;
+          aout[row * kTS + unit] = to_bf16(silu(z0));
+          aout[(row + 1) * kTS + unit] = to_bf16(silu(z1));
+          const uint16_t d0 = to_bf16(silu_prime(z0));
+          const uint16_t d1 = to_bf16(silu_prime(z1));
+          if (l < 2) {
+            dl[l][row * kTS + unit] = d0;
+            dl[l][(row + 1) * kTS + unit] = d1;
+          } else {
+            D[l - 2][rb][r >> 1] = (uint32_t)d0 | ((uint32_t)d1 << 16);
+          }
+        }
+      __syncthreads();
+    }
+    // y from A4 (tile 0), one thread per row, in the layered kernel's order
+    if (threadIdx.x < kTileRows) {
+      const int64_t m = row0 + threadIdx.x;
+      const uint16_t *a = tl[0] + threadIdx.x * kTS;
+      float s = 0.f;
+      for (int c = 0; c < kHid; ++c)
+        s += from_bf16(a[c]) * from_bf16(w.W[kLayers][c]);
+      if (m < n) y[m] = (s + p[layer_desc(kLayers).b_off]) * out_scale;
+    }
+    if (gx) {
+      // dZ3 = bf16(out_scale W4 (.) D3) into tile 1 (A3 is consumed)
+      const float da3 = out_scale * from_bf16(w.W[kLayers][unit]);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int row = rb * 32 + acc_row(r, lane);
+          const uint32_t d = D[1][rb][r >> 1];
+          tl[1][row * kTS + unit] = to_bf16(da3 * from_bf16(lo16(d)));
+          tl[1][(row + 1) * kTS + unit] = to_bf16(da3 * from_bf16(hi16(d)));
+        }
+      __syncthreads();
+      // dZ_{l-1} = bf16((dZ_l W_l) (.) D_{l-1}): layer l reads tile l&1,
+      // writes tile (l+1)&1
+#pragma unroll
+      for (int l = kLayers - 1; l >= 1; --l) {
+        tile_gemm<kHid>(tl[l & 1], w.Wt[l], unit, lane, acc);
+        uint16_t *zout = tl[(l + 1) & 1];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int r = 0; r < 16; r += 2) {
+            const int row = rb * 32 + acc_row(r, lane);
+            uint16_t d0, d1;  // D_{l-1} at (row, unit), (row + 1, unit)
+            if (l - 1 >= 2) {
+              const uint32_t d = D[l - 3][rb][r >> 1];
+              d0 = lo16(d);
+              d1 = hi16(d);
+            } else {
+              d0 = dl[l - 1][row * kTS + unit];
+              d1 = dl[l - 1][(row + 1) * kTS + unit];
+            }
+            zout[row * kTS + unit] = to_bf16(acc[rb][r] * from_bf16(d0));
+            zout[(row + 1) * kTS + unit] =
+                to_bf16(acc[rb][r + 1] * from_bf16(d1));
+          }
+        __syncthreads();
+      }
+      // dy/dx = (dZ0 W0) * scale: wave w forms row block w, columns 0..31
+      f32x16 g;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) g[r] = 0.f;
+      const uint16_t *zrow =
+          tl[0] + (wave * 32 + (lane & 31)) * kTS + 8 * (lane >> 5);
+      const uint16_t *brow = w.Wt[0] + (size_t)(lane & 31) * kHid +
+                             8 * (lane >> 5);
+#pragma unroll
+      for (int ks = 0; ks < kHid / 16; ++ks)
+        g = mfma(load8(zrow + ks * 16), load8(brow + ks * 16), g);
+      const int col = lane & 31;
+      if (col < kIn) {
+        const float sc = scale[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t m = row0 + wave * 32 + acc_row(r, lane);
+          if (m < n) gx[m * kIn + col] = g[r] * sc;
+        }
+      }
+    }
+    __syncthreads();  // the tiles are reused by the next tile of rows
+  }
+}
+
+}  // namespace pcsdf

@@ -159,14 +159,34 @@ __device__ __forceinline__ int32_t scan_disk(const Tab &ch, int4 b, int k,
   return scan_rows(ch, k * ny, i, j, j0 - 1, b.z, -1, dxb2, best);
 }
 
+// Row-pass values of the free set at column i: precomputed (f1[j*nx] is
+// row j) or computed from the chords on demand.
+struct RowFreeTable {
+  const int32_t *f1;
+  int nx;
+  __device__ __forceinline__ int32_t operator()(int jr) const {
+    return f1[(int64_t)jr * nx];
+  }
+};
+template <class Tab>
+struct RowFreeChords {
+  const Tab &ch;
+  int K, ny, nx, i;
+  __device__ __forceinline__ int32_t operator()(int jr) const {
+    return row_free_dist(ch, K, ny, nx, jr, i);
+  }
+};
+
 // Planar signed value of pixel (i, j): E_D outside the disk union, -E of
 // its complement inside (+-kInfP when the other set is empty).  `ch` is the
-// slice's chord table [K][ny], `box` its K boxes, f1 the slice's row pass
-// of the free set offset to column i (f1[j*nx] is row j).
-template <class Tab, class BoxTab>
-__device__ __forceinline__ int32_t plane_value(const Tab &ch, const BoxTab &box,
-                                               const int32_t *f1, int K,
-                                               int nx, int ny, int i, int j) {
+// slice's chord table [K][ny], `box` its K boxes, rf the row pass of the
+// free set at column i.
+template <class Tab, class BoxTab, class RowFree>
+__device__ __forceinline__ int32_t plane_value_rf(const Tab &ch,
+                                                  const BoxTab &box,
+                                                  const RowFree &rf, int K,
+                                                  int nx, int ny, int i,
+                                                  int j) {
   bool inside = false;
   for (int k = 0; k < K; ++k) inside |= covers(ch[k * ny + j], i);
   int32_t out;
@@ -194,7 +214,7 @@ __device__ __forceinline__ int32_t plane_value(const Tab &ch, const BoxTab &box,
   } else {
     // Rows outward from j, eight rows (four distances) per step so the
     // loads of the precomputed row distances overlap.
-    int32_t best = f1[(int64_t)j * nx];
+    int32_t best = rf(j);
     const int dmax = max(j, ny - 1 - j);
     for (int d0 = 1; d0 <= dmax; d0 += 4) {
       if (d0 * d0 >= best) break;
@@ -202,11 +222,8 @@ __device__ __forceinline__ int32_t plane_value(const Tab &ch, const BoxTab &box,
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int d = d0 + u;
-        v[2 * u] = (d <= dmax && j - d >= 0) ? f1[(int64_t)(j - d) * nx]
-                                             : kInfP;
-        v[2 * u + 1] = (d <= dmax && j + d < ny)
-                           ? f1[(int64_t)(j + d) * nx]
-                           : kInfP;
+        v[2 * u] = (d <= dmax && j - d >= 0) ? rf(j - d) : kInfP;
+        v[2 * u + 1] = (d <= dmax && j + d < ny) ? rf(j + d) : kInfP;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -218,6 +235,14 @@ __device__ __forceinline__ int32_t plane_value(const Tab &ch, const BoxTab &box,
     out = best == kInfP ? -kInfP : -best;
   }
   return out;
+}
+
+// The same with the row pass precomputed: f1 offset to column i.
+template <class Tab, class BoxTab>
+__device__ __forceinline__ int32_t plane_value(const Tab &ch, const BoxTab &box,
+                                               const int32_t *f1, int K,
+                                               int nx, int ny, int i, int j) {
+  return plane_value_rf(ch, box, RowFreeTable{f1, nx}, K, nx, ny, i, j);
 }
 
 }  // namespace pcsdf

@@ -106,19 +106,23 @@ __global__ __launch_bounds__(256) void k_planes(
   }
 }
 
+int launch_chords(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
+                  int2 *chords, int nx, int ny, int n_slices,
+                  const int32_t *need, hipStream_t s) {
+  const int64_t total = (int64_t)n_slices * K * ny;
+  if (total <= 0) return PCSDF_OK;
+  hipLaunchKernelGGL(k_chords, dim3((unsigned)((total + 255) / 256)),
+                     dim3(256), 0, s, xy, K, Rs, nx, ny, total, need, chords);
+  return check_launch(h, "chords");
+}
+
 int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
                   bool empty,
                   int2 *chords, int32_t *P, int nx, int ny, int n_slices,
                   const int32_t *need, hipStream_t s) {
   const int Keff = empty ? 0 : K;
-  const int64_t total = (int64_t)n_slices * Keff * ny;
-  if (total > 0) {
-    hipLaunchKernelGGL(k_chords, dim3((unsigned)((total + 255) / 256)),
-                       dim3(256), 0, s, xy, Keff, Rs, nx, ny, total, need,
-                       chords);
-    int rc = check_launch(h, "chords");
-    if (rc) return rc;
-  }
+  int rc0 = launch_chords(h, xy, Keff, Rs, chords, nx, ny, n_slices, need, s);
+  if (rc0) return rc0;
   const int npx = nx * ny;
   int32_t *F1 = P + (int64_t)n_slices * npx;
   const int64_t npix = (int64_t)n_slices * npx;

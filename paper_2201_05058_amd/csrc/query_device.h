@@ -19,42 +19,44 @@ struct Trilinear {
   bool inf;       // a corner is infinite: D is that corner's value
 };
 
-__device__ __forceinline__ Trilinear trilinear(const float *__restrict__ field,
-                                               int nx, int ny, int nz,
-                                               double h, double ox, double oy,
-                                               double oz,
-                                               const float *__restrict__ p) {
-  Trilinear T;
-  T.status = 0;
-  const int n[3] = {nx, ny, nz};
-  const double o[3] = {ox, oy, oz};
+// The cell of point p: lower corner idx[3], fractions fr[3], clamp bits.
+struct Cell {
   int idx[3];
   double fr[3];
+  uint32_t status;
+};
+
+__device__ __forceinline__ Cell cell_of(int nx, int ny, int nz, double h,
+                                        double ox, double oy, double oz,
+                                        const float *__restrict__ p) {
+  Cell C;
+  C.status = 0;
+  const int n[3] = {nx, ny, nz};
+  const double o[3] = {ox, oy, oz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double gc = ((double)p[a] - o[a]) / h - 0.5;
     if (gc < 0.0) {
       gc = 0.0;
-      T.status |= 1u << a;
+      C.status |= 1u << a;
     } else if (gc > (double)(n[a] - 1)) {
       gc = (double)(n[a] - 1);
-      T.status |= 1u << a;
+      C.status |= 1u << a;
     }
     int i = (int)floor(gc);
     if (i > n[a] - 2) i = n[a] - 2;
-    idx[a] = i;
-    fr[a] = gc - (double)i;
+    C.idx[a] = i;
+    C.fr[a] = gc - (double)i;
   }
-  const int64_t base = ((int64_t)idx[2] * ny + idx[1]) * nx + idx[0];
-  const int64_t sy = nx, sz = (int64_t)nx * ny;
-  double c[2][2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-        c[a][b][e] = (double)field[base + a + b * sy + e * sz];
+  return C;
+}
+
+// Value and per-voxel gradient from the eight corners c[a][b][e] (a along
+// x, b along y, e along z) of a cell with fractions fr.
+__device__ __forceinline__ Trilinear interpolate(const double c[2][2][2],
+                                                 const double fr[3]) {
+  Trilinear T;
+  T.status = 0;
   T.inf = false;
   T.D = 0.0;
 #pragma unroll
@@ -102,6 +104,27 @@ __device__ __forceinline__ Trilinear trilinear(const float *__restrict__ field,
   T.g[0] = gx;
   T.g[1] = gy;
   T.g[2] = gz;
+  return T;
+}
+
+__device__ __forceinline__ Trilinear trilinear(const float *__restrict__ field,
+                                               int nx, int ny, int nz,
+                                               double h, double ox, double oy,
+                                               double oz,
+                                               const float *__restrict__ p) {
+  const Cell C = cell_of(nx, ny, nz, h, ox, oy, oz, p);
+  const int64_t base = ((int64_t)C.idx[2] * ny + C.idx[1]) * nx + C.idx[0];
+  const int64_t sy = nx, sz = (int64_t)nx * ny;
+  double c[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        c[a][b][e] = (double)field[base + a + b * sy + e * sz];
+  Trilinear T = interpolate(c, C.fr);
+  T.status = C.status;
   return T;
 }
 

@@ -22,9 +22,9 @@
 //   3. decide:    surrogate answers are written out; fallback queries are
 //                 appended to a compact list (wave ballot + one atomic per
 //                 wave) and their slices marked as needed;
-//   4. fields:    the exact composite of the marked slices only (the other
-//                 slices' kernels exit at once);
-//   5. exact:     the sphere query kernel over the compact list.
+//   4. chords:    the humans' chords of the marked slices only;
+//   5. exact:     the fallback list answered exactly from the chords and
+//                 the static field (direct.hip), without building a field.
 #include <cmath>
 #include <cstring>
 
@@ -55,6 +55,28 @@ __global__ __launch_bounds__(256) void k_features(
   row[3] = (float)s * dt;
 #pragma unroll
   for (int c = 0; c < kState; ++c) row[4 + c] = st.v[c];
+}
+
+// Pool variant: query q belongs to human configuration c = slice[q] /
+// n_slices (its state is states[c]) and slice slice[q] % n_slices.
+__global__ __launch_bounds__(256) void k_features_pool(
+    const float *__restrict__ centre, const int32_t *__restrict__ slice,
+    int n_slices, int n_configs, float dt, const float *__restrict__ states,
+    int n, float *__restrict__ x) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  int g = slice[q];
+  const int total = n_slices * n_configs;
+  g = g < 0 ? 0 : (g > total - 1 ? total - 1 : g);
+  const int c = g / n_slices, s = g - c * n_slices;
+  float *row = x + (int64_t)q * kNetIn;
+  row[0] = centre[3 * q];
+  row[1] = centre[3 * q + 1];
+  row[2] = centre[3 * q + 2];
+  row[3] = (float)s * dt;
+  const float *st = states + (int64_t)c * kState;
+#pragma unroll
+  for (int k = 0; k < kState; ++k) row[4 + k] = st[k];
 }
 
 __global__ void k_clear(int32_t *__restrict__ p, int n) {
@@ -193,6 +215,34 @@ extern "C" int pcsdf_surrogate_features(pcsdf_handle *hp, int32_t n_queries,
   return check_launch(h, "surrogate features");
 }
 
+extern "C" int pcsdf_surrogate_features_pool(
+    pcsdf_handle *hp, int32_t n_queries, const float *centre_dev,
+    const int32_t *slice_dev, int32_t n_slices, int32_t n_configs,
+    double dt_s, const float *states_dev, float *x_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (n_queries < 0 || n_slices < 1 || n_configs < 1 ||
+      (int64_t)n_slices * n_configs > INT32_MAX)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "need n_queries >= 0, n_slices >= 1, n_configs >= 1");
+  if (!std::isfinite(dt_s) || dt_s < 0)
+    return fail(h, PCSDF_ERR_NUMERIC, "dt_s must be finite and >= 0");
+  if (n_queries == 0) return PCSDF_OK;
+  if (!centre_dev || !slice_dev || !states_dev || !x_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "centre, slice, states and x are required");
+  if (((uintptr_t)centre_dev | (uintptr_t)slice_dev | (uintptr_t)states_dev |
+       (uintptr_t)x_dev) & 3)
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  int rc;
+  if ((rc = bind_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_features_pool, dim3(nblocks(n_queries)), dim3(256), 0,
+                     s, centre_dev, slice_dev, n_slices, n_configs,
+                     (float)dt_s, states_dev, n_queries, x_dev);
+  return check_launch(h, "surrogate features (pool)");
+}
+
 extern "C" int pcsdf_query_spheres_surrogate(
     pcsdf_handle *hp, pcsdf_mlp *m, const pcsdf_grid *g,
     const int32_t *static_ssq_dev, const float *static_sdf_dev,
@@ -200,8 +250,8 @@ extern "C" int pcsdf_query_spheres_surrogate(
     double radius_m, double height_m, const float *state_host, double dt_s,
     double fallback_margin_m,
     int32_t n_queries, const float *centre_dev, const float *radius_dev,
-    const int32_t *slice_dev, double hinge_eps_m, float *field_work_dev,
-    float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,
+    const int32_t *slice_dev, double hinge_eps_m, float *dist_dev,
+    float *grad_dev, uint8_t *status_dev, float *cost_dev,
     uint8_t *used_fallback_dev, void *stream) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return PCSDF_ERR_INVALID_ARG;
@@ -233,14 +283,12 @@ extern "C" int pcsdf_query_spheres_surrogate(
     if (!std::isfinite(state_host[c]))
       return fail(h, PCSDF_ERR_NUMERIC, "non-finite state entry");
   if (n_queries == 0) return PCSDF_OK;
-  if (!centre_dev || !radius_dev || !slice_dev || !dist_dev || !grad_dev ||
-      !field_work_dev)
+  if (!centre_dev || !radius_dev || !slice_dev || !dist_dev || !grad_dev)
     return fail(h, PCSDF_ERR_INVALID_ARG,
-                "centre, radius, slice, field_work, dist and grad are "
-                "required");
+                "centre, radius, slice, dist and grad are required");
   if (((uintptr_t)centre_dev | (uintptr_t)radius_dev |
        (uintptr_t)slice_dev | (uintptr_t)dist_dev | (uintptr_t)grad_dev |
-       (uintptr_t)cost_dev | (uintptr_t)field_work_dev |
+       (uintptr_t)cost_dev | (uintptr_t)static_ssq_dev |
        (uintptr_t)static_sdf_dev) & 3)
     return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
   if ((rc = bind_device(h))) return rc;
@@ -298,15 +346,14 @@ extern "C" int pcsdf_query_spheres_surrogate(
     hipLaunchKernelGGL(k_decide, dim3(nblocks(n_queries)), dim3(256), 0, s, A);
     if ((rc = check_launch(h, "surrogate decide"))) return rc;
   }
-  // Exact fields of the slices some fallback query reads, then the exact
-  // queries of the fallback list.
-  if ((rc = composite_run(h, g, static_ssq_dev, n_slices, n_humans,
-                          human_xy_host, radius_m, nullptr, height_m, nullptr,
-                          field_work_dev, need, s)))
+  // The exact answers of the fallback list, straight from the chords of
+  // the slices they read and the static field.
+  DirectSet d;
+  if ((rc = direct_setup(h, g, static_ssq_dev, n_slices, n_humans,
+                         human_xy_host, radius_m, height_m, need, s, &d)))
     return rc;
   ProfScope pq(h, PCSDF_KERNEL_QUERY, s);
-  return launch_query_list(h, g, field_work_dev, n_slices, list, count,
-                           n_queries, centre_dev, radius_dev, slice_dev,
-                           hinge_eps_m, dist_dev, grad_dev, status_dev,
-                           cost_dev, s);
+  return launch_direct_list(h, g, d, n_slices, list, count, n_queries,
+                            centre_dev, radius_dev, slice_dev, hinge_eps_m,
+                            dist_dev, grad_dev, status_dev, cost_dev, s);
 }

@@ -40,10 +40,13 @@ def _declare(lib):
     lib.pcsdf_surrogate_features.argtypes = [P, i32, P, P, i32, C.c_double,
                                              P, P, P]
     lib.pcsdf_surrogate_features.restype = C.c_int
+    lib.pcsdf_surrogate_features_pool.argtypes = [P, i32, P, P, i32, i32,
+                                                  C.c_double, P, P, P]
+    lib.pcsdf_surrogate_features_pool.restype = C.c_int
     d = C.c_double
     lib.pcsdf_query_spheres_surrogate.argtypes = [
         P, P, P, P, P, i32, i32, P, d, d, P, d, d, i32, P, P, P, d, P, P, P,
-        P, P, P, P]
+        P, P, P]
     lib.pcsdf_query_spheres_surrogate.restype = C.c_int
     lib._mlp_declared = True
 
@@ -177,17 +180,37 @@ def surrogate_features(centre, slice_, n_slices, dt, state,
     return x
 
 
+def surrogate_features_pool(centre, slice_, n_slices, n_configs, dt,
+                            states, handle: Handle | None = None):
+    """Network input [n, 22] for queries over a pool of configurations
+    (pcsdf_surrogate_features_pool): slice_[q] = config * n_slices + s,
+    states float32 [n_configs, 18] on the GPU."""
+    import torch
+    from . import _dev_ptr, _stream
+    h = handle or default_handle()
+    lib = load_library()
+    _declare(lib)
+    n = slice_.numel()
+    x = torch.empty((n, NIN), dtype=torch.float32, device=centre.device)
+    h.check(lib.pcsdf_surrogate_features_pool(
+        h.ptr, n, _dev_ptr(centre, torch.float32, "centre", 3 * n),
+        _dev_ptr(slice_, torch.int32, "slice", n), int(n_slices),
+        int(n_configs), float(dt),
+        _dev_ptr(states, torch.float32, "states", n_configs * (NIN - 4)),
+        _dev_ptr(x, torch.float32, "x"), _stream(centre.device)))
+    return x
+
+
 def query_spheres_surrogate(net: Mlp, grid, static_ssq, human_xy, radius,
                             height, state, dt, centre, sphere_radius, slice_,
                             fallback_margin=0.10, hinge_eps=0.0,
-                            field_work=None, want_status=True,
-                            want_cost=False, static_sdf=None):
+                            want_status=True, want_cost=False,
+                            static_sdf=None):
     """Sphere queries by the network with exact fallback
     (pcsdf_query_spheres_surrogate).  With static_sdf (the environment's
     fp32 field) the network predicts the humans' part and the prediction is
     the smaller of it and the environment field.  Returns a dict with dist,
-    grad, status, cost (or None), used_fallback and the field work buffer
-    (exact fields of the slices some fallback query read)."""
+    grad, status, cost (or None) and used_fallback."""
     import torch
     from . import _dev_ptr, _stream
     g = as_grid(grid)
@@ -199,9 +222,6 @@ def query_spheres_surrogate(net: Mlp, grid, static_ssq, human_xy, radius,
     V = g.nvox
     dev = centre.device
     n = slice_.numel()
-    if field_work is None:
-        field_work = torch.empty((n_slices,) + g.shape_zyx,
-                                 dtype=torch.float32, device=dev)
     dist = torch.empty(n, dtype=torch.float32, device=dev)
     grad = torch.empty((n, 3), dtype=torch.float32, device=dev)
     status = torch.empty(n, dtype=torch.uint8, device=dev) \
@@ -220,11 +240,10 @@ def query_spheres_surrogate(net: Mlp, grid, static_ssq, human_xy, radius,
         _dev_ptr(centre, torch.float32, "centre", 3 * n),
         _dev_ptr(sphere_radius, torch.float32, "radius", n),
         _dev_ptr(slice_, torch.int32, "slice", n), float(hinge_eps),
-        _dev_ptr(field_work, torch.float32, "field_work", n_slices * V),
         _dev_ptr(dist, torch.float32, "dist"),
         _dev_ptr(grad, torch.float32, "grad"),
         _dev_ptr(status, torch.uint8, "status"),
         _dev_ptr(cost, torch.float32, "cost"),
         _dev_ptr(used, torch.uint8, "used"), _stream(dev)))
     return {"dist": dist, "grad": grad, "status": status, "cost": cost,
-            "used_fallback": used, "field_work": field_work}
+            "used_fallback": used}

@@ -1,13 +1,16 @@
 """Trainer of the sphere-query surrogate for one static room.
 
 Each step of the data pipeline and of the optimisation runs in the
-library's kernels: for every fresh draw of three constant-velocity humans
-the exact composite fields of all slices are built
-(pcsdf_predicted_composite_sdf); uniformly drawn sphere centres and slices
-are labelled with the exact distance at the centre (pcsdf_query_spheres
-with zero radius); the network input is assembled on the device
-(pcsdf_surrogate_features); and one Adam step is taken on the squared
-error (pcsdf_mlp_train_step).  This module only draws the random inputs
+library's kernels.  A pool of P draws of three constant-velocity humans is
+kept on the device with the exact fields of all their slices
+(pcsdf_predicted_composite_sdf); every step replaces one draw, labels a
+batch of sphere centres drawn over all configurations and slices with the
+exact distance at the centre (pcsdf_query_spheres with zero radius),
+assembles the network input on the device
+(pcsdf_surrogate_features_pool) and takes one Adam step on the squared
+error (pcsdf_mlp_train_step).  Mixing many configurations in every batch
+matters: batches of a single configuration teach the network that
+configuration's field, not its dependence on the humans' state.  This module only draws the random inputs
 (human starts and velocities on the host, centres and slices with a seeded
 torch generator on the device) and sequences the calls.
 
@@ -42,8 +45,9 @@ import numpy as np
 import scenegen
 
 from . import (build_static_sdf, default_handle, predicted_composite_sdf,
-               query_spheres)
-from .surrogate import NIN, Mlp, init_params, surrogate_features
+               query_spheres, query_spheres_direct)
+from .surrogate import (NIN, Mlp, init_params, surrogate_features,
+                        surrogate_features_pool)
 
 LABEL_FLOOR = -0.1
 # Labels of the env mode are capped just above the room's largest
@@ -94,8 +98,6 @@ class Room:
         self.dt = scene.dt
         self.fields = torch.empty((self.n_slices,) + self.grid.shape_zyx,
                                   dtype=torch.float32, device=dev)
-        self.label_fields = (torch.empty_like(self.fields) if mode == "env"
-                             else self.fields)
         fin = self.static_sdf[torch.isfinite(self.static_sdf)]
         self.cap = (float(fin.max()) + CAP_ABOVE_ENV if mode == "env"
                     and fin.numel() else float("inf"))
@@ -112,23 +114,17 @@ class Room:
                                 scenegen.HUMAN_RADIUS, scenegen.HUMAN_HEIGHT,
                                 out_sdf=self.fields, want_ssq=False)
 
-    def build_labels(self, xy):
-        """The fields the network is trained on (see the module note)."""
-        if self.mode == "pure":
-            self.build(xy)
-            return
-        predicted_composite_sdf(self.grid, self.empty_ssq, xy,
-                                scenegen.HUMAN_RADIUS, scenegen.HUMAN_HEIGHT,
-                                out_sdf=self.label_fields, want_ssq=False)
+    @property
+    def label_static(self):
+        """The environment the training labels are composited with."""
+        return self.empty_ssq if self.mode == "env" else self.static_ssq
 
     @property
     def env_sdf(self):
         return self.static_sdf if self.mode == "env" else None
 
-    def draw_queries(self, gen, n, xy=None, near=0.0):
-        """Centres uniform over the span of voxel centres, slices uniform;
-        with near > 0 that fraction of the centres is drawn within 1 m
-        (in x and y) of a random human's position in the sample's slice."""
+    def draw_queries(self, gen, n):
+        """Centres uniform over the span of voxel centres, slices uniform."""
         import torch
         g = self.grid
         lo = torch.tensor(np.array(g.origin) + g.h / 2, dtype=torch.float32,
@@ -138,30 +134,76 @@ class Room:
         c = torch.rand((n, 3), generator=gen, device=self.dev) * span + lo
         s = torch.randint(0, self.n_slices, (n,), generator=gen,
                           device=self.dev, dtype=torch.int32)
-        m = int(n * near)
-        if m > 0 and xy is not None and xy.shape[1] > 0:
-            pos = torch.tensor(xy, dtype=torch.float32, device=self.dev)
-            k = torch.randint(0, xy.shape[1], (m,), generator=gen,
-                              device=self.dev)
-            p = pos[s[:m].long(), k]
-            off = (torch.rand((m, 2), generator=gen, device=self.dev) * 2
-                   - 1)
-            near_xy = p + off
-            c[:m, :2] = torch.minimum(torch.maximum(near_xy, lo[:2]),
-                                      lo[:2] + span[:2])
         return c.contiguous(), s
 
-    def label(self, c, s):
+
+class Pool:
+    """Label fields of P human configurations at once, so that every
+    training batch mixes many configurations: pool slice c*n + s is slice s
+    of configuration c.  One configuration is replaced by a fresh draw per
+    refresh."""
+
+    def __init__(self, room, P, rng):
         import torch
-        zero = torch.zeros(s.numel(), dtype=torch.float32, device=self.dev)
-        d, _, _, _ = query_spheres(self.grid, self.label_fields, c, zero, s,
+        self.room, self.P, self.rng = room, P, rng
+        n = room.n_slices
+        self.fields = torch.empty((P * n,) + room.grid.shape_zyx,
+                                  dtype=torch.float32, device=room.dev)
+        self.states = torch.zeros((P, NIN - 4), dtype=torch.float32,
+                                  device=room.dev)
+        self.xy = torch.zeros((P, n, 3, 2), dtype=torch.float32,
+                              device=room.dev)
+        self.next = 0
+        for _ in range(P):
+            self.refresh()
+
+    def refresh(self):
+        import torch
+        room, p = self.room, self.next
+        n = room.n_slices
+        xy, state = room.draw_humans(self.rng)
+        predicted_composite_sdf(room.grid, room.label_static, xy,
+                                scenegen.HUMAN_RADIUS, scenegen.HUMAN_HEIGHT,
+                                out_sdf=self.fields[p * n:(p + 1) * n],
+                                want_ssq=False)
+        self.states[p] = torch.from_numpy(state).to(room.dev)
+        self.xy[p] = torch.from_numpy(xy.astype(np.float32)).to(room.dev)
+        self.next = (p + 1) % self.P
+
+    def batch(self, gen, n, near):
+        """(features [n, 22], labels [n]): centres uniform over the span of
+        voxel centres (a fraction `near` within 1 m in x, y of a random
+        human of the sample's configuration and slice), configurations and
+        slices uniform."""
+        import torch
+        room = self.room
+        c, s = room.draw_queries(gen, n)
+        cfg = torch.randint(0, self.P, (n,), generator=gen, device=room.dev)
+        m = int(n * near)
+        if m > 0:
+            k = torch.randint(0, 3, (m,), generator=gen, device=room.dev)
+            p = self.xy[cfg[:m], s[:m].long(), k]
+            off = torch.rand((m, 2), generator=gen, device=room.dev) * 2 - 1
+            g = room.grid
+            lo = torch.tensor(np.array(g.origin[:2]) + g.h / 2,
+                              dtype=torch.float32, device=room.dev)
+            hi = torch.tensor(np.array(g.origin[:2]) + np.array(g.extent[:2])
+                              - g.h / 2, dtype=torch.float32,
+                              device=room.dev)
+            c[:m, :2] = torch.minimum(torch.maximum(p + off, lo), hi)
+        gs = (cfg.to(torch.int32) * room.n_slices + s).contiguous()
+        zero = torch.zeros(n, dtype=torch.float32, device=room.dev)
+        d, _, _, _ = query_spheres(room.grid, self.fields, c, zero, gs,
                                    want_status=False)
-        return d.clamp_(min=LABEL_FLOOR, max=self.cap)
+        y = d.clamp_(min=LABEL_FLOOR, max=room.cap)
+        x = surrogate_features_pool(c, gs, room.n_slices, self.P, room.dt,
+                                    self.states)
+        return x, y
 
 
-def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
+def train(scene, dev, samples=50_000_000, batch=16384, pool=48,
           lr=1e-3, lr_min=1e-5, seed=0, log_every=1000, log=print,
-          mode="env", near=0.5):
+          mode="env", near=0.25):
     import torch
     room = Room(scene, dev, mode)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -171,36 +213,29 @@ def train(scene, dev, samples=50_000_000, batch=16384, per_draw=32768,
     off, scl = normalisation(room.grid)
     net.set_params(init_params(rng), off, scl, 1.0)
     steps = max(1, samples // batch)
-    per_draw = max(batch, per_draw // batch * batch)
+    P = Pool(room, pool, rng)
     loss = torch.zeros(1, device=dev)
     hist = []
     t0 = time.time()
-    step = 0
-    while step < steps:
-        xy, state = room.draw_humans(rng)
-        room.build_labels(xy)
-        c, s = room.draw_queries(gen, per_draw, xy, near)
-        y = room.label(c, s)
-        x = surrogate_features(c, s, room.n_slices, room.dt, state)
-        for b in range(0, per_draw, batch):
-            if step >= steps:
-                break
-            a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step
-                                                             / steps))
-            net.train_step(x[b:b + batch], y[b:b + batch], a, loss=loss)
-            step += 1
-            if step % log_every == 0 or step == steps:
-                l = float(loss.cpu()[0])
-                if not math.isfinite(l):
-                    raise FloatingPointError(f"loss {l} at step {step}")
-                hist.append((step, l))
-                log(json.dumps({"step": step, "loss": l, "lr": a,
-                                "s": round(time.time() - t0, 1)}))
+    for step in range(1, steps + 1):
+        P.refresh()
+        x, y = P.batch(gen, batch, near)
+        a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step
+                                                         / steps))
+        net.train_step(x, y, a, loss=loss)
+        if step % log_every == 0 or step == steps:
+            l = float(loss.cpu()[0])
+            if not math.isfinite(l):
+                raise FloatingPointError(f"loss {l} at step {step}")
+            hist.append((step, l))
+            log(json.dumps({"step": step, "loss": l, "lr": a,
+                            "s": round(time.time() - t0, 1)}))
     torch.cuda.synchronize()
     return net, {"steps": steps, "batch": batch, "samples": steps * batch,
                  "seconds": time.time() - t0, "loss": hist,
                  "in_offset": off, "in_scale": scl, "mode": mode,
-                 "near": near, "lr": lr, "label_cap": room.cap}
+                 "near": near, "lr": lr, "label_cap": room.cap,
+                 "pool": pool}
 
 
 def save(path, net, info, scene):
@@ -212,7 +247,7 @@ def save(path, net, info, scene):
                               "voxel_m": scene.grid.h,
                               "n_slices": scene.n_slices, "dt": scene.dt,
                               "mode": info["mode"], "near": info["near"],
-                              "lr": info["lr"],
+                              "lr": info["lr"], "pool": info["pool"],
                               "label_cap": info["label_cap"],
                               "samples": info["samples"],
                               "steps": info["steps"],
@@ -254,7 +289,8 @@ def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
     path on fields already built, and the end-to-end cost per new human
     state at the room's own query load (time_queries, default: the scene's
     query count), where the exact path builds every slice and the surrogate
-    path only the slices its fallback queries read."""
+    path evaluates its fallback queries directly from the chords and the
+    static field (as does the direct exact path, timed alongside)."""
     import torch
 
     from .surrogate import query_spheres_surrogate
@@ -268,13 +304,12 @@ def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
     r = (torch.rand(n_queries, generator=gen, device=dev) * 0.10 + 0.05)
     d_ex, g_ex, _, _ = query_spheres(room.grid, room.fields, c, r, s,
                                      want_status=False)
-    work = torch.empty_like(room.fields)
 
     def sur(cc=c, rr=r, ss=s):
         return query_spheres_surrogate(
             net, room.grid, room.static_ssq, xy, scenegen.HUMAN_RADIUS,
             scenegen.HUMAN_HEIGHT, state, room.dt, cc, rr, ss,
-            fallback_margin=margin, field_work=work, want_status=False,
+            fallback_margin=margin, want_status=False,
             static_sdf=room.env_sdf)
     out = sur()
     torch.cuda.synchronize()
@@ -312,13 +347,21 @@ def evaluate(net, scene, dev, n_queries=1_000_000, seed=40, margin=0.10,
     def exact_e2e():
         room.build(xy)
         query_spheres(room.grid, room.fields, cq, rq, sq, want_status=False)
+    def direct(cc, rr, ss):
+        return query_spheres_direct(room.grid, room.static_ssq, xy,
+                                    scenegen.HUMAN_RADIUS,
+                                    scenegen.HUMAN_HEIGHT, cc, rr, ss,
+                                    want_status=False)
+    res["exact_direct_ms_1M"] = _time_ms(lambda: direct(c, r, s))
     res["e2e_queries"] = nq
     res["e2e_exact_ms"] = _time_ms(exact_e2e)
+    res["e2e_exact_direct_ms"] = _time_ms(lambda: direct(cq, rq, sq))
     res["e2e_surrogate_ms"] = _time_ms(lambda: sur(cq, rq, sq))
     o2 = sur(cq, rq, sq)
     used_q = o2["used_fallback"].bool().cpu().numpy()
     res["e2e_fallback_fraction"] = float(used_q.mean())
-    res["e2e_slices_built"] = int(len(np.unique(sq.cpu().numpy()[used_q])))
+    res["e2e_slices_with_fallback"] = int(len(np.unique(
+        sq.cpu().numpy()[used_q])))
     res["n_slices"] = room.n_slices
     return res
 
@@ -329,9 +372,10 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--samples", type=float, default=50e6)
     ap.add_argument("--batch", type=int, default=16384)
-    ap.add_argument("--per-draw", type=int, default=32768)
+    ap.add_argument("--pool", type=int, default=48,
+                    help="human configurations mixed in every batch")
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--near", type=float, default=0.5)
+    ap.add_argument("--near", type=float, default=0.25)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval", action="store_true",
                     help="evaluate the trained network on 1M queries")
@@ -340,7 +384,7 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     scene = scenegen.room256()
     net, info = train(scene, dev, samples=int(a.samples), batch=a.batch,
-                      per_draw=a.per_draw, lr=a.lr, seed=a.seed,
+                      pool=a.pool, lr=a.lr, seed=a.seed,
                       log=lambda s: print(s, flush=True), mode=a.mode,
                       near=a.near)
     save(a.out, net, info, scene)

@@ -184,8 +184,7 @@ def test_surrogate_validation(h):
     # no network
     assert h.lib.pcsdf_query_spheres_surrogate(
         h.ptr, None, C.byref(g), FAKE, None, 2, 0, None, 0.25, 1.8, st, 0.1,
-        0.1,
-        10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, FAKE, None, None, None,
+        0.1, 10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, None, None, None,
         None) == 1
 
     def feat(n=5, centre=FAKE, slices=FAKE, n_slices=2, dt=0.1, state=st,

@@ -165,3 +165,68 @@ def test_floor_sdf_matches_oracle(pc, dev, seed, dims, zr):
     np.testing.assert_array_equal(ssq.cpu().numpy(), want)
     np.testing.assert_array_equal(sdf.cpu().numpy(),
                                   oracle.to_float(want, sc.grid.h))
+
+
+def _queries(sc, Q, seed):
+    rng = np.random.default_rng(seed)
+    L = np.array(sc.grid.extent)
+    c = (rng.uniform(-0.1, 1.1, size=(Q, 3)) * L).astype(np.float32)
+    r = rng.uniform(0.0, 0.15, size=Q).astype(np.float32)
+    s = rng.integers(-1, sc.n_slices + 2, size=Q).astype(np.int32)
+    return c, r, s
+
+
+@pytest.mark.parametrize("seed,dims,n,K", CASES)
+def test_direct_queries_match_oracle_and_fields(pc, dev, seed, dims, n, K):
+    sc = scenegen.small_scene(seed, *dims, h=0.05, n_humans=K, n_slices=n)
+    c, r, s = _queries(sc, 3000, seed)
+    say(f"direct queries seed={seed} dims={dims} n={n} K={K}")
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    _, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                       sc.height)
+    wd, wg, wst, wc = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.3)
+    s_ssq, _ = pc.build_static_sdf(sc.grid, to_dev(sc.occ, dev))
+    cd, rd, sd = to_dev(c, dev), to_dev(r, dev), to_dev(s, dev)
+    d, g, st, cost = pc.query_spheres_direct(
+        sc.grid, s_ssq, sc.human_xy, sc.radius, sc.height, cd, rd, sd,
+        hinge_eps=0.3, want_cost=True)
+    _, cf = pc.predicted_composite_sdf(sc.grid, s_ssq, sc.human_xy,
+                                       sc.radius, sc.height, want_ssq=False)
+    fd, fg, fst, fc = pc.query_spheres(sc.grid, cf, cd, rd, sd, hinge_eps=0.3,
+                                       want_cost=True)
+    torch.cuda.synchronize()
+    d, g, st, cost = (t.cpu().numpy() for t in (d, g, st, cost))
+    # bit-identical to sampling the built fields
+    for a, b in zip((d, g, st, cost), (fd, fg, fst, fc)):
+        np.testing.assert_array_equal(a, b.cpu().numpy())
+    # and to the oracle within the query contract
+    np.testing.assert_array_equal(st, wst)
+    h = sc.grid.h
+    for got, want, floor in ((d, wd, h), (cost, wc, h)):
+        nanw = np.isnan(want)
+        assert (np.isnan(got) == nanw).all()
+        fin = np.isfinite(want)
+        np.testing.assert_array_equal(got[~fin & ~nanw], want[~fin & ~nanw])
+        err = np.abs(got[fin].astype(np.float64) - want[fin])
+        assert (err <= 1e-6 * np.maximum(np.abs(want[fin]), floor)).all()
+    nanw = np.isnan(wg)
+    err = np.abs(g[~nanw].astype(np.float64) - wg[~nanw])
+    assert (err <= 1e-6 * np.maximum(np.abs(wg[~nanw]), 1.0)).all()
+
+
+def test_direct_queries_room256_bit_identical(pc, dev):
+    sc = scenegen.room256()
+    q = sc.queries
+    say("direct queries room256, 10k")
+    s_ssq, _ = pc.build_static_sdf(sc.grid, to_dev(sc.occ, dev))
+    cd, rd, sd = to_dev(q.centre, dev), to_dev(q.radius, dev), \
+        to_dev(q.slice, dev)
+    d, g, st, _ = pc.query_spheres_direct(sc.grid, s_ssq, sc.human_xy,
+                                          sc.radius, sc.height, cd, rd, sd)
+    _, cf = pc.predicted_composite_sdf(sc.grid, s_ssq, sc.human_xy,
+                                       sc.radius, sc.height, want_ssq=False)
+    fd, fg, fst, _ = pc.query_spheres(sc.grid, cf, cd, rd, sd)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d.cpu().numpy(), fd.cpu().numpy())
+    np.testing.assert_array_equal(g.cpu().numpy(), fg.cpu().numpy())
+    np.testing.assert_array_equal(st.cpu().numpy(), fst.cpu().numpy())

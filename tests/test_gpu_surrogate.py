@@ -11,9 +11,7 @@ the output RMS (1.03% measured), gradients within 5%, medians within 5e-5,
 and at most 5% of the answers off by more than 1e-3 of RMS.  The decision
 itself depends on the network's value, which the GPU computes with FP32
 accumulation: the two sides may only disagree for queries whose oracle
-value lies within the output bound of the margin.  Fields are built only
-for the slices that some fallback query reads, bit-identical to the
-oracle's composite; the other slices of the work buffer stay untouched.
+value lies within the output bound of the margin.
 """
 import sys
 
@@ -27,9 +25,6 @@ from oracle import surrogate as osur
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-
-SENTINEL = 12345.0
-
 
 def say(*a):
     print(*a, flush=True)
@@ -74,12 +69,10 @@ def run_gpu(sg, dev, sc, rs, c, r, s, st, params, off, scl, osc, margin,
             eps, static_sdf=None):
     net = sg.Mlp()
     net.set_params(params, off, scl, osc)
-    fw = torch.full((sc.n_slices,) + sc.grid.shape_zyx, SENTINEL,
-                    dtype=torch.float32, device=dev)
     out = sg.query_spheres_surrogate(
         net, sc.grid, to_dev(rs, dev), sc.human_xy, sc.radius, sc.height, st,
         sc.dt, to_dev(c, dev), to_dev(r, dev), to_dev(s, dev),
-        fallback_margin=margin, hinge_eps=eps, field_work=fw, want_cost=True,
+        fallback_margin=margin, hinge_eps=eps, want_cost=True,
         static_sdf=static_sdf)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None)
@@ -101,18 +94,6 @@ def check_exact(got_d, got_g, got_st, got_c, wd, wg, wst, wc, h):
     assert (np.isnan(got_g) == nanw).all()
     err = np.abs(got_g[~nanw].astype(np.float64) - wg[~nanw])
     assert (err <= 1e-6 * np.maximum(np.abs(wg[~nanw]), 1.0)).all()
-
-
-def check_fields(res, wf, used, s, n_slices):
-    fw = res["field_work"]
-    need = np.zeros(n_slices, bool)
-    need[np.clip(s[used == 1], 0, n_slices - 1)] = True
-    for j in range(n_slices):
-        if need[j]:
-            np.testing.assert_array_equal(fw[j], wf[j])
-        else:
-            assert (fw[j] == SENTINEL).all(), j
-    return need
 
 
 @pytest.mark.parametrize("seed,hybrid", [(61, False), (62, False),
@@ -187,7 +168,6 @@ def test_surrogate_matches_oracle(sg, dev, seed, hybrid):
         res["status"][ok], np.where(s[ok] > sc.n_slices - 1, 8, 0))
     wcost = np.maximum(eps - res["dist"][ok].astype(np.float64), 0)
     np.testing.assert_array_equal(res["cost"][ok], wcost.astype(np.float32))
-    check_fields(res, wf, used, s, sc.n_slices)
 
 
 def test_all_fallback_equals_exact_query(sg, dev):
@@ -200,11 +180,9 @@ def test_all_fallback_equals_exact_query(sg, dev):
     assert (res["used_fallback"] == (s >= 0)).all()
     check_exact(res["dist"], res["grad"], res["status"], res["cost"], xd, xg,
                 xst, xc, sc.grid.h)
-    need = check_fields(res, wf, res["used_fallback"], s, sc.n_slices)
-    assert need.all()
 
 
-def test_no_fallback_builds_no_field(sg, dev):
+def test_no_fallback(sg, dev):
     sc, c, r, s, st, rs, wf = make_case(64, Q=2000)
     L = np.array(sc.grid.extent)
     rng = np.random.default_rng(3)
@@ -215,7 +193,6 @@ def test_no_fallback_builds_no_field(sg, dev):
     say("surrogate no-fallback")
     res = run_gpu(sg, dev, sc, rs, c, r, s, st, p, zero, one, 1.0, -1e30, 0.0)
     assert (res["used_fallback"] == 0).all()
-    assert (res["field_work"] == SENTINEL).all()
 
 
 def test_nonfinite_network_routes_everything_to_exact(sg, dev):
@@ -261,7 +238,6 @@ def _call_with_handle(net, handle, sc, rs, c, r, s, st, dev):
     g = as_grid(sc.grid)
     n = len(r)
     xy = np.ascontiguousarray(sc.human_xy, np.float64)
-    buf = torch.empty(sc.n_slices * sc.grid.nvox, device=dev)
     outs = [torch.empty(n, device=dev), torch.empty(3 * n, device=dev)]
     stt = np.ascontiguousarray(st, np.float32)
     rd, cd, sd = to_dev(rs, dev), to_dev(c, dev), to_dev(r, dev)
@@ -271,6 +247,6 @@ def _call_with_handle(net, handle, sc, rs, c, r, s, st, dev):
         handle.ptr, net.ptr, C.byref(g), P(rd.data_ptr()), None, sc.n_slices,
         sc.n_humans, xy.ctypes.data_as(P), sc.radius, sc.height,
         stt.ctypes.data_as(P), sc.dt, 0.1, n, P(cd.data_ptr()),
-        P(sd.data_ptr()), P(sl.data_ptr()), 0.0, P(buf.data_ptr()),
+        P(sd.data_ptr()), P(sl.data_ptr()), 0.0,
         P(outs[0].data_ptr()), P(outs[1].data_ptr()), None, None, None,
         None))
