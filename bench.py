@@ -278,8 +278,10 @@ def surrogate_section(pc, torch, dev, weights: str):
     net, meta = train.load(weights)
     sc = scenegen.room256()
     res = train.evaluate(net, sc, dev, mode=meta.get("mode", "env"))
-    # matrix-core work of the network: forward + input gradient per query
-    flop = 2 * (22 * 128 + 3 * 128 * 128 + 128) * 2 - 2 * 22 * 128
+    # algorithmic work of one query: the forward pass (22 -> 3 x 128 -> 1)
+    # and the reverse pass down to the three centre coordinates
+    flop = (2 * (22 * 128 + 3 * 128 * 128 + 128)
+            + 2 * (3 * 128 * 128 + 3 * 128))
     ms = res["mlp_forward_grad_ms_1M"]
     res["mlp_flop_per_query"] = flop
     res["mlp_tflops"] = flop * res["queries"] / (ms / 1e3) / 1e12

@@ -28,6 +28,7 @@ PER_FILE = {
     "query.hip": ["-ffp-contract=off"],
     "surrogate.hip": ["-ffp-contract=off"],
     "factors.hip": ["-ffp-contract=off"],
+    "direct.hip": ["-ffp-contract=off"],
 }
 
 

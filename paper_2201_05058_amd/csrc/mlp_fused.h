@@ -19,7 +19,9 @@
 // The rounding points are those of the layered kernels and of the oracle:
 // A_{l+1} = bf16(SiLU(Z_l)), D_l = bf16(SiLU'(Z_l)), dZ_3 = bf16(out_scale
 // W4 (.) D_3), dZ_{l-1} = bf16((dZ_l W_l) (.) D_{l-1}); y and the input
-// gradient are FP32.
+// gradient are FP32.  SiLU and SiLU' share one logistic value computed with
+// the approximate exponential and reciprocal: the epilogue of a layer is
+// VALU work of the same order as the layer's matrix products.
 #pragma once
 
 #include "mlp_kernels.h"
@@ -33,6 +35,16 @@ struct NetWeights {
   const uint16_t *W[kLayers + 1];  // W_l [128][in_pad] (W4: [128])
   const uint16_t *Wt[kLayers];     // W_l^T [in_pad][128]
 };
+
+// SiLU and its derivative from one logistic value, with the hardware's
+// approximate exponential and reciprocal (a few ulp of fp32; the results
+// are rounded to BF16 next, whose unit is 2^16 fp32 ulps).
+__device__ __forceinline__ void silu_pair(float z, float *a, float *d) {
+  const float e = __expf(-z);
+  const float sg = __builtin_amdgcn_rcpf(1.f + e);
+  *a = z * sg;
+  *d = sg * (1.f + z * (1.f - sg));
+}
 
 __device__ __forceinline__ uint16_t lo16(uint32_t v) { return (uint16_t)v; }
 __device__ __forceinline__ uint16_t hi16(uint32_t v) {
@@ -98,11 +110,13 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
           const int row = rb * 32 + acc_row(r, lane);  // r+1: row+1
-          const float z0 = acc[rb][r] + bias, z1 = acc[rb][r + 1] + bias;
-          aout[row * kTS + unit] = to_bf16(silu(z0));
-          aout[(row + 1) * kTS + unit] = to_bf16(silu(z1));
-          const uint16_t d0 = to_bf16(silu_prime(z0));
-          const uint16_t d1 = to_bf16(silu_prime(z1));
+          float a0, a1, s0, s1;
+          silu_pair(acc[rb][r] + bias, &a0, &s0);
+          silu_pair(acc[rb][r + 1] + bias, &a1, &s1);
+          aout[row * kTS + unit] = to_bf16(a0);
+          aout[(row + 1) * kTS + unit] = to_bf16(a1);
+          const uint16_t d0 = to_bf16(s0);
+          const uint16_t d1 = to_bf16(s1);
           if (l < 2) {
             dl[l][row * kTS + unit] = d0;
             dl[l][(row + 1) * kTS + unit] = d1;
@@ -112,14 +126,28 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
         }
       __syncthreads();
     }
-    // y from A4 (tile 0), one thread per row, in the layered kernel's order
-    if (threadIdx.x < kTileRows) {
-      const int64_t m = row0 + threadIdx.x;
-      const uint16_t *a = tl[0] + threadIdx.x * kTS;
+    // y from A4 (tile 0): two threads per row, 64 units each
+    {
+      const int row = threadIdx.x >> 1, half = threadIdx.x & 1;
+      const uint16_t *a = tl[0] + row * kTS + half * 64;
+      const uint16_t *w4 = w.W[kLayers] + half * 64;
       float s = 0.f;
-      for (int c = 0; c < kHid; ++c)
-        s += from_bf16(a[c]) * from_bf16(w.W[kLayers][c]);
-      if (m < n) y[m] = (s + p[layer_desc(kLayers).b_off]) * out_scale;
+#pragma unroll
+      for (int c = 0; c < 64; c += 8) {
+        const uint4 av = *reinterpret_cast<const uint4 *>(a + c);
+        const uint4 wv = *reinterpret_cast<const uint4 *>(w4 + c);
+        const uint32_t aw[4] = {av.x, av.y, av.z, av.w};
+        const uint32_t ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s += from_bf16(lo16(aw[q])) * from_bf16(lo16(ww[q]));
+          s += from_bf16(hi16(aw[q])) * from_bf16(hi16(ww[q]));
+        }
+      }
+      s += __shfl_xor(s, 1);
+      const int64_t m = row0 + row;
+      if (half == 0 && m < n)
+        y[m] = (s + p[layer_desc(kLayers).b_off]) * out_scale;
     }
     if (gx) {
       // dZ3 = bf16(out_scale W4 (.) D3) into tile 1 (A3 is consumed)
