@@ -234,12 +234,11 @@ int pcsdf_query_spheres(pcsdf_handle *h, const pcsdf_grid *grid,
  * without building them: the humans' voxels of a slice are D x {0..Kt}
  * (a disk union times the cylinders' layers), so the composite at voxel
  * (i, j, k) is min(static SSQ, the humans' value from the planar signed
- * field of D at pixel (i, j) and layer k), and the planar value of one
- * pixel is a search over the slice's chords.  Each query evaluates the
- * planar field at the four pixels of its cell and reads eight static
- * values.  Outputs, status bits and layouts as pcsdf_query_spheres, and
- * bit-identical to building the fields and sampling them.  Uses the
- * chords' workspace only. */
+ * field of D at pixel (i, j) and layer k).  Only the planar fields are
+ * built (n_slices * nx * ny values); each query reads four planar and
+ * eight static values.  Outputs, status bits and layouts as
+ * pcsdf_query_spheres, and bit-identical to building the fields and
+ * sampling them.  Uses the planes' workspace only. */
 int pcsdf_query_spheres_direct(
     pcsdf_handle *h, const pcsdf_grid *grid, const int32_t *static_ssq_dev,
     int32_t n_slices, int32_t n_humans, const double *human_xy_host,
@@ -302,9 +301,9 @@ int pcsdf_get_tuning(const pcsdf_handle *h, pcsdf_tuning *t);
 
 /* All scenes' composite fields in two persistent launches: the same
  * outputs, byte for byte, as one pcsdf_predicted_composite_sdf call per
- * scene.  A fixed grid strides over the (scene, slice) planar-field items
- * of all scenes, then a second over the (scene, slice group, voxel chunk)
- * composite items; no workgroup waits on another.  Host arrays are read
+ * scene.  A fixed grid strides over the (scene, slice, pixel tile)
+ * planar-field items of all scenes, then a second over the (scene, slice
+ * group, voxel chunk) composite items; no workgroup waits on another.  Host arrays are read
  * before the call returns.  Workspace: per scene
  * 8*n_slices*nx*ny + 8*n_slices*max(n_humans,1)*ny bytes, plus the work
  * list.  Errors as pcsdf_predicted_composite_sdf, prefixed with the scene
@@ -422,8 +421,9 @@ int pcsdf_surrogate_features_pool(pcsdf_handle *h, int32_t n_queries,
  * other queries get dist = y - r, grad = dy/dc, status = SLICE_CLAMPED or 0,
  * cost = max(0, hinge_eps_m - dist).  Queries with slice < 0 get NaN and
  * SLICE_NEG.  used_fallback_dev [n] (nullable) is 1 for exact answers,
- * which are computed as pcsdf_query_spheres_direct computes them: no field
- * is built, only the chords of the slices that some fallback query reads.
+ * which are computed as pcsdf_query_spheres_direct computes them: no 3-D
+ * field is built, only the planar fields of the slices that some fallback
+ * query reads.
  * No host synchronisation: the fallback list and the slice marks live on
  * the device.  The network must belong to handle `h`.
  * The net takes the features of pcsdf_surrogate_features; its state

@@ -26,10 +26,12 @@ int bind_device(Handle *h) {
       return fail(h, PCSDF_ERR_HIP,
                   std::string("hipDeviceGetAttribute: ") +
                       hipGetErrorString(e));
-    e = hipEventCreateWithFlags(&h->staging_done, hipEventDisableTiming);
-    if (e != hipSuccess)
-      return fail(h, PCSDF_ERR_HIP,
-                  std::string("hipEventCreate: ") + hipGetErrorString(e));
+    for (auto &sl : h->staging) {
+      e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+      if (e != hipSuccess)
+        return fail(h, PCSDF_ERR_HIP,
+                    std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
     h->max_lds = lds;
     h->device = d;
   } else if (d != h->device) {
@@ -68,35 +70,43 @@ int ensure_buffer(Handle *h, DevBuf &b, size_t bytes, hipStream_t stream) {
 }
 
 int acquire_staging(Handle *h, size_t bytes) {
-  if (h->staging_pending) {
-    hipError_t e = hipEventSynchronize(h->staging_done);
+  const int k = h->staging_next;
+  Handle::StagingSlot &sl = h->staging[k];
+  if (sl.pending) {
+    hipError_t e = hipEventSynchronize(sl.done);
     if (e != hipSuccess)
       return fail(h, PCSDF_ERR_HIP,
                   std::string("hipEventSynchronize: ") +
                       hipGetErrorString(e));
-    h->staging_pending = false;
+    sl.pending = false;
   }
-  if (h->pinned_bytes >= bytes && h->pinned) return PCSDF_OK;
-  if (h->pinned) (void)hipHostFree(h->pinned);
-  h->pinned = nullptr;
-  h->pinned_bytes = 0;
-  const size_t want = align_up(bytes > 0 ? bytes : 64, 4096);
-  hipError_t e = hipHostMalloc(&h->pinned, want, hipHostMallocDefault);
-  if (e != hipSuccess) {
-    h->pinned = nullptr;
-    (void)hipGetLastError();
-    return fail(h, PCSDF_ERR_OOM, "pinned staging allocation failed");
+  h->staging_cur = k;
+  if (!(sl.bytes >= bytes && sl.p)) {
+    if (sl.p) (void)hipHostFree(sl.p);
+    sl.p = nullptr;
+    sl.bytes = 0;
+    const size_t want = align_up(bytes > 0 ? bytes : 64, 4096);
+    hipError_t e = hipHostMalloc(&sl.p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      sl.p = nullptr;
+      h->pinned = nullptr;
+      (void)hipGetLastError();
+      return fail(h, PCSDF_ERR_OOM, "pinned staging allocation failed");
+    }
+    sl.bytes = want;
   }
-  h->pinned_bytes = want;
+  h->pinned = sl.p;
   return PCSDF_OK;
 }
 
 int release_staging(Handle *h, hipStream_t stream) {
-  hipError_t e = hipEventRecord(h->staging_done, stream);
+  Handle::StagingSlot &sl = h->staging[h->staging_cur];
+  hipError_t e = hipEventRecord(sl.done, stream);
   if (e != hipSuccess)
     return fail(h, PCSDF_ERR_HIP,
                 std::string("hipEventRecord: ") + hipGetErrorString(e));
-  h->staging_pending = true;
+  sl.pending = true;
+  h->staging_next = (h->staging_cur + 1) % Handle::kStagingSlots;
   return PCSDF_OK;
 }
 
@@ -217,7 +227,8 @@ extern "C" int pcsdf_create(pcsdf_handle **out) {
 extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return;
-  if (h->staging_pending) (void)hipEventSynchronize(h->staging_done);
+  for (auto &sl : h->staging)
+    if (sl.pending) (void)hipEventSynchronize(sl.done);
   DevBuf *bufs[] = {&h->tmp_buf,       &h->plane_buf,      &h->chord_buf,
                     &h->param_buf,     &h->stack_buf,      &h->batch_params,
                     &h->batch_scratch, &h->sur_buf,     &h->union_buf,
@@ -227,8 +238,10 @@ extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
   if (any) (void)hipDeviceSynchronize();
   for (DevBuf *b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
-  if (h->pinned) (void)hipHostFree(h->pinned);
-  if (h->staging_done) (void)hipEventDestroy(h->staging_done);
+  for (auto &sl : h->staging) {
+    if (sl.p) (void)hipHostFree(sl.p);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
   for (auto &p : h->prof_pending) {
     (void)hipEventSynchronize(p.b);
     h->prof_pool.push_back(p.a);

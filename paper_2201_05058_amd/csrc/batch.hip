@@ -307,8 +307,8 @@ extern "C" int pcsdf_autotune_batch(pcsdf_handle *hp, int32_t n_scenes,
   pcsdf_tuning win = base;
   double win_ms = -1.0;
   const int Gs[] = {1, 2, 4};
-  const int Cs[] = {2048, 8192, 32768};
-  const int Bs[] = {2, 4, 8};
+  const int Cs[] = {256, 1024, 4096};
+  const int Bs[] = {4, 8, 16};
   for (int G : Gs)
     for (int C : Cs)
       for (int B : Bs) {

@@ -28,44 +28,60 @@ struct SceneDev {
 
 constexpr int kItemPlane = 0;
 constexpr int kItemComposite = 1;
+// Pixels of one planar item when the slice's chords fit in LDS.
+constexpr int kPlaneTile = 4096;
+
+__host__ __device__ inline bool chords_in_lds(int K, int ny, int lds_cap) {
+  return K * 16 + K * ny * 8 <= lds_cap;
+}
 
 // ------------------------------------------------------------ device side
 
-__device__ inline void plane_item(const SceneDev &sc, int s, int4 *lds, int lds_cap) {
+// Planar field of slice s.  When the chords fit in LDS the slice is split
+// into tiles of kPlaneTile pixels, each an item of its own: the item
+// builds the slice's chords and boxes in LDS and evaluates its pixels, the
+// row pass of the free set being computed from the chords where a pixel
+// inside the disks needs it.  Otherwise one item does the whole slice with
+// the chords and the row pass in global memory.
+__device__ inline void plane_item(const SceneDev &sc, int s, int tile,
+                                  int4 *lds, int lds_cap) {
   const int K = sc.K, nx = sc.nx, ny = sc.ny;
   const int64_t npx = (int64_t)nx * ny;
   const int64_t *xy = sc.xy + (int64_t)s * K * 2;
   int4 *box = lds;
-  const bool in_lds = K * 16 + K * ny * 8 <= lds_cap;
-  int2 *lch = reinterpret_cast<int2 *>(lds + K);
+  const bool in_lds = chords_in_lds(K, ny, lds_cap);
+  if (in_lds) {
+    int2 *lch = reinterpret_cast<int2 *>(lds + K);
+    for (int t = threadIdx.x; t < K; t += blockDim.x)
+      box[t] = disk_box(xy[2 * t], xy[2 * t + 1], sc.R, nx, ny);
+    for (int t = threadIdx.x; t < K * ny; t += blockDim.x) {
+      const int k = t / ny, j = t - k * ny;
+      lch[t] = disk_chord(xy[2 * k], xy[2 * k + 1], sc.R, nx, j);
+    }
+    __syncthreads();
+    const LdsTab ch{lch};
+    int32_t *P = sc.P + (int64_t)s * npx;
+    const int64_t p1 = min(npx, (int64_t)(tile + 1) * kPlaneTile);
+    for (int64_t p = (int64_t)tile * kPlaneTile + threadIdx.x; p < p1;
+         p += blockDim.x) {
+      const int j = (int)(p / nx), i = (int)(p - (int64_t)j * nx);
+      P[p] = plane_value_rf(ch, box, RowFreeChords<LdsTab>{ch, K, ny, nx, i},
+                            K, nx, ny, i, j);
+    }
+    return;
+  }
   int2 *gch = sc.chords + (int64_t)s * K * ny;
   for (int t = threadIdx.x; t < K; t += blockDim.x)
     box[t] = disk_box(xy[2 * t], xy[2 * t + 1], sc.R, nx, ny);
   for (int t = threadIdx.x; t < K * ny; t += blockDim.x) {
     const int k = t / ny, j = t - k * ny;
-    const int2 c = disk_chord(xy[2 * k], xy[2 * k + 1], sc.R, nx, j);
-    if (in_lds)
-      lch[t] = c;
-    else
-      gch[t] = c;
+    gch[t] = disk_chord(xy[2 * k], xy[2 * k + 1], sc.R, nx, j);
   }
   __threadfence();
   __syncthreads();
   int32_t *f1 = sc.F1 + (int64_t)s * npx;
   int32_t *P = sc.P + (int64_t)s * npx;
-  if (in_lds) {
-    const LdsTab ch{lch};
-    for (int64_t p = threadIdx.x; p < npx; p += blockDim.x) {
-      const int j = (int)(p / nx), i = (int)(p - (int64_t)j * nx);
-      f1[p] = row_free_dist(ch, K, ny, nx, j, i);
-    }
-    __threadfence();
-    __syncthreads();
-    for (int64_t p = threadIdx.x; p < npx; p += blockDim.x) {
-      const int j = (int)(p / nx), i = (int)(p - (int64_t)j * nx);
-      P[p] = plane_value(ch, box, f1 + i, K, nx, ny, i, j);
-    }
-  } else {
+  {
     const GlobalTab ch{gch};
     for (int64_t p = threadIdx.x; p < npx; p += blockDim.x) {
       const int j = (int)(p / nx), i = (int)(p - (int64_t)j * nx);
@@ -143,7 +159,7 @@ __device__ inline void batch_planes(const SceneDev *__restrict__ scenes,
                                     int n_items, int lds_cap, int4 *lds) {
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 w = items[it];
-    plane_item(scenes[w.y], w.z, lds, lds_cap);
+    plane_item(scenes[w.y], w.z, w.w, lds, lds_cap);
     __syncthreads();  // the next item reuses the LDS
   }
 }

@@ -101,11 +101,19 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
     lds_need = std::max(lds_need, d.K * 16 + d.K * d.ny * 8);
   }
   bp->lds_cap = std::min(lds_need, 48 * 1024);
-  // items: all planar items, then all composite items, scene-major
+  // items: all planar items (tiles of a slice when its chords fit in
+  // LDS), then all composite items, scene-major
   bp->items.clear();
-  for (int q = 0; q < n_scenes; ++q)
-    for (int s = 0; s < bp->scenes[q].n; ++s)
-      bp->items.push_back(make_int4(kItemPlane, q, s, 0));
+  for (int q = 0; q < n_scenes; ++q) {
+    const SceneDev &d = bp->scenes[q];
+    const int64_t npx = (int64_t)d.nx * d.ny;
+    const int tiles = chords_in_lds(d.K, d.ny, bp->lds_cap)
+                          ? (int)((npx + kPlaneTile - 1) / kPlaneTile)
+                          : 1;
+    for (int s = 0; s < d.n; ++s)
+      for (int t = 0; t < tiles; ++t)
+        bp->items.push_back(make_int4(kItemPlane, q, s, t));
+  }
   bp->n_plane_items = (int)bp->items.size();
   for (int q = 0; q < n_scenes; ++q) {
     const SceneDev &d = bp->scenes[q];

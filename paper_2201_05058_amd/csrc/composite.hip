@@ -240,6 +240,17 @@ int composite_run(Handle *h, const pcsdf_grid *g,
   if ((rc = planes_run(h, g, n_slices, n_humans, human_xy_host, radius_m,
                        radius_per_slice, height_m, need, s, &ps_)))
     return rc;
+  ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
+  return launch_composite(h, g, static_ssq_dev, ps_.P, need, ps_.Kt,
+                          ps_.has_above, n_slices, out_ssq_dev, out_sdf_dev,
+                          s);
+}
+
+int launch_composite(Handle *h, const pcsdf_grid *g,
+                     const int32_t *static_ssq_dev, const int32_t *P,
+                     const int32_t *need, int Kt, int has_above,
+                     int32_t n_slices, int32_t *out_ssq_dev,
+                     float *out_sdf_dev, hipStream_t s) {
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int64_t V = (int64_t)nx * ny * nz;
   // Streaming epilogue over all voxels and slices.
@@ -254,15 +265,12 @@ int composite_run(Handle *h, const pcsdf_grid *g,
               : 2;
   if (G > n_slices) G = n_slices;
   while ((n_slices + G - 1) / G > 65535) ++G;
-  ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
   if (vec4)
-    launch_comp<4>(static_ssq_dev, ps_.P, need, out_ssq_dev, out_sdf_dev, nx,
-                   ny, n_slices, G, ps_.Kt, ps_.has_above, hf, (uint32_t)V,
-                   s);
+    launch_comp<4>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, nx, ny,
+                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   else
-    launch_comp<1>(static_ssq_dev, ps_.P, need, out_ssq_dev, out_sdf_dev, nx,
-                   ny, n_slices, G, ps_.Kt, ps_.has_above, hf, (uint32_t)V,
-                   s);
+    launch_comp<1>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, nx, ny,
+                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   return check_launch(h, "composite");
 }
 

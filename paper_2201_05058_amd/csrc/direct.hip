@@ -1,51 +1,35 @@
-// Exact sphere queries without building any field.
+// Exact sphere queries without building the 3-D fields.
 //
 // A query reads eight voxels of one slice's composite.  By the product
 // structure of the humans' voxels (composite.hip), the composite at voxel
 // (i, j, k) of slice s is
 //   min(S(i,j,k), human_value(P_s(i, j), k)),
-// where P_s(i, j) is the planar signed field of the slice's disk union at
-// pixel (i, j) -- a function of the slice's chords alone (plane_device.h:
-// nearest chord by row search outside the disks, nearest uncovered pixel
-// by row search inside).  So a query needs the planar value of four pixels
-// and eight reads of the static field, and the answer is bit-identical to
-// sampling the built fields (same integers, same fp32 conversion, same
-// fp64 interpolation).  Only the chords of the slices are built.
-//
-// A planner's obstacle factors read a few thousand spheres per update,
-// while the fields of all slices hold n x V voxels: answering the queries
-// directly skips almost all of the composite's memory traffic.
+// where P_s is the slice's planar signed field of the humans' disk union
+// (n_slices * nx * ny values, built by the planar kernels).  So a query
+// needs four planar values and eight static values, and its answer is
+// bit-identical to sampling the built fields (same integers, same fp32
+// conversion, same fp64 interpolation).  Only the planes are built: at
+// 256 x 256 x 128 they are 1/128 of the fields' voxels, and a planner's
+// obstacle factors read a few thousand spheres per update.
 #include <cmath>
 
 #include "device_common.h"
 #include "internal.h"
-#include "plane_device.h"
 #include "query_device.h"
 
 namespace pcsdf {
 
 struct DirectArgs {
-  const int32_t *S;     // static SSQ [V]
-  const int2 *chords;   // [n_slices][K][ny]
-  const int64_t *xy;    // fixed-point centres [n_slices][K][2]
-  const int64_t *Rs;    // fixed-point radius per slice
-  int K, n_slices, nx, ny, nz, Kt, has_above;
+  const int32_t *S;  // static SSQ [V]
+  const int32_t *P;  // planar fields [n_slices][ny][nx]
+  const uint8_t *mask;  // answer only queries with mask[q] != 0 (nullable)
+  int n_slices, nx, ny, nz, Kt, has_above;
   float hf;
   double h, ox, oy, oz, eps;
   const float *centre, *radius;
   const int32_t *slice;
   float *dist, *grad, *cost;
   uint8_t *status;
-};
-
-// Disk bounding boxes of one slice, computed when asked for.
-struct BoxesOfSlice {
-  const int64_t *xy;  // this slice's [K][2]
-  int64_t R;
-  int nx, ny;
-  __device__ __forceinline__ int4 operator[](int k) const {
-    return disk_box(xy[2 * k], xy[2 * k + 1], R, nx, ny);
-  }
 };
 
 __device__ __forceinline__ void answer_direct(const DirectArgs &A, int q) {
@@ -68,26 +52,21 @@ __device__ __forceinline__ void answer_direct(const DirectArgs &A, int q) {
   const Cell C =
       cell_of(A.nx, A.ny, A.nz, A.h, A.ox, A.oy, A.oz, A.centre + 3 * q);
   st |= C.status;
-  const GlobalTab ch{A.chords + (int64_t)s * A.K * A.ny};
-  const BoxesOfSlice box{A.xy + (int64_t)s * A.K * 2, A.Rs[s], A.nx, A.ny};
+  const int32_t *P = A.P + (int64_t)s * A.nx * A.ny;
   double c[2][2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int i = C.idx[0] + a, j = C.idx[1] + b;
-      int32_t P = kInfP;  // no human voxel in the slice
-      if (A.K > 0)
-        P = plane_value_rf(ch, box,
-                           RowFreeChords<GlobalTab>{ch, A.K, A.ny, A.nx, i},
-                           A.K, A.nx, A.ny, i, j);
+      const int32_t p = P[(int64_t)j * A.nx + i];
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int k = C.idx[2] + e;
         const int dzo = k > A.Kt ? k - A.Kt : 0;
         const int32_t dz2i =
             A.has_above ? (A.Kt + 1 - k) * (A.Kt + 1 - k) : kInf;
-        const int32_t hv = human_value(P, dzo * dzo, k <= A.Kt, dz2i);
+        const int32_t hv = human_value(p, dzo * dzo, k <= A.Kt, dz2i);
         const int32_t sv = A.S[((int64_t)k * A.ny + j) * A.nx + i];
         c[a][b][e] = (double)ssq_to_metres(min(sv, hv), A.hf);
       }
@@ -116,50 +95,40 @@ __device__ __forceinline__ void answer_direct(const DirectArgs &A, int q) {
 
 __global__ __launch_bounds__(256) void k_query_direct(DirectArgs A, int n) {
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q < n) answer_direct(A, q);
-}
-
-__global__ __launch_bounds__(256) void k_query_direct_list(
-    DirectArgs A, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ count) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t < *count) answer_direct(A, list[t]);
+  if (q < n && (!A.mask || A.mask[q])) answer_direct(A, q);
 }
 
 int direct_setup(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
                  int32_t n_slices, int32_t n_humans, const double *xy_host,
                  double radius_m, double height_m, const int32_t *need,
                  hipStream_t s, DirectSet *out) {
-  HumanSet hs;
-  int rc = humans_upload(h, g, n_slices, n_humans, xy_host, radius_m, nullptr,
-                         height_m, s, &hs);
+  PlaneSet ps;
+  int rc = planes_run(h, g, n_slices, n_humans, xy_host, radius_m, nullptr,
+                      height_m, need, s, &ps);
   if (rc) return rc;
-  ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
-  if ((rc = launch_chords(h, hs.xy, hs.K, hs.Rs, hs.chords, g->nx, g->ny,
-                          n_slices, need, s)))
-    return rc;
-  out->hs = hs;
+  out->P = ps.P;
+  out->Kt = ps.Kt;
+  out->has_above = ps.has_above;
   out->S = static_ssq;
   return PCSDF_OK;
 }
 
-static DirectArgs direct_args(const pcsdf_grid *g, const DirectSet &d,
-                              int n_slices, const float *centre,
-                              const float *radius, const int32_t *slice,
-                              double eps, float *dist, float *grad,
-                              uint8_t *status, float *cost) {
+int launch_direct(Handle *h, const pcsdf_grid *g, const DirectSet &d,
+                  int n_slices, int n_queries, const uint8_t *mask,
+                  const float *centre, const float *radius,
+                  const int32_t *slice, double eps, float *dist, float *grad,
+                  uint8_t *status, float *cost, hipStream_t s) {
+  if (n_queries <= 0) return PCSDF_OK;
   DirectArgs A;
   A.S = d.S;
-  A.chords = d.hs.chords;
-  A.xy = d.hs.xy;
-  A.Rs = d.hs.Rs;
-  A.K = d.hs.K;
+  A.P = d.P;
+  A.mask = mask;
   A.n_slices = n_slices;
   A.nx = g->nx;
   A.ny = g->ny;
   A.nz = g->nz;
-  A.Kt = d.hs.Kt;
-  A.has_above = d.hs.has_above;
+  A.Kt = d.Kt;
+  A.has_above = d.has_above;
   A.hf = (float)g->voxel_m;
   A.h = g->voxel_m;
   A.ox = g->origin_m[0];
@@ -173,23 +142,9 @@ static DirectArgs direct_args(const pcsdf_grid *g, const DirectSet &d,
   A.grad = grad;
   A.cost = cost;
   A.status = status;
-  return A;
-}
-
-int launch_direct_list(Handle *h, const pcsdf_grid *g, const DirectSet &d,
-                       int n_slices, const int32_t *list,
-                       const int32_t *count, int max_count,
-                       const float *centre, const float *radius,
-                       const int32_t *slice, double eps, float *dist,
-                       float *grad, uint8_t *status, float *cost,
-                       hipStream_t s) {
-  if (max_count <= 0) return PCSDF_OK;
-  const DirectArgs A = direct_args(g, d, n_slices, centre, radius, slice, eps,
-                                   dist, grad, status, cost);
-  hipLaunchKernelGGL(k_query_direct_list,
-                     dim3((unsigned)((max_count + 255) / 256)), dim3(256), 0,
-                     s, A, list, count);
-  return check_launch(h, "direct query list");
+  hipLaunchKernelGGL(k_query_direct, dim3((unsigned)((n_queries + 255) / 256)),
+                     dim3(256), 0, s, A, n_queries);
+  return check_launch(h, "direct query");
 }
 
 }  // namespace pcsdf
@@ -228,12 +183,8 @@ extern "C" int pcsdf_query_spheres_direct(
   if ((rc = direct_setup(h, g, static_ssq_dev, n_slices, n_humans,
                          human_xy_host, radius_m, height_m, nullptr, s, &d)))
     return rc;
-  if (n_queries == 0) return PCSDF_OK;
-  const DirectArgs A =
-      direct_args(g, d, n_slices, centre_dev, radius_dev, slice_dev,
-                  hinge_eps_m, dist_dev, grad_dev, status_dev, cost_dev);
   ProfScope pq(h, PCSDF_KERNEL_QUERY, s);
-  hipLaunchKernelGGL(k_query_direct, dim3((unsigned)((n_queries + 255) / 256)),
-                     dim3(256), 0, s, A, n_queries);
-  return check_launch(h, "direct query");
+  return launch_direct(h, g, d, n_slices, n_queries, nullptr, centre_dev,
+                       radius_dev, slice_dev, hinge_eps_m, dist_dev, grad_dev,
+                       status_dev, cost_dev, s);
 }

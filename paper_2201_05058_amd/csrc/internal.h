@@ -40,11 +40,19 @@ struct Handle {
   DevBuf tmpl_buf;      // shifted-template composite: per-human windows
   std::vector<char> batch_host;  // batch parameter block before upload
   pcsdf_tuning tuning = {0, 0, 0, 0};  // launch shapes; 0 = default
-  // pinned host staging for small per-call parameter blocks
-  void *pinned = nullptr;
-  size_t pinned_bytes = 0;
-  hipEvent_t staging_done = nullptr;
-  bool staging_pending = false;
+  // pinned host staging for small per-call parameter blocks: a ring of
+  // slots, so that a call only waits for the upload made kStagingSlots
+  // calls before it
+  static constexpr int kStagingSlots = 4;
+  struct StagingSlot {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  };
+  StagingSlot staging[kStagingSlots];
+  int staging_next = 0, staging_cur = 0;
+  void *pinned = nullptr;  // the slot acquired by the current call
   std::vector<int64_t> host_xy;  // fixed-point centres before upload
   // kernel timing with HIP events on the launch stream (off by default)
   bool prof_on = false;
@@ -84,10 +92,11 @@ int bind_device(Handle *h);
 // allocation that work already enqueued may still use.
 int ensure_buffer(Handle *h, DevBuf &b, size_t bytes, hipStream_t stream);
 
-// Pinned staging buffer for an H2D parameter upload: waits until the
-// previous upload from it has completed, then guarantees `bytes`.
+// Pinned staging buffer (h->pinned) for an H2D parameter upload: the next
+// slot of the ring, after the upload last made from it has completed, with
+// at least `bytes`.
 int acquire_staging(Handle *h, size_t bytes);
-// Marks the staging buffer as in use by work enqueued on `stream`.
+// Marks the acquired slot as in use by work enqueued on `stream`.
 int release_staging(Handle *h, hipStream_t stream);
 
 // Checks the last launch; on failure records the HIP error.
@@ -163,6 +172,15 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
                const double *radius_per_slice, double height_m,
                const int32_t *need, hipStream_t s, PlaneSet *out);
 
+// The streaming epilogue alone: outputs of every slice (with `need`, of
+// the marked slices) from the static field and the planar fields P
+// [n_slices][ny][nx] of the humans (cylinder layers 0..Kt).
+int launch_composite(Handle *h, const pcsdf_grid *g,
+                     const int32_t *static_ssq_dev, const int32_t *P,
+                     const int32_t *need, int Kt, int has_above,
+                     int32_t n_slices, int32_t *out_ssq_dev,
+                     float *out_sdf_dev, hipStream_t s);
+
 // The whole predicted-composite call (validation, planes, streaming
 // epilogue).  With `need` (device int32 [n_slices]) only the slices whose
 // entry is non-zero are computed and written; the other slices of the
@@ -175,25 +193,25 @@ int composite_run(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
 
 // ---- implemented in direct.hip -----------------------------------------
 
-// Exact queries straight from the chords and the static field (no field
-// is built): the humans uploaded and the chords of the slices with a
-// non-zero `need` entry (all when null) built.
+// Exact queries from the planar fields and the static field (no 3-D field
+// is built): the planes of the slices with a non-zero `need` entry (all
+// when null) are built into the handle's plane buffer.
 struct DirectSet {
-  HumanSet hs;
+  const int32_t *P;  // planar fields [n_slices][ny][nx]
   const int32_t *S;  // static SSQ
+  int Kt, has_above;
 };
 int direct_setup(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
                  int32_t n_slices, int32_t n_humans, const double *xy_host,
                  double radius_m, double height_m, const int32_t *need,
                  hipStream_t s, DirectSet *out);
-// Exact queries for list[0 .. *count) (grid sized for max_count).
-int launch_direct_list(Handle *h, const pcsdf_grid *g, const DirectSet &d,
-                       int n_slices, const int32_t *list,
-                       const int32_t *count, int max_count,
-                       const float *centre, const float *radius,
-                       const int32_t *slice, double eps, float *dist,
-                       float *grad, uint8_t *status, float *cost,
-                       hipStream_t s);
+// Exact queries [0, n_queries), only those with mask[q] != 0 when a mask
+// is given (device uint8 [n_queries]).
+int launch_direct(Handle *h, const pcsdf_grid *g, const DirectSet &d,
+                  int n_slices, int n_queries, const uint8_t *mask,
+                  const float *centre, const float *radius,
+                  const int32_t *slice, double eps, float *dist, float *grad,
+                  uint8_t *status, float *cost, hipStream_t s);
 
 // ---- implemented in query.hip ------------------------------------------
 

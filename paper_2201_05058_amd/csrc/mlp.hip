@@ -11,6 +11,9 @@
 namespace pcsdf {
 
 constexpr int kChunk = 1024;  // rows per weight-gradient chunk
+// 32-row blocks per wave in fused inference: 2 fits two workgroups per CU
+// (70 KB of LDS each), 4 halves the weight reads per row.
+constexpr int kInferRowBlocks = 2;
 constexpr int kWofs[5] = {0, 4096, 20480, 36864, 53248};
 constexpr int kWbfTotal = 53376;
 
@@ -302,10 +305,11 @@ extern "C" int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
   NetWeights w;
   for (int l = 0; l <= kLayers; ++l) w.W[l] = wb(m, l);
   for (int l = 0; l < kLayers; ++l) w.Wt[l] = wtb(m, l);
-  const int tiles = (n + kTileRows - 1) / kTileRows;
-  const int grid = tiles < 1024 ? tiles : 1024;
+  constexpr int RB = kInferRowBlocks;
+  const int tiles = (n + 32 * RB - 1) / (32 * RB);
+  const int grid = tiles < 2048 ? tiles : 2048;
   ProfScope ps(m->h, PCSDF_KERNEL_MLP, s);
-  hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, s, x_dev, n,
+  hipLaunchKernelGGL(k_mlp_infer<RB>, dim3(grid), dim3(256), 0, s, x_dev, n,
                      reinterpret_cast<const float *>(m->norm.ptr), w, pf(m),
                      m->out_scale, y_dev, grad_x_dev, tiles);
   return check_launch(m->h, "mlp inference");

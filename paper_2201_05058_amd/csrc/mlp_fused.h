@@ -28,7 +28,6 @@
 
 namespace pcsdf {
 
-constexpr int kTileRows = 128;
 constexpr int kTS = kHid + 8;  // LDS row stride of a tile (bf16 elements)
 
 struct NetWeights {
@@ -46,19 +45,30 @@ __device__ __forceinline__ void silu_pair(float z, float *a, float *d) {
   *d = sg * (1.f + z * (1.f - sg));
 }
 
+// Two fp32 values to BF16 by round-to-nearest-even in one hardware
+// conversion (the same rounding as to_bf16 for finite values): a in the
+// low half, b in the high half.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cvt2(float a, float b) {
+  const f32x2_t v = {a, b};
+  const bf16x2_t r = __builtin_convertvector(v, bf16x2_t);
+  return __builtin_bit_cast(uint32_t, r);
+}
+
 __device__ __forceinline__ uint16_t lo16(uint32_t v) { return (uint16_t)v; }
 __device__ __forceinline__ uint16_t hi16(uint32_t v) {
   return (uint16_t)(v >> 16);
 }
 
 // acc[rb] = A_tile[rb rows] x B^T for this wave's 32 units: A from LDS
-// ([128][kTS], K columns used), B [128][K] in global memory, row `unit`.
-template <int K>
+// ([32 RB][kTS], K columns used), B [128][K] in global memory, row `unit`.
+template <int K, int RB>
 __device__ __forceinline__ void tile_gemm(const uint16_t *a_lds,
                                           const uint16_t *__restrict__ B,
-                                          int unit, int lane, f32x16 acc[4]) {
+                                          int unit, int lane, f32x16 acc[RB]) {
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
   const uint16_t *brow = B + (size_t)unit * K + 8 * (lane >> 5);
@@ -69,15 +79,18 @@ __device__ __forceinline__ void tile_gemm(const uint16_t *a_lds,
 #pragma unroll
   for (int ks = 0; ks < K / 16; ++ks)
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
       acc[rb] = mfma(load8(arow + rb * 32 * kTS + ks * 16), bv[ks], acc[rb]);
 }
 
-// y [n] and, when gx is given, dy/dx [n][22] for rows [0, n).
-__global__ __launch_bounds__(256, 1) void k_mlp_infer(
+// y [n] and, when gx is given, dy/dx [n][22] for rows [0, n), in tiles of
+// 32 RB rows (RB row blocks per wave).
+template <int RB>
+__global__ __launch_bounds__(256, RB == 4 ? 1 : 2) void k_mlp_infer(
     const float *__restrict__ x, int n, const float *__restrict__ norm,
     NetWeights w, const float *__restrict__ p, float out_scale,
     float *__restrict__ y, float *__restrict__ gx, int tiles) {
+  constexpr int kTileRows = 32 * RB;
   __shared__ uint16_t tl[2][kTileRows * kTS];
   __shared__ uint16_t dl[2][kTileRows * kTS];  // D_0, D_1
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -94,40 +107,39 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
                              : (uint16_t)0;
     }
     __syncthreads();
-    uint32_t D[2][4][8];  // bf16 SiLU' of layers 2, 3 for this wave, 2 a word
-    f32x16 acc[4];
+    uint32_t D[2][RB][8];  // bf16 SiLU' of layers 2, 3 for this wave, 2 a word
+    f32x16 acc[RB];
     // forward: layer l reads tile l&1 and writes tile (l+1)&1
 #pragma unroll
     for (int l = 0; l < kLayers; ++l) {
       if (l == 0)
-        tile_gemm<kInPad>(tl[0], w.W[0], unit, lane, acc);
+        tile_gemm<kInPad, RB>(tl[0], w.W[0], unit, lane, acc);
       else
-        tile_gemm<kHid>(tl[l & 1], w.W[l], unit, lane, acc);
+        tile_gemm<kHid, RB>(tl[l & 1], w.W[l], unit, lane, acc);
       uint16_t *aout = tl[(l + 1) & 1];
       const float bias = p[layer_desc(l).b_off + unit];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
           const int row = rb * 32 + acc_row(r, lane);  // r+1: row+1
           float a0, a1, s0, s1;
           silu_pair(acc[rb][r] + bias, &a0, &s0);
           silu_pair(acc[rb][r + 1] + bias, &a1, &s1);
-          aout[row * kTS + unit] = to_bf16(a0);
-          aout[(row + 1) * kTS + unit] = to_bf16(a1);
-          const uint16_t d0 = to_bf16(s0);
-          const uint16_t d1 = to_bf16(s1);
+          const uint32_t av = cvt2(a0, a1), dv = cvt2(s0, s1);
+          aout[row * kTS + unit] = lo16(av);
+          aout[(row + 1) * kTS + unit] = hi16(av);
           if (l < 2) {
-            dl[l][row * kTS + unit] = d0;
-            dl[l][(row + 1) * kTS + unit] = d1;
+            dl[l][row * kTS + unit] = lo16(dv);
+            dl[l][(row + 1) * kTS + unit] = hi16(dv);
           } else {
-            D[l - 2][rb][r >> 1] = (uint32_t)d0 | ((uint32_t)d1 << 16);
+            D[l - 2][rb][r >> 1] = dv;
           }
         }
       __syncthreads();
     }
     // y from A4 (tile 0): two threads per row, 64 units each
-    {
+    if (threadIdx.x < 2 * kTileRows) {
       const int row = threadIdx.x >> 1, half = threadIdx.x & 1;
       const uint16_t *a = tl[0] + row * kTS + half * 64;
       const uint16_t *w4 = w.W[kLayers] + half * 64;
@@ -153,23 +165,25 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
       // dZ3 = bf16(out_scale W4 (.) D3) into tile 1 (A3 is consumed)
       const float da3 = out_scale * from_bf16(w.W[kLayers][unit]);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
           const int row = rb * 32 + acc_row(r, lane);
           const uint32_t d = D[1][rb][r >> 1];
-          tl[1][row * kTS + unit] = to_bf16(da3 * from_bf16(lo16(d)));
-          tl[1][(row + 1) * kTS + unit] = to_bf16(da3 * from_bf16(hi16(d)));
+          const uint32_t zv = cvt2(da3 * from_bf16(lo16(d)),
+                                   da3 * from_bf16(hi16(d)));
+          tl[1][row * kTS + unit] = lo16(zv);
+          tl[1][(row + 1) * kTS + unit] = hi16(zv);
         }
       __syncthreads();
       // dZ_{l-1} = bf16((dZ_l W_l) (.) D_{l-1}): layer l reads tile l&1,
       // writes tile (l+1)&1
 #pragma unroll
       for (int l = kLayers - 1; l >= 1; --l) {
-        tile_gemm<kHid>(tl[l & 1], w.Wt[l], unit, lane, acc);
+        tile_gemm<kHid, RB>(tl[l & 1], w.Wt[l], unit, lane, acc);
         uint16_t *zout = tl[(l + 1) & 1];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
           for (int r = 0; r < 16; r += 2) {
             const int row = rb * 32 + acc_row(r, lane);
@@ -182,13 +196,16 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
               d0 = dl[l - 1][row * kTS + unit];
               d1 = dl[l - 1][(row + 1) * kTS + unit];
             }
-            zout[row * kTS + unit] = to_bf16(acc[rb][r] * from_bf16(d0));
-            zout[(row + 1) * kTS + unit] =
-                to_bf16(acc[rb][r + 1] * from_bf16(d1));
+            const uint32_t zv = cvt2(acc[rb][r] * from_bf16(d0),
+                                     acc[rb][r + 1] * from_bf16(d1));
+            zout[row * kTS + unit] = lo16(zv);
+            zout[(row + 1) * kTS + unit] = hi16(zv);
           }
         __syncthreads();
       }
-      // dy/dx = (dZ0 W0) * scale: wave w forms row block w, columns 0..31
+      // dy/dx = (dZ0 W0) * scale: wave w < RB forms row block w, columns
+      // 0..31
+      if (wave < RB) {
       f32x16 g;
 #pragma unroll
       for (int r = 0; r < 16; ++r) g[r] = 0.f;
@@ -207,6 +224,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
           const int64_t m = row0 + wave * 32 + acc_row(r, lane);
           if (m < n) gx[m * kIn + col] = g[r] * sc;
         }
+      }
       }
     }
     __syncthreads();  // the tiles are reused by the next tile of rows

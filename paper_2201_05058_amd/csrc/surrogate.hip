@@ -20,10 +20,9 @@
 //                 (slice clamped to the horizon as for exact queries);
 //   2. network:   value and input gradient (mlp.hip);
 //   3. decide:    surrogate answers are written out; fallback queries are
-//                 appended to a compact list (wave ballot + one atomic per
-//                 wave) and their slices marked as needed;
-//   4. chords:    the humans' chords of the marked slices only;
-//   5. exact:     the fallback list answered exactly from the chords and
+//                 flagged and their slices marked as needed;
+//   4. planes:    the humans' planar fields of the marked slices only;
+//   5. exact:     the flagged queries answered exactly from the planes and
 //                 the static field (direct.hip), without building a field.
 #include <cmath>
 #include <cstring>
@@ -93,10 +92,20 @@ struct DecideArgs {
   float margin;
   float *dist, *grad, *cost;
   uint8_t *status, *used;
-  int32_t *list, *count, *need;
+  int32_t *need;
 };
 
+// Slices a workgroup marks in LDS before marking them in global memory.
+constexpr int kNeedBits = 1024;
+
+// Decides every query: writes the network's answers, marks fallback
+// queries in `used` and their slices in `need` (through an LDS bitmap, so
+// that each workgroup writes each needed slice once; no atomics on global
+// memory).
 __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
+  __shared__ uint32_t bits[kNeedBits / 32];
+  for (int t = threadIdx.x; t < kNeedBits / 32; t += 256) bits[t] = 0u;
+  __syncthreads();
   const int q = blockIdx.x * 256 + threadIdx.x;
   bool fb = false;
   if (q < A.n) {
@@ -154,23 +163,17 @@ __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
           A.status[q] = (uint8_t)(s != sc ? PCSDF_Q_SLICE_CLAMPED : 0);
       } else {
         fb = true;
-        A.need[sc] = 1;
+        if (sc < kNeedBits)
+          atomicOr(&bits[sc >> 5], 1u << (sc & 31));
+        else
+          A.need[sc] = 1;
       }
-      if (A.used) A.used[q] = fb ? 1 : 0;
+      A.used[q] = fb ? 1 : 0;
     }
   }
-  // Append the wave's fallback queries to the list with one atomic.
-  const uint64_t mask = __ballot(fb);
-  if (mask == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(A.count, __popcll(mask));
-  base = __shfl(base, leader);
-  if (fb) {
-    const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
-    A.list[base + __popcll(below)] = q;
-  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kNeedBits && t < A.n_slices; t += 256)
+    if (bits[t >> 5] & (1u << (t & 31))) A.need[t] = 1;
 }
 
 static unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -294,27 +297,29 @@ extern "C" int pcsdf_query_spheres_surrogate(
   if ((rc = bind_device(h))) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
-  // workspace: x [n][22], gx [n][22], y [n], list [n], count, need [n_slices]
+  // workspace: x [n][22], gx [n][22], y [n], used [n], need [n_slices]
   const size_t n = (size_t)n_queries;
   const size_t bx = align_up(n * kNetIn * 4, 256);
   const size_t by = align_up(n * 4, 256);
-  const size_t bctl = align_up((1 + (size_t)n_slices) * 4, 256);
-  if ((rc = ensure_buffer(h, h->sur_buf, 2 * bx + 2 * by + bctl, s)))
+  const size_t bu = align_up(n, 256);
+  const size_t bneed = align_up((size_t)n_slices * 4, 256);
+  if ((rc = ensure_buffer(h, h->sur_buf, 2 * bx + by + bu + bneed, s)))
     return rc;
   char *base = reinterpret_cast<char *>(h->sur_buf.ptr);
   float *x = reinterpret_cast<float *>(base);
   float *gx = reinterpret_cast<float *>(base + bx);
   float *y = reinterpret_cast<float *>(base + 2 * bx);
-  int32_t *list = reinterpret_cast<int32_t *>(base + 2 * bx + by);
-  int32_t *ctl = reinterpret_cast<int32_t *>(base + 2 * bx + 2 * by);
-  int32_t *count = ctl, *need = ctl + 1;
+  uint8_t *used = used_fallback_dev
+                      ? used_fallback_dev
+                      : reinterpret_cast<uint8_t *>(base + 2 * bx + by);
+  int32_t *need = reinterpret_cast<int32_t *>(base + 2 * bx + by + bu);
 
   if ((rc = pcsdf_surrogate_features(hp, n_queries, centre_dev, slice_dev,
                                      n_slices, dt_s, state_host, x, stream)))
     return rc;
   if ((rc = pcsdf_mlp_forward(m, n_queries, x, y, gx, stream))) return rc;
-  hipLaunchKernelGGL(k_clear, dim3(nblocks(1 + n_slices)), dim3(256), 0, s,
-                     ctl, 1 + n_slices);
+  hipLaunchKernelGGL(k_clear, dim3(nblocks(n_slices)), dim3(256), 0, s, need,
+                     n_slices);
   DecideArgs A;
   A.y = y;
   A.gx = gx;
@@ -337,23 +342,21 @@ extern "C" int pcsdf_query_spheres_surrogate(
   A.grad = grad_dev;
   A.cost = cost_dev;
   A.status = status_dev;
-  A.used = used_fallback_dev;
-  A.list = list;
-  A.count = count;
+  A.used = used;
   A.need = need;
   {
     ProfScope ps(h, PCSDF_KERNEL_SURROGATE_DECIDE, s);
     hipLaunchKernelGGL(k_decide, dim3(nblocks(n_queries)), dim3(256), 0, s, A);
     if ((rc = check_launch(h, "surrogate decide"))) return rc;
   }
-  // The exact answers of the fallback list, straight from the chords of
-  // the slices they read and the static field.
+  // The exact answers of the fallback queries, from the planes of the
+  // slices they read and the static field.
   DirectSet d;
   if ((rc = direct_setup(h, g, static_ssq_dev, n_slices, n_humans,
                          human_xy_host, radius_m, height_m, need, s, &d)))
     return rc;
   ProfScope pq(h, PCSDF_KERNEL_QUERY, s);
-  return launch_direct_list(h, g, d, n_slices, list, count, n_queries,
-                            centre_dev, radius_dev, slice_dev, hinge_eps_m,
-                            dist_dev, grad_dev, status_dev, cost_dev, s);
+  return launch_direct(h, g, d, n_slices, n_queries, used, centre_dev,
+                       radius_dev, slice_dev, hinge_eps_m, dist_dev, grad_dev,
+                       status_dev, cost_dev, s);
 }

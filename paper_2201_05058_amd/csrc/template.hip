@@ -13,9 +13,10 @@
 // the whole number of voxels nearest to the human's displacement since the
 // first slice, and the composite is
 //   min(static, min over humans of the shifted templates),
-// a human contributing nothing where its window does not reach.  The
-// per-voxel work is a streaming epilogue with one cached template read per
-// human; no per-slice EDT runs.
+// a human contributing nothing where its window does not reach.  Per
+// slice the shifted templates are reduced to one plane (a min over humans
+// per pixel), and the voxels stream through the composite's epilogue; no
+// per-slice EDT runs.
 //
 // With whole-voxel motion, humans apart from each other and cylinders
 // inside the grid, this equals the exact per-slice composite; otherwise it
@@ -31,43 +32,30 @@
 
 namespace pcsdf {
 
-// T [K][Wy][Wx] planar templates; base [n_slices][K] = (b_x, b_y): grid
-// pixel (i, j) of slice s reads template pixel (i - b_x, j - b_y).
-template <bool kSsq, bool kSdf>
-__global__ __launch_bounds__(256) void k_template(
-    const int32_t *__restrict__ S, const int32_t *__restrict__ T,
-    const int2 *__restrict__ base, int K, int Wx, int Wy,
-    int32_t *__restrict__ oc, float *__restrict__ of, uint32_t nx,
-    uint32_t ny, int n_slices, int G, int Kt, int has_above, float hf,
-    uint32_t V) {
-  const uint32_t v = blockIdx.x * 256u + threadIdx.x;
-  if (v >= V) return;
-  const int s_begin = (int)blockIdx.y * G;
-  const int s_end = min(n_slices, s_begin + G);
-  const uint32_t row = v / nx;
-  const int i = (int)(v - row * nx);
-  const uint32_t k = row / ny;
-  const int j = (int)(row - k * ny);
-  const int kk = (int)k;
-  const int dzo = kk > Kt ? kk - Kt : 0;
-  const int dz2o = dzo * dzo;
-  const bool zin = kk <= Kt;
-  const int32_t dz2i = has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : kInf;
-  const int32_t sv = S[v];
+// P[s][j][i] = min over humans q of T_q[j - b_y][i - b_x] (INT32_MAX where
+// no window reaches), with T [K][Wy][Wx] the planar templates and base
+// [n_slices][K] = (b_x, b_y) the shifted windows.  The humans' value of a
+// voxel is non-decreasing in its planar value, so the min over humans of
+// their 3-D values is the 3-D value of this planar min, and the composite
+// then streams exactly as for the per-slice planes.
+__global__ __launch_bounds__(256) void k_template_planes(
+    const int32_t *__restrict__ T, const int2 *__restrict__ base, int K,
+    int Wx, int Wy, int nx, int ny, int64_t total, int32_t *__restrict__ P) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const int64_t row = t / nx;  // s*ny + j
+  const int i = (int)(t - row * nx);
+  const int s = (int)(row / ny);
+  const int j = (int)(row - (int64_t)s * ny);
   const size_t wplane = (size_t)Wx * Wy;
-  for (int sl = s_begin; sl < s_end; ++sl) {
-    int32_t c = sv;
-    for (int q = 0; q < K; ++q) {
-      const int2 b = base[sl * K + q];
-      const int tu = i - b.x, tv = j - b.y;
-      if (tu < 0 || tu >= Wx || tv < 0 || tv >= Wy) continue;
-      const int32_t p = T[q * wplane + (size_t)tv * Wx + tu];
-      c = min(c, human_value(p, dz2o, zin, dz2i));
-    }
-    const size_t o = (size_t)sl * V + v;
-    if (kSsq) oc[o] = c;
-    if (kSdf) of[o] = ssq_to_metres(c, hf);
+  int32_t m = kInf;
+  for (int q = 0; q < K; ++q) {
+    const int2 b = base[s * K + q];
+    const int tu = i - b.x, tv = j - b.y;
+    if (tu < 0 || tu >= Wx || tv < 0 || tv >= Wy) continue;
+    m = min(m, T[q * wplane + (size_t)tv * Wx + tu]);
   }
+  P[t] = m;
 }
 
 static bool to_fixed_t(double p, double o, double h, int64_t *out) {
@@ -194,37 +182,26 @@ extern "C" int pcsdf_template_composite_sdf(
     return fail(h, PCSDF_ERR_HIP, "upload of the template parameters failed");
   if ((rc = release_staging(h, s))) return rc;
   int32_t *T = reinterpret_cast<int32_t *>(h->tmpl_buf.ptr);
-  if (K > 0) {
-    // one "slice" per human: its single disk in its window
-    ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
-    if ((rc = launch_planes(h, dev, 1, dev + 2 * K, false,
-                            reinterpret_cast<int2 *>(h->chord_buf.ptr), T, Wx,
-                            Wy, K, nullptr, s)))
-      return rc;
-  }
   const int2 *bases_dev = reinterpret_cast<const int2 *>(dev + 3 * K);
-  int G = h->tuning.composite_slices_per_block > 0
-              ? h->tuning.composite_slices_per_block
-              : 2;
-  if (G > n_slices) G = n_slices;
-  while ((n_slices + G - 1) / G > 65535) ++G;
-  const dim3 grid((unsigned)((V + 255) / 256), (unsigned)((n_slices + G - 1) / G));
-  const float hf = (float)hv;
+  const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
+  if ((rc = ensure_buffer(h, h->plane_buf, plane_bytes, s))) return rc;
+  int32_t *P = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
+  {
+    ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
+    if (K > 0) {
+      // one "slice" per human: its single disk in its window
+      if ((rc = launch_planes(h, dev, 1, dev + 2 * K, false,
+                              reinterpret_cast<int2 *>(h->chord_buf.ptr), T,
+                              Wx, Wy, K, nullptr, s)))
+        return rc;
+    }
+    const int64_t total = (int64_t)n_slices * nx * ny;
+    hipLaunchKernelGGL(k_template_planes,
+                       dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       T, bases_dev, K, Wx, Wy, nx, ny, total, P);
+    if ((rc = check_launch(h, "template planes"))) return rc;
+  }
   ProfScope ps(h, PCSDF_KERNEL_TEMPLATE, s);
-  if (out_ssq_dev && out_sdf_dev)
-    hipLaunchKernelGGL((k_template<true, true>), grid, dim3(256), 0, s,
-                       static_ssq_dev, T, bases_dev, K, Wx, Wy, out_ssq_dev,
-                       out_sdf_dev, (uint32_t)nx, (uint32_t)ny, n_slices, G,
-                       Kt, has_above, hf, (uint32_t)V);
-  else if (out_ssq_dev)
-    hipLaunchKernelGGL((k_template<true, false>), grid, dim3(256), 0, s,
-                       static_ssq_dev, T, bases_dev, K, Wx, Wy, out_ssq_dev,
-                       out_sdf_dev, (uint32_t)nx, (uint32_t)ny, n_slices, G,
-                       Kt, has_above, hf, (uint32_t)V);
-  else
-    hipLaunchKernelGGL((k_template<false, true>), grid, dim3(256), 0, s,
-                       static_ssq_dev, T, bases_dev, K, Wx, Wy, out_ssq_dev,
-                       out_sdf_dev, (uint32_t)nx, (uint32_t)ny, n_slices, G,
-                       Kt, has_above, hf, (uint32_t)V);
-  return check_launch(h, "template composite");
+  return launch_composite(h, g, static_ssq_dev, P, nullptr, Kt, has_above,
+                          n_slices, out_ssq_dev, out_sdf_dev, s);
 }
