@@ -34,12 +34,15 @@ COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
 
 def source_hash(path: str) -> str:
     """Hash of the composite kernel's own source text (the k_composite
-    template), so host-side edits of the file keep a measurement valid."""
+    template and the shared epilogue in composite_device.h), so host-side
+    edits of composite.hip keep a measurement valid."""
     with open(path) as f:
         src = f.read()
     a = src.find("template <int VEC, bool kSsq, bool kSdf>")
     b = src.find("template <int VEC>", a)
     text = src[a:b] if a >= 0 and b > a else src
+    with open(os.path.join(os.path.dirname(path), "composite_device.h")) as f:
+        text += f.read()
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
@@ -110,8 +113,10 @@ def cpu_baseline(sc, max_slices: int):
 def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
     """64 uneven scenes (5-30 slices, 1-4 humans, grids 64..256 x 64..256 x
     64..128 at 0.02-0.05 m): one captured hipGraph replay of the batch
-    against 64 plain calls on one stream, same outputs.  Static fields are
-    built before timing."""
+    against 64 plain calls on one stream, same outputs, by wall time and by
+    GPU time (the plain calls' wall time includes the host's per-call
+    work).  Static fields are built before timing."""
+    from paper_2201_05058_amd import _native
     scs = scenegen.batch64()
     h = pc.Handle()
     scenes = []
@@ -151,10 +156,24 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
 
     g_ms = timed(graph.launch)
     p_ms = timed(plain_all)
+    # GPU time alone (HIP events on the stream around each library call):
+    # the plain calls' wall time also holds the host's per-call work
+    h.profile(True)
+    h.profile_reset()
+    timed(graph.launch)
+    g_gpu = h.profile_read(_native.KERNEL_BATCH)[0] / (reps + 1)
+    h.profile_reset()
+    timed(plain_all)
+    p_gpu = sum(h.profile_read(k)[0] for k in (_native.KERNEL_PLANES,
+                                               _native.KERNEL_COMPOSITE))
+    p_gpu /= reps + 1
+    h.profile(False)
     graph.close()
     h.close()
     return {"scenes": len(scs), "voxel_slices": vs,
             "graph_ms": g_ms, "plain_64_calls_ms": p_ms,
+            "graph_gpu_ms": g_gpu, "plain_64_calls_gpu_ms": p_gpu,
+            "speedup_vs_plain_gpu": p_gpu / g_gpu,
             "graph_voxel_slices_per_s": vs / (g_ms / 1e3),
             "plain_voxel_slices_per_s": vs / (p_ms / 1e3),
             "speedup_vs_plain": p_ms / g_ms,

@@ -64,7 +64,7 @@ enum pcsdf_status_code {
 #define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (two kernels) */
 #define PCSDF_KERNEL_QUERY 2     /* sphere query kernel */
 #define PCSDF_KERNEL_STATIC 3    /* the three passes of the static build */
-#define PCSDF_KERNEL_BATCH 4     /* a batch: both persistent launches */
+#define PCSDF_KERNEL_BATCH 4     /* a batch: both of its launches */
 #define PCSDF_KERNEL_MLP 5       /* surrogate forward (+ input gradient) */
 #define PCSDF_KERNEL_MLP_TRAIN 6 /* one surrogate training step */
 #define PCSDF_KERNEL_SURROGATE_DECIDE 7 /* surrogate accept / fallback split */
@@ -292,28 +292,31 @@ typedef struct pcsdf_tuning {
   int32_t batch_slices_per_item;      /* batch: slices per composite item */
   int32_t batch_chunk_quads;          /* batch: voxel quads per composite
                                          item, a multiple of 256 */
-  int32_t batch_blocks_per_cu;        /* batch: persistent workgroups per CU,
-                                         at most 32 */
+  int32_t batch_blocks_per_cu;        /* batch: persistent workgroups per CU
+                                         of both launches, at most 32; 0:
+                                         8 per CU for the planar items and
+                                         one workgroup per composite item */
 } pcsdf_tuning;
 
 int pcsdf_set_tuning(pcsdf_handle *h, const pcsdf_tuning *t);
 int pcsdf_get_tuning(const pcsdf_handle *h, pcsdf_tuning *t);
 
-/* All scenes' composite fields in two persistent launches: the same
- * outputs, byte for byte, as one pcsdf_predicted_composite_sdf call per
- * scene.  A fixed grid strides over the (scene, slice, pixel tile)
- * planar-field items of all scenes, then a second over the (scene, slice
- * group, voxel chunk) composite items; no workgroup waits on another.  Host arrays are read
+/* All scenes' composite fields in two launches: the same outputs, byte
+ * for byte, as one pcsdf_predicted_composite_sdf call per scene.  A
+ * persistent grid strides over the (scene, slice, pixel tile) planar-field
+ * items of all scenes; then the (scene, slice group, voxel chunk)
+ * composite items run one per workgroup or under a persistent grid (see
+ * pcsdf_tuning); no workgroup waits on another.  Host arrays are read
  * before the call returns.  Workspace: per scene
  * 8*n_slices*nx*ny + 8*n_slices*max(n_humans,1)*ny bytes, plus the work
  * list.  Errors as pcsdf_predicted_composite_sdf, prefixed with the scene
- * index. */
+ * index; PCSDF_ERR_DIMS when the batch has 2^31 or more composite items. */
 int pcsdf_predicted_composite_sdf_batch(pcsdf_handle *h, int32_t n_scenes,
                                         const pcsdf_scene *scenes,
                                         void *stream);
 
 /* The same batch captured once in a hipGraph (parameter upload from pinned
- * memory owned by the graph, then the two persistent launches) and
+ * memory owned by the graph, then the batch's two launches) and
  * replayed with one hipGraphLaunch.  The graph owns its workspace; the
  * scenes' device buffers must outlive it.  set_positions replaces one
  * scene's predicted positions for later launches (waiting for a launch

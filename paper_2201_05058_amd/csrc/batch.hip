@@ -1,16 +1,19 @@
 // Batched predicted composite fields: many scenes of uneven grid sizes and
-// slice counts in two persistent launches, optionally captured in one
-// hipGraph with the upload of their parameters.
+// slice counts in two launches, optionally captured in one hipGraph with
+// the upload of their parameters.
 //
-// Work list.  The planar-field items (scene, slice) and the composite items
-// (scene, slice group, voxel chunk) of all scenes, scene-major.  A fixed
-// persistent grid strides over the planar items, then a second over the
-// composite items; the only dependency (a composite item reads its
+// Work list.  The planar-field items (scene, slice, pixel tile) of all
+// scenes are listed, scene-major, and a persistent grid strides over them.
+// The composite items (scene, slice group, voxel chunk) are numbered by
+// per-scene prefix sums; the second launch covers them either with a
+// persistent grid (a given number of workgroups per CU) or with one
+// workgroup per item.  The only dependency (a composite item reads its
 // slices' planes) is the stream order of the two launches.  No workgroup
 // ever waits on another, so every workgroup runs a bounded number of
 // bounded items.  The launch shape (slices per composite item, voxels per
-// item, workgroups per CU) comes from the handle's tuning, which the
-// autotuner below fills by timing candidates on the caller's inputs.
+// item, persistent workgroups per CU or none) comes from the handle's
+// tuning, which the autotuner below fills by timing candidates on the
+// caller's inputs.
 //
 // The device code lives in batch_device.h and the planning in
 // batch_plan.h, so that both can also be compiled for the host.
@@ -33,22 +36,25 @@ __global__ __launch_bounds__(256) void k_batch_planes(
 }
 
 __global__ __launch_bounds__(256) void k_batch_composites(
-    const SceneDev *__restrict__ scenes, const int4 *__restrict__ items,
-    int n_items, int G, uint32_t chunk_voxels) {
-  batch_composites(scenes, items, n_items, G, chunk_voxels);
+    const SceneDev *__restrict__ scenes,
+    const uint32_t *__restrict__ tile_start, int n_scenes, int G,
+    uint32_t chunk_voxels) {
+  batch_composites(scenes, tile_start, n_scenes, G, chunk_voxels);
 }
 
 // -------------------------------------------------------------- host side
 
-// Enqueues the two persistent launches (parameters already uploaded to
-// pbase).
+// Enqueues the planar and the composite launch (parameters already
+// uploaded to pbase).
 static int enqueue_batch(Handle *h, const BatchPlan &bp, char *pbase,
                          hipStream_t s) {
+  const ParamLayout L = param_layout(bp);
   const SceneDev *scenes = reinterpret_cast<const SceneDev *>(pbase);
-  const int4 *items =
-      reinterpret_cast<const int4 *>(pbase + param_layout(bp).items);
-  const int np = bp.n_plane_items;
-  const int nc = (int)bp.items.size() - np;
+  const uint32_t *tiles = reinterpret_cast<const uint32_t *>(pbase + L.tiles);
+  const int4 *items = reinterpret_cast<const int4 *>(pbase + L.items);
+  const int np = (int)bp.items.size();
+  const int64_t nc = bp.tile_start.back();
+  const int n_sc = (int)bp.scenes.size();
   if (np > 0) {
     hipLaunchKernelGGL(k_batch_planes, dim3(std::min(np, bp.blocks)),
                        dim3(256), (size_t)bp.lds_cap, s, scenes, items, np,
@@ -57,9 +63,10 @@ static int enqueue_batch(Handle *h, const BatchPlan &bp, char *pbase,
     if (rc) return rc;
   }
   if (nc > 0) {
-    hipLaunchKernelGGL(k_batch_composites, dim3(std::min(nc, bp.blocks)),
-                       dim3(256), 0, s, scenes, items + np, nc, bp.G,
-                       bp.chunk_voxels);
+    const int64_t grid = bp.blocks_cu > 0 ? std::min<int64_t>(nc, bp.blocks_cu)
+                                          : nc;
+    hipLaunchKernelGGL(k_batch_composites, dim3((unsigned)grid), dim3(256), 0,
+                       s, scenes, tiles, n_sc, bp.G, bp.chunk_voxels);
     return check_launch(h, "batch_composites");
   }
   return PCSDF_OK;
@@ -308,7 +315,7 @@ extern "C" int pcsdf_autotune_batch(pcsdf_handle *hp, int32_t n_scenes,
   double win_ms = -1.0;
   const int Gs[] = {1, 2, 4};
   const int Cs[] = {256, 1024, 4096};
-  const int Bs[] = {4, 8, 16};
+  const int Bs[] = {0, 4, 8, 16};  // 0: one workgroup per composite item
   for (int G : Gs)
     for (int C : Cs)
       for (int B : Bs) {

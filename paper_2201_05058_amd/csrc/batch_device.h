@@ -6,6 +6,7 @@
 
 #include <cstdint>
 
+#include "composite_device.h"
 #include "device_common.h"
 #include "plane_device.h"
 
@@ -21,13 +22,48 @@ struct SceneDev {
   int32_t *F1;        // [n][ny][nx] row pass of the free set
   int64_t R;
   uint32_t V;
-  int nx, ny, nz, n, K, Kt, has_above, vec4;
+  int nx, ny, nz, n, K, Kt, has_above, vec;  // vec: 4, 2 or 1 voxels
   float hf;
   int pad[2];
 };
 
+// One scene-table entry, read field by field through the constant address
+// space: the compiler takes a pointer loaded from there to be global, so
+// every access through it is a global instruction rather than a flat one
+// (a wait for a flat access cannot be counted in order and so waits for
+// all outstanding loads and stores).  A whole-struct copy would lose the
+// address space.
+__device__ __forceinline__ SceneDev load_scene(const SceneDev *scenes, int q) {
+#if defined(__clang__)
+  typedef __attribute__((address_space(4))) const SceneDev ConstScene;
+#else  // a host compiler building the device code for CPU tests
+  typedef const SceneDev ConstScene;
+#endif
+  ConstScene *c = (ConstScene *)(scenes + q);
+  SceneDev d;
+  d.S = c->S;
+  d.oc = c->oc;
+  d.of = c->of;
+  d.xy = c->xy;
+  d.chords = c->chords;
+  d.P = c->P;
+  d.F1 = c->F1;
+  d.R = c->R;
+  d.V = c->V;
+  d.nx = c->nx;
+  d.ny = c->ny;
+  d.nz = c->nz;
+  d.n = c->n;
+  d.K = c->K;
+  d.Kt = c->Kt;
+  d.has_above = c->has_above;
+  d.vec = c->vec;
+  d.hf = c->hf;
+  d.pad[0] = d.pad[1] = 0;
+  return d;
+}
+
 constexpr int kItemPlane = 0;
-constexpr int kItemComposite = 1;
 // Pixels of one planar item when the slice's chords fit in LDS.
 constexpr int kPlaneTile = 4096;
 
@@ -97,85 +133,148 @@ __device__ inline void plane_item(const SceneDev &sc, int s, int tile,
 }
 
 // Composite of `count` consecutive voxels from v0 (VEC voxels per lane and
-// step) for slices [s0, s1).
+// step) for slices [s0, s1).  v0 is a multiple of the chunk size, itself a
+// multiple of 4.
+//
+// A persistent wave runs many (voxels, slice) steps back to back, and on
+// this GPU a wait for a load also waits for every store issued before it.
+// So each step's loads (static and planar packs) are issued before the
+// previous step's stores: the wait for them then covers only the loads.
 template <int VEC>
+struct CompositeStep {
+  typename Pack<VEC>::I s, p;
+  int32_t dz2o, dz2i;
+  bool zin;
+};
+
+template <int VEC>
+__device__ __forceinline__ void load_step(const SceneDev &sc, uint32_t plane,
+                                          uint32_t v, int sl,
+                                          CompositeStep<VEC> &st) {
+  const uint32_t k = v / plane;
+  const uint32_t pix = v - k * plane;
+  const int kk = (int)k;
+  const int dzo = kk > sc.Kt ? kk - sc.Kt : 0;
+  st.dz2o = dzo * dzo;
+  st.zin = kk <= sc.Kt;
+  st.dz2i = sc.has_above ? (sc.Kt + 1 - kk) * (sc.Kt + 1 - kk) : INT32_MAX;
+  st.s = load_i32<VEC>(sc.S + v);
+  st.p = load_i32<VEC>(sc.P + (size_t)sl * plane + pix);
+}
+
+template <int VEC, bool kSsq, bool kSdf>
 __device__ inline void composite_chunk(const SceneDev &sc, uint32_t v0,
-                                uint32_t count, int s0, int s1) {
-  const uint32_t nx = sc.nx, ny = sc.ny, V = sc.V;
-  const size_t plane = (size_t)nx * ny;
-  const uint32_t end = min(V, v0 + count);
-  for (uint32_t v = v0 + threadIdx.x * VEC; v < end; v += blockDim.x * VEC) {
-    const uint32_t row = v / nx;
-    const uint32_t i = v - row * nx;
-    const uint32_t k = row / ny;
-    const uint32_t j = row - k * ny;
-    const int kk = (int)k;
-    const int dzo = kk > sc.Kt ? kk - sc.Kt : 0;
-    const int dz2o = dzo * dzo;
-    const bool zin = kk <= sc.Kt;
-    const int32_t dz2i =
-        sc.has_above ? (sc.Kt + 1 - kk) * (sc.Kt + 1 - kk) : INT32_MAX;
-    const int32_t *prow = sc.P + (size_t)j * nx + i;
-    if constexpr (VEC == 4) {
-      const int4 s4 = *reinterpret_cast<const int4 *>(sc.S + v);
-      for (int sl = s0; sl < s1; ++sl) {
-        const int4 p4 = *reinterpret_cast<const int4 *>(prow + sl * plane);
-        int4 c;
-        c.x = min(s4.x, human_value(p4.x, dz2o, zin, dz2i));
-        c.y = min(s4.y, human_value(p4.y, dz2o, zin, dz2i));
-        c.z = min(s4.z, human_value(p4.z, dz2o, zin, dz2i));
-        c.w = min(s4.w, human_value(p4.w, dz2o, zin, dz2i));
-        const size_t o = (size_t)sl * V + v;
-        if (sc.oc) *reinterpret_cast<int4 *>(sc.oc + o) = c;
-        if (sc.of) {
-          float4 f;
-          f.x = ssq_to_metres(c.x, sc.hf);
-          f.y = ssq_to_metres(c.y, sc.hf);
-          f.z = ssq_to_metres(c.z, sc.hf);
-          f.w = ssq_to_metres(c.w, sc.hf);
-          *reinterpret_cast<float4 *>(sc.of + o) = f;
-        }
-      }
-    } else {
-      const int32_t s = sc.S[v];
-      for (int sl = s0; sl < s1; ++sl) {
-        const int32_t c =
-            min(s, human_value(prow[sl * plane], dz2o, zin, dz2i));
-        const size_t o = (size_t)sl * V + v;
-        if (sc.oc) sc.oc[o] = c;
-        if (sc.of) sc.of[o] = ssq_to_metres(c, sc.hf);
-      }
+                                       uint32_t count, int s0, int s1) {
+  const uint32_t plane = (uint32_t)sc.nx * (uint32_t)sc.ny;
+  const uint32_t end = min(sc.V, v0 + count);
+  const uint32_t stride = blockDim.x * VEC;
+  uint32_t v = v0 + threadIdx.x * VEC;
+  if (v >= end) return;
+  int sl = s0;
+  CompositeStep<VEC> cur;
+  load_step<VEC>(sc, plane, v, sl, cur);
+  // Make the first step's loads complete here, so that inside the loop
+  // the current step's data is known to be in registers and no wait there
+  // covers the previous stores.
+  wait_for<VEC>(cur.s);
+  wait_for<VEC>(cur.p);
+  for (;;) {
+    uint32_t vn = v;
+    int sn = sl + 1;
+    if (sn == s1) {
+      sn = s0;
+      vn = v + stride;
     }
+    const bool more = vn < end;
+    // Unconditional, so that the wait for these loads is counted exactly
+    // (a load on one side of a branch makes the wait for the current
+    // step's data a wait for everything); past the end it re-reads the
+    // current step's (valid) addresses.
+    CompositeStep<VEC> nxt;
+    load_step<VEC>(sc, plane, more ? vn : v, more ? sn : sl, nxt);
+    typename Pack<VEC>::I c;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      c[e] = min(cur.s[e],
+                 human_value(cur.p[e], cur.dz2o, cur.zin, cur.dz2i));
+    const size_t o = (size_t)sl * sc.V + v;
+    if (kSsq) store_i32<VEC>(sc.oc + o, c);
+    if (kSdf) {
+      typename Pack<VEC>::F f;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) f[e] = ssq_to_metres(c[e], sc.hf);
+      store_f32<VEC>(sc.of + o, f);
+    }
+    if (!more) break;
+    v = vn;
+    sl = sn;
+    cur = nxt;
   }
 }
 
-// Persistent workers.  A fixed grid strides over a list of work items;
-// nothing waits on anything, so every workgroup runs a bounded number of
-// bounded items.  The planar items of a batch are run by one launch and
-// its composite items by the next on the same stream, so stream order is
-// the only dependency between them.
+template <int VEC>
+__device__ inline void composite_chunk_any(const SceneDev &sc, uint32_t v0,
+                                           uint32_t count, int s0, int s1) {
+  if (sc.oc && sc.of)
+    composite_chunk<VEC, true, true>(sc, v0, count, s0, s1);
+  else if (sc.oc)
+    composite_chunk<VEC, true, false>(sc, v0, count, s0, s1);
+  else
+    composite_chunk<VEC, false, true>(sc, v0, count, s0, s1);
+}
+
+// Workers.  A grid strides over a list of work items; nothing waits on
+// anything, so every workgroup runs a bounded number of bounded items.
+// The planar items of a batch are run by one launch and its composite
+// items by the next on the same stream, so stream order is the only
+// dependency between them.
 __device__ inline void batch_planes(const SceneDev *__restrict__ scenes,
                                     const int4 *__restrict__ items,
                                     int n_items, int lds_cap, int4 *lds) {
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 w = items[it];
-    plane_item(scenes[w.y], w.z, w.w, lds, lds_cap);
+    plane_item(load_scene(scenes, w.y), w.z, w.w, lds, lds_cap);
     __syncthreads();  // the next item reuses the LDS
   }
 }
 
+// Composite items are not listed: item `it` of scene q (tile_start[q] <= it
+// < tile_start[q + 1]) is slice group (it - tile_start[q]) / chunks and
+// voxel chunk (it - tile_start[q]) % chunks of that scene, chunks =
+// ceil(V / chunk_voxels).  A workgroup finds the scene of its first item
+// by binary search over the n_scenes + 1 prefix sums and walks forward
+// from there (its items increase).
 __device__ inline void batch_composites(const SceneDev *__restrict__ scenes,
-                                        const int4 *__restrict__ items,
-                                        int n_items, int G,
+                                        const uint32_t *__restrict__ tile_start,
+                                        int n_scenes, int G,
                                         uint32_t chunk_voxels) {
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const int4 w = items[it];
-    const SceneDev sc = scenes[w.y];
-    const int s1 = min(sc.n, w.z + G);
-    if (sc.vec4)
-      composite_chunk<4>(sc, (uint32_t)w.w, chunk_voxels, w.z, s1);
+  const uint32_t total = tile_start[n_scenes];
+  uint32_t it = blockIdx.x;
+  if (it >= total) return;
+  int lo = 0, hi = n_scenes - 1;  // last q with tile_start[q] <= it
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= it)
+      lo = mid;
     else
-      composite_chunk<1>(sc, (uint32_t)w.w, chunk_voxels, w.z, s1);
+      hi = mid - 1;
+  }
+  int q = lo;
+  for (; it < total; it += gridDim.x) {
+    while (tile_start[q + 1] <= it) ++q;
+    const SceneDev sc = load_scene(scenes, q);
+    const uint32_t chunks = (sc.V + chunk_voxels - 1) / chunk_voxels;
+    const uint32_t local = it - tile_start[q];
+    const uint32_t sg = local / chunks;
+    const uint32_t v0 = (local - sg * chunks) * chunk_voxels;
+    const int s0 = (int)sg * G;
+    const int s1 = min(sc.n, s0 + G);
+    if (sc.vec == 4)
+      composite_chunk_any<4>(sc, v0, chunk_voxels, s0, s1);
+    else if (sc.vec == 2)
+      composite_chunk_any<2>(sc, v0, chunk_voxels, s0, s1);
+    else
+      composite_chunk_any<1>(sc, v0, chunk_voxels, s0, s1);
   }
 }
 

@@ -15,14 +15,15 @@ namespace pcsdf {
 
 struct BatchPlan {
   std::vector<SceneDev> scenes;
-  std::vector<int4> items;
+  std::vector<int4> items;          // planar items
+  std::vector<uint32_t> tile_start;  // [n_scenes + 1] composite item prefix
   std::vector<int64_t> xy;
   std::vector<size_t> xy_off;  // per scene, in int64 units
-  int n_plane_items = 0;  // items[0 .. n_plane_items) are planar items
   int lds_cap = 0;
   int G = 2;
   uint32_t chunk_voxels = 0;
-  int blocks = 0;
+  int blocks = 0;     // persistent grid of the planar launch
+  int blocks_cu = 0;  // persistent composite grid (0: one item per block)
 };
 
 inline bool fixed(double p, double o, double h, int64_t *out) {
@@ -40,10 +41,12 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
   if (n_scenes < 1 || !scenes)
     return fail(h, PCSDF_ERR_INVALID_ARG, "need at least one scene");
   bp->G = tu.batch_slices_per_item > 0 ? tu.batch_slices_per_item : 2;
-  const int quads = tu.batch_chunk_quads > 0 ? tu.batch_chunk_quads : 8192;
+  const int quads = tu.batch_chunk_quads > 0 ? tu.batch_chunk_quads : 256;
   bp->chunk_voxels = (uint32_t)quads * 4;
-  const int bpc = tu.batch_blocks_per_cu > 0 ? tu.batch_blocks_per_cu : 4;
-  bp->blocks = n_cu * bpc;
+  bp->blocks = n_cu * (tu.batch_blocks_per_cu > 0 ? tu.batch_blocks_per_cu
+                                                   : 8);
+  bp->blocks_cu = tu.batch_blocks_per_cu > 0 ? n_cu * tu.batch_blocks_per_cu
+                                             : 0;
   bp->scenes.resize(n_scenes);
   bp->xy_off.resize(n_scenes);
   bp->xy.clear();
@@ -82,9 +85,8 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
     d.has_above = d.Kt + 1 <= d.nz - 1;
     d.K = (d.Kt < 0) ? 0 : in.n_humans;
     d.hf = (float)hv;
-    d.vec4 = (d.nx % 4 == 0) &&
-             !(((uintptr_t)in.static_ssq_dev | (uintptr_t)in.out_ssq_dev |
-                (uintptr_t)in.out_sdf_dev) & 15);
+    d.vec = composite_vec((int64_t)d.nx * d.ny, in.static_ssq_dev,
+                          in.out_ssq_dev, in.out_sdf_dev);
     bp->xy_off[q] = bp->xy.size();
     for (int64_t t = 0; t < (int64_t)in.n_slices * in.n_humans; ++t) {
       int64_t X, Y;
@@ -101,9 +103,10 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
     lds_need = std::max(lds_need, d.K * 16 + d.K * d.ny * 8);
   }
   bp->lds_cap = std::min(lds_need, 48 * 1024);
-  // items: all planar items (tiles of a slice when its chords fit in
-  // LDS), then all composite items, scene-major
+  // planar items (tiles of a slice when its chords fit in LDS),
+  // scene-major; composite items are counted per scene
   bp->items.clear();
+  bp->tile_start.assign(1, 0u);
   for (int q = 0; q < n_scenes; ++q) {
     const SceneDev &d = bp->scenes[q];
     const int64_t npx = (int64_t)d.nx * d.ny;
@@ -113,14 +116,18 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
     for (int s = 0; s < d.n; ++s)
       for (int t = 0; t < tiles; ++t)
         bp->items.push_back(make_int4(kItemPlane, q, s, t));
+    const int64_t ct = (int64_t)((d.n + bp->G - 1) / bp->G) *
+                       (((int64_t)d.V + bp->chunk_voxels - 1) /
+                        bp->chunk_voxels);
+    const int64_t next = (int64_t)bp->tile_start.back() + ct;
+    if (next > (int64_t)INT32_MAX)
+      return fail(h, PCSDF_ERR_DIMS,
+                  "batch has more than 2^31 - 1 composite items; raise the "
+                  "chunk size or split the batch");
+    bp->tile_start.push_back((uint32_t)next);
   }
-  bp->n_plane_items = (int)bp->items.size();
-  for (int q = 0; q < n_scenes; ++q) {
-    const SceneDev &d = bp->scenes[q];
-    for (int s0 = 0; s0 < d.n; s0 += bp->G)
-      for (uint32_t v = 0; v < d.V; v += bp->chunk_voxels)
-        bp->items.push_back(make_int4(kItemComposite, q, s0, (int)v));
-  }
+  if (bp->items.size() > (size_t)INT32_MAX)
+    return fail(h, PCSDF_ERR_DIMS, "batch has too many planar items");
   return PCSDF_OK;
 }
 
@@ -130,32 +137,33 @@ inline size_t scratch_of(const SceneDev &d) {
          2 * align_up(plane * sizeof(int32_t), 256);
 }
 
-// Byte offsets of the parameter block: scene table, items, centres.
+// Byte offsets of the parameter block: scene table, composite item prefix
+// sums, planar items, centres.
 struct ParamLayout {
-  size_t items, xy, total;
+  size_t tiles, items, xy, total;
 };
 inline ParamLayout param_layout(const BatchPlan &bp) {
   ParamLayout L;
-  L.items = align_up(bp.scenes.size() * sizeof(SceneDev), 256);
+  L.tiles = align_up(bp.scenes.size() * sizeof(SceneDev), 256);
+  L.items = align_up(L.tiles + bp.tile_start.size() * 4, 256);
   L.xy = align_up(L.items + bp.items.size() * 16, 256);
   L.total = L.xy + bp.xy.size() * 8;
   return L;
 }
 
 // Assigns device addresses and serialises the parameter block into
-// `host` (scene table, items, centres).
+// `host`.
 inline void bind_plan(BatchPlan *bp, const pcsdf_scene *scenes, char *pbase,
                       char *sbase, std::vector<char> *host) {
   const size_t n_sc = bp->scenes.size();
   const ParamLayout L = param_layout(*bp);
-  const size_t off_items = L.items, off_xy = L.xy, total = L.total;
   size_t soff = 0;
   for (size_t q = 0; q < n_sc; ++q) {
     SceneDev &d = bp->scenes[q];
     d.S = scenes[q].static_ssq_dev;
     d.oc = scenes[q].out_ssq_dev;
     d.of = scenes[q].out_sdf_dev;
-    d.xy = reinterpret_cast<const int64_t *>(pbase + off_xy) + bp->xy_off[q];
+    d.xy = reinterpret_cast<const int64_t *>(pbase + L.xy) + bp->xy_off[q];
     const size_t plane = (size_t)d.n * d.nx * d.ny;
     d.chords = reinterpret_cast<int2 *>(sbase + soff);
     soff += align_up((size_t)d.n * std::max(d.K, 1) * d.ny * sizeof(int2), 256);
@@ -164,12 +172,14 @@ inline void bind_plan(BatchPlan *bp, const pcsdf_scene *scenes, char *pbase,
     d.F1 = reinterpret_cast<int32_t *>(sbase + soff);
     soff += align_up(plane * sizeof(int32_t), 256);
   }
-  host->assign(total, 0);
+  host->assign(L.total, 0);
   std::memcpy(host->data(), bp->scenes.data(), n_sc * sizeof(SceneDev));
-  std::memcpy(host->data() + off_items, bp->items.data(),
+  std::memcpy(host->data() + L.tiles, bp->tile_start.data(),
+              bp->tile_start.size() * 4);
+  std::memcpy(host->data() + L.items, bp->items.data(),
               bp->items.size() * 16);
   if (!bp->xy.empty())
-    std::memcpy(host->data() + off_xy, bp->xy.data(), bp->xy.size() * 8);
+    std::memcpy(host->data() + L.xy, bp->xy.data(), bp->xy.size() * 8);
 }
 
 inline size_t plan_scratch(const BatchPlan &bp) {

@@ -30,19 +30,20 @@
 #include <cstring>
 #include <vector>
 
+#include "composite_device.h"
 #include "device_common.h"
 #include "internal.h"
 
 namespace pcsdf {
 
-// Slices with need[sl] == 0 are skipped when `need` is non-null.
+// Slices with need[sl] == 0 are skipped when `need` is non-null.  Thread g
+// handles voxels VEC g .. VEC g + VEC - 1 (VEC divides nx ny, so V too).
 template <int VEC, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     const int32_t *__restrict__ need,
-    int32_t *__restrict__ oc, float *__restrict__ of, uint32_t nx,
-    uint32_t ny, int n_slices, int G, int Kt, int has_above, float hf,
-    uint32_t V) {
+    int32_t *__restrict__ oc, float *__restrict__ of, uint32_t plane,
+    int n_slices, int G, int Kt, int has_above, float hf, uint32_t V) {
   const uint32_t g = blockIdx.x * 256u + threadIdx.x;
   const uint32_t v0 = g * VEC;
   if (v0 >= V) return;
@@ -53,68 +54,30 @@ __global__ __launch_bounds__(256) void k_composite(
     for (int sl = s_begin; sl < s_end; ++sl) any = any || need[sl] != 0;
     if (!any) return;
   }
-  const uint32_t row = v0 / nx;
-  const uint32_t i = v0 - row * nx;
-  const uint32_t k = row / ny;
-  const uint32_t j = row - k * ny;
-  const int kk = (int)k;
-  const int dzo = kk > Kt ? kk - Kt : 0;
-  const int dz2o = dzo * dzo;
-  const bool zin = kk <= Kt;
-  const int32_t dz2i =
-      has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : kInf;
-  const size_t plane = (size_t)nx * ny;
-  const int32_t *prow = P + (size_t)j * nx + i;
-
-  if constexpr (VEC == 4) {
-    const int4 s4 = *reinterpret_cast<const int4 *>(S + v0);
-    for (int sl = s_begin; sl < s_end; ++sl) {
-      if (need && need[sl] == 0) continue;
-      const int4 p4 = *reinterpret_cast<const int4 *>(prow + sl * plane);
-      int4 c;
-      c.x = min(s4.x, human_value(p4.x, dz2o, zin, dz2i));
-      c.y = min(s4.y, human_value(p4.y, dz2o, zin, dz2i));
-      c.z = min(s4.z, human_value(p4.z, dz2o, zin, dz2i));
-      c.w = min(s4.w, human_value(p4.w, dz2o, zin, dz2i));
-      const size_t o = (size_t)sl * V + v0;
-      if (kSsq) *reinterpret_cast<int4 *>(oc + o) = c;
-      if (kSdf) {
-        float4 f;
-        f.x = ssq_to_metres(c.x, hf);
-        f.y = ssq_to_metres(c.y, hf);
-        f.z = ssq_to_metres(c.z, hf);
-        f.w = ssq_to_metres(c.w, hf);
-        *reinterpret_cast<float4 *>(of + o) = f;
-      }
-    }
-  } else {
-    const int32_t s = S[v0];
-    for (int sl = s_begin; sl < s_end; ++sl) {
-      if (need && need[sl] == 0) continue;
-      const int32_t c = min(s, human_value(prow[sl * plane], dz2o, zin, dz2i));
-      const size_t o = (size_t)sl * V + v0;
-      if (kSsq) oc[o] = c;
-      if (kSdf) of[o] = ssq_to_metres(c, hf);
-    }
-  }
+  if (need)
+    composite_pack<VEC, kSsq, kSdf, true>(S, P, need, oc, of, plane, V, v0,
+                                          s_begin, s_end, Kt, has_above, hf);
+  else
+    composite_pack<VEC, kSsq, kSdf, false>(S, P, need, oc, of, plane, V, v0,
+                                           s_begin, s_end, Kt, has_above, hf);
 }
 
 template <int VEC>
 static void launch_comp(const int32_t *S, const int32_t *P,
                         const int32_t *need, int32_t *oc, float *of,
-                        uint32_t nx, uint32_t ny, int n, int G, int Kt,
-                        int has_above, float hf, uint32_t V, hipStream_t s) {
-  const uint32_t nthreads = (V + VEC - 1) / VEC;
+                        uint32_t plane, int n, int G, int Kt, int has_above,
+                        float hf, uint32_t V, hipStream_t s) {
+  const uint32_t nthreads = V / VEC;
   const dim3 grid((nthreads + 255) / 256, (n + G - 1) / G), block(256);
   if (oc && of)
     hipLaunchKernelGGL((k_composite<VEC, true, true>), grid, block, 0, s, S,
-                       P, need, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
+                       P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
   else if (oc)
     hipLaunchKernelGGL((k_composite<VEC, true, false>), grid, block, 0, s, S,
-                       P, need, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
+                       P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
   else
     hipLaunchKernelGGL((k_composite<VEC, false, true>), grid, block, 0, s, S,
-                       P, need, oc, of, nx, ny, n, G, Kt, has_above, hf, V);
+                       P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
 }
 
 // Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
@@ -255,9 +218,8 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
   const int64_t V = (int64_t)nx * ny * nz;
   // Streaming epilogue over all voxels and slices.
   const float hf = (float)g->voxel_m;
-  const bool vec4 = (nx % 4 == 0) && !((uintptr_t)static_ssq_dev & 15) &&
-                    !((uintptr_t)out_ssq_dev & 15) &&
-                    !((uintptr_t)out_sdf_dev & 15);
+  const int vec = composite_vec((int64_t)nx * ny, static_ssq_dev,
+                                 out_ssq_dev, out_sdf_dev);
   // Slices per block row: consecutive blocks write the same slices, which
   // keeps the concurrent write streams few and contiguous.
   int G = h->tuning.composite_slices_per_block > 0
@@ -265,11 +227,15 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
               : 2;
   if (G > n_slices) G = n_slices;
   while ((n_slices + G - 1) / G > 65535) ++G;
-  if (vec4)
-    launch_comp<4>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, nx, ny,
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  if (vec == 4)
+    launch_comp<4>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, plane,
+                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+  else if (vec == 2)
+    launch_comp<2>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, plane,
                    n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   else
-    launch_comp<1>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, nx, ny,
+    launch_comp<1>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, plane,
                    n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
   return check_launch(h, "composite");
 }

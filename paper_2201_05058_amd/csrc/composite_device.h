@@ -1,0 +1,162 @@
+// The composite epilogue shared by the single-scene kernel (composite.hip)
+// and the batched workers (batch_device.h): for VEC consecutive voxels of
+// the flattened [nz][ny][nx] grid, read the static field once and write
+// min(static, humans' value) for a range of slices.
+//
+// The planar index of voxel v is v mod (nx ny), so VEC consecutive voxels
+// starting at a multiple of VEC read VEC consecutive planar values of one
+// layer whenever VEC divides nx ny: the vector width is set by the plane
+// size, not by nx.  With VEC | nx ny, VEC also divides V = nx ny nz, so the
+// outputs of every slice (at offset sl V) stay VEC-aligned.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.h"
+
+namespace pcsdf {
+
+// Packs of VEC int32 or fp32 values, and their loads and stores as global
+// memory instructions.  Pointers read from memory (the batch's scene
+// table) would otherwise be accessed with flat instructions, which the
+// compiler cannot count in order: every wait for one of them then waits
+// for all outstanding loads and stores.  The casts are written per
+// concrete type because a global address space on a template-dependent
+// type is not kept.
+#if defined(__clang__)
+#define PCSDF_GLOBAL_AS __attribute__((address_space(1)))
+typedef int32_t pk_i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t pk_i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t pk_i32x1 __attribute__((ext_vector_type(1)));
+typedef float pk_f32x4 __attribute__((ext_vector_type(4)));
+typedef float pk_f32x2 __attribute__((ext_vector_type(2)));
+typedef float pk_f32x1 __attribute__((ext_vector_type(1)));
+#else  // a host compiler building the device code for CPU tests
+#define PCSDF_GLOBAL_AS
+template <class T, int N>
+struct HostPack {
+  T v[N];
+  T &operator[](int i) { return v[i]; }
+  const T &operator[](int i) const { return v[i]; }
+};
+typedef HostPack<int32_t, 4> pk_i32x4;
+typedef HostPack<int32_t, 2> pk_i32x2;
+typedef HostPack<int32_t, 1> pk_i32x1;
+typedef HostPack<float, 4> pk_f32x4;
+typedef HostPack<float, 2> pk_f32x2;
+typedef HostPack<float, 1> pk_f32x1;
+#endif
+
+template <int VEC>
+struct Pack;
+template <>
+struct Pack<4> {
+  typedef pk_i32x4 I;
+  typedef pk_f32x4 F;
+};
+template <>
+struct Pack<2> {
+  typedef pk_i32x2 I;
+  typedef pk_f32x2 F;
+};
+template <>
+struct Pack<1> {
+  typedef pk_i32x1 I;
+  typedef pk_f32x1 F;
+};
+
+#define PCSDF_GLOBAL_IO(T)                                           \
+  __device__ __forceinline__ T ld_global(const T *p) {              \
+    return *(PCSDF_GLOBAL_AS const T *)p;                            \
+  }                                                                  \
+  __device__ __forceinline__ void st_global(T *p, T v) {            \
+    *(PCSDF_GLOBAL_AS T *)p = v;                                     \
+  }
+PCSDF_GLOBAL_IO(pk_i32x4)
+PCSDF_GLOBAL_IO(pk_i32x2)
+PCSDF_GLOBAL_IO(pk_i32x1)
+PCSDF_GLOBAL_IO(pk_f32x4)
+PCSDF_GLOBAL_IO(pk_f32x2)
+PCSDF_GLOBAL_IO(pk_f32x1)
+#undef PCSDF_GLOBAL_IO
+
+template <int VEC>
+__device__ __forceinline__ typename Pack<VEC>::I load_i32(const int32_t *p) {
+  return ld_global(reinterpret_cast<const typename Pack<VEC>::I *>(p));
+}
+template <int VEC>
+__device__ __forceinline__ void store_i32(int32_t *p,
+                                          typename Pack<VEC>::I v) {
+  st_global(reinterpret_cast<typename Pack<VEC>::I *>(p), v);
+}
+template <int VEC>
+__device__ __forceinline__ void store_f32(float *p, typename Pack<VEC>::F v) {
+  st_global(reinterpret_cast<typename Pack<VEC>::F *>(p), v);
+}
+
+// An empty statement that reads a pack's registers: the compiler makes the
+// loads that write them complete before it.
+template <int VEC>
+__device__ __forceinline__ void wait_for(const typename Pack<VEC>::I &v) {
+#if defined(__clang__)
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) asm volatile("" ::"v"(v[e]));
+#else
+  (void)v;
+#endif
+}
+
+// Widest vector (4, 2 or 1 voxels) that the plane size and the alignment
+// of the three streams allow.
+__host__ __device__ inline int composite_vec(int64_t plane, const void *S,
+                                             const void *oc, const void *of) {
+  const uintptr_t a = (uintptr_t)S | (uintptr_t)oc | (uintptr_t)of;
+  if (plane % 4 == 0 && !(a & 15)) return 4;
+  if (plane % 2 == 0 && !(a & 7)) return 2;
+  return 1;
+}
+
+// Voxels v0 .. v0+VEC-1 (v0 a multiple of VEC, all in [0, V)) for slices
+// [s_begin, s_end); with kNeed, slices with need[sl] == 0 are skipped (a
+// template parameter so that without it the stores are unconditional and
+// the compiler counts the waits exactly).
+template <int VEC, bool kSsq, bool kSdf, bool kNeed = false>
+__device__ __forceinline__ void composite_pack(
+    const int32_t *__restrict__ S, const int32_t *__restrict__ P,
+    const int32_t *__restrict__ need, int32_t *__restrict__ oc,
+    float *__restrict__ of, uint32_t plane, uint32_t V, uint32_t v0,
+    int s_begin, int s_end, int Kt, int has_above, float hf) {
+  const uint32_t k = v0 / plane;
+  const uint32_t pix = v0 - k * plane;
+  const int kk = (int)k;
+  const int dzo = kk > Kt ? kk - Kt : 0;
+  const int dz2o = dzo * dzo;
+  const bool zin = kk <= Kt;
+  const int32_t dz2i =
+      has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : INT32_MAX;
+  // A short loop (the tuned slice groups are 2 or 3 slices): loading the
+  // next slice's planar pack ahead of the stores was measured slower here
+  // than the waits it avoids, unlike the batch's longer persistent loops.
+  const typename Pack<VEC>::I s = load_i32<VEC>(S + v0);
+  for (int sl = s_begin; sl < s_end; ++sl) {
+    if (kNeed && need[sl] == 0) continue;
+    const typename Pack<VEC>::I p =
+        load_i32<VEC>(P + (size_t)sl * plane + pix);
+    typename Pack<VEC>::I c;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      c[e] = min(s[e], human_value(p[e], dz2o, zin, dz2i));
+    const size_t o = (size_t)sl * V + v0;
+    if (kSsq) store_i32<VEC>(oc + o, c);
+    if (kSdf) {
+      typename Pack<VEC>::F f;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) f[e] = ssq_to_metres(c[e], hf);
+      store_f32<VEC>(of + o, f);
+    }
+  }
+}
+
+}  // namespace pcsdf

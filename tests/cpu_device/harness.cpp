@@ -110,7 +110,8 @@ static int batch(FILE *f, FILE *o) {
   memcpy(pbase, host.data(), host.size());
   const SceneDev *scenes = (const SceneDev *)pbase;
   const int4 *items = (const int4 *)(pbase + param_layout(bp).items);
-  const int np = bp.n_plane_items, nc = (int)bp.items.size() - np;
+  const uint32_t *tiles = (const uint32_t *)(pbase + param_layout(bp).tiles);
+  const int np = (int)bp.items.size();
   for (int phase = 0; phase < 2; ++phase) {
     std::vector<std::thread> th;
     for (int b = 0; b < nthreads; ++b)
@@ -120,7 +121,7 @@ static int batch(FILE *f, FILE *o) {
         if (phase == 0)
           batch_planes(scenes, items, np, bp.lds_cap, lds.data());
         else
-          batch_composites(scenes, items + np, nc, bp.G, bp.chunk_voxels);
+          batch_composites(scenes, tiles, ns, bp.G, bp.chunk_voxels);
       });
     for (auto &t : th) t.join();
   }
@@ -128,7 +129,7 @@ static int batch(FILE *f, FILE *o) {
     fwrite(oc[q].data(), 4, oc[q].size(), o);
     fwrite(of[q].data(), 4, of[q].size(), o);
   }
-  printf("items %zu planar %d\n", bp.items.size(), np);
+  printf("planar items %d composite items %u\n", np, bp.tile_start.back());
   return 0;
 }
 

@@ -126,6 +126,37 @@ def test_composite_small_scenes(pc, dev, seed, dims, K, n):
     check_composite(pc, sc, dev)
 
 
+@pytest.mark.parametrize("dims", [(21, 60, 17), (130, 70, 9), (34, 27, 13),
+                                  (33, 27, 21)])
+@pytest.mark.parametrize("offset", [0, 1, 2])
+def test_composite_vector_widths_and_alignment(pc, dev, dims, offset):
+    """The composite streams 4, 2 or 1 voxels per lane by nx*ny mod 4 (0
+    with nx odd, 0 with nx = 2 mod 4, 2, odd) and by the alignment of its
+    three buffers: buffers offset by one or two elements (4- and 8-byte
+    aligned) take the narrower packs.  Every case gives the oracle's
+    bytes."""
+    sc = scenegen.small_scene(21, *dims, h=0.05, n_boxes=5, n_humans=3,
+                              n_slices=3)
+    say(f"composite widths grid={dims} offset={offset}")
+    n, V = sc.n_slices, sc.grid.nvox
+    shp = (n,) + sc.grid.shape_zyx
+    ssq_s, _ = gpu_static(pc, sc.grid, sc.occ, dev)
+    bs = torch.empty(V + offset, dtype=torch.int32, device=dev)
+    bs[offset:] = ssq_s.reshape(-1)
+    bi = torch.empty(n * V + offset, dtype=torch.int32, device=dev)
+    bf = torch.empty(n * V + offset, dtype=torch.float32, device=dev)
+    oc, of = bi[offset:].view(shp), bf[offset:].view(shp)
+    pc.predicted_composite_sdf(sc.grid, bs[offset:].view(sc.grid.shape_zyx),
+                               sc.human_xy, sc.radius, sc.height,
+                               out_ssq=oc, out_sdf=of)
+    torch.cuda.synchronize()
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                        sc.height)
+    np.testing.assert_array_equal(oc.cpu().numpy(), wc)
+    assert_f32_close(of.cpu().numpy(), wf)
+
+
 @pytest.mark.parametrize("r,H", [(0.25, 1.8), (0.0, 1.8), (0.25, 0.01),
                                  (0.25, 0.0249), (0.25, 0.025), (0.6, 100.0),
                                  (5.0, 0.5), (5.0, 100.0), (0.07, 0.3)])
