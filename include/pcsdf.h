@@ -296,6 +296,10 @@ typedef struct pcsdf_tuning {
                                          of both launches, at most 32; 0:
                                          8 per CU for the planar items and
                                          one workgroup per composite item */
+  int32_t static_segments;            /* static EDT column passes: segments
+                                         (one wave each) per column, 1, 2,
+                                         4 or 8; 0: one per 32 voxels of
+                                         the column, at most 8 */
 } pcsdf_tuning;
 
 int pcsdf_set_tuning(pcsdf_handle *h, const pcsdf_tuning *t);
@@ -331,10 +335,13 @@ int pcsdf_batch_graph_set_positions(pcsdf_batch_graph *g, int32_t scene,
 int pcsdf_batch_graph_launch(pcsdf_batch_graph *g, void *stream);
 void pcsdf_batch_graph_destroy(pcsdf_batch_graph *g);
 
-/* Autotuners: time candidate launch shapes (`reps` runs each, HIP events
- * on `stream`) on the caller's real inputs, store the fastest in the
- * handle's tuning and return it with its time in milliseconds.  Outputs
- * are written as by the tuned call.  They synchronise with the device. */
+/* Autotuners: time candidate launch shapes on the caller's real inputs by
+ * the GPU time of the kernels they shape (HIP events on `stream` around
+ * the launches, `reps` runs each after a warm-up run; host work between
+ * calls does not count), store the fastest in the handle's tuning and
+ * return it with its time in milliseconds per run.  Outputs are written as
+ * by the tuned call.  They synchronise with the device and leave the
+ * handle's profiling state and totals unchanged. */
 int pcsdf_autotune_batch(pcsdf_handle *h, int32_t n_scenes,
                          const pcsdf_scene *scenes, void *stream,
                          int32_t reps, pcsdf_tuning *best, double *best_ms);

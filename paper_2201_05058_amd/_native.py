@@ -72,7 +72,8 @@ class Tuning(C.Structure):
     _fields_ = [("composite_slices_per_block", C.c_int32),
                 ("batch_slices_per_item", C.c_int32),
                 ("batch_chunk_quads", C.c_int32),
-                ("batch_blocks_per_cu", C.c_int32)]
+                ("batch_blocks_per_cu", C.c_int32),
+                ("static_segments", C.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -163,7 +163,7 @@ void ProfScope::stop() {
   a_ = b_ = nullptr;
 }
 
-static int drain_profile(Handle *h) {
+int drain_profile(Handle *h) {
   for (auto &p : h->prof_pending) {
     float ms = 0.f;
     hipError_t e = hipEventSynchronize(p.b);
@@ -260,12 +260,15 @@ extern "C" int pcsdf_set_tuning(pcsdf_handle *hp, const pcsdf_tuning *t) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return PCSDF_ERR_INVALID_ARG;
   if (!t) return fail(h, PCSDF_ERR_INVALID_ARG, "tuning is NULL");
+  const int sg = t->static_segments;
   if (t->composite_slices_per_block < 0 || t->batch_slices_per_item < 0 ||
       t->batch_chunk_quads < 0 || t->batch_blocks_per_cu < 0 ||
-      t->batch_blocks_per_cu > 32 || t->batch_chunk_quads % 256 != 0)
+      t->batch_blocks_per_cu > 32 || t->batch_chunk_quads % 256 != 0 ||
+      !(sg == 0 || sg == 1 || sg == 2 || sg == 4 || sg == 8))
     return fail(h, PCSDF_ERR_INVALID_ARG,
-                "tuning values must be >= 0, blocks per CU <= 32 and chunk "
-                "quads a multiple of 256");
+                "tuning values must be >= 0, blocks per CU <= 32, chunk "
+                "quads a multiple of 256 and static segments 0, 1, 2, 4 "
+                "or 8");
   h->tuning = *t;
   return PCSDF_OK;
 }

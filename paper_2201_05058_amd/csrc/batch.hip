@@ -4,10 +4,11 @@
 //
 // Work list.  The planar-field items (scene, slice, pixel tile) of all
 // scenes are listed, scene-major, and a persistent grid strides over them.
-// The composite items (scene, slice group, voxel chunk) are numbered by
-// per-scene prefix sums; the second launch covers them either with a
-// persistent grid (a given number of workgroups per CU) or with one
-// workgroup per item.  The only dependency (a composite item reads its
+// The composite items (scene, slice group, voxel chunk) are numbered scene
+// by scene, each scene's count padded to a multiple of 64 so that one
+// table entry per 64 items names the scene; the second launch covers them
+// either with a persistent grid (a given number of workgroups per CU) or
+// with one workgroup per item.  The only dependency (a composite item reads its
 // slices' planes) is the stream order of the two launches.  No workgroup
 // ever waits on another, so every workgroup runs a bounded number of
 // bounded items.  The launch shape (slices per composite item, voxels per
@@ -36,10 +37,9 @@ __global__ __launch_bounds__(256) void k_batch_planes(
 }
 
 __global__ __launch_bounds__(256) void k_batch_composites(
-    const SceneDev *__restrict__ scenes,
-    const uint32_t *__restrict__ tile_start, int n_scenes, int G,
-    uint32_t chunk_voxels) {
-  batch_composites(scenes, tile_start, n_scenes, G, chunk_voxels);
+    const SceneDev *__restrict__ scenes, const int32_t *__restrict__ scene_of,
+    uint32_t total, int G, uint32_t chunk_voxels) {
+  batch_composites(scenes, scene_of, total, G, chunk_voxels);
 }
 
 // -------------------------------------------------------------- host side
@@ -50,11 +50,11 @@ static int enqueue_batch(Handle *h, const BatchPlan &bp, char *pbase,
                          hipStream_t s) {
   const ParamLayout L = param_layout(bp);
   const SceneDev *scenes = reinterpret_cast<const SceneDev *>(pbase);
-  const uint32_t *tiles = reinterpret_cast<const uint32_t *>(pbase + L.tiles);
+  const int32_t *scene_of =
+      reinterpret_cast<const int32_t *>(pbase + L.groups);
   const int4 *items = reinterpret_cast<const int4 *>(pbase + L.items);
   const int np = (int)bp.items.size();
-  const int64_t nc = bp.tile_start.back();
-  const int n_sc = (int)bp.scenes.size();
+  const int64_t nc = bp.composite_items;
   if (np > 0) {
     hipLaunchKernelGGL(k_batch_planes, dim3(std::min(np, bp.blocks)),
                        dim3(256), (size_t)bp.lds_cap, s, scenes, items, np,
@@ -66,7 +66,8 @@ static int enqueue_batch(Handle *h, const BatchPlan &bp, char *pbase,
     const int64_t grid = bp.blocks_cu > 0 ? std::min<int64_t>(nc, bp.blocks_cu)
                                           : nc;
     hipLaunchKernelGGL(k_batch_composites, dim3((unsigned)grid), dim3(256), 0,
-                       s, scenes, tiles, n_sc, bp.G, bp.chunk_voxels);
+                       s, scenes, scene_of, bp.composite_items, bp.G,
+                       bp.chunk_voxels);
     return check_launch(h, "batch_composites");
   }
   return PCSDF_OK;
@@ -277,25 +278,32 @@ extern "C" int pcsdf_batch_graph_launch(pcsdf_batch_graph *g, void *stream) {
 
 namespace {
 
-// Times `fn` (which enqueues on s) reps times with HIP events; -1 on error.
+// Milliseconds per call of the timed regions `id` inside `fn` (HIP events
+// on the stream around the kernels alone, so that host work between calls
+// does not count), over reps calls after one warm-up call; -1 on error.
+// The handle's profiling state and totals are left as they were.
 template <class F>
-double time_ms(hipStream_t s, int reps, F fn) {
-  hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-    return -1.0;
+double kernel_ms(Handle *h, int id, hipStream_t s, int reps, F fn) {
+  if (drain_profile(h)) return -1.0;
+  const bool on = h->prof_on;
+  double ms[PCSDF_KERNEL_COUNT];
+  int64_t n[PCSDF_KERNEL_COUNT];
+  std::memcpy(ms, h->prof_ms, sizeof ms);
+  std::memcpy(n, h->prof_n, sizeof n);
   double out = -1.0;
+  h->prof_on = false;
   if (fn() == PCSDF_OK && hipStreamSynchronize(s) == hipSuccess) {
-    (void)hipEventRecord(a, s);
+    h->prof_on = true;
+    const double before = h->prof_ms[id];
     int rc = PCSDF_OK;
     for (int r = 0; r < reps && rc == PCSDF_OK; ++r) rc = fn();
-    (void)hipEventRecord(b, s);
-    float ms = 0.f;
-    if (rc == PCSDF_OK && hipEventSynchronize(b) == hipSuccess &&
-        hipEventElapsedTime(&ms, a, b) == hipSuccess)
-      out = ms / reps;
+    if (rc == PCSDF_OK && hipStreamSynchronize(s) == hipSuccess &&
+        drain_profile(h) == PCSDF_OK)
+      out = (h->prof_ms[id] - before) / reps;
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  h->prof_on = on;
+  std::memcpy(h->prof_ms, ms, sizeof ms);
+  std::memcpy(h->prof_n, n, sizeof n);
   return out;
 }
 
@@ -323,7 +331,7 @@ extern "C" int pcsdf_autotune_batch(pcsdf_handle *hp, int32_t n_scenes,
         t.batch_slices_per_item = G;
         t.batch_chunk_quads = C;
         t.batch_blocks_per_cu = B;
-        const double ms = time_ms(s, reps, [&] {
+        const double ms = kernel_ms(h, PCSDF_KERNEL_BATCH, s, reps, [&] {
           return run_batch(h, n_scenes, scenes, t, s);
         });
         if (ms < 0) {
@@ -362,12 +370,16 @@ extern "C" int pcsdf_autotune_composite(pcsdf_handle *hp,
     if (G < 1 || G > n) continue;
     h->tuning = base;
     h->tuning.composite_slices_per_block = G;
-    const double ms = time_ms(reinterpret_cast<hipStream_t>(stream), reps, [&] {
-      return pcsdf_predicted_composite_sdf(
-          hp, &sc->grid, sc->static_ssq_dev, sc->n_slices, sc->n_humans,
-          sc->human_xy_host, sc->radius_m, sc->height_m, sc->out_ssq_dev,
-          sc->out_sdf_dev, stream);
-    });
+    // the composite kernel alone: the slice group changes nothing else,
+    // and a call's wall time can be the host's
+    const double ms = kernel_ms(
+        h, PCSDF_KERNEL_COMPOSITE, reinterpret_cast<hipStream_t>(stream),
+        reps, [&] {
+          return pcsdf_predicted_composite_sdf(
+              hp, &sc->grid, sc->static_ssq_dev, sc->n_slices, sc->n_humans,
+              sc->human_xy_host, sc->radius_m, sc->height_m, sc->out_ssq_dev,
+              sc->out_sdf_dev, stream);
+        });
     if (ms < 0) {
       h->tuning = base;
       return PCSDF_ERR_HIP;

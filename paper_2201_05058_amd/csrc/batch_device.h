@@ -22,10 +22,19 @@ struct SceneDev {
   int32_t *F1;        // [n][ny][nx] row pass of the free set
   int64_t R;
   uint32_t V;
-  int nx, ny, nz, n, K, Kt, has_above, vec;  // vec: 4, 2 or 1 voxels
+  int nx, ny, nz, n, K, Kt, has_above;
+  int vec, gather;  // pack shape of the composite (composite_shape)
   float hf;
-  int pad[2];
+  uint32_t item0;   // first composite item of the scene
+  uint32_t items;   // its composite items: slice groups x chunks
+  uint32_t chunks;  // voxel chunks per slice group
 };
+
+// Composite items are numbered scene by scene, each scene's count padded
+// to a multiple of kItemGroup, so that one table entry per kItemGroup
+// items names the scene (padding items do nothing).
+constexpr int kItemGroupShift = 6;
+constexpr int kItemGroup = 1 << kItemGroupShift;
 
 // One scene-table entry, read field by field through the constant address
 // space: the compiler takes a pointer loaded from there to be global, so
@@ -58,8 +67,11 @@ __device__ __forceinline__ SceneDev load_scene(const SceneDev *scenes, int q) {
   d.Kt = c->Kt;
   d.has_above = c->has_above;
   d.vec = c->vec;
+  d.gather = c->gather;
   d.hf = c->hf;
-  d.pad[0] = d.pad[1] = 0;
+  d.item0 = c->item0;
+  d.items = c->items;
+  d.chunks = c->chunks;
   return d;
 }
 
@@ -132,95 +144,33 @@ __device__ inline void plane_item(const SceneDev &sc, int s, int tile,
   }
 }
 
-// Composite of `count` consecutive voxels from v0 (VEC voxels per lane and
-// step) for slices [s0, s1).  v0 is a multiple of the chunk size, itself a
-// multiple of 4.
-//
-// A persistent wave runs many (voxels, slice) steps back to back, and on
-// this GPU a wait for a load also waits for every store issued before it.
-// So each step's loads (static and planar packs) are issued before the
-// previous step's stores: the wait for them then covers only the loads.
-template <int VEC>
-struct CompositeStep {
-  typename Pack<VEC>::I s, p;
-  int32_t dz2o, dz2i;
-  bool zin;
-};
-
-template <int VEC>
-__device__ __forceinline__ void load_step(const SceneDev &sc, uint32_t plane,
-                                          uint32_t v, int sl,
-                                          CompositeStep<VEC> &st) {
-  const uint32_t k = v / plane;
-  const uint32_t pix = v - k * plane;
-  const int kk = (int)k;
-  const int dzo = kk > sc.Kt ? kk - sc.Kt : 0;
-  st.dz2o = dzo * dzo;
-  st.zin = kk <= sc.Kt;
-  st.dz2i = sc.has_above ? (sc.Kt + 1 - kk) * (sc.Kt + 1 - kk) : INT32_MAX;
-  st.s = load_i32<VEC>(sc.S + v);
-  st.p = load_i32<VEC>(sc.P + (size_t)sl * plane + pix);
-}
-
-template <int VEC, bool kSsq, bool kSdf>
+// Composite of `count` consecutive voxels from v0 (VEC voxels per lane)
+// for slices [s0, s1); v0 is a multiple of the chunk size, itself a
+// multiple of 4.  Each lane runs the same epilogue as the single-scene
+// kernel; with the tuned chunk of 256 lanes x 4 voxels a lane handles one
+// pack and exits.  (A loop that loads the next step's data ahead of the
+// current stores was measured slower for these short item lengths, and
+// persistent grids slower than one workgroup per item.)
+template <int VEC, bool kGather, bool kSsq, bool kSdf>
 __device__ inline void composite_chunk(const SceneDev &sc, uint32_t v0,
                                        uint32_t count, int s0, int s1) {
   const uint32_t plane = (uint32_t)sc.nx * (uint32_t)sc.ny;
   const uint32_t end = min(sc.V, v0 + count);
-  const uint32_t stride = blockDim.x * VEC;
-  uint32_t v = v0 + threadIdx.x * VEC;
-  if (v >= end) return;
-  int sl = s0;
-  CompositeStep<VEC> cur;
-  load_step<VEC>(sc, plane, v, sl, cur);
-  // Make the first step's loads complete here, so that inside the loop
-  // the current step's data is known to be in registers and no wait there
-  // covers the previous stores.
-  wait_for<VEC>(cur.s);
-  wait_for<VEC>(cur.p);
-  for (;;) {
-    uint32_t vn = v;
-    int sn = sl + 1;
-    if (sn == s1) {
-      sn = s0;
-      vn = v + stride;
-    }
-    const bool more = vn < end;
-    // Unconditional, so that the wait for these loads is counted exactly
-    // (a load on one side of a branch makes the wait for the current
-    // step's data a wait for everything); past the end it re-reads the
-    // current step's (valid) addresses.
-    CompositeStep<VEC> nxt;
-    load_step<VEC>(sc, plane, more ? vn : v, more ? sn : sl, nxt);
-    typename Pack<VEC>::I c;
-#pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      c[e] = min(cur.s[e],
-                 human_value(cur.p[e], cur.dz2o, cur.zin, cur.dz2i));
-    const size_t o = (size_t)sl * sc.V + v;
-    if (kSsq) store_i32<VEC>(sc.oc + o, c);
-    if (kSdf) {
-      typename Pack<VEC>::F f;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) f[e] = ssq_to_metres(c[e], sc.hf);
-      store_f32<VEC>(sc.of + o, f);
-    }
-    if (!more) break;
-    v = vn;
-    sl = sn;
-    cur = nxt;
-  }
+  for (uint32_t v = v0 + threadIdx.x * VEC; v < end; v += blockDim.x * VEC)
+    composite_pack<VEC, kGather, kSsq, kSdf>(sc.S, sc.P, nullptr, sc.oc,
+                                             sc.of, plane, sc.V, v, s0, s1,
+                                             sc.Kt, sc.has_above, sc.hf);
 }
 
-template <int VEC>
+template <int VEC, bool kGather>
 __device__ inline void composite_chunk_any(const SceneDev &sc, uint32_t v0,
                                            uint32_t count, int s0, int s1) {
   if (sc.oc && sc.of)
-    composite_chunk<VEC, true, true>(sc, v0, count, s0, s1);
+    composite_chunk<VEC, kGather, true, true>(sc, v0, count, s0, s1);
   else if (sc.oc)
-    composite_chunk<VEC, true, false>(sc, v0, count, s0, s1);
+    composite_chunk<VEC, kGather, true, false>(sc, v0, count, s0, s1);
   else
-    composite_chunk<VEC, false, true>(sc, v0, count, s0, s1);
+    composite_chunk<VEC, kGather, false, true>(sc, v0, count, s0, s1);
 }
 
 // Workers.  A grid strides over a list of work items; nothing waits on
@@ -238,43 +188,31 @@ __device__ inline void batch_planes(const SceneDev *__restrict__ scenes,
   }
 }
 
-// Composite items are not listed: item `it` of scene q (tile_start[q] <= it
-// < tile_start[q + 1]) is slice group (it - tile_start[q]) / chunks and
-// voxel chunk (it - tile_start[q]) % chunks of that scene, chunks =
-// ceil(V / chunk_voxels).  A workgroup finds the scene of its first item
-// by binary search over the n_scenes + 1 prefix sums and walks forward
-// from there (its items increase).
+// Composite item `it` belongs to scene q = scene_of[it / kItemGroup]; it
+// is slice group (it - item0) / chunks and voxel chunk (it - item0) %
+// chunks of that scene, or padding when it - item0 >= items.
 __device__ inline void batch_composites(const SceneDev *__restrict__ scenes,
-                                        const uint32_t *__restrict__ tile_start,
-                                        int n_scenes, int G,
+                                        const int32_t *__restrict__ scene_of,
+                                        uint32_t total, int G,
                                         uint32_t chunk_voxels) {
-  const uint32_t total = tile_start[n_scenes];
-  uint32_t it = blockIdx.x;
-  if (it >= total) return;
-  int lo = 0, hi = n_scenes - 1;  // last q with tile_start[q] <= it
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tile_start[mid] <= it)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  int q = lo;
-  for (; it < total; it += gridDim.x) {
-    while (tile_start[q + 1] <= it) ++q;
-    const SceneDev sc = load_scene(scenes, q);
-    const uint32_t chunks = (sc.V + chunk_voxels - 1) / chunk_voxels;
-    const uint32_t local = it - tile_start[q];
-    const uint32_t sg = local / chunks;
-    const uint32_t v0 = (local - sg * chunks) * chunk_voxels;
+  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const SceneDev sc = load_scene(scenes, scene_of[it >> kItemGroupShift]);
+    const uint32_t local = it - sc.item0;
+    if (local >= sc.items) continue;
+    const uint32_t sg = local / sc.chunks;
+    const uint32_t v0 = (local - sg * sc.chunks) * chunk_voxels;
     const int s0 = (int)sg * G;
     const int s1 = min(sc.n, s0 + G);
-    if (sc.vec == 4)
-      composite_chunk_any<4>(sc, v0, chunk_voxels, s0, s1);
+    if (sc.vec == 4 && !sc.gather)
+      composite_chunk_any<4, false>(sc, v0, chunk_voxels, s0, s1);
+    else if (sc.vec == 4)
+      composite_chunk_any<4, true>(sc, v0, chunk_voxels, s0, s1);
+    else if (sc.vec == 2 && !sc.gather)
+      composite_chunk_any<2, false>(sc, v0, chunk_voxels, s0, s1);
     else if (sc.vec == 2)
-      composite_chunk_any<2>(sc, v0, chunk_voxels, s0, s1);
+      composite_chunk_any<2, true>(sc, v0, chunk_voxels, s0, s1);
     else
-      composite_chunk_any<1>(sc, v0, chunk_voxels, s0, s1);
+      composite_chunk_any<1, false>(sc, v0, chunk_voxels, s0, s1);
   }
 }
 

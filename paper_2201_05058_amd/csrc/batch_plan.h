@@ -16,7 +16,8 @@ namespace pcsdf {
 struct BatchPlan {
   std::vector<SceneDev> scenes;
   std::vector<int4> items;          // planar items
-  std::vector<uint32_t> tile_start;  // [n_scenes + 1] composite item prefix
+  std::vector<int32_t> scene_of;  // scene of each group of kItemGroup items
+  uint32_t composite_items = 0;   // including padding
   std::vector<int64_t> xy;
   std::vector<size_t> xy_off;  // per scene, in int64 units
   int lds_cap = 0;
@@ -40,7 +41,7 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
                       const pcsdf_tuning &tu, int n_cu, BatchPlan *bp) {
   if (n_scenes < 1 || !scenes)
     return fail(h, PCSDF_ERR_INVALID_ARG, "need at least one scene");
-  bp->G = tu.batch_slices_per_item > 0 ? tu.batch_slices_per_item : 2;
+  bp->G = tu.batch_slices_per_item > 0 ? tu.batch_slices_per_item : 4;
   const int quads = tu.batch_chunk_quads > 0 ? tu.batch_chunk_quads : 256;
   bp->chunk_voxels = (uint32_t)quads * 4;
   bp->blocks = n_cu * (tu.batch_blocks_per_cu > 0 ? tu.batch_blocks_per_cu
@@ -85,8 +86,11 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
     d.has_above = d.Kt + 1 <= d.nz - 1;
     d.K = (d.Kt < 0) ? 0 : in.n_humans;
     d.hf = (float)hv;
-    d.vec = composite_vec((int64_t)d.nx * d.ny, in.static_ssq_dev,
-                          in.out_ssq_dev, in.out_sdf_dev);
+    const PackShape ps =
+        composite_shape((int64_t)d.nx * d.ny, (int64_t)d.V, in.static_ssq_dev,
+                        in.out_ssq_dev, in.out_sdf_dev);
+    d.vec = ps.vec;
+    d.gather = ps.gather;
     bp->xy_off[q] = bp->xy.size();
     for (int64_t t = 0; t < (int64_t)in.n_slices * in.n_humans; ++t) {
       int64_t X, Y;
@@ -106,9 +110,10 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
   // planar items (tiles of a slice when its chords fit in LDS),
   // scene-major; composite items are counted per scene
   bp->items.clear();
-  bp->tile_start.assign(1, 0u);
+  bp->scene_of.clear();
+  int64_t next = 0;
   for (int q = 0; q < n_scenes; ++q) {
-    const SceneDev &d = bp->scenes[q];
+    SceneDev &d = bp->scenes[q];
     const int64_t npx = (int64_t)d.nx * d.ny;
     const int tiles = chords_in_lds(d.K, d.ny, bp->lds_cap)
                           ? (int)((npx + kPlaneTile - 1) / kPlaneTile)
@@ -116,16 +121,21 @@ inline int plan_batch(Handle *h, int n_scenes, const pcsdf_scene *scenes,
     for (int s = 0; s < d.n; ++s)
       for (int t = 0; t < tiles; ++t)
         bp->items.push_back(make_int4(kItemPlane, q, s, t));
-    const int64_t ct = (int64_t)((d.n + bp->G - 1) / bp->G) *
-                       (((int64_t)d.V + bp->chunk_voxels - 1) /
-                        bp->chunk_voxels);
-    const int64_t next = (int64_t)bp->tile_start.back() + ct;
-    if (next > (int64_t)INT32_MAX)
+    const int64_t chunks =
+        ((int64_t)d.V + bp->chunk_voxels - 1) / bp->chunk_voxels;
+    const int64_t ct = (int64_t)((d.n + bp->G - 1) / bp->G) * chunks;
+    const int64_t padded = (ct + kItemGroup - 1) / kItemGroup * kItemGroup;
+    if (next + padded > (int64_t)INT32_MAX)
       return fail(h, PCSDF_ERR_DIMS,
                   "batch has more than 2^31 - 1 composite items; raise the "
                   "chunk size or split the batch");
-    bp->tile_start.push_back((uint32_t)next);
+    d.item0 = (uint32_t)next;
+    d.items = (uint32_t)ct;
+    d.chunks = (uint32_t)chunks;
+    bp->scene_of.insert(bp->scene_of.end(), (size_t)(padded / kItemGroup), q);
+    next += padded;
   }
+  bp->composite_items = (uint32_t)next;
   if (bp->items.size() > (size_t)INT32_MAX)
     return fail(h, PCSDF_ERR_DIMS, "batch has too many planar items");
   return PCSDF_OK;
@@ -137,15 +147,15 @@ inline size_t scratch_of(const SceneDev &d) {
          2 * align_up(plane * sizeof(int32_t), 256);
 }
 
-// Byte offsets of the parameter block: scene table, composite item prefix
-// sums, planar items, centres.
+// Byte offsets of the parameter block: scene table, scene of each group
+// of composite items, planar items, centres.
 struct ParamLayout {
-  size_t tiles, items, xy, total;
+  size_t groups, items, xy, total;
 };
 inline ParamLayout param_layout(const BatchPlan &bp) {
   ParamLayout L;
-  L.tiles = align_up(bp.scenes.size() * sizeof(SceneDev), 256);
-  L.items = align_up(L.tiles + bp.tile_start.size() * 4, 256);
+  L.groups = align_up(bp.scenes.size() * sizeof(SceneDev), 256);
+  L.items = align_up(L.groups + bp.scene_of.size() * 4, 256);
   L.xy = align_up(L.items + bp.items.size() * 16, 256);
   L.total = L.xy + bp.xy.size() * 8;
   return L;
@@ -174,8 +184,8 @@ inline void bind_plan(BatchPlan *bp, const pcsdf_scene *scenes, char *pbase,
   }
   host->assign(L.total, 0);
   std::memcpy(host->data(), bp->scenes.data(), n_sc * sizeof(SceneDev));
-  std::memcpy(host->data() + L.tiles, bp->tile_start.data(),
-              bp->tile_start.size() * 4);
+  std::memcpy(host->data() + L.groups, bp->scene_of.data(),
+              bp->scene_of.size() * 4);
   std::memcpy(host->data() + L.items, bp->items.data(),
               bp->items.size() * 16);
   if (!bp->xy.empty())

@@ -37,8 +37,9 @@
 namespace pcsdf {
 
 // Slices with need[sl] == 0 are skipped when `need` is non-null.  Thread g
-// handles voxels VEC g .. VEC g + VEC - 1 (VEC divides nx ny, so V too).
-template <int VEC, bool kSsq, bool kSdf>
+// handles voxels VEC g .. VEC g + VEC - 1 (VEC divides V); kGather reads
+// their planar values one by one (VEC does not divide nx ny).
+template <int VEC, bool kGather, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     const int32_t *__restrict__ need,
@@ -55,14 +56,14 @@ __global__ __launch_bounds__(256) void k_composite(
     if (!any) return;
   }
   if (need)
-    composite_pack<VEC, kSsq, kSdf, true>(S, P, need, oc, of, plane, V, v0,
-                                          s_begin, s_end, Kt, has_above, hf);
+    composite_pack<VEC, kGather, kSsq, kSdf, true>(
+        S, P, need, oc, of, plane, V, v0, s_begin, s_end, Kt, has_above, hf);
   else
-    composite_pack<VEC, kSsq, kSdf, false>(S, P, need, oc, of, plane, V, v0,
-                                           s_begin, s_end, Kt, has_above, hf);
+    composite_pack<VEC, kGather, kSsq, kSdf, false>(
+        S, P, need, oc, of, plane, V, v0, s_begin, s_end, Kt, has_above, hf);
 }
 
-template <int VEC>
+template <int VEC, bool kGather>
 static void launch_comp(const int32_t *S, const int32_t *P,
                         const int32_t *need, int32_t *oc, float *of,
                         uint32_t plane, int n, int G, int Kt, int has_above,
@@ -70,14 +71,17 @@ static void launch_comp(const int32_t *S, const int32_t *P,
   const uint32_t nthreads = V / VEC;
   const dim3 grid((nthreads + 255) / 256, (n + G - 1) / G), block(256);
   if (oc && of)
-    hipLaunchKernelGGL((k_composite<VEC, true, true>), grid, block, 0, s, S,
-                       P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
+    hipLaunchKernelGGL((k_composite<VEC, kGather, true, true>), grid, block,
+                       0, s, S, P, need, oc, of, plane, n, G, Kt, has_above,
+                       hf, V);
   else if (oc)
-    hipLaunchKernelGGL((k_composite<VEC, true, false>), grid, block, 0, s, S,
-                       P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
+    hipLaunchKernelGGL((k_composite<VEC, kGather, true, false>), grid, block,
+                       0, s, S, P, need, oc, of, plane, n, G, Kt, has_above,
+                       hf, V);
   else
-    hipLaunchKernelGGL((k_composite<VEC, false, true>), grid, block, 0, s, S,
-                       P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
+    hipLaunchKernelGGL((k_composite<VEC, kGather, false, true>), grid, block,
+                       0, s, S, P, need, oc, of, plane, n, G, Kt, has_above,
+                       hf, V);
 }
 
 // Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
@@ -218,8 +222,8 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
   const int64_t V = (int64_t)nx * ny * nz;
   // Streaming epilogue over all voxels and slices.
   const float hf = (float)g->voxel_m;
-  const int vec = composite_vec((int64_t)nx * ny, static_ssq_dev,
-                                 out_ssq_dev, out_sdf_dev);
+  const PackShape ps = composite_shape((int64_t)nx * ny, V, static_ssq_dev,
+                                       out_ssq_dev, out_sdf_dev);
   // Slices per block row: consecutive blocks write the same slices, which
   // keeps the concurrent write streams few and contiguous.
   int G = h->tuning.composite_slices_per_block > 0
@@ -228,15 +232,22 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
   if (G > n_slices) G = n_slices;
   while ((n_slices + G - 1) / G > 65535) ++G;
   const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-  if (vec == 4)
-    launch_comp<4>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, plane,
-                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
-  else if (vec == 2)
-    launch_comp<2>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, plane,
-                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+  const uint32_t Vu = (uint32_t)V;
+  if (ps.vec == 4 && !ps.gather)
+    launch_comp<4, false>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
+  else if (ps.vec == 4)
+    launch_comp<4, true>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+                         plane, n_slices, G, Kt, has_above, hf, Vu, s);
+  else if (ps.vec == 2 && !ps.gather)
+    launch_comp<2, false>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
+  else if (ps.vec == 2)
+    launch_comp<2, true>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+                         plane, n_slices, G, Kt, has_above, hf, Vu, s);
   else
-    launch_comp<1>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev, plane,
-                   n_slices, G, Kt, has_above, hf, (uint32_t)V, s);
+    launch_comp<1, false>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
   return check_launch(h, "composite");
 }
 

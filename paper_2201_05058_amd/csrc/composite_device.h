@@ -3,11 +3,13 @@
 // the flattened [nz][ny][nx] grid, read the static field once and write
 // min(static, humans' value) for a range of slices.
 //
-// The planar index of voxel v is v mod (nx ny), so VEC consecutive voxels
-// starting at a multiple of VEC read VEC consecutive planar values of one
-// layer whenever VEC divides nx ny: the vector width is set by the plane
-// size, not by nx.  With VEC | nx ny, VEC also divides V = nx ny nz, so the
-// outputs of every slice (at offset sl V) stay VEC-aligned.
+// The static field and the outputs are flat streams: VEC consecutive
+// voxels starting at a multiple of VEC are one aligned VEC-wide access
+// whenever VEC divides V = nx ny nz (so that every slice's outputs, at
+// offset sl V, stay aligned) and the buffers are aligned.  The planar
+// index of voxel v is v mod (nx ny), so the same voxels read VEC
+// consecutive planar values of one layer when VEC also divides nx ny;
+// otherwise those VEC values are read one by one (from the cached plane).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -108,34 +110,87 @@ __device__ __forceinline__ void wait_for(const typename Pack<VEC>::I &v) {
 #endif
 }
 
-// Widest vector (4, 2 or 1 voxels) that the plane size and the alignment
-// of the three streams allow.
-__host__ __device__ inline int composite_vec(int64_t plane, const void *S,
-                                             const void *oc, const void *of) {
+// Pack shape of the streaming epilogue: `vec` voxels per lane (4, 2 or 1),
+// set by V and the alignment of the three streams; `gather` when the
+// plane size is not a multiple of vec, so that the vec planar values are
+// read one by one (a pack may then cross a layer boundary).
+struct PackShape {
+  int vec;
+  bool gather;
+};
+__host__ __device__ inline PackShape composite_shape(int64_t plane, int64_t V,
+                                                     const void *S,
+                                                     const void *oc,
+                                                     const void *of) {
   const uintptr_t a = (uintptr_t)S | (uintptr_t)oc | (uintptr_t)of;
-  if (plane % 4 == 0 && !(a & 15)) return 4;
-  if (plane % 2 == 0 && !(a & 7)) return 2;
-  return 1;
+  if (V % 4 == 0 && !(a & 15)) return PackShape{4, plane % 4 != 0};
+  if (V % 2 == 0 && !(a & 7)) return PackShape{2, plane % 2 != 0};
+  return PackShape{1, false};
+}
+
+// The humans' value at layer kk for planar value p.
+__device__ __forceinline__ int32_t human_at(int32_t p, int kk, int Kt,
+                                            int has_above) {
+  const int dzo = kk > Kt ? kk - Kt : 0;
+  const int32_t dz2i =
+      has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : INT32_MAX;
+  return human_value(p, dzo * dzo, kk <= Kt, dz2i);
+}
+
+// Planar index and layer of voxels v0 .. v0+VEC-1.  Without kGather they
+// share one layer and are consecutive in the plane; with it, each voxel
+// gets its own (a pack may cross layer boundaries, several when the
+// plane holds fewer than VEC pixels).
+template <int VEC, bool kGather>
+struct PackCoords {
+  uint32_t pix[kGather ? VEC : 1];
+  int k[kGather ? VEC : 1];
+};
+template <int VEC, bool kGather>
+__device__ __forceinline__ PackCoords<VEC, kGather> pack_coords(
+    uint32_t v0, uint32_t plane) {
+  PackCoords<VEC, kGather> c;
+  const uint32_t k0 = v0 / plane;
+  uint32_t pix = v0 - k0 * plane;
+  int kk = (int)k0;
+#pragma unroll
+  for (int e = 0; e < (kGather ? VEC : 1); ++e) {
+    c.pix[e] = pix;
+    c.k[e] = kk;
+    if (++pix == plane) {  // pix < plane before the step
+      pix = 0;
+      ++kk;
+    }
+  }
+  return c;
+}
+
+// The VEC planar values of a pack in slice plane Ps.
+template <int VEC, bool kGather>
+__device__ __forceinline__ typename Pack<VEC>::I load_planar(
+    const int32_t *Ps, const PackCoords<VEC, kGather> &c) {
+  if constexpr (kGather) {
+    typename Pack<VEC>::I p;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      p[e] = ld_global(reinterpret_cast<const pk_i32x1 *>(Ps + c.pix[e]))[0];
+    return p;
+  } else {
+    return load_i32<VEC>(Ps + c.pix[0]);
+  }
 }
 
 // Voxels v0 .. v0+VEC-1 (v0 a multiple of VEC, all in [0, V)) for slices
 // [s_begin, s_end); with kNeed, slices with need[sl] == 0 are skipped (a
 // template parameter so that without it the stores are unconditional and
 // the compiler counts the waits exactly).
-template <int VEC, bool kSsq, bool kSdf, bool kNeed = false>
+template <int VEC, bool kGather, bool kSsq, bool kSdf, bool kNeed = false>
 __device__ __forceinline__ void composite_pack(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     const int32_t *__restrict__ need, int32_t *__restrict__ oc,
     float *__restrict__ of, uint32_t plane, uint32_t V, uint32_t v0,
     int s_begin, int s_end, int Kt, int has_above, float hf) {
-  const uint32_t k = v0 / plane;
-  const uint32_t pix = v0 - k * plane;
-  const int kk = (int)k;
-  const int dzo = kk > Kt ? kk - Kt : 0;
-  const int dz2o = dzo * dzo;
-  const bool zin = kk <= Kt;
-  const int32_t dz2i =
-      has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : INT32_MAX;
+  const PackCoords<VEC, kGather> pc = pack_coords<VEC, kGather>(v0, plane);
   // A short loop (the tuned slice groups are 2 or 3 slices): loading the
   // next slice's planar pack ahead of the stores was measured slower here
   // than the waits it avoids, unlike the batch's longer persistent loops.
@@ -143,11 +198,11 @@ __device__ __forceinline__ void composite_pack(
   for (int sl = s_begin; sl < s_end; ++sl) {
     if (kNeed && need[sl] == 0) continue;
     const typename Pack<VEC>::I p =
-        load_i32<VEC>(P + (size_t)sl * plane + pix);
+        load_planar<VEC, kGather>(P + (size_t)sl * plane, pc);
     typename Pack<VEC>::I c;
 #pragma unroll
     for (int e = 0; e < VEC; ++e)
-      c[e] = min(s[e], human_value(p[e], dz2o, zin, dz2i));
+      c[e] = min(s[e], human_at(p[e], pc.k[kGather ? e : 0], Kt, has_above));
     const size_t o = (size_t)sl * V + v0;
     if (kSsq) store_i32<VEC>(oc + o, c);
     if (kSdf) {

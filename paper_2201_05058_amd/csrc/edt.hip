@@ -260,6 +260,162 @@ __global__ __launch_bounds__(64) void k_pass_col(
   }
 }
 
+// The same pass with each column split into S segments, one wave per
+// segment (workgroup = S waves, 32 columns x 2 channels per wave as
+// above).  Wave w builds the lower envelope of the sites in its segment;
+// after a barrier it fills its segment's voxels with the minimum over the
+// S envelopes, walking each one as the fill sweep above walks its single
+// envelope (the minimizing parabola of an envelope moves right as q
+// grows).  The envelope of the whole column is the lower envelope of the
+// segments' envelopes, so the result is exact.  Its own segment is
+// evaluated first and another segment only while it could still lower
+// the value (its nearest voxel is closer than the square root of the
+// value so far), so a fill usually reads one or two envelopes.  The
+// workgroup's LDS is the same as one wave's above (S segments of m/S
+// entries), so S times as many waves share a CU.
+template <int S, bool kWriteSdf>
+__global__ __launch_bounds__(64 * S) void k_pass_col_seg(
+    const int32_t *__restrict__ in, int32_t *__restrict__ out,
+    float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
+    int64_t outer_stride, int64_t nblocks, int tiles) {
+  extern __shared__ uint32_t lds_seg[];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = lane & 31;
+  const bool inside_ch = lane >= 32;  // channel of the free set
+  const int L = (m + S - 1) / S;
+  uint32_t *const stacks = lds_seg;                       // [S][L][64]
+  int *const tops = reinterpret_cast<int *>(lds_seg + (size_t)S * L * 64);
+  uint32_t *const stk = stacks + (size_t)w * L * 64;
+  const int q0 = w * L;
+  const int q1 = min(m, q0 + L);
+
+  for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const int64_t o = b / tiles;
+    const int tile = (int)(b - o * tiles);
+    const int i = tile * 32 + col;
+    const bool active = i < nfast;
+    const int32_t *src = in + o * outer_stride + (active ? i : 0);
+    int32_t *dst = out + o * outer_stride + (active ? i : 0);
+    float *dsdf = kWriteSdf ? sdf + o * outer_stride + (active ? i : 0)
+                            : nullptr;
+
+    // Envelope of this segment's sites.
+    int top = -1;
+    uint32_t etop = 0;  // stk[top] cached in a register
+    for (int qb = q0; qb < q1; qb += 8) {
+      int32_t xb[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = qb + t;
+        xb[t] = (active && q < q1) ? src[(int64_t)q * stride] : 0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = qb + t;
+        const int32_t x = xb[t];
+        bool site;
+        int f;
+        if (!inside_ch) {
+          site = x != kInf;
+          f = x > 0 ? x : 0;
+        } else {
+          site = x != -kInf;
+          f = x < 0 ? -x : 0;
+        }
+        site = site && active && q < q1;
+        if (site) {
+          const int fq = f + q * q;
+          while (top >= 1) {
+            const uint32_t eb = stk[(top - 1) * 64 + lane];
+            const int sa = site_of(etop), fa = val_of(etop);
+            const int sb = site_of(eb), fb = val_of(eb);
+            const int64_t lhs = (int64_t)(fq - fa - sa * sa) * (sa - sb);
+            const int64_t rhs =
+                (int64_t)(fa + sa * sa - fb - sb * sb) * (q - sa);
+            if (lhs <= rhs) {
+              --top;
+              etop = eb;
+            } else {
+              break;
+            }
+          }
+          ++top;
+          etop = ((uint32_t)q << 22) | (uint32_t)f;
+          stk[top * 64 + lane] = etop;
+        }
+      }
+    }
+    tops[w * 64 + lane] = top;
+    __syncthreads();
+
+    // Fill this segment from all S envelopes.
+    int tp[S], k[S];
+    uint32_t ek[S], ek1[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t *st = stacks + (size_t)s * L * 64;
+      tp[s] = tops[s * 64 + lane];
+      k[s] = 0;
+      ek[s] = tp[s] >= 0 ? st[lane] : 0;
+      ek1[s] = tp[s] >= 1 ? st[64 + lane] : 0;
+    }
+    for (int qb = q0; qb < q1; qb += 8) {
+      int32_t xb[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = qb + t;
+        xb[t] = (active && q < q1) ? src[(int64_t)q * stride] : 0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = qb + t;
+        if (q >= q1) break;
+        const int32_t x = xb[t];
+        const bool mine = inside_ch ? (x < 0) : (x > 0);
+        // Value of envelope s at q (its walk pointer moves right only; an
+        // envelope skipped for some q catches up when next evaluated).
+        auto eval = [&](int s) -> int32_t {
+          const uint32_t *st = stacks + (size_t)s * L * 64;
+          while (k[s] < tp[s]) {
+            const int dk = q - site_of(ek[s]), dk1 = q - site_of(ek1[s]);
+            const int vk = dk * dk + val_of(ek[s]);
+            const int vk1 = dk1 * dk1 + val_of(ek1[s]);
+            if (vk1 <= vk) {
+              ++k[s];
+              ek[s] = ek1[s];
+              ek1[s] = k[s] < tp[s] ? st[(k[s] + 1) * 64 + lane] : 0;
+            } else {
+              break;
+            }
+          }
+          const int d = q - site_of(ek[s]);
+          return d * d + val_of(ek[s]);
+        };
+        // Own segment first; another segment s is gap voxels away at
+        // least, so it cannot lower a value already <= gap^2.
+        int32_t val = kInf;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (s == w && tp[s] >= 0) val = eval(s);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          if (s == w || tp[s] < 0) continue;
+          const int gap = s < w ? q - ((s + 1) * L - 1) : s * L - q;
+          if (gap * gap >= val) continue;
+          val = min(val, eval(s));
+        }
+        if (mine && active) {
+          const int32_t v = inside_ch ? -val : val;
+          dst[(int64_t)q * stride] = v;
+          if (kWriteSdf) dsdf[(int64_t)q * stride] = ssq_to_metres(v, hf);
+        }
+      }
+    }
+    __syncthreads();  // the stacks are reused by the next column tile
+  }
+}
+
 template <bool G, bool W>
 static void set_lds_attr(size_t bytes) {
   static size_t done = 0;
@@ -271,12 +427,74 @@ static void set_lds_attr(size_t bytes) {
   }
 }
 
+template <int S, bool W>
+static void set_lds_attr_seg(size_t bytes) {
+  static size_t done = 0;
+  if (bytes > 65536 && bytes > done) {
+    (void)hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_pass_col_seg<S, W>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done = bytes;
+  }
+}
+
+template <int S>
+static void launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
+                       float h_f, int nfast, int m, int64_t stride,
+                       int64_t outer_stride, int64_t nblocks, int tiles,
+                       size_t lds, hipStream_t s) {
+  const unsigned grid =
+      (unsigned)(nblocks < (1LL << 30) ? nblocks : (1LL << 30));
+  if (sdf_out) {
+    set_lds_attr_seg<S, true>(lds);
+    hipLaunchKernelGGL((k_pass_col_seg<S, true>), dim3(grid), dim3(64 * S),
+                       lds, s, in, out, sdf_out, h_f, nfast, m, stride,
+                       outer_stride, nblocks, tiles);
+  } else {
+    set_lds_attr_seg<S, false>(lds);
+    hipLaunchKernelGGL((k_pass_col_seg<S, false>), dim3(grid), dim3(64 * S),
+                       lds, s, in, out, sdf_out, h_f, nfast, m, stride,
+                       outer_stride, nblocks, tiles);
+  }
+}
+
+// Segments per column: the tuning's, else one per 32 voxels of the column
+// (at most 8: 16 waves of this kernel exceed the registers of a CU's
+// share and were measured slower).
+static int column_segments(const Handle *h, int m) {
+  if (h->tuning.static_segments > 0) return h->tuning.static_segments;
+  return m >= 256 ? 8 : m >= 128 ? 4 : m >= 64 ? 2 : 1;
+}
+
 int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                     float *sdf_out, float h_f, int nfast, int nouter, int m,
                     int64_t stride, int64_t outer_stride, hipStream_t s) {
   if (nfast <= 0 || nouter <= 0 || m <= 0) return PCSDF_OK;
   const int tiles = (nfast + 31) / 32;
   const int64_t nblocks = (int64_t)tiles * nouter;
+  int S = column_segments(h, m);
+  while (S > 1 && S > m) S >>= 1;  // a power of two, at most m
+  if (S > 1) {
+    const int L = (m + S - 1) / S;
+    const size_t lds_seg = ((size_t)S * L * 64 + (size_t)S * 64) * 4;
+    if ((int64_t)lds_seg <= h->max_lds) {
+      switch (S) {
+        case 2:
+          launch_seg<2>(in, out, sdf_out, h_f, nfast, m, stride, outer_stride,
+                        nblocks, tiles, lds_seg, s);
+          break;
+        case 4:
+          launch_seg<4>(in, out, sdf_out, h_f, nfast, m, stride, outer_stride,
+                        nblocks, tiles, lds_seg, s);
+          break;
+        default:
+          launch_seg<8>(in, out, sdf_out, h_f, nfast, m, stride, outer_stride,
+                        nblocks, tiles, lds_seg, s);
+          break;
+      }
+      return check_launch(h, "pass_col_seg");
+    }
+  }
   const size_t lds = (size_t)m * 64 * sizeof(uint32_t);
   const dim3 block(64);
   if ((int64_t)lds <= h->max_lds) {

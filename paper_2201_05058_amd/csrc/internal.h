@@ -81,6 +81,10 @@ class ProfScope {
   hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
+// Waits for the handle's pending timed regions and adds them to its
+// totals.
+int drain_profile(Handle *h);
+
 // Records `msg` as the handle's last error and returns `code`.
 int fail(Handle *h, int code, const std::string &msg);
 

@@ -110,7 +110,7 @@ static int batch(FILE *f, FILE *o) {
   memcpy(pbase, host.data(), host.size());
   const SceneDev *scenes = (const SceneDev *)pbase;
   const int4 *items = (const int4 *)(pbase + param_layout(bp).items);
-  const uint32_t *tiles = (const uint32_t *)(pbase + param_layout(bp).tiles);
+  const int32_t *scene_of = (const int32_t *)(pbase + param_layout(bp).groups);
   const int np = (int)bp.items.size();
   for (int phase = 0; phase < 2; ++phase) {
     std::vector<std::thread> th;
@@ -121,7 +121,8 @@ static int batch(FILE *f, FILE *o) {
         if (phase == 0)
           batch_planes(scenes, items, np, bp.lds_cap, lds.data());
         else
-          batch_composites(scenes, tiles, ns, bp.G, bp.chunk_voxels);
+          batch_composites(scenes, scene_of, bp.composite_items, bp.G,
+                           bp.chunk_voxels);
       });
     for (auto &t : th) t.join();
   }
@@ -129,7 +130,7 @@ static int batch(FILE *f, FILE *o) {
     fwrite(oc[q].data(), 4, oc[q].size(), o);
     fwrite(of[q].data(), 4, of[q].size(), o);
   }
-  printf("planar items %d composite items %u\n", np, bp.tile_start.back());
+  printf("planar items %d composite items %u\n", np, bp.composite_items);
   return 0;
 }
 

@@ -71,11 +71,12 @@ def test_planar_helpers_match_oracle(harness, tmp_path, idx):
 
 
 def ragged(seed):
-    # nx*ny odd, divisible by 4 (also with nx odd), and 2 mod 4: the
-    # composite's 1-, 4- and 2-voxel packs
+    # nx*ny odd, divisible by 4 (also with nx odd), 2 mod 4, and odd with
+    # V divisible by 4: the composite's 1-, 4- and 2-voxel packs, and 4-wide
+    # packs whose planar values are gathered
     dims = [(37, 29, 23, 3, 2), (64, 48, 40, 5, 3), (21, 60, 17, 1, 1),
             (100, 36, 30, 7, 4), (8, 8, 8, 2, 0), (44, 44, 44, 6, 4),
-            (34, 27, 13, 3, 2)]
+            (34, 27, 13, 3, 2), (33, 27, 20, 2, 2)]
     out = []
     for q, (nx, ny, nz, n, K) in enumerate(dims):
         sc = scenegen.small_scene(seed + q, nx, ny, nz, h=0.05, n_boxes=5,

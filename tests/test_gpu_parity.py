@@ -85,6 +85,30 @@ def test_static_build_long_columns(pc, dev, shape):
     np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
 
 
+@pytest.mark.parametrize("shape", [(37, 29, 67), (600, 9, 40), (29, 131, 67)])
+def test_static_build_every_segment_count(pc, dev, shape):
+    """The column passes split each column into 1, 2, 4 or 8 segments (one
+    wave each); every count gives the oracle's bytes, also when the column
+    length is not a multiple of the count and when the segments' stacks
+    need more than 64 KB of LDS (600-voxel columns)."""
+    rng = np.random.default_rng(11)
+    grid = scenegen.Grid(shape[2], shape[1], shape[0], 0.05)
+    occ = (rng.random(shape) < 0.02).astype(np.uint8)
+    rs, rf = oracle.build_static(grid, occ)
+    occ_d = to_dev(occ, dev)
+    h = pc.Handle()
+    try:
+        for S in (1, 2, 4, 8):
+            say(f"static segments shape={shape} S={S}")
+            h.set_tuning({"static_segments": S})
+            ssq, sdf = pc.build_static_sdf(grid, occ_d, handle=h)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
+            assert_f32_close(sdf.cpu().numpy(), rf)
+    finally:
+        h.close()
+
+
 def test_static_build_cube64_and_fp32_exact(pc, dev):
     sc = scenegen.cube64()
     ssq, sdf = gpu_static(pc, sc.grid, sc.occ, dev)
@@ -126,17 +150,41 @@ def test_composite_small_scenes(pc, dev, seed, dims, K, n):
     check_composite(pc, sc, dev)
 
 
-@pytest.mark.parametrize("dims", [(21, 60, 17), (130, 70, 9), (34, 27, 13),
-                                  (33, 27, 21)])
+def width_case_scene(dims):
+    """Scenes for the composite's pack shapes.  Planes of fewer than four
+    pixels get one free-standing human on a nearly empty grid, tall enough
+    to end inside it, so that every layer (and every layer boundary a pack
+    crosses) has its own value."""
+    nx, ny, nz = dims
+    if nx * ny >= 4:
+        return scenegen.small_scene(21, nx, ny, nz, h=0.05, n_boxes=5,
+                                    n_humans=3, n_slices=3)
+    sc = scenegen.small_scene(22, nx, ny, nz, h=0.25, n_boxes=1, n_humans=1,
+                              n_slices=3, height=0.6)
+    ext = sc.grid.extent
+    sc.occ[:] = 0
+    sc.occ[-1, 0, 0] = 1
+    sc.human_xy = np.array([[[(0.3 + 0.3 * s) * ext[0], 0.5 * ext[1]]]
+                            for s in range(3)])
+    return sc
+
+
+@pytest.mark.parametrize("dims", [
+    (21, 60, 17), (130, 70, 9),   # 4-wide, nx odd / nx = 2 mod 4
+    (34, 27, 13),                 # 2-wide planar packs (V = 2 mod 4)
+    (33, 27, 20), (34, 27, 12),   # 4-wide streams, planar values gathered
+    (33, 27, 22),                 # 2-wide streams, gathered
+    (33, 27, 21),                 # 1-wide (V odd)
+    (1, 1, 8), (3, 1, 4), (2, 1, 6)])  # planes smaller than a pack
 @pytest.mark.parametrize("offset", [0, 1, 2])
 def test_composite_vector_widths_and_alignment(pc, dev, dims, offset):
-    """The composite streams 4, 2 or 1 voxels per lane by nx*ny mod 4 (0
-    with nx odd, 0 with nx = 2 mod 4, 2, odd) and by the alignment of its
-    three buffers: buffers offset by one or two elements (4- and 8-byte
-    aligned) take the narrower packs.  Every case gives the oracle's
-    bytes."""
-    sc = scenegen.small_scene(21, *dims, h=0.05, n_boxes=5, n_humans=3,
-                              n_slices=3)
+    """The composite streams 4, 2 or 1 voxels per lane by V mod 4 and the
+    alignment of its three buffers, reading the planar values as one
+    vector when the pack width divides nx*ny and one by one otherwise
+    (a pack may then cross layer boundaries).  Buffers offset by one or two
+    elements (4- and 8-byte aligned) take the narrower packs.  Every case
+    gives the oracle's bytes."""
+    sc = width_case_scene(dims)
     say(f"composite widths grid={dims} offset={offset}")
     n, V = sc.n_slices, sc.grid.nvox
     shp = (n,) + sc.grid.shape_zyx
@@ -153,6 +201,7 @@ def test_composite_vector_widths_and_alignment(pc, dev, dims, offset):
     rs, _ = oracle.build_static(sc.grid, sc.occ)
     wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
                                         sc.height)
+    assert np.unique(wc).size > 2  # the case has structure to get wrong
     np.testing.assert_array_equal(oc.cpu().numpy(), wc)
     assert_f32_close(of.cpu().numpy(), wf)
 
