@@ -104,8 +104,17 @@ def cpu_baseline(sc, max_slices: int):
     oracle.predicted_composite(sc.grid, rs, sc.human_xy[:n], sc.radius,
                                sc.height)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": sc.grid.nvox * n / dt, "unit": "voxel-slices/s",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", "cpu_model": model,
             "sample": f"{n} of {sc.n_slices} slices of the same workload "
                       f"(single-threaded C oracle, {dt:.1f} s)"}
 
@@ -115,11 +124,18 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
     64..128 at 0.02-0.05 m): one captured hipGraph replay of the batch
     against 64 plain calls on one stream, same outputs, by wall time and by
     GPU time (the plain calls' wall time includes the host's per-call
-    work).  Static fields are built before timing."""
+    work).  Static fields are built before timing; their GPU time is
+    reported beside it (the variant that includes them)."""
     from paper_2201_05058_amd import _native
     scs = scenegen.batch64()
     h = pc.Handle()
     scenes = []
+    occ0 = torch.from_numpy(scs[0].occ).to(dev)  # warm the static kernels
+    pc.build_static_sdf(scs[0].grid, occ0, want_sdf=False, handle=h)
+    torch.cuda.synchronize()
+    del occ0
+    h.profile(True)
+    h.profile_reset()
     for sc in scs:
         occ = torch.from_numpy(sc.occ).to(dev)
         ssq, _ = pc.build_static_sdf(sc.grid, occ, want_sdf=False, handle=h)
@@ -132,6 +148,9 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
                                               device=dev),
                        "out_sdf": torch.empty(shp, dtype=torch.float32,
                                               device=dev)})
+    torch.cuda.synchronize()
+    static_gpu = h.profile_read(_native.KERNEL_STATIC)[0]
+    h.profile(False)
     vs = sum(sc.grid.nvox * sc.n_slices for sc in scs)
     tuning, _, _ = autotune.tuned(
         h, autotune.batch_signature(scenes),
@@ -173,11 +192,98 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
     return {"scenes": len(scs), "voxel_slices": vs,
             "graph_ms": g_ms, "plain_64_calls_ms": p_ms,
             "graph_gpu_ms": g_gpu, "plain_64_calls_gpu_ms": p_gpu,
+            "static_builds_64_gpu_ms": static_gpu,
+            "graph_plus_static_builds_gpu_ms": g_gpu + static_gpu,
             "speedup_vs_plain_gpu": p_gpu / g_gpu,
             "graph_voxel_slices_per_s": vs / (g_ms / 1e3),
             "plain_voxel_slices_per_s": vs / (p_ms / 1e3),
             "speedup_vs_plain": p_ms / g_ms,
             "graph_gbs_8B_basis": 8.0 * vs / (g_ms / 1e3) / 1e9,
+            "tuning": tuning}
+
+
+def room512_section(pc, autotune, scenegen, torch, dev, reps: int = 3):
+    """The largest workload, 512x512x256 at 0.01 m with 200 boxes, 8 humans
+    on piecewise-linear paths, 50 slices at dt = 0.05 s and 100k spheres
+    per slice (5M): the static build, the composite of all 50 slices (26.8
+    GB of outputs) and the 5M exact queries, on fields and without them,
+    by GPU time (HIP events around the kernels)."""
+    from paper_2201_05058_amd import _native
+    sc = scenegen.room512()
+    g = sc.grid
+    n, V = sc.n_slices, g.nvox
+    q = sc.queries
+    h = pc.Handle()
+    occ = torch.from_numpy(sc.occ).to(dev)
+    ssq_s, sdf_s = pc.build_static_sdf(g, occ, handle=h)
+    torch.cuda.synchronize()
+    h.profile(True)
+    h.profile_reset()
+    for _ in range(reps):
+        pc.build_static_sdf(g, occ, ssq=ssq_s, sdf=sdf_s, handle=h)
+    torch.cuda.synchronize()
+    static_ms = h.profile_read(_native.KERNEL_STATIC)[0] / reps
+    del occ, sdf_s
+    shp = (n,) + g.shape_zyx
+    out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
+    out_sdf = torch.empty(shp, dtype=torch.float32, device=dev)
+    scene = {"grid": g, "static_ssq": ssq_s, "human_xy": sc.human_xy,
+             "radius": sc.radius, "height": sc.height, "out_ssq": out_ssq,
+             "out_sdf": out_sdf}
+    tuning, _, _ = autotune.tuned(
+        h, autotune.composite_signature(g, n, sc.n_humans),
+        lambda: pc.autotune_composite(scene, reps=2, handle=h)[:2])
+    h.profile(True)
+
+    def run():
+        pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
+                                   sc.height, out_ssq=out_ssq,
+                                   out_sdf=out_sdf, handle=h)
+    run()
+    torch.cuda.synchronize()
+    h.profile_reset()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    comp_ms = h.profile_read(_native.KERNEL_COMPOSITE)[0] / reps
+    planes_ms = h.profile_read(_native.KERNEL_PLANES)[0] / reps
+    centre = torch.from_numpy(q.centre).to(dev)
+    radius = torch.from_numpy(q.radius).to(dev)
+    slices = torch.from_numpy(q.slice).to(dev)
+    Q = len(q.radius)
+    pc.query_spheres(g, out_sdf, centre, radius, slices, handle=h)
+    torch.cuda.synchronize()
+    h.profile_reset()
+    for _ in range(reps):
+        pc.query_spheres(g, out_sdf, centre, radius, slices, handle=h)
+    torch.cuda.synchronize()
+    query_ms = h.profile_read(_native.KERNEL_QUERY)[0] / reps
+    del out_ssq, out_sdf
+    torch.cuda.empty_cache()
+    pc.query_spheres_direct(g, ssq_s, sc.human_xy, sc.radius, sc.height,
+                            centre, radius, slices, handle=h)
+    torch.cuda.synchronize()
+    h.profile_reset()
+    for _ in range(reps):
+        pc.query_spheres_direct(g, ssq_s, sc.human_xy, sc.radius, sc.height,
+                                centre, radius, slices, handle=h)
+    torch.cuda.synchronize()
+    direct_ms = (h.profile_read(_native.KERNEL_QUERY)[0] +
+                 h.profile_read(_native.KERNEL_PLANES)[0]) / reps
+    h.close()
+    b = (8.0 + 4.0 / n) * V * n
+    return {"grid": [g.nx, g.ny, g.nz], "n_slices": n,
+            "n_humans": sc.n_humans, "voxel_slices": V * n,
+            "static_build_ms": static_ms,
+            "static_build_gbs_9B_basis": 9.0 * V / (static_ms * 1e-3) / 1e9,
+            "composite_ms": comp_ms, "planes_ms": planes_ms,
+            "composite_gbs_8B_basis": b / (comp_ms * 1e-3) / 1e9,
+            "composite_frac_8B_basis": b / (comp_ms * 1e-3) / 1e9 /
+            HBM_PEAK_GBS,
+            "voxel_slices_per_s": V * n / ((comp_ms + planes_ms) * 1e-3),
+            "queries": Q, "exact_query_ms": query_ms,
+            "queries_per_s_exact": Q / (query_ms * 1e-3),
+            "direct_query_ms_incl_planes": direct_ms,
             "tuning": tuning}
 
 
@@ -337,6 +443,8 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-scene batch measurement")
+    ap.add_argument("--no-room512", action="store_true",
+                    help="skip the 512x512x256 x 50-slice measurement")
     ap.add_argument("--no-recompute", action="store_true",
                     help="skip the composite vs full recompute measurement")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -480,6 +588,8 @@ def main():
     if not args.no_batch:
         line["batch64"] = batch_section(pc, autotune, scenegen, torch,
                                               dev)
+    if not args.no_room512:
+        line["room512"] = room512_section(pc, autotune, scenegen, torch, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_slices)
     print(json.dumps(line), flush=True)
