@@ -416,46 +416,42 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
   }
 }
 
-template <bool G, bool W>
-static void set_lds_attr(size_t bytes) {
-  static size_t done = 0;
-  if (bytes > 65536 && bytes > done) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass_col<G, W>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
-    done = bytes;
-  }
-}
-
-template <int S, bool W>
-static void set_lds_attr_seg(size_t bytes) {
-  static size_t done = 0;
-  if (bytes > 65536 && bytes > done) {
-    (void)hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&k_pass_col_seg<S, W>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    done = bytes;
-  }
+// Workgroups using more than 64 KB of LDS need the kernel's limit raised
+// on the current device; the call is cheap and made before each such
+// launch (a cached flag would be process-wide, not per device, and shared
+// between threads).
+static hipError_t allow_lds(const void *kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
 template <int S>
-static void launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
-                       float h_f, int nfast, int m, int64_t stride,
-                       int64_t outer_stride, int64_t nblocks, int tiles,
-                       size_t lds, hipStream_t s) {
+static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
+                             float h_f, int nfast, int m, int64_t stride,
+                             int64_t outer_stride, int64_t nblocks, int tiles,
+                             size_t lds, hipStream_t s) {
   const unsigned grid =
       (unsigned)(nblocks < (1LL << 30) ? nblocks : (1LL << 30));
   if (sdf_out) {
-    set_lds_attr_seg<S, true>(lds);
+    const hipError_t e =
+        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, true>),
+                  lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_pass_col_seg<S, true>), dim3(grid), dim3(64 * S),
                        lds, s, in, out, sdf_out, h_f, nfast, m, stride,
                        outer_stride, nblocks, tiles);
   } else {
-    set_lds_attr_seg<S, false>(lds);
+    const hipError_t e =
+        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, false>),
+                  lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_pass_col_seg<S, false>), dim3(grid), dim3(64 * S),
                        lds, s, in, out, sdf_out, h_f, nfast, m, stride,
                        outer_stride, nblocks, tiles);
   }
+  return hipSuccess;
 }
 
 // Segments per column: the tuning's, else one per 32 voxels of the column
@@ -478,20 +474,25 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
     const int L = (m + S - 1) / S;
     const size_t lds_seg = ((size_t)S * L * 64 + (size_t)S * 64) * 4;
     if ((int64_t)lds_seg <= h->max_lds) {
+      hipError_t e;
       switch (S) {
         case 2:
-          launch_seg<2>(in, out, sdf_out, h_f, nfast, m, stride, outer_stride,
-                        nblocks, tiles, lds_seg, s);
+          e = launch_seg<2>(in, out, sdf_out, h_f, nfast, m, stride,
+                            outer_stride, nblocks, tiles, lds_seg, s);
           break;
         case 4:
-          launch_seg<4>(in, out, sdf_out, h_f, nfast, m, stride, outer_stride,
-                        nblocks, tiles, lds_seg, s);
+          e = launch_seg<4>(in, out, sdf_out, h_f, nfast, m, stride,
+                            outer_stride, nblocks, tiles, lds_seg, s);
           break;
         default:
-          launch_seg<8>(in, out, sdf_out, h_f, nfast, m, stride, outer_stride,
-                        nblocks, tiles, lds_seg, s);
+          e = launch_seg<8>(in, out, sdf_out, h_f, nfast, m, stride,
+                            outer_stride, nblocks, tiles, lds_seg, s);
           break;
       }
+      if (e != hipSuccess)
+        return fail(h, PCSDF_ERR_HIP,
+                    std::string("raising the LDS limit of pass_col_seg: ") +
+                        hipGetErrorString(e));
       return check_launch(h, "pass_col_seg");
     }
   }
@@ -500,17 +501,22 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   if ((int64_t)lds <= h->max_lds) {
     const unsigned grid = (unsigned)(nblocks < (1LL << 30) ? nblocks
                                                            : (1LL << 30));
-    if (sdf_out) {
-      set_lds_attr<false, true>(lds);
+    const void *kfn =
+        sdf_out ? reinterpret_cast<const void *>(&k_pass_col<false, true>)
+                : reinterpret_cast<const void *>(&k_pass_col<false, false>);
+    const hipError_t e = allow_lds(kfn, lds);
+    if (e != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("raising the LDS limit of pass_col: ") +
+                      hipGetErrorString(e));
+    if (sdf_out)
       hipLaunchKernelGGL((k_pass_col<false, true>), dim3(grid), block, lds,
                          s, in, out, sdf_out, h_f, nfast, m, stride,
                          outer_stride, nblocks, tiles, nullptr);
-    } else {
-      set_lds_attr<false, false>(lds);
+    else
       hipLaunchKernelGGL((k_pass_col<false, false>), dim3(grid), block, lds,
                          s, in, out, sdf_out, h_f, nfast, m, stride,
                          outer_stride, nblocks, tiles, nullptr);
-    }
     return check_launch(h, "pass_col");
   }
   // Columns too long for LDS: stacks in a workspace slab, a bounded
