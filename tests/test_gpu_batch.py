@@ -107,7 +107,8 @@ def test_two_launch_batch_matches_plain_and_oracle(pc, dev):
 
 
 @pytest.mark.parametrize("G,C,B", [(1, 256, 1), (3, 512, 2), (2, 8192, 4),
-                                   (7, 32768, 8), (30, 1024, 32)])
+                                   (7, 32768, 8), (30, 1024, 32),
+                                   (4, 256, 0), (1, 1024, 0), (3, 4096, 0)])
 def test_batch_any_tuning_gives_identical_bytes(pc, dev, G, C, B):
     h = pc.Handle()
     h.set_tuning({"batch_slices_per_item": G, "batch_chunk_quads": C,

@@ -251,10 +251,45 @@ def test_composite_cube64(pc, dev):
     check_composite(pc, scenegen.cube64(), dev)
 
 
+@pytest.fixture(scope="module")
+def room256_ref():
+    sc = scenegen.room256()
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                        sc.height)
+    return sc, wc, wf
+
+
 @pytest.mark.slow
-def test_composite_room256_full(pc, dev):
+def test_composite_room256_full(pc, dev, room256_ref):
     """The full 256x256x128 x 20-slice workload, element by element."""
-    check_composite(pc, scenegen.room256(), dev)
+    sc, wc, wf = room256_ref
+    say("composite room256 full")
+    _, c, cf = run_composite(pc, sc, dev)
+    np.testing.assert_array_equal(c.cpu().numpy(), wc)
+    assert_f32_close(cf.cpu().numpy(), wf)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("G", [1, 3, 5, 10, 20])
+def test_composite_room256_every_slice_group(pc, dev, room256_ref, G):
+    """The same workload in the other launch shapes the autotuner chooses
+    between (slices per block row): the oracle's bytes in each."""
+    sc, wc, wf = room256_ref
+    say(f"composite room256 with {G} slices per block row")
+    occ_d = to_dev(sc.occ.astype(np.uint8), dev)
+    h = pc.Handle()
+    try:
+        h.set_tuning({"composite_slices_per_block": G})
+        ssq_s, _ = pc.build_static_sdf(sc.grid, occ_d, want_sdf=False,
+                                       handle=h)
+        c, cf = pc.predicted_composite_sdf(sc.grid, ssq_s, sc.human_xy,
+                                           sc.radius, sc.height, handle=h)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(c.cpu().numpy(), wc)
+        assert_f32_close(cf.cpu().numpy(), wf)
+    finally:
+        h.close()
 
 
 def test_composite_deterministic_and_on_side_stream(pc, dev):

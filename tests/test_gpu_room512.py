@@ -110,3 +110,25 @@ def test_queries_on_oracle_slices(run, slice_oracle):
     assert (err <= 1e-6 * np.maximum(np.abs(wd), sc.grid.h)).all()
     err = np.abs(g.astype(np.float64) - wg)
     assert (err <= 1e-6 * np.maximum(np.abs(wg), 1.0)).all()
+
+
+@pytest.mark.parametrize("G", [5, 10, 25])
+def test_other_slice_groups_give_identical_bytes(run, G):
+    """The composite in the launch shapes the autotuner picks for this
+    workload (it has chosen 10 slices per block row): the same bytes as
+    the default shape checked above, for all 50 slices."""
+    import paper_2201_05058_amd as pc
+    sc = run["sc"]
+    say(f"room512: composite with {G} slices per block row")
+    h = pc.Handle()
+    try:
+        h.set_tuning({"composite_slices_per_block": G})
+        c, cf = pc.predicted_composite_sdf(sc.grid, run["ssq_s"], sc.human_xy,
+                                           sc.radius, sc.height, handle=h)
+        torch.cuda.synchronize()
+        assert torch.equal(c, run["c"])
+        assert torch.equal(cf.view(torch.int32), run["cf"].view(torch.int32))
+        del c, cf
+    finally:
+        h.close()
+    torch.cuda.empty_cache()
