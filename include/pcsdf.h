@@ -390,11 +390,15 @@ int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n, const float *x_dev,
                          float beta2, float eps, float *loss_dev,
                          void *stream);
 
-/* Network input for sphere queries: x[q] = [c_x, c_y, c_z, t, state[0..17]]
- * with t = dt_s * clamp(slice[q], 0, n_slices - 1).  state_host holds the
- * 18 state features (three humans' position x, y, z and velocity x, y, z
- * in metres and metres per second, at t = 0).  centre_dev [n][3],
- * slice_dev [n], x_dev [n][22] (fp32, caller-owned). */
+/* Network input for sphere queries, a fixed transform of the query and the
+ * humans' state: x[q] = [c_x, c_y, c_z, t, then per human k
+ * (dx_k, dy_k, rho_k, vx_k, vy_k, 0)] with t = dt_s * clamp(slice[q], 0,
+ * n_slices - 1), (dx_k, dy_k) = c_xy - (p_k + v_k t) the offset from the
+ * human's axis at t and rho_k = |(dx_k, dy_k)| (fp32, in that order of
+ * operations, no contraction, correctly rounded square root).  state_host
+ * holds the 18 state floats: per human its position (x, y, 0) and
+ * velocity (vx, vy, 0) at t = 0, in metres and metres per second.
+ * centre_dev [n][3], slice_dev [n], x_dev [n][22] (fp32, caller-owned). */
 int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
                              const float *centre_dev,
                              const int32_t *slice_dev, int32_t n_slices,
@@ -425,6 +429,9 @@ int pcsdf_surrogate_features_pool(pcsdf_handle *h, int32_t n_queries,
  * fp32); where s wins (ties included) the gradient is the environment's.
  * A query falls back to the exact path when
  *   - its predicted sphere distance y(c, t) - r is below fallback_margin_m,
+ *     (dy/dc is the network's feature gradient taken through the transform
+ *     of pcsdf_surrogate_features: G_c + sum_k (G_dk + G_rhok (dx_k, dy_k)
+ *     / rho_k) in x and y, 0 for the ratio on an axis),
  *   - the network's value or gradient is not finite, or
  *   - its centre lies outside the span of voxel centres (the exact path then
  *     clamps and flags it);

@@ -6,9 +6,25 @@ Not in the paper: a learned stand-in for the obstacle factors' field
 lookups (RHAP-GPMP2 section: distance and gradient of the composite field
 at the collision spheres, with a hinge cost).  Definition:
 
-  x   = [c_x, c_y, c_z, t, state (18)],  t = fp32(clamp(s, 0, n-1)) * fp32(dt)
-        (one fp32 product, as the network's input is fp32);
-  y   = network(x) in metres, g = dy/d(c_x, c_y, c_z)  (oracle/mlp.py);
+  inputs: the centre c, the slice s and the humans' state (18 floats: per
+        human k its position (px_k, py_k, 0) at t = 0 and its velocity
+        (vx_k, vy_k, 0));
+  t   = fp32(clamp(s, 0, n-1)) * fp32(dt) (one fp32 product);
+  x   = the network's 22 features, a fixed transform of the inputs, all in
+        fp32 in this order of operations:
+          x[0:3] = c,  x[3] = t,
+          per human k (x[4+6k : 10+6k]):
+            qx = px_k + vx_k * t,  qy = py_k + vy_k * t   (its axis at t),
+            dx = c_x - qx,  dy = c_y - qy,
+            rho = sqrt(dx * dx + dy * dy)      (horizontal distance to the
+                                                axis; correctly rounded),
+            [dx, dy, rho, vx_k, vy_k, 0];
+  y   = network(x) in metres (oracle/mlp.py), G = dy/dx (22);
+  g   = dy/dc through the transform:
+          g_x = G[0] + sum_k (G[4+6k] + G[6+6k] * dx_k / rho_k),
+          g_y = G[1] + sum_k (G[5+6k] + G[6+6k] * dy_k / rho_k),
+          g_z = G[2],
+        the ratios taken as 0 where rho_k = 0, the sums in k order in fp32;
   a query with slice s < 0 returns NaN and the SLICE_NEG bit (as exact);
   it is answered exactly (oracle.query on the composite fields) when its
   centre lies outside the span of voxel centres, or when y - r is below the
@@ -34,15 +50,46 @@ SLICE_CLAMPED, SLICE_NEG = 8, 32
 
 
 def features(centre, slices, n_slices: int, dt: float, state) -> np.ndarray:
+    """The network's 22 features (module docstring), fp32."""
     c = np.asarray(centre, np.float32).reshape(-1, 3)
     s = np.clip(np.asarray(slices, np.int64).reshape(-1), 0, n_slices - 1)
     st = np.asarray(state, np.float32).reshape(-1)
     assert st.size == 18
-    x = np.empty((c.shape[0], 22), np.float32)
+    t = s.astype(np.float32) * np.float32(dt)
+    x = np.zeros((c.shape[0], 22), np.float32)
     x[:, 0:3] = c
-    x[:, 3] = s.astype(np.float32) * np.float32(dt)
-    x[:, 4:] = st[None, :]
+    x[:, 3] = t
+    for k in range(3):
+        px, py, vx, vy = st[6 * k], st[6 * k + 1], st[6 * k + 3], st[6 * k + 4]
+        qx = px + vx * t
+        qy = py + vy * t
+        dx = c[:, 0] - qx
+        dy = c[:, 1] - qy
+        b = 4 + 6 * k
+        x[:, b] = dx
+        x[:, b + 1] = dy
+        x[:, b + 2] = np.sqrt(dx * dx + dy * dy)
+        x[:, b + 3] = vx
+        x[:, b + 4] = vy
     return x
+
+
+def centre_gradient(x, G) -> np.ndarray:
+    """dy/dc from the feature gradient G [n, 22] (module docstring), fp32."""
+    x = np.asarray(x, np.float32)
+    G = np.asarray(G).astype(np.float32)
+    gx, gy, gz = G[:, 0].copy(), G[:, 1].copy(), G[:, 2].copy()
+    for k in range(3):
+        b = 4 + 6 * k
+        rho = x[:, b + 2]
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ux = np.where(rho > 0, x[:, b] / rho, np.float32(0))
+            uy = np.where(rho > 0, x[:, b + 1] / rho, np.float32(0))
+        gx = gx + G[:, b]
+        gx = gx + G[:, b + 2] * ux.astype(np.float32)
+        gy = gy + G[:, b + 1]
+        gy = gy + G[:, b + 2] * uy.astype(np.float32)
+    return np.stack([gx, gy, gz], axis=1).astype(np.float32)
 
 
 def in_span(grid, centre) -> np.ndarray:
@@ -68,7 +115,7 @@ def query(grid, sdf, params, in_offset, in_scale, out_scale, state, dt,
         y, _ = _mlp.forward(p, x, in_offset, in_scale, out_scale)
         gx = _mlp.input_gradient(p, x, in_offset, in_scale, out_scale)
     y32 = np.asarray(y).astype(np.float32).copy()
-    g32 = np.asarray(gx)[:, :3].astype(np.float32).copy()
+    g32 = centre_gradient(x, gx)
     if static_sdf is not None:
         e, eg, _, _ = _exact_query(
             grid, np.asarray(static_sdf, np.float32).reshape(

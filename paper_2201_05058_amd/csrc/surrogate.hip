@@ -40,6 +40,40 @@ struct NetState {
 };
 
 // x[q][0..21] for queries [0, n): one lane per query, constant indices only.
+// The network's 22 features of one query (fp32, no contraction: this
+// file is built with -ffp-contract=off): the centre, t, then per human k
+// its horizontal offset from the centre to its axis at t, the distance to
+// that axis (correctly rounded sqrtf) and its velocity:
+//   [c, t, (dx_k, dy_k, rho_k, vx_k, vy_k, 0) for k = 0, 1, 2],
+//   dx_k = c_x - (px_k + vx_k t), dy_k = c_y - (py_k + vy_k t),
+// from the 18-float state (per human: px, py, 0, vx, vy, 0).  A fixed
+// transform of the query and the state: the distance to a human is a
+// simple function of its offset, which a small network fits far better
+// than the products v t it would otherwise have to learn.
+__device__ __forceinline__ void fill_features(float *row, float cx, float cy,
+                                              float cz, float t,
+                                              const float *st) {
+  row[0] = cx;
+  row[1] = cy;
+  row[2] = cz;
+  row[3] = t;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float *h = st + 6 * k;
+    const float qx = h[0] + h[3] * t;
+    const float qy = h[1] + h[4] * t;
+    const float dx = cx - qx;
+    const float dy = cy - qy;
+    float *f = row + 4 + 6 * k;
+    f[0] = dx;
+    f[1] = dy;
+    f[2] = sqrtf(dx * dx + dy * dy);
+    f[3] = h[3];
+    f[4] = h[4];
+    f[5] = 0.f;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_features(
     const float *__restrict__ centre, const int32_t *__restrict__ slice,
     int n_slices, float dt, NetState st, int n, float *__restrict__ x) {
@@ -47,13 +81,8 @@ __global__ __launch_bounds__(256) void k_features(
   if (q >= n) return;
   int s = slice[q];
   s = s < 0 ? 0 : (s > n_slices - 1 ? n_slices - 1 : s);
-  float *row = x + (int64_t)q * kNetIn;
-  row[0] = centre[3 * q];
-  row[1] = centre[3 * q + 1];
-  row[2] = centre[3 * q + 2];
-  row[3] = (float)s * dt;
-#pragma unroll
-  for (int c = 0; c < kState; ++c) row[4 + c] = st.v[c];
+  fill_features(x + (int64_t)q * kNetIn, centre[3 * q], centre[3 * q + 1],
+                centre[3 * q + 2], (float)s * dt, st.v);
 }
 
 // Pool variant: query q belongs to human configuration c = slice[q] /
@@ -68,14 +97,32 @@ __global__ __launch_bounds__(256) void k_features_pool(
   const int total = n_slices * n_configs;
   g = g < 0 ? 0 : (g > total - 1 ? total - 1 : g);
   const int c = g / n_slices, s = g - c * n_slices;
-  float *row = x + (int64_t)q * kNetIn;
-  row[0] = centre[3 * q];
-  row[1] = centre[3 * q + 1];
-  row[2] = centre[3 * q + 2];
-  row[3] = (float)s * dt;
-  const float *st = states + (int64_t)c * kState;
+  fill_features(x + (int64_t)q * kNetIn, centre[3 * q], centre[3 * q + 1],
+                centre[3 * q + 2], (float)s * dt,
+                states + (int64_t)c * kState);
+}
+
+// dy/dc from the network's feature gradient G (22) through the transform
+// above: g_x = G0 + sum_k (G[4+6k] + G[6+6k] dx_k / rho_k), likewise g_y
+// with dy_k, g_z = G2; the ratios are 0 on an axis (rho_k = 0).
+__device__ __forceinline__ void centre_gradient(const float *x,
+                                                const float *G, float *g0,
+                                                float *g1, float *g2) {
+  float gx = G[0], gy = G[1];
 #pragma unroll
-  for (int k = 0; k < kState; ++k) row[4 + k] = st[k];
+  for (int k = 0; k < 3; ++k) {
+    const int b = 4 + 6 * k;
+    const float rho = x[b + 2];
+    const float ux = rho > 0.f ? x[b] / rho : 0.f;
+    const float uy = rho > 0.f ? x[b + 1] / rho : 0.f;
+    gx = gx + G[b];
+    gx = gx + G[b + 2] * ux;
+    gy = gy + G[b + 1];
+    gy = gy + G[b + 2] * uy;
+  }
+  *g0 = gx;
+  *g1 = gy;
+  *g2 = G[2];
 }
 
 __global__ void k_clear(int32_t *__restrict__ p, int n) {
@@ -84,7 +131,7 @@ __global__ void k_clear(int32_t *__restrict__ p, int n) {
 }
 
 struct DecideArgs {
-  const float *y, *gx, *centre, *radius;
+  const float *y, *gx, *x, *centre, *radius;
   const float *static_sdf;  // [V] or null (network answers alone)
   const int32_t *slice;
   int n, n_slices, nx, ny, nz;
@@ -130,9 +177,9 @@ __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
         inside = inside && g >= 0.0 && g <= (double)(n3[a] - 1);
       }
       float v = A.y[q];
-      float g0 = A.gx[(int64_t)q * kNetIn];
-      float g1 = A.gx[(int64_t)q * kNetIn + 1];
-      float g2 = A.gx[(int64_t)q * kNetIn + 2];
+      float g0, g1, g2;
+      centre_gradient(A.x + (int64_t)q * kNetIn, A.gx + (int64_t)q * kNetIn,
+                      &g0, &g1, &g2);
       if (A.static_sdf && inside) {
         // the network predicts the humans' part: the answer is the smaller
         // of it and the environment field (exact, sampled as the exact
@@ -323,6 +370,7 @@ extern "C" int pcsdf_query_spheres_surrogate(
   DecideArgs A;
   A.y = y;
   A.gx = gx;
+  A.x = x;
   A.centre = centre_dev;
   A.radius = radius_dev;
   A.static_sdf = static_sdf_dev;

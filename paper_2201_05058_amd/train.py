@@ -56,12 +56,19 @@ LABEL_FLOOR = -0.1
 CAP_ABOVE_ENV = 0.2
 
 
+# Name of the network's input transform (the features kernels): weights
+# trained on another transform are refused by load().
+FEATURES = "axis-offsets-v1"
+
+
 def normalisation(grid):
-    """Input offset/scale mapping the room to [-1, 1], the slice time and
-    speeds to about unit range.  Feature order: centre x y z, t, then per
-    human position x y z and velocity x y z."""
+    """Input offset/scale bringing the features to about unit range.
+    Feature order: centre x y z, t, then per human the offset (dx, dy) from
+    its axis at t to the centre, the distance rho to that axis, its
+    velocity (vx, vy) and a zero slot."""
     L = np.array(grid.extent, np.float64)
     o = np.array(grid.origin, np.float64)
+    D = float(np.hypot(L[0], L[1]))
     off = np.zeros(NIN, np.float64)
     scl = np.ones(NIN, np.float64)
     off[0:3] = o + L / 2
@@ -69,8 +76,8 @@ def normalisation(grid):
     off[3], scl[3] = 1.0, 1.0
     for k in range(3):
         b = 4 + 6 * k
-        off[b:b + 2] = o[:2] + L[:2] / 2
-        scl[b:b + 2] = 2.0 / L[:2]
+        scl[b:b + 2] = 1.0 / L[:2]
+        off[b + 2], scl[b + 2] = D / 2, 2.0 / D
         scl[b + 3:b + 5] = 1.0 / 1.5
     return off.astype(np.float32), scl.astype(np.float32)
 
@@ -241,7 +248,8 @@ def train(scene, dev, samples=50_000_000, batch=16384, pool=48,
 def save(path, net, info, scene):
     np.savez(path, params=net.get_params(), in_offset=info["in_offset"],
              in_scale=info["in_scale"], out_scale=np.float32(1.0),
-             meta=json.dumps({"room": scene.name, "seed": scene.seed,
+             meta=json.dumps({"features": FEATURES,
+                              "room": scene.name, "seed": scene.seed,
                               "grid": [scene.grid.nx, scene.grid.ny,
                                        scene.grid.nz],
                               "voxel_m": scene.grid.h,
@@ -258,10 +266,15 @@ def save(path, net, info, scene):
 def load(path, handle=None):
     """(network, meta dict) from a file written by save()."""
     d = np.load(path, allow_pickle=False)
+    meta = json.loads(str(d["meta"]))
+    if meta.get("features") != FEATURES:
+        raise ValueError(
+            f"{path}: weights trained on input transform "
+            f"{meta.get('features')!r}, this library computes {FEATURES!r}")
     net = Mlp(handle or default_handle())
     net.set_params(d["params"], d["in_offset"], d["in_scale"],
                    float(d["out_scale"]))
-    return net, json.loads(str(d["meta"]))
+    return net, meta
 
 
 def _time_ms(fn, reps=5, warmup=2):

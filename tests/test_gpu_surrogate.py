@@ -101,10 +101,16 @@ def check_exact(got_d, got_g, got_st, got_c, wd, wg, wst, wc, h):
 def test_surrogate_matches_oracle(sg, dev, seed, hybrid):
     sc, c, r, s, st, rs, wf = make_case(seed)
     rng = np.random.default_rng(seed + 7)
-    p = rand_net(seed, gain=2.5)  # outputs spread across the margin
+    p = rand_net(seed, gain=2.5)  # outputs spread widely
     off = (rng.normal(size=22) * 0.1).astype(np.float32)
     scl = (0.5 + rng.random(22)).astype(np.float32)
     osc, margin, eps = 0.4, 0.10, 0.3
+    # centre the outputs on the decision boundary (the output bias moves
+    # every output by the same amount) so that both branches are taken
+    x0 = osur.features(c, s, sc.n_slices, sc.dt, st)
+    y0 = omlp.forward(p.astype(np.float64), x0, off, scl, osc)[0]
+    p[-1] += np.float32((margin + np.median(r) - np.median(y0[s >= 0]))
+                        / osc)
     say(f"surrogate parity seed={seed} hybrid={hybrid} Q={len(r)}")
     env_gpu = env = None
     if hybrid:
@@ -117,7 +123,8 @@ def test_surrogate_matches_oracle(sg, dev, seed, hybrid):
         sc.grid, wf, p, off, scl, osc, st, sc.dt, c, r, s, margin, eps,
         static_sdf=env)
     x = osur.features(c, s, sc.n_slices, sc.dt, st)
-    wgx = omlp.input_gradient(p.astype(np.float64), x, off, scl, osc)[:, :3]
+    wgx = osur.centre_gradient(
+        x, omlp.input_gradient(p.astype(np.float64), x, off, scl, osc))
     used = res["used_fallback"]
     neg = s < 0
     rms = np.sqrt(np.mean(wy[~neg] ** 2))

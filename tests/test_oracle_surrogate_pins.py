@@ -87,13 +87,70 @@ def test_nonfinite_network_falls_back():
 
 
 def test_feature_layout():
-    st = np.arange(18, dtype=np.float32)
-    x = osur.features(np.array([[1, 2, 3], [4, 5, 6]], np.float32),
-                      np.array([7, -2]), 5, 0.1, st)
-    np.testing.assert_array_equal(x[0, :3], [1, 2, 3])
-    assert x[0, 3] == np.float32(4) * np.float32(0.1)  # clamped to n-1 = 4
-    assert x[1, 3] == 0.0
-    np.testing.assert_array_equal(x[:, 4:], np.stack([st, st]))
+    """A worked example with exact binary values: human 0 starts at (1, 1)
+    with velocity (2, -2); at slice 2 of dt = 0.25 (t = 0.5) its axis is at
+    (2, 0), so a centre at (5, 4) is 3, 4 from it and 5 from the axis.
+    Slices are clamped to [0, n-1] for t."""
+    st = np.zeros(18, np.float32)
+    st[0:6] = [1, 1, 0, 2, -2, 0]
+    st[6:12] = [5, 4, 0, 0, 0, 0]      # on the centre: rho = 0
+    st[12:18] = [-1, 4, 0, 0.5, 0, 0]  # axis at (-0.75, 4) at t = 0.5
+    c = np.array([[5, 4, 7], [5, 4, 7]], np.float32)
+    x = osur.features(c, np.array([2, 9]), 3, 0.25, st)
+    np.testing.assert_array_equal(x[0, :4], [5, 4, 7, 0.5])
+    np.testing.assert_array_equal(x[0, 4:10], [3, 4, 5, 2, -2, 0])
+    np.testing.assert_array_equal(x[0, 10:16], [0, 0, 0, 0, 0, 0])
+    np.testing.assert_array_equal(x[0, 16:22], [5.75, 0, 5.75, 0.5, 0, 0])
+    assert x[1, 3] == np.float32(2) * np.float32(0.25)  # slice 9 -> n-1 = 2
+
+
+def test_centre_gradient_unit_cases():
+    """dy/dc through the transform for unit feature gradients: the centre
+    itself, a human's offsets (+1 along their axis) and its axis distance
+    (the unit vector away from the axis, 0 on the axis)."""
+    st = np.zeros(18, np.float32)
+    st[0:6] = [1, 1, 0, 2, -2, 0]
+    st[6:12] = [5, 4, 0, 0, 0, 0]
+    x = osur.features(np.array([[5, 4, 7]], np.float32), np.array([2]), 3,
+                      0.25, st)
+    cases = {0: [1, 0, 0], 1: [0, 1, 0], 2: [0, 0, 1], 3: [0, 0, 0],
+             4: [1, 0, 0], 5: [0, 1, 0], 6: [0.6, 0.8, 0], 7: [0, 0, 0],
+             12: [0, 0, 0]}  # 12: rho of human 1, who stands on the centre
+    for f, want in cases.items():
+        G = np.zeros((1, 22))
+        G[0, f] = 1.0
+        np.testing.assert_allclose(osur.centre_gradient(x, G)[0], want,
+                                   rtol=0, atol=1e-7, err_msg=str(f))
+
+
+def test_centre_gradient_matches_finite_differences():
+    """The chain rule against central differences of the fp64 network
+    (no rounding) composed with the feature transform, away from the
+    humans' axes."""
+    rng = np.random.default_rng(5)
+    p = omlp.pack([rng.normal(0, 0.3, s) for s in omlp.SHAPES])
+    off = np.zeros(22)
+    scl = np.full(22, 0.4)
+    st = np.zeros(18, np.float32)
+    st[0:6] = [1.0, 1.5, 0, 0.5, -0.25, 0]
+    st[6:12] = [3.0, 0.5, 0, -0.5, 0.75, 0]
+    st[12:18] = [0.5, 3.5, 0, 1.0, 0.0, 0]
+    c = np.array([[2.2, 2.9, 1.1], [0.4, 0.9, 0.3], [3.3, 3.1, 1.9]],
+                 np.float64)
+    s = np.array([1, 3, 2])
+
+    def y_of(cc):
+        xx = osur.features(cc.astype(np.float32), s, 5, 0.25, st)
+        return omlp.forward(p, xx, off, scl, 1.0, rounding=False)[0]
+    x = osur.features(c.astype(np.float32), s, 5, 0.25, st)
+    G = omlp.input_gradient(p, x, off, scl, 1.0, rounding=False)
+    g = osur.centre_gradient(x, G)
+    eps = 1e-2
+    for a in range(3):
+        d = np.zeros(3)
+        d[a] = eps
+        num = (y_of(c + d) - y_of(c - d)) / (2 * eps)
+        np.testing.assert_allclose(g[:, a], num, rtol=2e-3, atol=2e-4)
 
 
 def test_span_boundary():
