@@ -55,6 +55,7 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
     import statistics
 
     def load(sub):
+        # per kernel: {grid size: [counter values]}
         d = {}
         path = None
         for root, _, files in os.walk(os.path.join(prof_dir, sub)):
@@ -62,17 +63,27 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
                 if fn.endswith("counter_collection.csv"):
                     path = os.path.join(root, fn)
         for r in csv.DictReader(open(path)):
-            d.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+            d.setdefault(r["Kernel_Name"], {}).setdefault(
+                int(r["Grid_Size"]), []).append(float(r["Counter_Value"]))
         return d
+
+    def step_launches(d):
+        # the timed step's launch shape: the one dispatched most often
+        by_grid = d["k_composite"]
+        g = max(by_grid, key=lambda k: len(by_grid[k]))
+        return g, by_grid[g]
     f, w = load("prof_fetch"), load("prof_write")
     cf, cw = load("prof_cfetch"), load("prof_cwrite")
     ck = [k for k in cf if "copyBuffer" in k][0]
     copy = 1024 * 2 ** 20
-    fs = copy / (statistics.mean(cf[ck]) * 1024)
-    ws = copy / (statistics.mean(cw[ck]) * 1024)
-    fb = statistics.mean(f["k_composite"]) * 1024 * fs
-    wb = statistics.mean(w["k_composite"]) * 1024 * ws
+    fs = copy / (statistics.mean(sum(cf[ck].values(), [])) * 1024)
+    ws = copy / (statistics.mean(sum(cw[ck].values(), [])) * 1024)
+    grid, fv = step_launches(f)
+    _, wv = step_launches(w)
+    fb = statistics.mean(fv) * 1024 * fs
+    wb = statistics.mean(wv) * 1024 * ws
     return {"kernel": "k_composite", "V": V, "n_slices": n,
+            "grid_size": grid, "launches": len(fv),
             "fetch_bytes": fb, "write_bytes": wb,
             "bytes_per_launch": fb + wb, "fetch_scale": fs,
             "write_scale": ws,

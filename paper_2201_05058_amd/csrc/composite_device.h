@@ -20,8 +20,8 @@
 
 namespace pcsdf {
 
-// Packs of VEC int32 or fp32 values, and their loads and stores as global
-// memory instructions.  Pointers read from memory (the batch's scene
+// Packs of VEC int32 or fp32 values, and their loads as global memory
+// instructions.  Pointers read from memory (the batch's scene
 // table) would otherwise be accessed with flat instructions, which the
 // compiler cannot count in order: every wait for one of them then waits
 // for all outstanding loads and stores.  The casts are written per
@@ -72,9 +72,6 @@ struct Pack<1> {
 #define PCSDF_GLOBAL_IO(T)                                           \
   __device__ __forceinline__ T ld_global(const T *p) {              \
     return *(PCSDF_GLOBAL_AS const T *)p;                            \
-  }                                                                  \
-  __device__ __forceinline__ void st_global(T *p, T v) {            \
-    *(PCSDF_GLOBAL_AS T *)p = v;                                     \
   }
 PCSDF_GLOBAL_IO(pk_i32x4)
 PCSDF_GLOBAL_IO(pk_i32x2)
@@ -88,14 +85,17 @@ template <int VEC>
 __device__ __forceinline__ typename Pack<VEC>::I load_i32(const int32_t *p) {
   return ld_global(reinterpret_cast<const typename Pack<VEC>::I *>(p));
 }
+// The outputs are written once and not read back by the kernel: stores
+// with the nontemporal hint (no write-allocation in the caches; measured
+// as fast at 256 x 256 x 128 and up to a quarter faster on smaller grids).
 template <int VEC>
 __device__ __forceinline__ void store_i32(int32_t *p,
                                           typename Pack<VEC>::I v) {
-  st_global(reinterpret_cast<typename Pack<VEC>::I *>(p), v);
+  __builtin_nontemporal_store(v, reinterpret_cast<typename Pack<VEC>::I *>(p));
 }
 template <int VEC>
 __device__ __forceinline__ void store_f32(float *p, typename Pack<VEC>::F v) {
-  st_global(reinterpret_cast<typename Pack<VEC>::F *>(p), v);
+  __builtin_nontemporal_store(v, reinterpret_cast<typename Pack<VEC>::F *>(p));
 }
 
 // An empty statement that reads a pack's registers: the compiler makes the

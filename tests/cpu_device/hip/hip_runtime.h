@@ -31,6 +31,7 @@ inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ
 #define __builtin_amdgcn_s_sleep(n) sched_yield()
 #define __builtin_amdgcn_fence(o, s) __atomic_thread_fence(o)
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
 typedef int hipError_t;
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
