@@ -298,6 +298,72 @@ def room512_section(pc, autotune, scenegen, torch, dev, reps: int = 3):
             "tuning": tuning}
 
 
+def next_rows_section(pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h,
+                      reps: int = 5):
+    """The adjacent variants on the same workload, by GPU time: the
+    composite with radii growing over the horizon (r0 + 0.05 m/s * t), the
+    map collapsed to the floor plane and its 2-D signed EDT, and GPMP2
+    obstacle factors (hinge errors, Jacobians, per-state costs) of 64
+    spheres at 100 support states spread over the 20 slices."""
+    import numpy as np
+    from paper_2201_05058_amd import _native
+    g = sc.grid
+    n = sc.n_slices
+    dev = ssq_s.device
+    radii = sc.radius + 0.05 * sc.dt * np.arange(n)
+
+    def grow():
+        pc.predicted_composite_sdf_growing(g, ssq_s, sc.human_xy, radii,
+                                           sc.height, out_ssq=out_ssq,
+                                           out_sdf=out_sdf, handle=h)
+    grow()
+    torch.cuda.synchronize()
+    h.profile_reset()
+    for _ in range(reps):
+        grow()
+    torch.cuda.synchronize()
+    grow_ms = (h.profile_read(_native.KERNEL_COMPOSITE)[0] +
+               h.profile_read(_native.KERNEL_PLANES)[0]) / reps
+
+    def stream_ms(fn):
+        fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+    floor_ms = stream_ms(lambda: pc.build_floor_sdf(g, occ, handle=h))
+
+    S, J = 100, 64
+    rng = np.random.Generator(np.random.PCG64(9))
+    lo = np.array(g.origin) + 0.1
+    span = np.array(g.extent) - 0.2
+    centre = torch.from_numpy((rng.random((S, J, 3)) * span + lo)
+                              .astype(np.float32)).to(dev)
+    radius = torch.from_numpy(rng.uniform(0.05, 0.15, J)
+                              .astype(np.float32)).to(dev)
+    st_slice = torch.from_numpy((np.arange(S) * n // S)
+                                .astype(np.int32)).to(dev)
+    pc.obstacle_factors(g, out_sdf, centre, radius, st_slice, 0.2, 0.1,
+                        handle=h)
+    torch.cuda.synchronize()
+    h.profile_reset()
+    for _ in range(reps):
+        pc.obstacle_factors(g, out_sdf, centre, radius, st_slice, 0.2, 0.1,
+                            handle=h)
+    torch.cuda.synchronize()
+    fac_ms = h.profile_read(_native.KERNEL_FACTORS)[0] / reps
+    return {"growing_radius_composite_ms": grow_ms,
+            "growing_radius_voxel_slices_per_s": g.nvox * n / (grow_ms / 1e3),
+            "floor_edt_ms": floor_ms, "floor_grid": [g.nx, g.ny],
+            "obstacle_factors_ms": fac_ms,
+            "obstacle_factors_sphere_states": S * J,
+            "sphere_states_per_s": S * J / (fac_ms / 1e3)}
+
+
 def recompute_section(pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h,
                       reps: int = 3):
     """The paper's composite benchmark (mapping section, Fig. 6) on this
@@ -593,6 +659,8 @@ def main():
             pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h)
         line["template_composite"] = template_section(
             pc, torch, sc, ssq_s, out_ssq, out_sdf, h)
+        line["next_rows"] = next_rows_section(pc, torch, sc, occ, ssq_s,
+                                              out_ssq, out_sdf, h)
     del out_ssq, out_sdf
     if not args.no_surrogate:
         line["surrogate"] = surrogate_section(pc, torch, dev, args.weights)

@@ -326,7 +326,7 @@ class _BatchScenes:
 
 
 def predicted_composite_sdf_batch(scenes, handle: Handle | None = None):
-    """All scenes in two persistent launches
+    """All scenes in two launches, planar items then composite items
     (pcsdf_predicted_composite_sdf_batch).  `scenes` is a list of dicts
     with keys grid, static_ssq, human_xy, radius, height and optionally
     out_ssq / out_sdf / want_ssq / want_sdf.  Returns [(ssq, sdf), ...]."""

@@ -1,5 +1,5 @@
 // Device side of the batched composite (see batch.hip): scene table entry,
-// planar-field item, composite chunk and the persistent worker loop.
+// planar-field item, composite chunk and the worker loops.
 #pragma once
 
 #include <hip/hip_runtime.h>

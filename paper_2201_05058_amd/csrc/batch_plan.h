@@ -198,7 +198,4 @@ inline size_t plan_scratch(const BatchPlan &bp) {
   return t;
 }
 
-// Enqueues counter reset and the persistent kernel (parameters already
-// uploaded to bufs.params).
-
 }  // namespace pcsdf

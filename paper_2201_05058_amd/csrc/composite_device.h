@@ -98,18 +98,6 @@ __device__ __forceinline__ void store_f32(float *p, typename Pack<VEC>::F v) {
   __builtin_nontemporal_store(v, reinterpret_cast<typename Pack<VEC>::F *>(p));
 }
 
-// An empty statement that reads a pack's registers: the compiler makes the
-// loads that write them complete before it.
-template <int VEC>
-__device__ __forceinline__ void wait_for(const typename Pack<VEC>::I &v) {
-#if defined(__clang__)
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) asm volatile("" ::"v"(v[e]));
-#else
-  (void)v;
-#endif
-}
-
 // Pack shape of the streaming epilogue: `vec` voxels per lane (4, 2 or 1),
 // set by V and the alignment of the three streams; `gather` when the
 // plane size is not a multiple of vec, so that the vec planar values are
@@ -192,8 +180,8 @@ __device__ __forceinline__ void composite_pack(
     int s_begin, int s_end, int Kt, int has_above, float hf) {
   const PackCoords<VEC, kGather> pc = pack_coords<VEC, kGather>(v0, plane);
   // A short loop (the tuned slice groups are 2 or 3 slices): loading the
-  // next slice's planar pack ahead of the stores was measured slower here
-  // than the waits it avoids, unlike the batch's longer persistent loops.
+  // next slice's planar pack ahead of the stores was measured slower than
+  // the waits it avoids.
   const typename Pack<VEC>::I s = load_i32<VEC>(S + v0);
   for (int sl = s_begin; sl < s_end; ++sl) {
     if (kNeed && need[sl] == 0) continue;

@@ -1,5 +1,5 @@
 // Device helpers of the humans' planar field, shared by the per-call
-// kernels (planes.hip) and the persistent batch kernel (batch.hip).
+// kernels (planes.hip) and the batch's planar workers (batch.hip).
 // See planes.hip for the method: exact integer chords of the voxelised
 // disks, a row pass of the free set, and bounded row searches.
 #pragma once
