@@ -416,6 +416,55 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
   }
 }
 
+// The same pass with one lane per voxel, for passes with few columns (a
+// one-layer grid, e.g. the map collapsed to the floor, has only nx/32 column
+// tiles): voxel q of its channel takes g(q) = min_p f(p) + (q - p)^2 by
+// searching p = q -+ d for d = 1, 2, ... until d^2 >= the best value so
+// far (no farther p can be smaller, f >= 0).  Exact, like the envelope;
+// its work grows with the distance found, so it is kept to small passes.
+template <bool kWriteSdf>
+__global__ __launch_bounds__(256) void k_pass_col_search(
+    const int32_t *__restrict__ in, int32_t *__restrict__ out,
+    float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
+    int64_t outer_stride, int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const int i = (int)(t % nfast);
+  const int64_t rest = t / nfast;
+  const int q = (int)(rest % m);
+  const int64_t o = rest / m;
+  const int32_t *src = in + o * outer_stride + i;
+  const int32_t x = src[(int64_t)q * stride];
+  const bool inside = x < 0;  // occupied: the free set's channel
+  // value of row p in this voxel's channel (kInf: no site in that row)
+  auto f_of = [&](int32_t v) -> int32_t {
+    if (!inside) return v == kInf ? kInf : (v > 0 ? v : 0);
+    return v == -kInf ? kInf : (v < 0 ? -v : 0);
+  };
+  int32_t best = f_of(x);
+  const int dmax = max(q, m - 1 - q);
+  for (int d = 1; d <= dmax; ++d) {
+    const int32_t d2 = d * d;
+    if (d2 >= best) break;
+    if (q - d >= 0) {
+      const int32_t f = f_of(src[(int64_t)(q - d) * stride]);
+      if (f != kInf) best = min(best, d2 + f);
+    }
+    if (q + d < m) {
+      const int32_t f = f_of(src[(int64_t)(q + d) * stride]);
+      if (f != kInf) best = min(best, d2 + f);
+    }
+  }
+  const int32_t v = inside ? (best == kInf ? -kInf : -best) : best;
+  int32_t *dst = out + o * outer_stride + i;
+  dst[(int64_t)q * stride] = v;
+  if (kWriteSdf)
+    sdf[o * outer_stride + i + (int64_t)q * stride] = ssq_to_metres(v, hf);
+}
+
+// Column tiles below which a pass runs one lane per voxel.
+constexpr int64_t kSearchTiles = 64;
+
 // Workgroups using more than 64 KB of LDS need the kernel's limit raised
 // on the current device; the call is cheap and made before each such
 // launch (a cached flag would be process-wide, not per device, and shared
@@ -468,6 +517,19 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   if (nfast <= 0 || nouter <= 0 || m <= 0) return PCSDF_OK;
   const int tiles = (nfast + 31) / 32;
   const int64_t nblocks = (int64_t)tiles * nouter;
+  if (nblocks < kSearchTiles && h->tuning.static_segments == 0) {
+    const int64_t total = (int64_t)nfast * m * nouter;
+    const unsigned grid = (unsigned)((total + 255) / 256);
+    if (sdf_out)
+      hipLaunchKernelGGL((k_pass_col_search<true>), dim3(grid), dim3(256), 0,
+                         s, in, out, sdf_out, h_f, nfast, m, stride,
+                         outer_stride, total);
+    else
+      hipLaunchKernelGGL((k_pass_col_search<false>), dim3(grid), dim3(256),
+                         0, s, in, out, sdf_out, h_f, nfast, m, stride,
+                         outer_stride, total);
+    return check_launch(h, "pass_col_search");
+  }
   int S = column_segments(h, m);
   while (S > 1 && S > m) S >>= 1;  // a power of two, at most m
   if (S > 1) {

@@ -53,9 +53,13 @@ def gpu_static(pc, grid, occ, dev):
 
 # ------------------------------------------------------------ static build
 
+# Passes with fewer than 64 column tiles of 32 run one lane per voxel (a
+# search outward along the column), the others the segmented envelopes:
+# the small and one-layer shapes take the first, the larger the second.
 STATIC_SHAPES = [  # (nz, ny, nx)
     (1, 1, 1), (1, 1, 9), (1, 7, 1), (5, 1, 1), (4, 5, 6), (12, 12, 12),
     (29, 131, 67), (33, 70, 130), (3, 2, 200), (7, 64, 64), (2, 3, 1024),
+    (1, 300, 257), (1, 256, 256),
 ]
 
 
