@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -116,15 +117,6 @@ __host__ __device__ inline PackShape composite_shape(int64_t plane, int64_t V,
   return PackShape{1, false};
 }
 
-// The humans' value at layer kk for planar value p.
-__device__ __forceinline__ int32_t human_at(int32_t p, int kk, int Kt,
-                                            int has_above) {
-  const int dzo = kk > Kt ? kk - Kt : 0;
-  const int32_t dz2i =
-      has_above ? (Kt + 1 - kk) * (Kt + 1 - kk) : INT32_MAX;
-  return human_value(p, dzo * dzo, kk <= Kt, dz2i);
-}
-
 // Planar index and layer of voxels v0 .. v0+VEC-1.  Without kGather they
 // share one layer and are consecutive in the plane; with it, each voxel
 // gets its own (a pack may cross layer boundaries, several when the
@@ -153,6 +145,18 @@ __device__ __forceinline__ PackCoords<VEC, kGather> pack_coords(
   return c;
 }
 
+// Element `byte_off` bytes past a base pointer.  With a base that is the
+// same for the whole wave and a 32-bit offset, the access is a global
+// instruction with the base in scalar registers and only the offset in a
+// vector register, so no 64-bit address arithmetic runs per lane.
+template <class T>
+__device__ __forceinline__ T *at_bytes(T *base, uint32_t byte_off) {
+  return reinterpret_cast<T *>(
+      reinterpret_cast<typename std::conditional<
+          std::is_const<T>::value, const char, char>::type *>(base) +
+      byte_off);
+}
+
 // The VEC planar values of a pack in slice plane Ps.
 template <int VEC, bool kGather>
 __device__ __forceinline__ typename Pack<VEC>::I load_planar(
@@ -161,10 +165,11 @@ __device__ __forceinline__ typename Pack<VEC>::I load_planar(
     typename Pack<VEC>::I p;
 #pragma unroll
     for (int e = 0; e < VEC; ++e)
-      p[e] = ld_global(reinterpret_cast<const pk_i32x1 *>(Ps + c.pix[e]))[0];
+      p[e] = ld_global(reinterpret_cast<const pk_i32x1 *>(
+          at_bytes(Ps, c.pix[e] * 4u)))[0];
     return p;
   } else {
-    return load_i32<VEC>(Ps + c.pix[0]);
+    return load_i32<VEC>(at_bytes(Ps, c.pix[0] * 4u));
   }
 }
 
@@ -179,10 +184,24 @@ __device__ __forceinline__ void composite_pack(
     float *__restrict__ of, uint32_t plane, uint32_t V, uint32_t v0,
     int s_begin, int s_end, int Kt, int has_above, float hf) {
   const PackCoords<VEC, kGather> pc = pack_coords<VEC, kGather>(v0, plane);
+  constexpr int NL = kGather ? VEC : 1;
+  HumanLayer hl[NL];
+#pragma unroll
+  for (int e = 0; e < NL; ++e) {
+    hl[e] = human_layer(pc.k[e], Kt, has_above);
+#if defined(__clang__)
+    // Opaque to the optimiser, which would otherwise apply the addition
+    // under a select of its own in the loop (one more instruction per
+    // voxel and slice).
+    asm("" : "+v"(hl[e].lo), "+v"(hl[e].add));
+#endif
+  }
+  // V <= 2^30, so byte offsets within one slice fit in 32 bits.
+  const uint32_t vb = v0 * 4u;
   // A short loop (the tuned slice groups are 2 or 3 slices): loading the
   // next slice's planar pack ahead of the stores was measured slower than
   // the waits it avoids.
-  const typename Pack<VEC>::I s = load_i32<VEC>(S + v0);
+  const typename Pack<VEC>::I s = load_i32<VEC>(at_bytes(S, vb));
   for (int sl = s_begin; sl < s_end; ++sl) {
     if (kNeed && need[sl] == 0) continue;
     const typename Pack<VEC>::I p =
@@ -190,14 +209,13 @@ __device__ __forceinline__ void composite_pack(
     typename Pack<VEC>::I c;
 #pragma unroll
     for (int e = 0; e < VEC; ++e)
-      c[e] = min(s[e], human_at(p[e], pc.k[kGather ? e : 0], Kt, has_above));
-    const size_t o = (size_t)sl * V + v0;
-    if (kSsq) store_i32<VEC>(oc + o, c);
+      c[e] = min(s[e], human_value(p[e], hl[kGather ? e : 0]));
+    if (kSsq) store_i32<VEC>(at_bytes(oc + (size_t)sl * V, vb), c);
     if (kSdf) {
       typename Pack<VEC>::F f;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) f[e] = ssq_to_metres(c[e], hf);
-      store_f32<VEC>(of + o, f);
+      store_f32<VEC>(at_bytes(of + (size_t)sl * V, vb), f);
     }
   }
 }

@@ -7,32 +7,77 @@
 
 namespace pcsdf {
 
-// Signed squared voxel distance -> signed metres:
-// F(x) = sign(x) * ((float)h * sqrtf(|x|)), +-inf for +-INT32_MAX.
-// The square root is taken first, then one fp32 multiply; hipcc's default
-// -fhip-fp32-correctly-rounded-divide-sqrt makes sqrtf correctly rounded.
-__device__ __forceinline__ float ssq_to_metres(int32_t x, float hf) {
-  const float a = (float)(x < 0 ? -x : x);  // exact: |x| < 2^24
-  const float r = hf * sqrtf(a);
-  const float m = (x == INT32_MAX || x == -INT32_MAX) ? __builtin_inff() : r;
-  return x < 0 ? -m : m;
+// Saturating int32 addition.
+__device__ __forceinline__ int32_t add_sat(int32_t a, int32_t b) {
+#if defined(__clang__)
+  return __builtin_elementwise_add_sat(a, b);
+#else  // a host compiler building the device code for CPU tests
+  const int64_t s = (int64_t)a + b;
+  return s > INT32_MAX ? INT32_MAX : (s < INT32_MIN ? INT32_MIN : (int32_t)s);
+#endif
 }
 
-// Value of the humans' signed field at a voxel of layer k whose planar
-// signed value is p (E_D outside D, -E_{Gxy\D} inside, +-INT32_MAX if the other
-// set is empty).  dz2o = max(0, k-Kt)^2; zin = (k <= Kt); dz2i =
-// (Kt+1-k)^2 when layer Kt+1 exists, else INT32_MAX.
-__device__ __forceinline__ int32_t human_value(int32_t p, int dz2o, bool zin,
-                                               int32_t dz2i) {
-  // Written as selects (no branches): p + dz2o outside the disks (wrapping
-  // arithmetic, used only when p < INT32_MAX), the top of the cylinders
-  // above them, min(-p, dz2i) negated inside (-p is INT32_MAX when the
-  // disks cover the plane), INT32_MAX when the slice has no human voxel.
-  const int32_t outside = (int32_t)((uint32_t)p + (uint32_t)dz2o);
-  const int32_t din = -p;  // p >= -INT32_MAX, so no overflow
-  const int32_t inside = zin ? -(din < dz2i ? din : dz2i) : dz2o;
-  const int32_t r = p > 0 ? outside : inside;
-  return p == INT32_MAX ? INT32_MAX : r;
+// Correctly rounded square root of a float a that is 0 or at least 1 (here
+// the magnitude of an integer squared distance).  The hardware root r is
+// within one ulp for such inputs, so the rounded root is r or one of its
+// neighbouring floats r- < r < r+; Tuckerman's rounding test picks it:
+// r- when a <= r- r, r+ when a > r r+, else r (each residual a - r' r
+// formed by one fused multiply-add, whose sign is exact).  For a = 0 the
+// hardware returns 0, r- is a NaN, and both tests keep 0.  No scaling is
+// needed: the inputs are never subnormal.
+__device__ __forceinline__ float sqrt_rn_nonneg(float a) {
+#if defined(__clang__)
+  const float r = __builtin_amdgcn_sqrtf(a);
+#else  // a host compiler building the device code for CPU tests
+  const float r = __builtin_sqrtf(a);
+#endif
+  const float rm = __builtin_bit_cast(float, __builtin_bit_cast(int32_t, r) - 1);
+  const float rp = __builtin_bit_cast(float, __builtin_bit_cast(int32_t, r) + 1);
+  const float em = __builtin_fmaf(-rm, r, a);
+  const float ep = __builtin_fmaf(-rp, r, a);
+  const float lo = em <= 0.f ? rm : r;
+  return ep > 0.f ? rp : lo;
+}
+
+// Signed squared voxel distance -> signed metres:
+// F(x) = sign(x) * ((float)h * sqrtf(|x|)), +-inf for +-INT32_MAX.
+// The square root is correctly rounded, then one fp32 multiply.  |x| is
+// below 2^22 for grids of at most 1024 voxels per axis, so its conversion
+// is exact; +-INT32_MAX converts to +-2^31, which no distance reaches and
+// which is replaced by infinity before the root (whose rounding test keeps
+// it: both residuals are NaN), so that no lane branches.
+__device__ __forceinline__ float ssq_to_metres(int32_t x, float hf) {
+  const float xf = (float)x;
+  const float a0 = __builtin_fabsf(xf);
+  const float a = a0 == 2147483648.0f ? __builtin_inff() : a0;
+  return __builtin_copysignf(hf * sqrt_rn_nonneg(a), xf);
+}
+
+// The humans' signed value at layer k is a function of the pixel's planar
+// signed value p (E_D outside the disk union D, -E of its complement
+// inside, +-INT32_MAX when the other set is empty) and two constants of
+// the layer.  At or below the cylinders' top layer Kt: p outside the
+// disks, and inside the larger (nearer to zero) of p and -(Kt+1-k)^2, the
+// squared distance to the free layer above (none when Kt is the grid's
+// last layer); together, max(p, lo).  Above Kt: (k-Kt)^2 plus the planar
+// distance outside the disks, (k-Kt)^2 over them; together, max(p, 0) +
+// add.  The addition saturates, so that p = INT32_MAX (no human voxel in
+// the slice) stays INT32_MAX.
+struct HumanLayer {
+  int32_t lo, add;
+};
+__device__ __forceinline__ HumanLayer human_layer(int k, int Kt,
+                                                  int has_above) {
+  const int dz = k - Kt;  // > 0 above the cylinders
+  const int dzp = max(dz, 0);
+  const int upp = max(Kt + 1 - k, 0);  // 0 above the cylinders
+  HumanLayer t;
+  t.lo = has_above ? -(upp * upp) : (dz > 0 ? 0 : -INT32_MAX);
+  t.add = dzp * dzp;
+  return t;
+}
+__device__ __forceinline__ int32_t human_value(int32_t p, HumanLayer t) {
+  return add_sat(max(p, t.lo), t.add);
 }
 
 }  // namespace pcsdf

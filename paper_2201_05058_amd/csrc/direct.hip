@@ -53,6 +53,8 @@ __device__ __forceinline__ void answer_direct(const DirectArgs &A, int q) {
       cell_of(A.nx, A.ny, A.nz, A.h, A.ox, A.oy, A.oz, A.centre + 3 * q);
   st |= C.status;
   const int32_t *P = A.P + (int64_t)s * A.nx * A.ny;
+  const HumanLayer hl[2] = {human_layer(C.idx[2], A.Kt, A.has_above),
+                            human_layer(C.idx[2] + 1, A.Kt, A.has_above)};
   double c[2][2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -63,10 +65,7 @@ __device__ __forceinline__ void answer_direct(const DirectArgs &A, int q) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int k = C.idx[2] + e;
-        const int dzo = k > A.Kt ? k - A.Kt : 0;
-        const int32_t dz2i =
-            A.has_above ? (A.Kt + 1 - k) * (A.Kt + 1 - k) : kInf;
-        const int32_t hv = human_value(p, dzo * dzo, k <= A.Kt, dz2i);
+        const int32_t hv = human_value(p, hl[e]);
         const int32_t sv = A.S[((int64_t)k * A.ny + j) * A.nx + i];
         c[a][b][e] = (double)ssq_to_metres(min(sv, hv), A.hf);
       }
