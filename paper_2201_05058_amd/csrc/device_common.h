@@ -28,6 +28,8 @@ __device__ __forceinline__ int32_t add_sat(int32_t a, int32_t b) {
 __device__ __forceinline__ float sqrt_rn_nonneg(float a) {
 #if defined(__clang__)
   const float r = __builtin_amdgcn_sqrtf(a);
+#elif defined(PCSDF_HOST_ROOT_START)  // CPU test of the rounding step
+  const float r = PCSDF_HOST_ROOT_START(a);
 #else  // a host compiler building the device code for CPU tests
   const float r = __builtin_sqrtf(a);
 #endif

@@ -121,3 +121,16 @@ def test_batch_planner_and_workers_match_oracle(harness, tmp_path, threads,
                                             sc.height)
         np.testing.assert_array_equal(c, wc)
         np.testing.assert_array_equal(f, wf.view(np.int32))
+
+
+def test_signed_root_rounding(tmp_path):
+    """The signed root's rounding step (device_common.h) against IEEE sqrt:
+    start values one ulp off either way, every integer up to 2^22."""
+    exe = str(tmp_path / "root_check")
+    subprocess.run(["g++", "-O1", "-std=c++20", "-ffp-contract=off",
+                    "-I" + os.path.join(HERE, "cpu_device"), "-o", exe,
+                    os.path.join(HERE, "cpu_device", "root_check.cpp")],
+                   check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "mismatches 0" in r.stdout
