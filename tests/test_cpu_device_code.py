@@ -76,7 +76,8 @@ def ragged(seed):
     # packs whose planar values are gathered
     dims = [(37, 29, 23, 3, 2), (64, 48, 40, 5, 3), (21, 60, 17, 1, 1),
             (100, 36, 30, 7, 4), (8, 8, 8, 2, 0), (44, 44, 44, 6, 4),
-            (34, 27, 13, 3, 2), (33, 27, 20, 2, 2)]
+            (34, 27, 13, 3, 2), (33, 27, 20, 2, 2),
+            (30, 1000, 6, 2, 8)]  # chord table beyond the items' LDS
     out = []
     for q, (nx, ny, nz, n, K) in enumerate(dims):
         sc = scenegen.small_scene(seed + q, nx, ny, nz, h=0.05, n_boxes=5,

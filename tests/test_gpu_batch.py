@@ -106,6 +106,27 @@ def test_two_launch_batch_matches_plain_and_oracle(pc, dev):
         np.testing.assert_array_equal(c.cpu().numpy(), wc)
 
 
+def test_batch_with_chord_tables_beyond_lds(pc, dev):
+    """A scene whose chord table (K x ny pairs) exceeds the planar items'
+    LDS takes the path with chords and row passes in global memory, beside
+    scenes that keep theirs in LDS."""
+    scs = ragged_scenes(200)[:3]
+    scs.append(scenegen.small_scene(250, 30, 1000, 6, h=0.05, n_boxes=5,
+                                    n_humans=8, n_slices=2))
+    ds = [scene_dict(pc, sc, dev) for sc in scs]
+    refs = [plain(pc, d) for d in ds]
+    torch.cuda.synchronize()
+    say("batch with a 30x1000x6 scene of 8 humans")
+    outs = pc.predicted_composite_sdf_batch(ds)
+    torch.cuda.synchronize()
+    assert_same(outs, refs)
+    sc = scs[-1]
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    wc, _ = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                       sc.height)
+    np.testing.assert_array_equal(outs[-1][0].cpu().numpy(), wc)
+
+
 @pytest.mark.parametrize("G,C,B", [(1, 256, 1), (3, 512, 2), (2, 8192, 4),
                                    (7, 32768, 8), (30, 1024, 32),
                                    (4, 256, 0), (1, 1024, 0), (3, 4096, 0)])

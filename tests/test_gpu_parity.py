@@ -154,6 +154,18 @@ def test_composite_small_scenes(pc, dev, seed, dims, K, n):
     check_composite(pc, sc, dev)
 
 
+@pytest.mark.parametrize("seed,dims,K,n", [
+    (11, (1024, 1024, 3), 5, 2),   # the largest plane the interface takes
+    (12, (1024, 9, 5), 3, 2), (13, (7, 1024, 6), 4, 2)])
+def test_composite_maximum_axis_lengths(pc, dev, seed, dims, K, n):
+    """Axes of 1024 voxels (the interface's limit): chord tables and row
+    passes of 1024 rows or columns, planes of a million pixels."""
+    sc = scenegen.small_scene(seed, *dims, h=0.02, n_boxes=5, n_humans=K,
+                              n_slices=n)
+    say(f"composite maximum axes dims={dims} K={K} n={n}")
+    check_composite(pc, sc, dev)
+
+
 def width_case_scene(dims):
     """Scenes for the composite's pack shapes.  Planes of fewer than four
     pixels get one free-standing human on a nearly empty grid, tall enough
