@@ -34,15 +34,17 @@ COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
 
 def source_hash(path: str) -> str:
     """Hash of the composite kernel's own source text (the k_composite
-    template and the shared epilogue in composite_device.h), so host-side
-    edits of composite.hip keep a measurement valid."""
+    template, the shared epilogue in composite_device.h and the helpers of
+    device_common.h), so host-side edits of composite.hip keep a
+    measurement valid."""
     with open(path) as f:
         src = f.read()
     a = src.find("template <int VEC, bool kGather, bool kSsq, bool kSdf>")
     b = src.find("template <int VEC, bool kGather>", a)
     text = src[a:b] if a >= 0 and b > a else src
-    with open(os.path.join(os.path.dirname(path), "composite_device.h")) as f:
-        text += f.read()
+    for dep in ("composite_device.h", "device_common.h"):
+        with open(os.path.join(os.path.dirname(path), dep)) as f:
+            text += f.read()
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
@@ -599,6 +601,10 @@ def main():
         return pc.query_spheres(g, out_sdf, centre, radius, slices,
                                 handle=h)
 
+    # The timed steps time the composite kernel alone (a timed kernel
+    # costs the stream a few microseconds before it); the planes and
+    # queries are timed over as many steps right after.
+    h.profile(True, only=[_native.KERNEL_COMPOSITE])
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -609,10 +615,16 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-
     comp_ms, comp_n = h.profile_read(_native.KERNEL_COMPOSITE)
+
+    h.profile(True, only=[_native.KERNEL_PLANES, _native.KERNEL_QUERY])
+    h.profile_reset()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     pl_ms, pl_n = h.profile_read(_native.KERNEL_PLANES)
     qy_ms, qy_n = h.profile_read(_native.KERNEL_QUERY)
+    h.profile(True)
     comp_avg_s = comp_ms / comp_n / 1e3
     # compulsory bytes of one composite launch: read the static field once
     # (4 B/voxel) and write both outputs (8 B/voxel-slice)

@@ -61,7 +61,7 @@ enum pcsdf_status_code {
 
 /* Timed regions of pcsdf_profile_read. */
 #define PCSDF_KERNEL_COMPOSITE 0 /* streaming composite epilogue kernel */
-#define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (two kernels) */
+#define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (chords, row pass, planes) */
 #define PCSDF_KERNEL_QUERY 2     /* sphere query kernel */
 #define PCSDF_KERNEL_STATIC 3    /* the three passes of the static build */
 #define PCSDF_KERNEL_BATCH 4     /* a batch: both of its launches */
@@ -456,13 +456,24 @@ int pcsdf_query_spheres_surrogate(
     float *grad_dev, uint8_t *status_dev, float *cost_dev,
     uint8_t *used_fallback_dev, void *stream);
 
-/* Kernel timing for measurement.  When on, each timed region (the
- * PCSDF_KERNEL_* ids) is bracketed by two hipEventRecord calls on the
- * launch stream.  pcsdf_profile_read waits for the recorded events and
- * returns the accumulated milliseconds and region count of one id.
+/* Kernel timing for measurement.  When on, the kernels of the planar
+ * fields, the composite and the sphere queries (PCSDF_KERNEL_PLANES,
+ * _COMPOSITE, _QUERY) are each timed by their own dispatch
+ * (hipExtLaunchKernel's start and stop events), which adds no packets
+ * between kernels, and a region's time is the sum of its kernels'
+ * durations; these are not timed while the stream is being captured.
+ * The other regions are bracketed by two hipEventRecord calls on the
+ * launch stream.  pcsdf_profile_read waits for the events and returns
+ * the accumulated milliseconds and region count (calls) of one id.
  * pcsdf_profile_enable(h, 0) stops recording; pcsdf_profile_reset clears
  * the totals (waiting for pending events first). */
 int pcsdf_profile_enable(pcsdf_handle *h, int on);
+/* Times only the regions whose bit (1 << PCSDF_KERNEL_<id>) is set in
+ * region_mask; pcsdf_profile_enable(h, 1) sets every bit, (h, 0) none.
+ * A timed kernel costs the stream a few microseconds of idle time before
+ * it, so a measurement of whole steps selects only what it reads.
+ * PCSDF_ERR_INVALID_ARG for bits at or beyond PCSDF_KERNEL_COUNT. */
+int pcsdf_profile_select(pcsdf_handle *h, uint32_t region_mask);
 int pcsdf_profile_read(pcsdf_handle *h, int kernel_id, double *total_ms,
                        int64_t *count);
 int pcsdf_profile_reset(pcsdf_handle *h);

@@ -146,6 +146,8 @@ def load_library():
         lib.pcsdf_query_spheres.restype = C.c_int
         lib.pcsdf_profile_enable.argtypes = [P, C.c_int]
         lib.pcsdf_profile_enable.restype = C.c_int
+        lib.pcsdf_profile_select.argtypes = [P, C.c_uint32]
+        lib.pcsdf_profile_select.restype = C.c_int
         lib.pcsdf_profile_read.argtypes = [P, C.c_int,
                                            C.POINTER(C.c_double),
                                            C.POINTER(C.c_int64)]
@@ -196,8 +198,16 @@ class Handle:
             raise PcsdfError(rc, msg)
 
     # -- kernel timing with HIP events (PCSDF_KERNEL_* ids) --
-    def profile(self, on: bool = True):
-        self.check(self.lib.pcsdf_profile_enable(self.ptr, int(bool(on))))
+    def profile(self, on: bool = True, only=None):
+        """Kernel timing on or off; `only` lists the PCSDF_KERNEL_* ids to
+        time (every id when None)."""
+        if on and only is not None:
+            mask = 0
+            for k in only:
+                mask |= 1 << int(k)
+            self.check(self.lib.pcsdf_profile_select(self.ptr, mask))
+        else:
+            self.check(self.lib.pcsdf_profile_enable(self.ptr, int(bool(on))))
 
     def profile_reset(self):
         self.check(self.lib.pcsdf_profile_reset(self.ptr))

@@ -148,18 +148,48 @@ static hipEvent_t take_event(Handle *h) {
   return e;
 }
 
-ProfScope::ProfScope(Handle *h, int id, hipStream_t s)
+ProfScope::ProfScope(Handle *h, int id, hipStream_t s, bool per_launch)
     : h_(h), id_(id), s_(s) {
-  if (!h_->prof_on) return;
+  if (!((h_->prof_mask >> id_) & 1u)) return;
+  if (per_launch) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s_, &st) != hipSuccess ||
+        st != hipStreamCaptureStatusNone)
+      return;
+    active_ = true;
+    prev_ = h_->prof_scope;
+    h_->prof_scope = this;
+    return;
+  }
   a_ = take_event(h_);
   b_ = take_event(h_);
   if (a_ && b_) (void)hipEventRecord(a_, s_);
 }
 
+void ProfScope::attach(hipEvent_t *a, hipEvent_t *b) {
+  *a = *b = nullptr;
+  if (!active_) return;
+  hipEvent_t ea = take_event(h_), eb = take_event(h_);
+  if (!ea || !eb) {
+    if (ea) h_->prof_pool.push_back(ea);
+    if (eb) h_->prof_pool.push_back(eb);
+    return;
+  }
+  *a = ea;
+  *b = eb;
+  h_->prof_pending.push_back({id_, ea, eb, counted_ ? 0 : 1});
+  counted_ = true;
+}
+
 void ProfScope::stop() {
+  if (active_) {
+    h_->prof_scope = prev_;
+    active_ = false;
+    return;
+  }
   if (!a_ || !b_) return;
   (void)hipEventRecord(b_, s_);
-  h_->prof_pending.push_back({id_, a_, b_});
+  h_->prof_pending.push_back({id_, a_, b_, 1});
   a_ = b_ = nullptr;
 }
 
@@ -174,7 +204,7 @@ int drain_profile(Handle *h) {
                   std::string("profile events: ") + hipGetErrorString(e));
     }
     h->prof_ms[p.id] += ms;
-    h->prof_n[p.id] += 1;
+    h->prof_n[p.id] += p.count;
     h->prof_pool.push_back(p.a);
     h->prof_pool.push_back(p.b);
   }
@@ -189,7 +219,17 @@ using namespace pcsdf;
 extern "C" int pcsdf_profile_enable(pcsdf_handle *hp, int on) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return PCSDF_ERR_INVALID_ARG;
-  h->prof_on = on != 0;
+  h->prof_mask = on ? (1u << PCSDF_KERNEL_COUNT) - 1u : 0u;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_profile_select(pcsdf_handle *hp, uint32_t region_mask) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  if (region_mask >> PCSDF_KERNEL_COUNT)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "region mask has bits beyond PCSDF_KERNEL_COUNT");
+  h->prof_mask = region_mask;
   return PCSDF_OK;
 }
 

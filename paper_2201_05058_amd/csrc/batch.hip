@@ -285,15 +285,15 @@ namespace {
 template <class F>
 double kernel_ms(Handle *h, int id, hipStream_t s, int reps, F fn) {
   if (drain_profile(h)) return -1.0;
-  const bool on = h->prof_on;
+  const uint32_t mask = h->prof_mask;
   double ms[PCSDF_KERNEL_COUNT];
   int64_t n[PCSDF_KERNEL_COUNT];
   std::memcpy(ms, h->prof_ms, sizeof ms);
   std::memcpy(n, h->prof_n, sizeof n);
   double out = -1.0;
-  h->prof_on = false;
+  h->prof_mask = 0;
   if (fn() == PCSDF_OK && hipStreamSynchronize(s) == hipSuccess) {
-    h->prof_on = true;
+    h->prof_mask = 1u << id;
     const double before = h->prof_ms[id];
     int rc = PCSDF_OK;
     for (int r = 0; r < reps && rc == PCSDF_OK; ++r) rc = fn();
@@ -301,7 +301,7 @@ double kernel_ms(Handle *h, int id, hipStream_t s, int reps, F fn) {
         drain_profile(h) == PCSDF_OK)
       out = (h->prof_ms[id] - before) / reps;
   }
-  h->prof_on = on;
+  h->prof_mask = mask;
   std::memcpy(h->prof_ms, ms, sizeof ms);
   std::memcpy(h->prof_n, n, sizeof n);
   return out;

@@ -64,24 +64,21 @@ __global__ __launch_bounds__(256) void k_composite(
 }
 
 template <int VEC, bool kGather>
-static void launch_comp(const int32_t *S, const int32_t *P,
+static void launch_comp(Handle *h, const int32_t *S, const int32_t *P,
                         const int32_t *need, int32_t *oc, float *of,
                         uint32_t plane, int n, int G, int Kt, int has_above,
                         float hf, uint32_t V, hipStream_t s) {
   const uint32_t nthreads = V / VEC;
   const dim3 grid((nthreads + 255) / 256, (n + G - 1) / G), block(256);
   if (oc && of)
-    hipLaunchKernelGGL((k_composite<VEC, kGather, true, true>), grid, block,
-                       0, s, S, P, need, oc, of, plane, n, G, Kt, has_above,
-                       hf, V);
+    launch_timed(h, k_composite<VEC, kGather, true, true>, grid, block, 0u,
+                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
   else if (oc)
-    hipLaunchKernelGGL((k_composite<VEC, kGather, true, false>), grid, block,
-                       0, s, S, P, need, oc, of, plane, n, G, Kt, has_above,
-                       hf, V);
+    launch_timed(h, k_composite<VEC, kGather, true, false>, grid, block, 0u,
+                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
   else
-    hipLaunchKernelGGL((k_composite<VEC, kGather, false, true>), grid, block,
-                       0, s, S, P, need, oc, of, plane, n, G, Kt, has_above,
-                       hf, V);
+    launch_timed(h, k_composite<VEC, kGather, false, true>, grid, block, 0u,
+                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
 }
 
 // Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
@@ -177,7 +174,7 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   if ((rc = ensure_buffer(h, h->plane_buf, 2 * plane_bytes, s))) return rc;
   int32_t *p2 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
   // Planar signed field of the disk union, per slice.
-  ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
+  ProfScope pp(h, PCSDF_KERNEL_PLANES, s, true);
   if ((rc = launch_planes(h, hs.xy, n_humans, hs.Rs, hs.K == 0, hs.chords, p2,
                           nx, ny, n_slices, need, s)))
     return rc;
@@ -207,7 +204,7 @@ int composite_run(Handle *h, const pcsdf_grid *g,
   if ((rc = planes_run(h, g, n_slices, n_humans, human_xy_host, radius_m,
                        radius_per_slice, height_m, need, s, &ps_)))
     return rc;
-  ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s);
+  ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s, true);
   return launch_composite(h, g, static_ssq_dev, ps_.P, need, ps_.Kt,
                           ps_.has_above, n_slices, out_ssq_dev, out_sdf_dev,
                           s);
@@ -234,19 +231,19 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
   const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
   const uint32_t Vu = (uint32_t)V;
   if (ps.vec == 4 && !ps.gather)
-    launch_comp<4, false>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+    launch_comp<4, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
                           plane, n_slices, G, Kt, has_above, hf, Vu, s);
   else if (ps.vec == 4)
-    launch_comp<4, true>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+    launch_comp<4, true>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
   else if (ps.vec == 2 && !ps.gather)
-    launch_comp<2, false>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+    launch_comp<2, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
                           plane, n_slices, G, Kt, has_above, hf, Vu, s);
   else if (ps.vec == 2)
-    launch_comp<2, true>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+    launch_comp<2, true>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
   else
-    launch_comp<1, false>(static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
+    launch_comp<1, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
                           plane, n_slices, G, Kt, has_above, hf, Vu, s);
   return check_launch(h, "composite");
 }

@@ -141,8 +141,8 @@ int launch_direct(Handle *h, const pcsdf_grid *g, const DirectSet &d,
   A.grad = grad;
   A.cost = cost;
   A.status = status;
-  hipLaunchKernelGGL(k_query_direct, dim3((unsigned)((n_queries + 255) / 256)),
-                     dim3(256), 0, s, A, n_queries);
+  launch_timed(h, k_query_direct, dim3((unsigned)((n_queries + 255) / 256)),
+               dim3(256), 0u, s, A, n_queries);
   return check_launch(h, "direct query");
 }
 
@@ -182,7 +182,7 @@ extern "C" int pcsdf_query_spheres_direct(
   if ((rc = direct_setup(h, g, static_ssq_dev, n_slices, n_humans,
                          human_xy_host, radius_m, height_m, nullptr, s, &d)))
     return rc;
-  ProfScope pq(h, PCSDF_KERNEL_QUERY, s);
+  ProfScope pq(h, PCSDF_KERNEL_QUERY, s, true);
   return launch_direct(h, g, d, n_slices, n_queries, nullptr, centre_dev,
                        radius_dev, slice_dev, hinge_eps_m, dist_dev, grad_dev,
                        status_dev, cost_dev, s);

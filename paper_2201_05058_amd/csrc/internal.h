@@ -3,6 +3,7 @@
 // kernel launchers each unit exports to the others.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -13,6 +14,8 @@
 #include "../../include/pcsdf.h"
 
 namespace pcsdf {
+
+class ProfScope;
 
 constexpr int32_t kInf = INT32_MAX;  // "no site" / empty set
 constexpr int kMaxDim = 1024;
@@ -54,32 +57,59 @@ struct Handle {
   int staging_next = 0, staging_cur = 0;
   void *pinned = nullptr;  // the slot acquired by the current call
   std::vector<int64_t> host_xy;  // fixed-point centres before upload
-  // kernel timing with HIP events on the launch stream (off by default)
-  bool prof_on = false;
+  // kernel timing with HIP events on the launch stream: bit `id` set =
+  // region PCSDF_KERNEL_<id> timed (none by default)
+  uint32_t prof_mask = 0;
   std::vector<hipEvent_t> prof_pool;
   struct Pending {
     int id;
     hipEvent_t a, b;
+    int count;  // 1 for the first timed part of a region, else 0
   };
   std::vector<Pending> prof_pending;
+  ProfScope *prof_scope = nullptr;  // innermost open per-launch region
   double prof_ms[PCSDF_KERNEL_COUNT] = {};
   int64_t prof_n[PCSDF_KERNEL_COUNT] = {};
 };
 
-// Brackets the launches of one timed region with HIP events when the
-// handle's profiling is on; a no-op otherwise.
+// Times one region of launches when the handle's profiling is on; a no-op
+// otherwise.  By default the region is bracketed by two event records on
+// the stream.  A per-launch region instead times each of its kernels by
+// the kernel's own dispatch (hipExtLaunchKernel's start and stop events),
+// which puts no marker packets between the kernels; its kernels must be
+// launched with launch_timed, and its time is the sum of their durations.
+// Per-launch regions are not timed while the stream is being captured.
 class ProfScope {
  public:
-  ProfScope(Handle *h, int id, hipStream_t s);
+  ProfScope(Handle *h, int id, hipStream_t s, bool per_launch = false);
   ~ProfScope() { stop(); }
   void stop();
+  // Start and stop events for one kernel of an open per-launch region
+  // (both nullptr when it is not timed).
+  void attach(hipEvent_t *a, hipEvent_t *b);
 
  private:
   Handle *h_;
   int id_;
   hipStream_t s_;
   hipEvent_t a_ = nullptr, b_ = nullptr;
+  bool active_ = false;   // an open per-launch region
+  bool counted_ = false;  // its first kernel has been attached
+  ProfScope *prev_ = nullptr;
 };
+
+// Launches `kernel`, timed by its dispatch when a per-launch region is
+// open on the handle.
+template <class F, class... Args>
+inline void launch_timed(Handle *h, F kernel, dim3 grid, dim3 block,
+                         uint32_t shmem, hipStream_t s, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (h->prof_scope) h->prof_scope->attach(&a, &b);
+  if (a)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 // Waits for the handle's pending timed regions and adds them to its
 // totals.

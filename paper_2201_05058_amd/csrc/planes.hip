@@ -111,8 +111,8 @@ int launch_chords(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
                   const int32_t *need, hipStream_t s) {
   const int64_t total = (int64_t)n_slices * K * ny;
   if (total <= 0) return PCSDF_OK;
-  hipLaunchKernelGGL(k_chords, dim3((unsigned)((total + 255) / 256)),
-                     dim3(256), 0, s, xy, K, Rs, nx, ny, total, need, chords);
+  launch_timed(h, k_chords, dim3((unsigned)((total + 255) / 256)), dim3(256),
+               0, s, xy, K, Rs, nx, ny, total, need, chords);
   return check_launch(h, "chords");
 }
 
@@ -127,8 +127,8 @@ int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
   int32_t *F1 = P + (int64_t)n_slices * npx;
   const int64_t npix = (int64_t)n_slices * npx;
   if (Keff > 0) {
-    hipLaunchKernelGGL(k_rowfree, dim3((unsigned)((npix + 255) / 256)),
-                       dim3(256), 0, s, chords, Keff, nx, ny, npix, need, F1);
+    launch_timed(h, k_rowfree, dim3((unsigned)((npix + 255) / 256)),
+                 dim3(256), 0, s, chords, Keff, nx, ny, npix, need, F1);
     int rc = check_launch(h, "rowfree");
     if (rc) return rc;
   }
@@ -141,11 +141,12 @@ int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
   const bool use_lds = box_bytes + ch_bytes <= 48 * 1024;
   const dim3 grid((unsigned)((int64_t)tiles * n_slices)), block(256);
   if (use_lds)
-    hipLaunchKernelGGL(k_planes<true>, grid, block, box_bytes + ch_bytes, s,
-                       chords, xy, Keff, Rs, nx, ny, tiles, F1, need, P);
+    launch_timed(h, k_planes<true>, grid, block,
+                 (uint32_t)(box_bytes + ch_bytes), s, chords, xy, Keff, Rs,
+                 nx, ny, tiles, F1, need, P);
   else
-    hipLaunchKernelGGL(k_planes<false>, grid, block, box_bytes, s, chords, xy,
-                       Keff, Rs, nx, ny, tiles, F1, need, P);
+    launch_timed(h, k_planes<false>, grid, block, (uint32_t)box_bytes, s,
+                 chords, xy, Keff, Rs, nx, ny, tiles, F1, need, P);
   return check_launch(h, "planes");
 }
 

@@ -168,10 +168,10 @@ extern "C" int pcsdf_query_spheres(pcsdf_handle *hp, const pcsdf_grid *g,
   if ((rc = bind_device(h))) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)((n_queries + 255) / 256)), block(256);
-  ProfScope ps(h, PCSDF_KERNEL_QUERY, s);
+  ProfScope ps(h, PCSDF_KERNEL_QUERY, s, true);
   const QueryArgs A =
       query_args(g, sdf_dev, n_slices, centre_dev, radius_dev, slice_dev,
                  hinge_eps_m, dist_dev, grad_dev, status_dev, cost_dev);
-  hipLaunchKernelGGL(k_query, grid, block, 0, s, A, n_queries);
+  launch_timed(h, k_query, grid, block, 0u, s, A, n_queries);
   return check_launch(h, "query_spheres");
 }

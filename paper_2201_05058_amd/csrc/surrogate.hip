@@ -403,7 +403,7 @@ extern "C" int pcsdf_query_spheres_surrogate(
   if ((rc = direct_setup(h, g, static_ssq_dev, n_slices, n_humans,
                          human_xy_host, radius_m, height_m, need, s, &d)))
     return rc;
-  ProfScope pq(h, PCSDF_KERNEL_QUERY, s);
+  ProfScope pq(h, PCSDF_KERNEL_QUERY, s, true);
   return launch_direct(h, g, d, n_slices, n_queries, used, centre_dev,
                        radius_dev, slice_dev, hinge_eps_m, dist_dev, grad_dev,
                        status_dev, cost_dev, s);

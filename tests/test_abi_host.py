@@ -174,6 +174,10 @@ def test_profile_calls_without_device(h):
     h.profile_reset()
     with pytest.raises(pc.PcsdfError):
         h.profile_read(17)
+    h.profile(True, only=[_native.KERNEL_COMPOSITE, _native.KERNEL_QUERY])
+    assert h.lib.pcsdf_profile_select(h.ptr, 1 << 11) == 1  # beyond COUNT
+    assert h.lib.pcsdf_profile_select(h.ptr, (1 << 11) - 1) == 0
+    h.profile(False)
 
 
 def test_surrogate_validation(h):
