@@ -336,12 +336,13 @@ int pcsdf_batch_graph_launch(pcsdf_batch_graph *g, void *stream);
 void pcsdf_batch_graph_destroy(pcsdf_batch_graph *g);
 
 /* Autotuners: time candidate launch shapes on the caller's real inputs by
- * the GPU time of the kernels they shape (HIP events on `stream` around
- * the launches, `reps` runs each after a warm-up run; host work between
- * calls does not count), store the fastest in the handle's tuning and
- * return it with its time in milliseconds per run.  Outputs are written as
- * by the tuned call.  They synchronise with the device and leave the
- * handle's profiling state and totals unchanged. */
+ * the GPU time of the kernels they shape (HIP events on `stream`, `reps`
+ * runs each after a warm-up run; host work between calls does not count),
+ * store the fastest in the handle's tuning and return it with its time in
+ * milliseconds per run.  The composite tuner makes three interleaved
+ * rounds over its slice groups and keeps each group's fastest round.
+ * Outputs are written as by the tuned call.  They synchronise with the
+ * device and leave the handle's profiling state and totals unchanged. */
 int pcsdf_autotune_batch(pcsdf_handle *h, int32_t n_scenes,
                          const pcsdf_scene *scenes, void *stream,
                          int32_t reps, pcsdf_tuning *best, double *best_ms);

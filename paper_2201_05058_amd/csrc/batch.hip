@@ -365,28 +365,43 @@ extern "C" int pcsdf_autotune_composite(pcsdf_handle *hp,
   pcsdf_tuning win = base;
   double win_ms = -1.0;
   const int n = sc->n_slices;
-  const int Gs[] = {1, 2, 3, 4, 5, 10, n};
-  for (int G : Gs) {
-    if (G < 1 || G > n) continue;
-    h->tuning = base;
-    h->tuning.composite_slices_per_block = G;
-    // the composite kernel alone: the slice group changes nothing else,
-    // and a call's wall time can be the host's
-    const double ms = kernel_ms(
-        h, PCSDF_KERNEL_COMPOSITE, reinterpret_cast<hipStream_t>(stream),
-        reps, [&] {
-          return pcsdf_predicted_composite_sdf(
-              hp, &sc->grid, sc->static_ssq_dev, sc->n_slices, sc->n_humans,
-              sc->human_xy_host, sc->radius_m, sc->height_m, sc->out_ssq_dev,
-              sc->out_sdf_dev, stream);
-        });
-    if (ms < 0) {
+  constexpr int kCand = 7;
+  const int Gs[kCand] = {1, 2, 3, 4, 5, 10, n};
+  double best_of[kCand];
+  for (int c = 0; c < kCand; ++c) best_of[c] = -1.0;
+  // Three interleaved rounds over the candidates, each keeping its fastest
+  // round: the candidates neighbouring ones differ by a few per cent, less
+  // than the drift of a single pass.
+  for (int round = 0; round < 3; ++round)
+    for (int c = 0; c < kCand; ++c) {
+      const int G = Gs[c];
+      bool seen = false;  // n may repeat an earlier candidate
+      for (int e = 0; e < c; ++e) seen = seen || Gs[e] == G;
+      if (G < 1 || G > n || seen) continue;
       h->tuning = base;
-      return PCSDF_ERR_HIP;
+      h->tuning.composite_slices_per_block = G;
+      // the composite kernel alone: the slice group changes nothing else,
+      // and a call's wall time can be the host's
+      const double ms = kernel_ms(
+          h, PCSDF_KERNEL_COMPOSITE, reinterpret_cast<hipStream_t>(stream),
+          reps, [&] {
+            return pcsdf_predicted_composite_sdf(
+                hp, &sc->grid, sc->static_ssq_dev, sc->n_slices,
+                sc->n_humans, sc->human_xy_host, sc->radius_m, sc->height_m,
+                sc->out_ssq_dev, sc->out_sdf_dev, stream);
+          });
+      if (ms < 0) {
+        h->tuning = base;
+        return PCSDF_ERR_HIP;
+      }
+      if (best_of[c] < 0 || ms < best_of[c]) best_of[c] = ms;
     }
-    if (win_ms < 0 || ms < win_ms) {
-      win_ms = ms;
-      win = h->tuning;
+  for (int c = 0; c < kCand; ++c) {
+    if (best_of[c] < 0) continue;
+    if (win_ms < 0 || best_of[c] < win_ms) {
+      win_ms = best_of[c];
+      win = base;
+      win.composite_slices_per_block = Gs[c];
     }
   }
   h->tuning = win;

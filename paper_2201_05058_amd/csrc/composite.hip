@@ -144,16 +144,24 @@ int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   const size_t chord_bytes =
       (size_t)n_slices * (n_humans > 0 ? n_humans : 1) * ny * sizeof(int2);
   if ((rc = ensure_buffer(h, h->chord_buf, chord_bytes, s))) return rc;
-  if ((rc = ensure_buffer(h, h->param_buf, xy_bytes, s))) return rc;
-  int64_t *xy_dev = reinterpret_cast<int64_t *>(h->param_buf.ptr);
-  if ((rc = acquire_staging(h, xy_bytes))) return rc;
-  std::memcpy(h->pinned, xy.data(), xy_bytes);
-  if (hipMemcpyAsync(xy_dev, h->pinned, xy_bytes, hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return fail(h, PCSDF_ERR_HIP, "upload of human positions failed");
-  if ((rc = release_staging(h, s))) return rc;
-  out->xy = xy_dev;
-  out->Rs = xy_dev + 2 * ncent;
+  if (xy.size() <= (size_t)kCentresInArgs) {
+    // small sets travel in the planar kernels' arguments
+    out->C.xy = nullptr;
+    out->C.Rs = nullptr;
+    out->C.rs_off = (int32_t)(2 * ncent);
+    std::memcpy(out->C.w, xy.data(), xy_bytes);
+  } else {
+    if ((rc = ensure_buffer(h, h->param_buf, xy_bytes, s))) return rc;
+    int64_t *xy_dev = reinterpret_cast<int64_t *>(h->param_buf.ptr);
+    if ((rc = acquire_staging(h, xy_bytes))) return rc;
+    std::memcpy(h->pinned, xy.data(), xy_bytes);
+    if (hipMemcpyAsync(xy_dev, h->pinned, xy_bytes, hipMemcpyHostToDevice,
+                       s) != hipSuccess)
+      return fail(h, PCSDF_ERR_HIP, "upload of human positions failed");
+    if ((rc = release_staging(h, s))) return rc;
+    out->C.xy = xy_dev;
+    out->C.Rs = xy_dev + 2 * ncent;
+  }
   out->chords = reinterpret_cast<int2 *>(h->chord_buf.ptr);
   out->K = empty ? 0 : n_humans;
   out->Kt = empty ? -1 : Kt;
@@ -175,7 +183,7 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   int32_t *p2 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
   // Planar signed field of the disk union, per slice.
   ProfScope pp(h, PCSDF_KERNEL_PLANES, s, true);
-  if ((rc = launch_planes(h, hs.xy, n_humans, hs.Rs, hs.K == 0, hs.chords, p2,
+  if ((rc = launch_planes(h, hs.C, n_humans, hs.K == 0, hs.chords, p2,
                           nx, ny, n_slices, need, s)))
     return rc;
   out->P = p2;

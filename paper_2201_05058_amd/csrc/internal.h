@@ -159,30 +159,48 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
 
 // ---- implemented in planes.hip -----------------------------------------
 
+// Fixed-point disk centres [n_slices][K][2] and radii [n_slices] of the
+// humans, read by the planar kernels: in device memory, or, when they fit,
+// carried in the kernel arguments themselves, so that a call needs no
+// upload before its first kernel.
+constexpr int kCentresInArgs = 240;  // int64 words
+struct Centres {
+  const int64_t *xy = nullptr;  // device centres, or null: words below
+  const int64_t *Rs = nullptr;  // device radii (with xy)
+  int32_t rs_off = 0;           // index of the radii in w (without xy)
+  int64_t w[kCentresInArgs];    // centres, then radii (without xy)
+};
+__device__ __forceinline__ int64_t centre_word(const Centres &c,
+                                               int64_t i) {
+  return c.xy ? c.xy[i] : c.w[i];
+}
+__device__ __forceinline__ int64_t radius_of(const Centres &c, int64_t s) {
+  return c.xy ? c.Rs[s] : c.w[c.rs_off + s];
+}
+
 // Planar signed field of the humans' disk union for every slice, into
 // P [n_slices][ny][nx]: chords per (slice, human, row) into `chords`, then
-// one lane per pixel.  xy holds fixed-point centres [n_slices][K][2]; no
-// human voxel at all when `empty` is set.  Rs [n_slices] holds each
-// slice's fixed-point disk radius.  With `need` (device int32 [n_slices])
-// only slices with a non-zero entry are computed.
-int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
-                  bool empty, int2 *chords, int32_t *P, int nx, int ny,
-                  int n_slices, const int32_t *need, hipStream_t s);
+// one lane per pixel.  C holds the fixed-point centres [n_slices][K][2]
+// and each slice's fixed-point disk radius; no human voxel at all when
+// `empty` is set.  With `need` (device int32 [n_slices]) only slices with
+// a non-zero entry are computed.
+int launch_planes(Handle *h, const Centres &C, int K, bool empty,
+                  int2 *chords, int32_t *P, int nx, int ny, int n_slices,
+                  const int32_t *need, hipStream_t s);
 
 // Chords only (the first step of launch_planes): chords[s][k][j], K humans
 // per slice (0: nothing to do).
-int launch_chords(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
-                  int2 *chords, int nx, int ny, int n_slices,
-                  const int32_t *need, hipStream_t s);
+int launch_chords(Handle *h, const Centres &C, int K, int2 *chords, int nx,
+                  int ny, int n_slices, const int32_t *need, hipStream_t s);
 
 // ---- implemented in composite.hip --------------------------------------
 
-// The humans of every slice validated, converted to the fixed-point
-// lattice and uploaded (one pinned staging copy): xy [n_slices][K][2] and
-// Rs [n_slices] on the device, chords buffer sized for them.
+// The humans of every slice validated and converted to the fixed-point
+// lattice: centres [n_slices][K][2] and radii [n_slices], kept for the
+// kernel arguments when they fit in kCentresInArgs words, else uploaded
+// (one pinned staging copy); the chords buffer sized for them.
 struct HumanSet {
-  const int64_t *xy;  // device
-  const int64_t *Rs;  // device
+  Centres C;          // fixed-point centres and radii
   int2 *chords;       // device, [n_slices][K][ny] (K >= 1 rows reserved)
   int K;              // humans per slice after dropping empty cylinders
   int Kt;             // highest voxel layer of the cylinders, -1 if none

@@ -34,10 +34,8 @@ namespace pcsdf {
 // Slices whose entry in `need` is zero are skipped (all slices when `need`
 // is null) by this kernel and the two below.
 // Rs[s] is slice s's fixed-point disk radius.
-__global__ __launch_bounds__(256) void k_chords(const int64_t *__restrict__ xy,
-                                                int K,
-                                                const int64_t *__restrict__ Rs,
-                                                int nx, int ny, int64_t total,
+__global__ __launch_bounds__(256) void k_chords(Centres C, int K, int nx,
+                                                int ny, int64_t total,
                                                 const int32_t *__restrict__ need,
                                                 int2 *__restrict__ chords) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -45,8 +43,8 @@ __global__ __launch_bounds__(256) void k_chords(const int64_t *__restrict__ xy,
   const int j = (int)(t % ny);
   const int64_t sk = t / ny;  // s*K + k
   if (need && need[sk / K] == 0) return;
-  const int64_t X = xy[2 * sk], Y = xy[2 * sk + 1];
-  const int2 c = disk_chord(X, Y, Rs[sk / K], nx, j);
+  const int64_t X = centre_word(C, 2 * sk), Y = centre_word(C, 2 * sk + 1);
+  const int2 c = disk_chord(X, Y, radius_of(C, sk / K), nx, j);
   chords[t] = c;
 }
 
@@ -72,23 +70,22 @@ __global__ __launch_bounds__(256) void k_rowfree(
 // memory; the disks' bounding boxes always live in LDS.
 template <bool kLds>
 __global__ __launch_bounds__(256) void k_planes(
-    const int2 *__restrict__ chords, const int64_t *__restrict__ xy, int K,
-    const int64_t *__restrict__ Rs, int nx, int ny, int tiles,
-    const int32_t *__restrict__ F1, const int32_t *__restrict__ need,
-    int32_t *__restrict__ P) {
+    const int2 *__restrict__ chords, Centres C, int K, int nx, int ny,
+    int tiles, const int32_t *__restrict__ F1,
+    const int32_t *__restrict__ need, int32_t *__restrict__ P) {
   extern __shared__ int4 sh4[];
   const int s = blockIdx.x / tiles;
   const int tile = blockIdx.x - s * tiles;
   if (need && need[s] == 0) return;  // uniform over the block
-  const int64_t R = Rs[s];
+  const int64_t R = radius_of(C, s);
   const int2 *gch = chords + (int64_t)s * K * ny;
   int4 *box = sh4;                                   // K boxes
   int2 *lch = reinterpret_cast<int2 *>(sh4 + K);     // K*ny chords
   if (kLds)
     for (int t = threadIdx.x; t < K * ny; t += 256) lch[t] = gch[t];
   for (int k = threadIdx.x; k < K; k += 256) {
-    const int64_t X = xy[2 * ((int64_t)s * K + k)];
-    const int64_t Y = xy[2 * ((int64_t)s * K + k) + 1];
+    const int64_t X = centre_word(C, 2 * ((int64_t)s * K + k));
+    const int64_t Y = centre_word(C, 2 * ((int64_t)s * K + k) + 1);
     const int4 b = disk_box(X, Y, R, nx, ny);
     box[k] = b;
   }
@@ -106,22 +103,20 @@ __global__ __launch_bounds__(256) void k_planes(
   }
 }
 
-int launch_chords(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
-                  int2 *chords, int nx, int ny, int n_slices,
-                  const int32_t *need, hipStream_t s) {
+int launch_chords(Handle *h, const Centres &C, int K, int2 *chords, int nx,
+                  int ny, int n_slices, const int32_t *need, hipStream_t s) {
   const int64_t total = (int64_t)n_slices * K * ny;
   if (total <= 0) return PCSDF_OK;
   launch_timed(h, k_chords, dim3((unsigned)((total + 255) / 256)), dim3(256),
-               0, s, xy, K, Rs, nx, ny, total, need, chords);
+               0u, s, C, K, nx, ny, total, need, chords);
   return check_launch(h, "chords");
 }
 
-int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
-                  bool empty,
+int launch_planes(Handle *h, const Centres &C, int K, bool empty,
                   int2 *chords, int32_t *P, int nx, int ny, int n_slices,
                   const int32_t *need, hipStream_t s) {
   const int Keff = empty ? 0 : K;
-  int rc0 = launch_chords(h, xy, Keff, Rs, chords, nx, ny, n_slices, need, s);
+  int rc0 = launch_chords(h, C, Keff, chords, nx, ny, n_slices, need, s);
   if (rc0) return rc0;
   const int npx = nx * ny;
   int32_t *F1 = P + (int64_t)n_slices * npx;
@@ -142,11 +137,11 @@ int launch_planes(Handle *h, const int64_t *xy, int K, const int64_t *Rs,
   const dim3 grid((unsigned)((int64_t)tiles * n_slices)), block(256);
   if (use_lds)
     launch_timed(h, k_planes<true>, grid, block,
-                 (uint32_t)(box_bytes + ch_bytes), s, chords, xy, Keff, Rs,
-                 nx, ny, tiles, F1, need, P);
+                 (uint32_t)(box_bytes + ch_bytes), s, chords, C, Keff, nx, ny,
+                 tiles, F1, need, P);
   else
     launch_timed(h, k_planes<false>, grid, block, (uint32_t)box_bytes, s,
-                 chords, xy, Keff, Rs, nx, ny, tiles, F1, need, P);
+                 chords, C, Keff, nx, ny, tiles, F1, need, P);
   return check_launch(h, "planes");
 }
 

@@ -190,7 +190,10 @@ extern "C" int pcsdf_template_composite_sdf(
     ProfScope pp(h, PCSDF_KERNEL_PLANES, s);
     if (K > 0) {
       // one "slice" per human: its single disk in its window
-      if ((rc = launch_planes(h, dev, 1, dev + 2 * K, false,
+      Centres C;
+      C.xy = dev;
+      C.Rs = dev + 2 * K;
+      if ((rc = launch_planes(h, C, 1, false,
                               reinterpret_cast<int2 *>(h->chord_buf.ptr), T,
                               Wx, Wy, K, nullptr, s)))
         return rc;

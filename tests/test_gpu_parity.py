@@ -147,7 +147,10 @@ def check_composite(pc, sc, dev):
 @pytest.mark.parametrize("seed,dims,K,n", [
     (1, (33, 27, 21), 3, 4), (2, (67, 131, 29), 2, 3), (3, (64, 64, 40), 8, 2),
     (4, (5, 7, 3), 1, 2), (5, (130, 70, 33), 4, 5), (6, (1, 40, 40), 2, 2),
-    (7, (40, 1, 40), 2, 2), (8, (257, 65, 9), 3, 2)])
+    (7, (40, 1, 40), 2, 2), (8, (257, 65, 9), 3, 2),
+    # 16 x (2 x 7 + 1) = 240 words of centres and radii, the most the
+    # planar kernels take in their arguments; 17 slices are uploaded
+    (9, (30, 41, 12), 7, 16), (10, (30, 41, 12), 7, 17)])
 def test_composite_small_scenes(pc, dev, seed, dims, K, n):
     sc = scenegen.small_scene(seed, *dims, h=0.05, n_boxes=5, n_humans=K,
                               n_slices=n)
