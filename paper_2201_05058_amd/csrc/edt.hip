@@ -273,6 +273,9 @@ __global__ __launch_bounds__(64) void k_pass_col(
 // value so far), so a fill usually reads one or two envelopes.  The
 // workgroup's LDS is the same as one wave's above (S segments of m/S
 // entries), so S times as many waves share a CU.
+// Column values read per batch of loads in the segmented pass.
+constexpr int kSegBatch = 16;
+
 template <int S, bool kWriteSdf>
 __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     const int32_t *__restrict__ in, int32_t *__restrict__ out,
@@ -303,15 +306,15 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     // Envelope of this segment's sites.
     int top = -1;
     uint32_t etop = 0;  // stk[top] cached in a register
-    for (int qb = q0; qb < q1; qb += 8) {
-      int32_t xb[8];
+    for (int qb = q0; qb < q1; qb += kSegBatch) {
+      int32_t xb[kSegBatch];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < kSegBatch; ++t) {
         const int q = qb + t;
         xb[t] = (active && q < q1) ? src[(int64_t)q * stride] : 0;
       }
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < kSegBatch; ++t) {
         const int q = qb + t;
         const int32_t x = xb[t];
         bool site;
@@ -360,19 +363,8 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
       ek[s] = tp[s] >= 0 ? st[lane] : 0;
       ek1[s] = tp[s] >= 1 ? st[64 + lane] : 0;
     }
-    for (int qb = q0; qb < q1; qb += 8) {
-      int32_t xb[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int q = qb + t;
-        xb[t] = (active && q < q1) ? src[(int64_t)q * stride] : 0;
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int q = qb + t;
-        if (q >= q1) break;
-        const int32_t x = xb[t];
-        const bool mine = inside_ch ? (x < 0) : (x > 0);
+    for (int q = q0; q < q1; ++q) {
+      {
         // Value of envelope s at q (its walk pointer moves right only; an
         // envelope skipped for some q catches up when next evaluated).
         auto eval = [&](int s) -> int32_t {
@@ -405,7 +397,11 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
           if (gap * gap >= val) continue;
           val = min(val, eval(s));
         }
-        if (mine && active) {
+        // A voxel of this channel's own set (free for the outside
+        // channel, occupied for the inside one) is a site of the other
+        // channel at distance 0, so each channel's value is positive
+        // exactly on the voxels it owns: no second read of the input.
+        if (val > 0 && active) {
           const int32_t v = inside_ch ? -val : val;
           dst[(int64_t)q * stride] = v;
           if (kWriteSdf) dsdf[(int64_t)q * stride] = ssq_to_metres(v, hf);
