@@ -112,9 +112,13 @@ __device__ __forceinline__ void centre_gradient(const float *x,
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int b = 4 + 6 * k;
-    const float rho = x[b + 2];
-    const float ux = rho > 0.f ? x[b] / rho : 0.f;
-    const float uy = rho > 0.f ? x[b + 1] / rho : 0.f;
+    // read and divided unconditionally (the result is selected), so that
+    // no read waits behind a branch on another
+    const float dx = x[b], dy = x[b + 1], rho = x[b + 2];
+    const float den = rho > 0.f ? rho : 1.f;
+    const float qx = dx / den, qy = dy / den;
+    const float ux = rho > 0.f ? qx : 0.f;
+    const float uy = rho > 0.f ? qy : 0.f;
     gx = gx + G[b];
     gx = gx + G[b + 2] * ux;
     gy = gy + G[b + 1];
@@ -156,7 +160,15 @@ __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   bool fb = false;
   if (q < A.n) {
+    // Every read that does not depend on another is issued here, before
+    // any branch, so that they share one wait.
     const int s = A.slice[q];
+    const float c3[3] = {A.centre[3 * q], A.centre[3 * q + 1],
+                         A.centre[3 * q + 2]};
+    const float yq = A.y[q], rq = A.radius[q];
+    float g0, g1, g2;
+    centre_gradient(A.x + (int64_t)q * kNetIn, A.gx + (int64_t)q * kNetIn,
+                    &g0, &g1, &g2);
     if (s < 0) {  // same answer as the exact path
       const float nan = __builtin_nanf("");
       A.dist[q] = nan;
@@ -173,13 +185,10 @@ __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
       bool inside = true;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const double g = ((double)A.centre[3 * q + a] - o3[a]) / A.h - 0.5;
+        const double g = ((double)c3[a] - o3[a]) / A.h - 0.5;
         inside = inside && g >= 0.0 && g <= (double)(n3[a] - 1);
       }
-      float v = A.y[q];
-      float g0, g1, g2;
-      centre_gradient(A.x + (int64_t)q * kNetIn, A.gx + (int64_t)q * kNetIn,
-                      &g0, &g1, &g2);
+      float v = yq;
       if (A.static_sdf && inside) {
         // the network predicts the humans' part: the answer is the smaller
         // of it and the environment field (exact, sampled as the exact
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(256) void k_decide(DecideArgs A) {
           g2 = (float)(T.g[2] / A.h);
         }
       }
-      const float ds = v - A.radius[q];
+      const float ds = v - rq;
       const bool ok = inside && isfinite(ds) && ds >= A.margin &&
                       isfinite(g0) && isfinite(g1) && isfinite(g2);
       if (ok) {
