@@ -551,9 +551,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus "
-              f"{args.gpus} is not supported (slices shard across GPUs by "
-              f"design, but no multi-GPU path is built).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not "
+              f"supported (slices shard across GPUs by design, but the "
+              f"library has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib, max(1, args.steps))
