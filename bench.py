@@ -53,7 +53,9 @@ def composite_outputs(torch, n, shape_zyx, dev):
     field starting 4 KiB past the end of the int32 one.  Two output streams
     whose starts differ by a multiple of 8 KiB (as two separate large
     allocations do) write measurably more slowly on this GPU; the layout is
-    the caller's choice, the library takes any 16-byte-aligned pointers."""
+    the caller's choice.  The fp32 field keeps the alignment the library's
+    pack width for these dimensions asks for (16 B when V is a multiple of
+    4, 8 B when it is even)."""
     cnt = n
     for d in shape_zyx:
         cnt *= d
@@ -169,14 +171,11 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
         occ = torch.from_numpy(sc.occ).to(dev)
         ssq, _ = pc.build_static_sdf(sc.grid, occ, want_sdf=False, handle=h)
         del occ
-        shp = (sc.n_slices,) + sc.grid.shape_zyx
+        oc, of = composite_outputs(torch, sc.n_slices, sc.grid.shape_zyx,
+                                   dev)
         scenes.append({"grid": sc.grid, "static_ssq": ssq,
                        "human_xy": sc.human_xy, "radius": sc.radius,
-                       "height": sc.height,
-                       "out_ssq": torch.empty(shp, dtype=torch.int32,
-                                              device=dev),
-                       "out_sdf": torch.empty(shp, dtype=torch.float32,
-                                              device=dev)})
+                       "height": sc.height, "out_ssq": oc, "out_sdf": of})
     torch.cuda.synchronize()
     static_gpu = h.profile_read(_native.KERNEL_STATIC)[0]
     h.profile(False)
