@@ -1,9 +1,9 @@
 // Fused inference of the surrogate MLP (included by mlp.hip): forward pass
-// and input gradient of a tile of 128 rows in one workgroup, with no
+// and input gradient of a tile of 32 RB rows in one workgroup, with no
 // intermediate in HBM.
 //
 // Layout.  Four waves; wave w owns hidden units 32w..32w+31 of every layer
-// for all 128 rows of the tile (four 32-row blocks): in the forward pass as
+// for all rows of the tile (RB 32-row blocks): in the forward pass as
 // its output columns, in the backward pass as the input units whose
 // gradient it forms.  The forward output block of layer l and the backward
 // output block of layer l+1 therefore cover the same rows and units in the
