@@ -81,6 +81,80 @@ static void launch_comp(Handle *h, const int32_t *S, const int32_t *P,
                  s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
 }
 
+// The same composite over the flattened outputs [n][V] in aligned packs of
+// four, for grids whose V is odd (so that a pack of one slice's voxels
+// would start at a different alignment in every slice).
+// Pack t holds flat positions 4t .. 4t+3, each its own (slice, voxel): the
+// static field is read per voxel-slice (from the caches for the slices
+// after the first) so that every store is one aligned 16-byte pack.  The
+// output bases are 16-byte aligned; a last partial pack is stored element
+// by element.  N = n V < 2^32 - 4.
+template <bool kSsq, bool kSdf>
+__global__ __launch_bounds__(256) void k_composite_flat(
+    const int32_t *__restrict__ S, const int32_t *__restrict__ P,
+    int32_t *__restrict__ oc, float *__restrict__ of, uint32_t plane,
+    uint32_t V, uint64_t N, int Kt, int has_above, float hf) {
+  typedef uint32_t U;
+  const U t = (U)blockIdx.x * 256u + threadIdx.x;
+  const U f0 = t * 4u;
+  if ((uint64_t)f0 >= N) return;
+  U sl = f0 / V;
+  uint32_t v = (uint32_t)(f0 - sl * V);
+  uint32_t k = v / plane;
+  uint32_t pix = v - k * plane;
+  pk_i32x4 c;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if ((uint64_t)f0 + e < N) {
+      const int32_t p = P[(size_t)sl * plane + pix];
+      c[e] = min(S[v], human_value(p, human_layer((int)k, Kt, has_above)));
+    } else {
+      c[e] = 0;
+    }
+    // next flat position (V may be below four: a pack may span slices)
+    ++v;
+    if (++pix == plane) {
+      pix = 0;
+      ++k;
+    }
+    while (v >= V) {
+      v -= V;
+      ++sl;
+      k = v / plane;
+      pix = v - k * plane;
+    }
+  }
+  pk_f32x4 fv;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) fv[e] = ssq_to_metres(c[e], hf);
+  if ((uint64_t)f0 + 4 <= N) {
+    if (kSsq) store_i32<4>(oc + f0, c);
+    if (kSdf) store_f32<4>(of + f0, fv);
+  } else {
+    for (int e = 0; (uint64_t)f0 + e < N; ++e) {
+      if (kSsq) oc[f0 + e] = c[e];
+      if (kSdf) of[f0 + e] = fv[e];
+    }
+  }
+}
+
+static void launch_comp_flat(Handle *h, const int32_t *S, const int32_t *P,
+                             int32_t *oc, float *of, uint32_t plane,
+                             uint32_t V, uint64_t N, int Kt, int has_above,
+                             float hf, hipStream_t s) {
+  const uint64_t packs = (N + 3) / 4;
+  const dim3 grid((unsigned)((packs + 255) / 256)), block(256);
+  if (oc && of)
+    launch_timed(h, k_composite_flat<true, true>, grid, block, 0u, s,
+                 S, P, oc, of, plane, V, N, Kt, has_above, hf);
+  else if (oc)
+    launch_timed(h, k_composite_flat<true, false>, grid, block, 0u,
+                 s, S, P, oc, of, plane, V, N, Kt, has_above, hf);
+  else
+    launch_timed(h, k_composite_flat<false, true>, grid, block, 0u,
+                 s, S, P, oc, of, plane, V, N, Kt, has_above, hf);
+}
+
 // Fixed-point conversion of a coordinate to the 2^-16 voxel lattice:
 // rint(((p - o)/h) * 2^16), each step an IEEE fp64 operation.
 static bool to_fixed(double p, double o, double h, int64_t *out) {
@@ -238,6 +312,18 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
   while ((n_slices + G - 1) / G > 65535) ++G;
   const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
   const uint32_t Vu = (uint32_t)V;
+  const uintptr_t out_bits =
+      (uintptr_t)out_ssq_dev | (uintptr_t)out_sdf_dev;
+  const uint64_t N = (uint64_t)n_slices * (uint64_t)V;
+  if (V % 2 != 0 && !need && !(out_bits & 15) && N + 4 <= 0xFFFFFFFFull) {
+    // aligned packs of the flattened outputs (see k_composite_flat): for
+    // odd V they beat one voxel per lane (255x255x127 x 20: 0.39 -> 0.34
+    // ms); for V = 2 mod 4 two-voxel packs that read the static field once
+    // stay faster.  Larger outputs take the per-slice packs below.
+    launch_comp_flat(h, static_ssq_dev, P, out_ssq_dev, out_sdf_dev,
+                            plane, Vu, N, Kt, has_above, hf, s);
+    return check_launch(h, "composite");
+  }
   if (ps.vec == 4 && !ps.gather)
     launch_comp<4, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
                           plane, n_slices, G, Kt, has_above, hf, Vu, s);

@@ -194,7 +194,8 @@ def width_case_scene(dims):
     (33, 27, 20), (34, 27, 12),   # 4-wide streams, planar values gathered
     (33, 27, 22),                 # 2-wide streams, gathered
     (33, 27, 21),                 # 1-wide (V odd)
-    (1, 1, 8), (3, 1, 4), (2, 1, 6)])  # planes smaller than a pack
+    (1, 1, 8), (3, 1, 4), (2, 1, 6),  # planes smaller than a pack
+    (3, 1, 1), (1, 1, 7), (3, 1, 2)])  # V of 3, 7 and 6 voxels
 @pytest.mark.parametrize("offset", [0, 1, 2])
 def test_composite_vector_widths_and_alignment(pc, dev, dims, offset):
     """The composite streams 4, 2 or 1 voxels per lane by V mod 4 and the
