@@ -351,10 +351,12 @@ int pcsdf_autotune_composite(pcsdf_handle *h, const pcsdf_scene *scene,
                              double *best_ms);
 
 /* ---- Learned surrogate for sphere queries (not in the paper) ----------
- * A multilayer perceptron mapping 22 features (sphere centre x, y, z in
- * metres, slice time t in seconds, and for each of three humans its
- * position x, y, z and velocity x, y, z at t = 0) to the composite distance
- * at the centre in metres:  u = (x - offset) * scale;  4 hidden layers of
+ * A multilayer perceptron mapping 22 input features (those written by
+ * pcsdf_surrogate_features: a fixed transform of the sphere centre, the
+ * slice time and three humans' state) to a distance in metres (the
+ * humans' part of the composite when the surrogate query is given the
+ * environment field, else the whole composite):
+ * u = (x - offset) * scale;  4 hidden layers of
  * 128 SiLU units;  y = out_scale * (W4 a4 + b4).  Weights are fp32 masters
  * used as BF16 on the matrix cores with FP32 accumulation; activations,
  * SiLU derivatives and backward pre-activation gradients are rounded to
@@ -385,11 +387,42 @@ int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n, const float *x_dev,
                         float *grad_x_dev, void *stream);
 /* One Adam step (bias-corrected) on the mean squared error between y(x)
  * and target [n] (metres); loss_dev [1] receives the loss before the
- * step, if given. */
+ * step, if given.  The same as pcsdf_mlp_loss_gradients followed by
+ * pcsdf_mlp_adam_step with that gradient. */
 int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n, const float *x_dev,
                          const float *target_dev, float lr, float beta1,
                          float beta2, float eps, float *loss_dev,
                          void *stream);
+/* Gradient of the mean squared error (1/n) sum_m (y(x_m) - target_m)^2
+ * w.r.t. every parameter, grad_params_dev fp32 [PCSDF_MLP_NPARAM] (device,
+ * written), as the training step forms it; loss_dev [1] (nullable) gets the
+ * loss.  No parameter changes. */
+int pcsdf_mlp_loss_gradients(pcsdf_mlp *m, int32_t n, const float *x_dev,
+                             const float *target_dev, float *grad_params_dev,
+                             float *loss_dev, void *stream);
+/* One Adam step (Kingma and Ba, with bias correction) from the gradient
+ * grad_params_dev fp32 [PCSDF_MLP_NPARAM] (device, read): with t the step
+ * count after it is advanced by one,
+ *   m1 = beta1 m1 + (1 - beta1) g,  m2 = beta2 m2 + (1 - beta2) g^2,
+ *   p -= lr (m1 / c1) / (sqrt(m2 / c2) + eps),
+ *   c1 = fp32(1 - beta1^t), c2 = fp32(1 - beta2^t) (powers in fp64),
+ * in fp32 per parameter, then the BF16 weight copies are refreshed.
+ * PCSDF_ERR_NUMERIC for lr < 0, betas outside [0, 1) or eps <= 0. */
+int pcsdf_mlp_adam_step(pcsdf_mlp *m, const float *grad_params_dev, float lr,
+                        float beta1, float beta2, float eps, void *stream);
+/* The optimiser's whole state for checkpoints: the fp32 masters, Adam's
+ * first and second moments (each fp32 [PCSDF_MLP_NPARAM], host) and the
+ * step count.  get waits for the device.  set uploads all of it with the
+ * normalisation (as pcsdf_mlp_set_params, which it calls first, but keeps
+ * the given moments and step instead of resetting them); a network
+ * restored this way continues training exactly as the saved one would.
+ * PCSDF_ERR_NUMERIC on non-finite values or a negative second moment. */
+int pcsdf_mlp_get_state(pcsdf_mlp *m, float *params_host, float *m1_host,
+                        float *m2_host, int64_t *step);
+int pcsdf_mlp_set_state(pcsdf_mlp *m, const float *params_host,
+                        const float *m1_host, const float *m2_host,
+                        int64_t step, const float *in_offset_host,
+                        const float *in_scale_host, float out_scale);
 
 /* Network input for sphere queries, a fixed transform of the query and the
  * humans' state: x[q] = [c_x, c_y, c_z, t, then per human k

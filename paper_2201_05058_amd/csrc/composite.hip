@@ -17,15 +17,20 @@
 // the z pass of the separable EDT done in closed form: the column input
 // is constant on 0..Kt and empty elsewhere, and its lower envelope is that
 // constant plus the squared distance to the interval.  So the exact 3-D
-// field of the humans needs only a 2-D signed EDT per slice (x pass by
-// wave ballot over the disk predicate, y pass by lower envelope, both in
-// edt.hip), and the per-voxel work is a streaming epilogue:
+// field of the humans needs only a 2-D signed EDT per slice (planes.hip:
+// each disk's chord per row from an exact integer square root of the
+// voxelisation predicate, a row pass giving every pixel's distance to the
+// nearest pixel outside the disks, and a bounded per-pixel search over
+// rows for both signs), and the per-voxel work is a streaming epilogue:
 //   read the static field once, then for every slice compute the humans'
 //   value from the slice's plane, take the signed min, convert to metres
 //   and write both outputs.
 // The epilogue moves the compulsory bytes only: 4 B of static field per
 // voxel (read once for all slices) and 8 B per voxel-slice of output; the
-// planes (nx*ny*4 B per slice) stay in cache.
+// planes (nx*ny*4 B per slice) stay in cache.  When V is odd a pack of one
+// slice's voxels would start at a different alignment in every slice, so
+// k_composite_flat walks the flattened outputs [n][V] in aligned packs
+// instead, reading the static field per voxel-slice.
 #include <cmath>
 #include <cstring>
 #include <vector>

@@ -21,7 +21,7 @@ struct Mlp {
   Handle *h = nullptr;
   DevBuf params, grad, m1, m2, wbf, wtbf, norm, wofs;
   float out_scale = 1.f;
-  int step = 0;
+  int64_t step = 0;  // Adam steps taken
   // workspace, grown with the batch
   int cap = 0;
   DevBuf a0, act, dact, dz, seed, y, wpart, bpart, lpart;
@@ -333,6 +333,84 @@ extern "C" int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n,
   return backward(m, n, npad, grad_params_dev, grad_x_dev, s);
 }
 
+// dLoss/dparams of the mean squared error into gp [kNParam] (and the loss
+// into loss_dev): the forward pass, k_mse's seed and the backward pass.
+static int loss_gradients(Mlp *m, int n, const float *x_dev,
+                          const float *target_dev, float *gp,
+                          float *loss_dev, hipStream_t s) {
+  const int npad = pad_rows(n);
+  int rc;
+  if ((rc = ws(m, npad, s))) return rc;
+  float *y = reinterpret_cast<float *>(m->y.ptr);
+  if ((rc = forward(m, n, npad, x_dev, y, s))) return rc;
+  float *lpart = reinterpret_cast<float *>(m->lpart.ptr);
+  hipLaunchKernelGGL(k_mse, dim3(blocks(npad, 256)), dim3(256), 0, s, y,
+                     target_dev, n, npad,
+                     reinterpret_cast<float *>(m->seed.ptr), lpart);
+  if (loss_dev)
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, lpart,
+                       (int)blocks(npad, 256), 1.f / (float)n, loss_dev);
+  return backward(m, n, npad, gp, nullptr, s);
+}
+
+// One bias-corrected Adam step from the gradient g (device, fp32
+// [kNParam]); the step counter advances first, so the first step uses
+// c1 = 1 - beta1, c2 = 1 - beta2.
+static int adam(Mlp *m, const float *g, float lr, float beta1, float beta2,
+                float eps, hipStream_t s) {
+  m->step += 1;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)m->step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)m->step));
+  hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam, 256)), dim3(256), 0, s,
+                     reinterpret_cast<float *>(m->params.ptr), g,
+                     reinterpret_cast<float *>(m->m1.ptr),
+                     reinterpret_cast<float *>(m->m2.ptr), lr, beta1, beta2,
+                     eps, c1, c2, reinterpret_cast<uint16_t *>(m->wbf.ptr),
+                     reinterpret_cast<uint16_t *>(m->wtbf.ptr),
+                     reinterpret_cast<const int *>(m->wofs.ptr));
+  return check_launch(m->h, "mlp adam step");
+}
+
+static int check_adam(Mlp *m, float lr, float beta1, float beta2, float eps) {
+  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+      !(eps > 0) || !std::isfinite(lr) || !std::isfinite(eps))
+    return fail(m->h, PCSDF_ERR_NUMERIC, "bad optimiser hyper-parameters");
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_mlp_loss_gradients(pcsdf_mlp *m, int32_t n,
+                                        const float *x_dev,
+                                        const float *target_dev,
+                                        float *grad_params_dev,
+                                        float *loss_dev, void *stream) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  int rc = check_rows(m, n, x_dev);
+  if (rc) return rc;
+  if (n == 0 || !target_dev || !grad_params_dev)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG,
+                "need n > 0, targets and a gradient buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (((uintptr_t)x_dev | (uintptr_t)target_dev | (uintptr_t)grad_params_dev |
+       (uintptr_t)loss_dev) & 3)
+    return fail(m->h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  return loss_gradients(m, n, x_dev, target_dev, grad_params_dev, loss_dev,
+                        s);
+}
+
+extern "C" int pcsdf_mlp_adam_step(pcsdf_mlp *m, const float *grad_params_dev,
+                                   float lr, float beta1, float beta2,
+                                   float eps, void *stream) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  if (!grad_params_dev)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "gradient is NULL");
+  if ((uintptr_t)grad_params_dev & 3)
+    return fail(m->h, PCSDF_ERR_ALIGN, "gradient must be 4-byte aligned");
+  int rc;
+  if ((rc = check_adam(m, lr, beta1, beta2, eps))) return rc;
+  return adam(m, grad_params_dev, lr, beta1, beta2, eps,
+              reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n,
                                     const float *x_dev,
                                     const float *target_dev, float lr,
@@ -343,33 +421,54 @@ extern "C" int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n,
   if (rc) return rc;
   if (n == 0 || !target_dev)
     return fail(m->h, PCSDF_ERR_INVALID_ARG, "need n > 0 and targets");
-  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
-      !(eps > 0))
-    return fail(m->h, PCSDF_ERR_NUMERIC, "bad optimiser hyper-parameters");
+  if ((rc = check_adam(m, lr, beta1, beta2, eps))) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int npad = pad_rows(n);
-  if ((rc = ws(m, npad, s))) return rc;
   ProfScope ps(m->h, PCSDF_KERNEL_MLP_TRAIN, s);
-  float *y = reinterpret_cast<float *>(m->y.ptr);
-  if ((rc = forward(m, n, npad, x_dev, y, s))) return rc;
-  float *lpart = reinterpret_cast<float *>(m->lpart.ptr);
-  hipLaunchKernelGGL(k_mse, dim3(blocks(npad, 256)), dim3(256), 0, s, y,
-                     target_dev, n, npad,
-                     reinterpret_cast<float *>(m->seed.ptr), lpart);
-  if (loss_dev)
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, lpart,
-                       (int)blocks(npad, 256), 1.f / (float)n, loss_dev);
   float *gp = reinterpret_cast<float *>(m->grad.ptr);
-  if ((rc = backward(m, n, npad, gp, nullptr, s))) return rc;
-  m->step += 1;
-  const float c1 = 1.f - std::pow(beta1, (float)m->step);
-  const float c2 = 1.f - std::pow(beta2, (float)m->step);
-  hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam, 256)), dim3(256), 0, s,
-                     reinterpret_cast<float *>(m->params.ptr), gp,
-                     reinterpret_cast<float *>(m->m1.ptr),
-                     reinterpret_cast<float *>(m->m2.ptr), lr, beta1, beta2,
-                     eps, c1, c2, reinterpret_cast<uint16_t *>(m->wbf.ptr),
-                     reinterpret_cast<uint16_t *>(m->wtbf.ptr),
-                     reinterpret_cast<const int *>(m->wofs.ptr));
-  return check_launch(m->h, "mlp train step");
+  if ((rc = loss_gradients(m, n, x_dev, target_dev, gp, loss_dev, s)))
+    return rc;
+  return adam(m, gp, lr, beta1, beta2, eps, s);
+}
+
+extern "C" int pcsdf_mlp_get_state(pcsdf_mlp *m, float *params_host,
+                                   float *m1_host, float *m2_host,
+                                   int64_t *step) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  if (!params_host || !m1_host || !m2_host || !step)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "every output is required");
+  const size_t P = (size_t)kNParam * 4;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(params_host, m->params.ptr, P, hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(m1_host, m->m1.ptr, P, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(m2_host, m->m2.ptr, P, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(m->h, PCSDF_ERR_HIP, "reading the optimiser state failed");
+  *step = m->step;
+  return PCSDF_OK;
+}
+
+extern "C" int pcsdf_mlp_set_state(pcsdf_mlp *m, const float *params_host,
+                                   const float *m1_host, const float *m2_host,
+                                   int64_t step, const float *in_offset_host,
+                                   const float *in_scale_host,
+                                   float out_scale) {
+  if (!m) return PCSDF_ERR_INVALID_ARG;
+  if (!m1_host || !m2_host)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "moments are required");
+  if (step < 0 || step > (int64_t)1 << 40)
+    return fail(m->h, PCSDF_ERR_INVALID_ARG, "step out of range");
+  for (int i = 0; i < kNParam; ++i)
+    if (!std::isfinite(m1_host[i]) || !std::isfinite(m2_host[i]) ||
+        m2_host[i] < 0.f)
+      return fail(m->h, PCSDF_ERR_NUMERIC,
+                  "bad moment at index " + std::to_string(i));
+  int rc = pcsdf_mlp_set_params(m, params_host, in_offset_host,
+                                in_scale_host, out_scale);
+  if (rc) return rc;
+  const size_t P = (size_t)kNParam * 4;
+  if (hipMemcpy(m->m1.ptr, m1_host, P, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->m2.ptr, m2_host, P, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(m->h, PCSDF_ERR_HIP, "uploading the moments failed");
+  m->step = step;
+  return PCSDF_OK;
 }

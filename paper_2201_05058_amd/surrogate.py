@@ -37,6 +37,14 @@ def _declare(lib):
     lib.pcsdf_mlp_train_step.argtypes = [P, i32, P, P, f32, f32, f32, f32, P,
                                          P]
     lib.pcsdf_mlp_train_step.restype = C.c_int
+    lib.pcsdf_mlp_loss_gradients.argtypes = [P, i32, P, P, P, P, P]
+    lib.pcsdf_mlp_loss_gradients.restype = C.c_int
+    lib.pcsdf_mlp_adam_step.argtypes = [P, P, f32, f32, f32, f32, P]
+    lib.pcsdf_mlp_adam_step.restype = C.c_int
+    lib.pcsdf_mlp_get_state.argtypes = [P, P, P, P, C.POINTER(C.c_int64)]
+    lib.pcsdf_mlp_get_state.restype = C.c_int
+    lib.pcsdf_mlp_set_state.argtypes = [P, P, P, P, C.c_int64, P, P, f32]
+    lib.pcsdf_mlp_set_state.restype = C.c_int
     lib.pcsdf_surrogate_features.argtypes = [P, i32, P, P, i32, C.c_double,
                                              P, P, P]
     lib.pcsdf_surrogate_features.restype = C.c_int
@@ -139,6 +147,50 @@ class Mlp:
             self.ptr, n, self._ptr(x), self._ptr(target), float(lr),
             float(beta1), float(beta2), float(eps), self._ptr(loss),
             self._stream(x)))
+
+    def loss_gradients(self, x, target, loss=None):
+        """Gradient of the mean squared error w.r.t. every parameter
+        (pcsdf_mlp_loss_gradients): float32 [NPARAM] on the GPU."""
+        import torch
+        n = x.shape[0]
+        gp = torch.empty(NPARAM, dtype=torch.float32, device=x.device)
+        self.h.check(self.lib.pcsdf_mlp_loss_gradients(
+            self.ptr, n, self._ptr(x), self._ptr(target), self._ptr(gp),
+            self._ptr(loss), self._stream(x)))
+        return gp
+
+    def adam_step(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step from a float32 [NPARAM] gradient on the GPU."""
+        import torch
+        assert grad.dtype == torch.float32 and grad.numel() == NPARAM
+        self.h.check(self.lib.pcsdf_mlp_adam_step(
+            self.ptr, self._ptr(grad), float(lr), float(beta1), float(beta2),
+            float(eps), self._stream(grad)))
+
+    def get_state(self):
+        """(params, m1, m2, step): the optimiser's state, for checkpoints."""
+        p, m1, m2 = (np.empty(NPARAM, np.float32) for _ in range(3))
+        step = C.c_int64()
+        self.h.check(self.lib.pcsdf_mlp_get_state(
+            self.ptr, p.ctypes.data_as(C.c_void_p),
+            m1.ctypes.data_as(C.c_void_p), m2.ctypes.data_as(C.c_void_p),
+            C.byref(step)))
+        return p, m1, m2, int(step.value)
+
+    def set_state(self, params, m1, m2, step, in_offset, in_scale,
+                  out_scale):
+        """Restores what get_state returned, with the normalisation."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float32)
+                for a in (params, m1, m2)]
+        if any(a.size != NPARAM for a in arrs):
+            raise ValueError(f"need {NPARAM} values per array")
+        self.in_offset = np.ascontiguousarray(in_offset, np.float32)
+        self.in_scale = np.ascontiguousarray(in_scale, np.float32)
+        self.out_scale = float(out_scale)
+        self.h.check(self.lib.pcsdf_mlp_set_state(
+            self.ptr, *(a.ctypes.data_as(C.c_void_p) for a in arrs),
+            int(step), self.in_offset.ctypes.data_as(C.c_void_p),
+            self.in_scale.ctypes.data_as(C.c_void_p), self.out_scale))
 
     def close(self):
         if getattr(self, "ptr", None):

@@ -254,8 +254,12 @@ def test_composite_no_humans_and_empty_static(pc, dev):
     check_composite(pc, sc3, dev)
 
 
-def test_composite_single_output_modes(pc, dev):
-    sc = scenegen.small_scene(15, 36, 30, 20, n_humans=2, n_slices=3)
+@pytest.mark.parametrize("dims", [(36, 30, 20), (35, 29, 21)])
+def test_composite_single_output_modes(pc, dev, dims):
+    # 35 x 29 x 21 has odd V (the flattened-pack kernels, one per output
+    # mode) and 3 V = 1 mod 4 (a partial last pack)
+    say(f"composite single outputs {dims}")
+    sc = scenegen.small_scene(15, *dims, n_humans=2, n_slices=3)
     rs, _ = oracle.build_static(sc.grid, sc.occ)
     wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
                                         sc.height)

@@ -114,9 +114,9 @@ def test_queries_on_oracle_slices(run, slice_oracle):
 
 @pytest.mark.parametrize("G", [5, 10, 25])
 def test_other_slice_groups_give_identical_bytes(run, G):
-    """The composite in the launch shapes the autotuner picks for this
-    workload (it has chosen 10 slices per block row): the same bytes as
-    the default shape checked above, for all 50 slices."""
+    """The composite in other launch shapes the autotuner may pick for
+    this workload (slice groups of 5, 10 and 25 per block row): the same
+    bytes as the default shape checked above, for all 50 slices."""
     import paper_2201_05058_amd as pc
     sc = run["sc"]
     say(f"room512: composite with {G} slices per block row")

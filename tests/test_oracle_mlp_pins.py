@@ -95,15 +95,16 @@ def test_rounding_changes_little():
     assert not np.array_equal(y0, y1)
 
 
-def test_adam_matches_torch():
+@pytest.mark.parametrize("b1,b2,eps", [(0.9, 0.999, 1e-8), (0.8, 0.95, 1e-6)])
+def test_adam_matches_torch(b1, b2, eps):
     p = rng.normal(size=300)
     m = np.zeros(300)
     v = np.zeros(300)
     tp = torch.tensor(p.copy(), dtype=torch.float64, requires_grad=True)
-    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(b1, b2), eps=eps)
     for step in range(1, 6):
         g = rng.normal(size=300)
-        p, m, v = mlp.adam_step(p, g, m, v, step, 1e-2)
+        p, m, v = mlp.adam_step(p, g, m, v, step, 1e-2, b1, b2, eps)
         opt.zero_grad()
         tp.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()

@@ -5,6 +5,7 @@ first slice a lone human inside the grid always gives the exact field; and
 in general it differs from the exact field by at most the sub-voxel shift
 and re-voxelisation (bounded here in metres)."""
 import numpy as np
+import pytest
 
 import oracle
 import scenegen
@@ -55,3 +56,37 @@ def test_subvoxel_motion_close_to_exact():
     # a half-voxel shift per axis plus one voxel of re-voxelisation
     assert np.abs(gf[free] - wf[free]).max() <= 2.0 * sc.grid.h
     assert ((got < 0) == (want < 0)).mean() > 0.99
+
+
+# Worked example of the shift rule (the nearest whole-voxel displacement,
+# ties upward): a displacement of delta voxels moves the template by
+#   +0.5 -> 1,  -0.5 -> 0,  -0.51 -> -1,  +1.49 -> 1   voxels.
+# Truncation gives (0, 0, 0, 1), plain floor (0, -1, -1, 1), rounding
+# half away from zero (1, -1, -1, 1) and half to even (0, 0, -1, 1): each
+# differs from the rule in one case at least.  With h a power of two the
+# fixed-point displacements are exact (32768, -32768, -33423, 97648 in
+# units of 2^-16 voxel), and a lone human inside the grid shifted by d
+# whole voxels has exactly the exact field of the human at x0 + d h.
+@pytest.mark.parametrize("delta,d", [(0.5, 1), (-0.5, 0), (-0.51, -1),
+                                     (1.49, 1)])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_shift_rule_worked_example(delta, d, axis):
+    h = 0.0625
+    sc, rs = _room(84, nx=28, ny=24, nz=6, h=h)
+    x0 = np.array([12.5 * h, 11.5 * h])  # a voxel centre
+    x1 = x0.copy()
+    x1[axis] += delta * h
+    xy = np.stack([x0, x1])[:, None, :]
+    got, _ = template_composite(sc.grid, rs, xy, 0.2, 0.25)
+    whole = x0.copy()
+    whole[axis] += d * h
+    want, _ = oracle.predicted_composite(sc.grid, rs, whole[None, None, :],
+                                         0.2, 0.25)
+    np.testing.assert_array_equal(got[1], want[0])
+    # the neighbouring whole shifts give other fields, so the check tells
+    for other in (d - 1, d + 1):
+        alt = x0.copy()
+        alt[axis] += other * h
+        wa, _ = oracle.predicted_composite(sc.grid, rs, alt[None, None, :],
+                                           0.2, 0.25)
+        assert (got[1] != wa[0]).any()
