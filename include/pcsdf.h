@@ -155,6 +155,25 @@ int pcsdf_predicted_composite_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                                   int32_t *out_ssq_dev, float *out_sdf_dev,
                                   void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same call
+ * and result as pcsdf_predicted_composite_sdf, with the planar fields, row
+ * passes and chords in a library-owned device array of 64 MiB per device
+ * (held until the process ends) instead of the handle's workspace.  It
+ * calls no allocating routine; the caller passes every input and output.
+ * Limits (PCSDF_ERR_INVALID_ARG beyond them):
+ *   2*n_slices*n_humans + n_slices <= 240 (the fixed-point centres travel
+ *   in the kernels' arguments), and
+ *   align256(8*n_slices*nx*ny) + 8*n_slices*max(n_humans,1)*ny <= 64 MiB.
+ * Every call on one device shares that array: calls that overlap on one
+ * device (other streams, other handles, other threads) race and must be
+ * ordered by the caller.  No profiling region is timed. */
+int pcsdf_predicted_composite_sdf_noalloc(
+    pcsdf_handle *h, const pcsdf_grid *grid, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, int32_t *out_ssq_dev,
+    float *out_sdf_dev, void *stream);
+
 /* The same sequence with a radius per slice (discussion section: the
  * cylinders could grow over the prediction horizon to account for the
  * growing uncertainty of the predicted positions, e.g. r(t) = r0 + sigma*t).

@@ -128,6 +128,32 @@ def predicted_composite_sdf(grid, static_ssq, human_xy, radius, height,
     return out_ssq, out_sdf
 
 
+def predicted_composite_sdf_noalloc(grid, static_ssq, human_xy, radius,
+                                    height, out_ssq, out_sdf,
+                                    handle: Handle | None = None):
+    """The composite without any allocation by the library
+    (pcsdf_predicted_composite_sdf_noalloc): the caller passes both output
+    tensors ([n, nz, ny, nx] int32 / float32, either may be None); the
+    planar fields live in the library's fixed per-device scratch."""
+    torch = _torch()
+    g = as_grid(grid)
+    h = handle or default_handle()
+    xy = np.ascontiguousarray(np.asarray(human_xy, dtype=np.float64))
+    if xy.ndim != 3 or xy.shape[2] != 2:
+        raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
+    n, K = xy.shape[0], xy.shape[1]
+    V = g.nvox
+    dev = static_ssq.device
+    rc = h.lib.pcsdf_predicted_composite_sdf_noalloc(
+        h.ptr, C.byref(g), _dev_ptr(static_ssq, torch.int32, "static_ssq", V),
+        n, K, xy.ctypes.data_as(C.c_void_p) if K > 0 else None,
+        float(radius), float(height),
+        _dev_ptr(out_ssq, torch.int32, "out_ssq", n * V),
+        _dev_ptr(out_sdf, torch.float32, "out_sdf", n * V), _stream(dev))
+    h.check(rc)
+    return out_ssq, out_sdf
+
+
 def predicted_composite_sdf_growing(grid, static_ssq, human_xy,
                                     radius_per_slice, height, out_ssq=None,
                                     out_sdf=None, want_ssq=True,

@@ -124,6 +124,9 @@ def load_library():
         lib.pcsdf_predicted_composite_sdf.argtypes = [
             P, GP, P, i32, i32, P, f64, f64, P, P, P]
         lib.pcsdf_predicted_composite_sdf.restype = C.c_int
+        lib.pcsdf_predicted_composite_sdf_noalloc.argtypes = [
+            P, GP, P, i32, i32, P, f64, f64, P, P, P]
+        lib.pcsdf_predicted_composite_sdf_noalloc.restype = C.c_int
         lib.pcsdf_predicted_composite_sdf_growing.argtypes = [
             P, GP, P, i32, i32, P, P, f64, P, P, P]
         lib.pcsdf_predicted_composite_sdf_growing.restype = C.c_int

@@ -33,6 +33,7 @@
 // instead, reading the static field per voxel-slice.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "composite_device.h"
@@ -171,53 +172,78 @@ static bool to_fixed(double p, double o, double h, int64_t *out) {
   return true;
 }
 
-int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
-                  int32_t n_humans, const double *human_xy_host,
-                  double radius_m, const double *radius_per_slice,
-                  double height_m, hipStream_t s, HumanSet *out) {
-  if (n_slices < 1)
-    return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
-  if (n_humans < 0 || n_humans > kMaxHumans)
-    return fail(h, PCSDF_ERR_INVALID_ARG, "n_humans must be in [0, 256]");
-  if (n_humans > 0 && !human_xy_host)
-    return fail(h, PCSDF_ERR_INVALID_ARG, "human_xy_host is required");
+// Validates the humans of every slice and converts them to the fixed-point
+// lattice: words [0, 2 n_slices n_humans) are the centres, then one radius
+// per slice.  `w` must hold humans_words() values.
+static size_t humans_words(int32_t n_slices, int32_t n_humans) {
+  return 2 * (size_t)n_slices * (size_t)n_humans + (size_t)n_slices;
+}
+
+static int humans_fixed(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+                        int32_t n_humans, const double *human_xy_host,
+                        double radius_m, const double *radius_per_slice,
+                        double height_m, int64_t *w, int *Kt_out) {
   const double hv = g->voxel_m;
   if (!std::isfinite(height_m) || height_m < 0)
     return fail(h, PCSDF_ERR_NUMERIC, "height_m must be finite, >= 0");
   int64_t Hq;
   if (!to_fixed(height_m, 0.0, hv, &Hq))
     return fail(h, PCSDF_ERR_NUMERIC, "height out of range");
+  const size_t ncent = (size_t)n_slices * n_humans;
   // Fixed-point radius of every slice.
-  std::vector<int64_t> Rs((size_t)n_slices);
   for (int32_t j = 0; j < n_slices; ++j) {
     const double r = radius_per_slice ? radius_per_slice[j] : radius_m;
     if (!std::isfinite(r) || r < 0)
       return fail(h, PCSDF_ERR_NUMERIC, "radius must be finite, >= 0");
-    if (!to_fixed(r, 0.0, hv, &Rs[j]))
+    int64_t R;
+    if (!to_fixed(r, 0.0, hv, &R))
       return fail(h, PCSDF_ERR_NUMERIC, "radius out of range");
-    if (Rs[j] >= (1LL << 31))
+    if (R >= (1LL << 31))
       return fail(h, PCSDF_ERR_NUMERIC, "radius/voxel_m must be < 32768");
+    w[2 * ncent + j] = R;
   }
-  const int ny = g->ny, nz = g->nz;
   // Highest layer whose centre lies at or under the cylinder top.
-  const int Kt =
-      Hq >= 32768 ? (int)std::min<int64_t>((Hq - 32768) / 65536, nz - 1) : -1;
-  const bool empty = Kt < 0 || n_humans == 0;
-
+  *Kt_out = Hq >= 32768
+                ? (int)std::min<int64_t>((Hq - 32768) / 65536, g->nz - 1)
+                : -1;
   // Fixed-point centres, validated on the host before anything is queued.
-  const size_t ncent = (size_t)n_slices * n_humans;
-  std::vector<int64_t> &xy = h->host_xy;
-  xy.resize(2 * ncent + (size_t)n_slices);
   for (size_t t = 0; t < ncent; ++t) {
-    if (!to_fixed(human_xy_host[2 * t], g->origin_m[0], hv, &xy[2 * t]) ||
+    if (!to_fixed(human_xy_host[2 * t], g->origin_m[0], hv, &w[2 * t]) ||
         !to_fixed(human_xy_host[2 * t + 1], g->origin_m[1], hv,
-                  &xy[2 * t + 1]))
+                  &w[2 * t + 1]))
       return fail(h, PCSDF_ERR_NUMERIC,
                   "human position non-finite or out of range at index " +
                       std::to_string(t));
   }
-  std::memcpy(xy.data() + 2 * ncent, Rs.data(), Rs.size() * sizeof(int64_t));
-  int rc;
+  return PCSDF_OK;
+}
+
+static int check_human_args(Handle *h, int32_t n_slices, int32_t n_humans,
+                            const double *human_xy_host) {
+  if (n_slices < 1)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_slices must be >= 1");
+  if (n_humans < 0 || n_humans > kMaxHumans)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_humans must be in [0, 256]");
+  if (n_humans > 0 && !human_xy_host)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "human_xy_host is required");
+  return PCSDF_OK;
+}
+
+int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+                  int32_t n_humans, const double *human_xy_host,
+                  double radius_m, const double *radius_per_slice,
+                  double height_m, hipStream_t s, HumanSet *out) {
+  int rc = check_human_args(h, n_slices, n_humans, human_xy_host);
+  if (rc) return rc;
+  const int ny = g->ny;
+  const size_t ncent = (size_t)n_slices * n_humans;
+  std::vector<int64_t> &xy = h->host_xy;
+  xy.resize(humans_words(n_slices, n_humans));
+  int Kt;
+  if ((rc = humans_fixed(h, g, n_slices, n_humans, human_xy_host, radius_m,
+                         radius_per_slice, height_m, xy.data(), &Kt)))
+    return rc;
+  const bool empty = Kt < 0 || n_humans == 0;
   if ((rc = bind_device(h))) return rc;
   const size_t xy_bytes = xy.size() * sizeof(int64_t);
   const size_t chord_bytes =
@@ -244,7 +270,7 @@ int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   out->chords = reinterpret_cast<int2 *>(h->chord_buf.ptr);
   out->K = empty ? 0 : n_humans;
   out->Kt = empty ? -1 : Kt;
-  out->has_above = out->Kt + 1 <= nz - 1;
+  out->has_above = out->Kt + 1 <= g->nz - 1;
   return PCSDF_OK;
 }
 
@@ -377,4 +403,107 @@ extern "C" int pcsdf_predicted_composite_sdf_growing(
                        human_xy_host, 0.0, radius_per_slice_m, height_m,
                        out_ssq_dev, out_sdf_dev, nullptr,
                        reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---- The composite without allocation -----------------------------------
+// One call's planar fields, row passes and chords live in a file-scope
+// device array instead of the handle's workspace, for callers that cannot
+// allocate device memory (graph capture, serving loops).  Each device the
+// library runs on holds its own copy of the array until the process ends;
+// every call on a device shares it, so calls that overlap on one device
+// race.  Nothing in it needs to start at zero: each call writes every
+// chord, row-pass value and plane pixel before it reads them.
+namespace pcsdf {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kNoAllocMaxDevices];
+
+// The device address of `scratch` on the handle's (current) device, taken
+// once per device: in host code the array's name is not a device address.
+static int scratch_address(Handle *h, unsigned char **out) {
+  if (h->device < 0 || h->device >= kNoAllocMaxDevices)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "device index beyond the no-allocation entry point's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  void *&p = g_scratch_ptr[h->device];
+  if (!p) {
+    void *q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !q) {
+      (void)hipGetLastError();
+      return fail(h, PCSDF_ERR_HIP,
+                  std::string("hipGetSymbolAddress(scratch): ") +
+                      hipGetErrorString(e));
+    }
+    p = q;
+  }
+  *out = static_cast<unsigned char *>(p);
+  return PCSDF_OK;
+}
+
+}  // namespace pcsdf
+
+extern "C" int pcsdf_predicted_composite_sdf_noalloc(
+    pcsdf_handle *hp, const pcsdf_grid *g, const int32_t *static_ssq_dev,
+    int32_t n_slices, int32_t n_humans, const double *human_xy_host,
+    double radius_m, double height_m, int32_t *out_ssq_dev,
+    float *out_sdf_dev, void *stream) {
+  Handle *h = reinterpret_cast<Handle *>(hp);
+  if (!h) return PCSDF_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = check_grid(h, g);
+  if (rc) return rc;
+  if (!static_ssq_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "static_ssq_dev is required");
+  if (!out_ssq_dev && !out_sdf_dev)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "at least one of out_ssq_dev / out_sdf_dev is required");
+  if (((uintptr_t)static_ssq_dev & 3) || ((uintptr_t)out_ssq_dev & 3) ||
+      ((uintptr_t)out_sdf_dev & 3))
+    return fail(h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
+  if ((rc = check_human_args(h, n_slices, n_humans, human_xy_host))) return rc;
+  const size_t words = humans_words(n_slices, n_humans);
+  if (words > (size_t)kCentresInArgs)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "no-allocation composite: 2*n_slices*n_humans + n_slices = " +
+                    std::to_string(words) + " exceeds " +
+                    std::to_string(kCentresInArgs));
+  const int nx = g->nx, ny = g->ny;
+  const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
+  const size_t chord_off = align_up(2 * plane_bytes, 256);
+  const size_t chord_bytes =
+      (size_t)n_slices * (n_humans > 0 ? n_humans : 1) * ny * sizeof(int2);
+  if (chord_off + chord_bytes > kNoAllocScratchBytes)
+    return fail(h, PCSDF_ERR_INVALID_ARG,
+                "no-allocation composite: needs " +
+                    std::to_string(chord_off + chord_bytes) +
+                    " bytes of scratch (8*n_slices*nx*ny, then "
+                    "8*n_slices*max(n_humans,1)*ny), the maximum is " +
+                    std::to_string(kNoAllocScratchBytes));
+  Centres C;
+  C.xy = nullptr;
+  C.Rs = nullptr;
+  C.rs_off = (int32_t)(2 * (size_t)n_slices * n_humans);
+  int Kt;
+  if ((rc = humans_fixed(h, g, n_slices, n_humans, human_xy_host, radius_m,
+                         nullptr, height_m, C.w, &Kt)))
+    return rc;
+  if ((rc = bind_device(h))) return rc;
+  unsigned char *base;
+  if ((rc = scratch_address(h, &base))) return rc;
+  const bool empty = Kt < 0 || n_humans == 0;
+  int32_t *P = reinterpret_cast<int32_t *>(base);
+  int2 *chords = reinterpret_cast<int2 *>(base + chord_off);
+  if ((rc = launch_planes(h, C, n_humans, empty, chords, P, nx, ny, n_slices,
+                          nullptr, s)))
+    return rc;
+  const int Kt_eff = empty ? -1 : Kt;
+  return launch_composite(h, g, static_ssq_dev, P, nullptr, Kt_eff,
+                          Kt_eff + 1 <= g->nz - 1, n_slices, out_ssq_dev,
+                          out_sdf_dev, s);
 }

@@ -224,3 +224,23 @@ def test_tuning_validation_without_device(h):
         t = Tuning.from_dict(bad)
         assert h.lib.pcsdf_set_tuning(h.ptr, C.byref(t)) == 1, bad
     assert h.get_tuning().as_dict() == good  # rejected calls change nothing
+
+
+def test_noalloc_composite_rejects_on_the_host(h):
+    """The no-allocation composite refuses centre sets beyond its kernel
+    arguments and planes beyond its scratch before touching a device."""
+    import numpy as np
+    f = h.lib.pcsdf_predicted_composite_sdf_noalloc
+    g = grid(40, 40, 20)
+    xy = np.zeros((50, 8, 2))
+    rc = f(h.ptr, C.byref(g), FAKE, 50, 8, xy.ctypes.data_as(C.c_void_p),
+           0.25, 1.8, FAKE, None, None)
+    assert rc == 1 and b"exceeds 240" in h.lib.pcsdf_last_error(h.ptr)
+    g = grid(1024, 1024, 2)
+    xy = np.zeros((20, 1, 2))
+    rc = f(h.ptr, C.byref(g), FAKE, 20, 1, xy.ctypes.data_as(C.c_void_p),
+           0.25, 1.8, FAKE, None, None)
+    assert rc == 1 and b"scratch" in h.lib.pcsdf_last_error(h.ptr)
+    rc = f(h.ptr, C.byref(grid()), FAKE_MIS, 2, 1,
+           xy.ctypes.data_as(C.c_void_p), 0.25, 1.8, FAKE, None, None)
+    assert rc == 3
