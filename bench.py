@@ -2,15 +2,19 @@
 """Throughput of the predicted composite distance field on one MI355X.
 
 One step = the whole hot path over one batch of synthetic input: the
-per-slice composite fields of a 256x256x128 grid at 0.02 m (40 static
-boxes, 3 constant-velocity humans, 20 slices at dt = 0.1 s; the static
-field is built once beforehand, as the paper's environment field is) and
-10k exact sphere queries on those fields.
+per-slice composite fields of a 512x512x256 grid at 0.01 m (200 static
+boxes, 8 humans on piecewise-linear paths, 50 slices at dt = 0.05 s; the
+static field is built once beforehand, as the paper's environment field
+is) and 100k exact sphere queries per slice (5M) on those fields.
+`--workload room256` times the 256x256x128 grid (40 boxes, 3
+constant-velocity humans, 20 slices at 0.1 s, 10k spheres) instead; it is
+also measured as a section of the default run.
 
 Prints one JSON line.  `value` is voxel-slices/s of whole steps with the
 inputs resident in HBM.  `roofline` covers the dominant kernel (the
 streaming composite), timed with HIP events on its own launch stream.
-`cpu_baseline` times the CPU oracle on the same workload (rank 0, N=1).
+`cpu_baseline` times the CPU oracle on a sample of the same workload
+(rank 0, N=1), on one core and on all the cores it may use.
 """
 from __future__ import annotations
 
@@ -27,7 +31,20 @@ sys.path.insert(0, ROOT)
 METRIC = ("composite-EDT voxel-slices/s (% HBM peak); "
           "sphere queries/s surrogate vs exact")
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_room256_traffic.json")
+WORKLOADS = {
+    "room512": "512x512x256 grid at 0.01 m, 200 seeded boxes, 8 cylinder "
+               "humans on piecewise-linear paths, 50 slices at dt=0.05 s, "
+               "100k exact sphere queries per slice (5M)",
+    "room256": "256x256x128 grid at 0.02 m, 40 seeded boxes, 3 "
+               "constant-velocity cylinder humans, 20 slices at dt=0.1 s, "
+               "10k exact sphere queries",
+}
+
+
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles",
+                        f"composite_{workload}_traffic.json")
+
 COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
                              "composite.hip")
 
@@ -110,12 +127,12 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
             "composite_hip_sha256_16": source_hash(COMPOSITE_SRC)}
 
 
-def load_traffic(V: int, n: int):
+def load_traffic(workload: str, V: int, n: int):
     """Measured HBM bytes per composite launch (rocprofv3 PMC FETCH_SIZE +
     WRITE_SIZE, scaled by a copy-kernel calibration), or None when absent
     or taken on a different version of the kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -126,28 +143,51 @@ def load_traffic(V: int, n: int):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(sc, max_slices: int):
-    import numpy as np
-    import oracle
-    n = min(max_slices, sc.n_slices)
-    rs, _ = oracle.build_static(sc.grid, sc.occ)
-    t0 = time.perf_counter()
-    oracle.predicted_composite(sc.grid, rs, sc.human_xy[:n], sc.radius,
-                               sc.height)
-    dt = time.perf_counter() - t0
-    model = ""
+def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
             for ln in f:
                 if ln.startswith("model name"):
-                    model = ln.split(":", 1)[1].strip()
-                    break
+                    return ln.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": sc.grid.nvox * n / dt, "unit": "voxel-slices/s",
-            "cores": 1, "kind": "oracle", "cpu_model": model,
-            "sample": f"{n} of {sc.n_slices} slices of the same workload "
-                      f"(single-threaded C oracle, {dt:.1f} s)"}
+    return ""
+
+
+def cpu_baseline(sc, single_slices: int, omp_slices: int, runs: int = 3):
+    """The oracle on a bounded sample of the workload: the first
+    `single_slices` slices on one core (one run), and the first
+    `omp_slices` slices with the same C built with OpenMP on every core it
+    may use (median of `runs`).  The static field (not part of a step) is
+    built beforehand by the OpenMP build."""
+    import statistics
+    import oracle
+    rs, _ = oracle.build_static(sc.grid, sc.occ, omp=True)
+    V = sc.grid.nvox
+
+    def once(n, omp):
+        t0 = time.perf_counter()
+        oracle.predicted_composite(sc.grid, rs, sc.human_xy[:n], sc.radius,
+                                   sc.height, omp=omp)
+        return time.perf_counter() - t0
+    n1 = min(single_slices, sc.n_slices)
+    t1 = once(n1, False)
+    nm = min(omp_slices, sc.n_slices)
+    tm = statistics.median(once(nm, True) for _ in range(runs))
+    threads = oracle.threads(omp=True)
+    return {"value": V * nm / tm, "unit": "voxel-slices/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"slices 0-{nm - 1} of {sc.n_slices} of the same "
+                      f"workload, OpenMP build of the C oracle on {threads} "
+                      f"threads, median of {runs} runs of {tm:.2f} s",
+            "cpu_model": cpu_model(),
+            "cores_available": len(os.sched_getaffinity(0)),
+            "single_thread": {
+                "value": V * n1 / t1, "unit": "voxel-slices/s", "cores": 1,
+                "sample": f"slice{'s 0-' if n1 > 1 else ' '}"
+                          f"{n1 - 1 if n1 > 1 else 0} of {sc.n_slices}, "
+                          f"plain single-threaded build, one run of "
+                          f"{t1:.2f} s"}}
 
 
 def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
@@ -230,88 +270,134 @@ def batch_section(pc, autotune, scenegen, torch, dev, reps: int = 5):
             "tuning": tuning}
 
 
-def room512_section(pc, autotune, scenegen, torch, dev, reps: int = 3):
-    """The largest workload, 512x512x256 at 0.01 m with 200 boxes, 8 humans
-    on piecewise-linear paths, 50 slices at dt = 0.05 s and 100k spheres
-    per slice (5M): the static build, the composite of all 50 slices (26.8
-    GB of outputs) and the 5M exact queries, on fields and without them,
-    by GPU time (HIP events around the kernels)."""
+def measure_workload(pc, autotune, torch, dev, sc, name: str, steps: int,
+                     warmup: int, sections=None):
+    """Whole steps of one workload (composite of every slice, then the exact
+    sphere queries on the fields): wall time per step over `steps` timed
+    steps, the composite kernel's own time during them (HIP events of its
+    dispatch on the launch stream), then the planes and the queries timed
+    over as many steps right after.  The static build (once per scene) is
+    timed apart.  `sections(h, occ, ssq_s, out_ssq, out_sdf)` may add
+    measurements on the same buffers; its dict is merged into the result."""
     from paper_2201_05058_amd import _native
-    sc = scenegen.room512()
     g = sc.grid
-    n, V = sc.n_slices, g.nvox
+    V, n, K = g.nvox, sc.n_slices, sc.n_humans
     q = sc.queries
+    Q = len(q.radius)
     h = pc.Handle()
     occ = torch.from_numpy(sc.occ).to(dev)
+    centre = torch.from_numpy(q.centre).to(dev)
+    radius = torch.from_numpy(q.radius).to(dev)
+    slices = torch.from_numpy(q.slice).to(dev)
+    out_ssq, out_sdf = composite_outputs(torch, n, g.shape_zyx, dev)
+
+    # static field, built once per scene (not part of a step); timed warm
+    # over three builds with both outputs
+    h.profile(True)
     ssq_s, sdf_s = pc.build_static_sdf(g, occ, handle=h)
     torch.cuda.synchronize()
-    h.profile(True)
     h.profile_reset()
-    for _ in range(reps):
+    for _ in range(3):
         pc.build_static_sdf(g, occ, ssq=ssq_s, sdf=sdf_s, handle=h)
     torch.cuda.synchronize()
-    static_ms = h.profile_read(_native.KERNEL_STATIC)[0] / reps
-    del occ, sdf_s
-    shp = (n,) + g.shape_zyx
-    out_ssq, out_sdf = composite_outputs(torch, shp[0], shp[1:], dev)
+    st_ms, st_n = h.profile_read(_native.KERNEL_STATIC)
+    static_ms = st_ms / max(st_n, 1)
+    del sdf_s
+
+    # launch shape of the composite, tuned on this workload (cached)
     scene = {"grid": g, "static_ssq": ssq_s, "human_xy": sc.human_xy,
              "radius": sc.radius, "height": sc.height, "out_ssq": out_ssq,
              "out_sdf": out_sdf}
     tuning, _, _ = autotune.tuned(
-        h, autotune.composite_signature(g, n, sc.n_humans),
-        lambda: pc.autotune_composite(scene, reps=2, handle=h)[:2])
-    h.profile(True)
+        h, autotune.composite_signature(g, n, K),
+        lambda: pc.autotune_composite(scene, reps=3 if V * n < 1e9 else 2,
+                                      handle=h)[:2])
 
-    def run():
+    def step():
         pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
                                    sc.height, out_ssq=out_ssq,
                                    out_sdf=out_sdf, handle=h)
-    run()
+        return pc.query_spheres(g, out_sdf, centre, radius, slices,
+                                handle=h)
+
+    # The timed steps time the composite kernel alone (a timed kernel
+    # costs the stream a few microseconds before it); the planes and
+    # queries are timed over as many steps right after.
+    h.profile(True, only=[_native.KERNEL_COMPOSITE])
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     h.profile_reset()
-    for _ in range(reps):
-        run()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
     torch.cuda.synchronize()
-    comp_ms = h.profile_read(_native.KERNEL_COMPOSITE)[0] / reps
-    planes_ms = h.profile_read(_native.KERNEL_PLANES)[0] / reps
-    centre = torch.from_numpy(q.centre).to(dev)
-    radius = torch.from_numpy(q.radius).to(dev)
-    slices = torch.from_numpy(q.slice).to(dev)
-    Q = len(q.radius)
-    pc.query_spheres(g, out_sdf, centre, radius, slices, handle=h)
-    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    comp_ms, comp_n = h.profile_read(_native.KERNEL_COMPOSITE)
+
+    h.profile(True, only=[_native.KERNEL_PLANES, _native.KERNEL_QUERY])
     h.profile_reset()
-    for _ in range(reps):
-        pc.query_spheres(g, out_sdf, centre, radius, slices, handle=h)
+    for _ in range(steps):
+        step()
     torch.cuda.synchronize()
-    query_ms = h.profile_read(_native.KERNEL_QUERY)[0] / reps
+    pl_ms, pl_n = h.profile_read(_native.KERNEL_PLANES)
+    qy_ms, qy_n = h.profile_read(_native.KERNEL_QUERY)
+    h.profile(True)
+    comp_avg_s = comp_ms / comp_n / 1e3
+    # compulsory bytes of one composite launch: read the static field once
+    # (4 B/voxel) and write both outputs (8 B/voxel-slice)
+    alg_bytes = (8.0 + 4.0 / n) * V * n
+    achieved = alg_bytes / comp_avg_s / 1e9
+    qy_avg = qy_ms / max(qy_n, 1)
+    res = {
+        "value": V * n / (ms_per_step / 1e3),
+        "ms_per_step": ms_per_step,
+        "config": {"workload": WORKLOADS[name],
+                   "grid": [g.nx, g.ny, g.nz], "voxel_m": g.h,
+                   "n_slices": n, "n_humans": K, "n_queries": Q,
+                   "seed": sc.seed},
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": load_traffic(name, V, n),
+            "kernel": "k_composite",
+            "kernel_ms": comp_avg_s * 1e3,
+            "kernel_launches_timed": comp_n,
+            "bytes_per_voxel_slice": 8.0 + 4.0 / n,
+            "frac_12B_basis": 12.0 * V * n / comp_avg_s / 1e9 / HBM_PEAK_GBS,
+        },
+        "kernels_ms": {"composite": comp_avg_s * 1e3,
+                       "planes": pl_ms / max(pl_n, 1),
+                       "query": qy_avg,
+                       "static_build_once": static_ms},
+        "static_build_gbs_9B_basis": 9.0 * V / (static_ms * 1e-3) / 1e9,
+        "queries_per_s_exact_kernel": Q / (qy_avg / 1e3)
+        if qy_ms > 0 else None,
+        "tuning": tuning,
+    }
+    if sections is not None:
+        res.update(sections(h, occ, ssq_s, out_ssq, out_sdf))
     del out_ssq, out_sdf
     torch.cuda.empty_cache()
+    # exact queries answered without fields (planes + static field only)
     pc.query_spheres_direct(g, ssq_s, sc.human_xy, sc.radius, sc.height,
                             centre, radius, slices, handle=h)
     torch.cuda.synchronize()
+    h.profile(True, only=[_native.KERNEL_PLANES, _native.KERNEL_QUERY])
     h.profile_reset()
+    reps = 3
     for _ in range(reps):
         pc.query_spheres_direct(g, ssq_s, sc.human_xy, sc.radius, sc.height,
                                 centre, radius, slices, handle=h)
     torch.cuda.synchronize()
-    direct_ms = (h.profile_read(_native.KERNEL_QUERY)[0] +
-                 h.profile_read(_native.KERNEL_PLANES)[0]) / reps
+    res["direct_query_ms_incl_planes"] = (
+        h.profile_read(_native.KERNEL_QUERY)[0] +
+        h.profile_read(_native.KERNEL_PLANES)[0]) / reps
     h.close()
-    b = (8.0 + 4.0 / n) * V * n
-    return {"grid": [g.nx, g.ny, g.nz], "n_slices": n,
-            "n_humans": sc.n_humans, "voxel_slices": V * n,
-            "static_build_ms": static_ms,
-            "static_build_gbs_9B_basis": 9.0 * V / (static_ms * 1e-3) / 1e9,
-            "composite_ms": comp_ms, "planes_ms": planes_ms,
-            "composite_gbs_8B_basis": b / (comp_ms * 1e-3) / 1e9,
-            "composite_frac_8B_basis": b / (comp_ms * 1e-3) / 1e9 /
-            HBM_PEAK_GBS,
-            "voxel_slices_per_s": V * n / ((comp_ms + planes_ms) * 1e-3),
-            "queries": Q, "exact_query_ms": query_ms,
-            "queries_per_s_exact": Q / (query_ms * 1e-3),
-            "direct_query_ms_incl_planes": direct_ms,
-            "tuning": tuning}
+    del occ, ssq_s
+    torch.cuda.empty_cache()
+    return res
 
 
 def next_rows_section(pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h,
@@ -529,15 +615,20 @@ def calibrate_copy(mib: int, reps: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices", type=int, default=20)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS),
+                    default="room512")
+    ap.add_argument("--cpu-slices", type=int, default=1,
+                    help="slices of the single-threaded oracle sample")
+    ap.add_argument("--cpu-omp-slices", type=int, default=4,
+                    help="slices of the all-core oracle sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-scene batch measurement")
-    ap.add_argument("--no-room512", action="store_true",
-                    help="skip the 512x512x256 x 50-slice measurement")
+    ap.add_argument("--no-room256", action="store_true",
+                    help="skip the 256x256x128 x 20-slice section")
     ap.add_argument("--no-recompute", action="store_true",
                     help="skip the composite vs full recompute measurement")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -558,144 +649,64 @@ def main():
         calibrate_copy(args.calibrate_copy_mib, max(1, args.steps))
         return
     if args.traffic_from:
-        t = traffic_from(args.traffic_from, 256 * 256 * 128, 20)
-        with open(TRAFFIC_FILE, "w") as fh:
+        V, n = {"room512": (512 * 512 * 256, 50),
+                "room256": (256 * 256 * 128, 20)}[args.workload]
+        t = traffic_from(args.traffic_from, V, n)
+        with open(traffic_file(args.workload), "w") as fh:
             json.dump(t, fh, indent=1)
         print(json.dumps(t))
         return
 
-    import numpy as np
     import torch
 
     import paper_2201_05058_amd as pc
     import scenegen
-    from paper_2201_05058_amd import _native, autotune
+    from paper_2201_05058_amd import autotune
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    sc = scenegen.room256()
-    g = sc.grid
-    V, n, K = g.nvox, sc.n_slices, sc.n_humans
-    q = sc.queries
-    Q = len(q.radius)
-
-    h = pc.Handle()
-    occ = torch.from_numpy(sc.occ).to(dev)
-    centre = torch.from_numpy(q.centre).to(dev)
-    radius = torch.from_numpy(q.radius).to(dev)
-    slices = torch.from_numpy(q.slice).to(dev)
-    out_ssq, out_sdf = composite_outputs(torch, n, g.shape_zyx, dev)
-
-    # static field, built once per scene (not part of a step); timed warm
-    # over three builds with both outputs
-    h.profile(True)
-    ssq_s, sdf_s = pc.build_static_sdf(g, occ, handle=h)
-    torch.cuda.synchronize()
-    h.profile_reset()
-    for _ in range(3):
-        pc.build_static_sdf(g, occ, ssq=ssq_s, sdf=sdf_s, handle=h)
-    torch.cuda.synchronize()
-    st_ms, st_n = h.profile_read(_native.KERNEL_STATIC)
-    static_ms = st_ms / max(st_n, 1)
-    del sdf_s
-
-    # launch shape of the composite, tuned on this workload (cached)
-    scene = {"grid": g, "static_ssq": ssq_s, "human_xy": sc.human_xy,
-             "radius": sc.radius, "height": sc.height, "out_ssq": out_ssq,
-             "out_sdf": out_sdf}
-    tuning, _, _ = autotune.tuned(
-        h, autotune.composite_signature(g, n, K),
-        lambda: pc.autotune_composite(scene, reps=3, handle=h)[:2])
-
-    def step():
-        pc.predicted_composite_sdf(g, ssq_s, sc.human_xy, sc.radius,
-                                   sc.height, out_ssq=out_ssq,
-                                   out_sdf=out_sdf, handle=h)
-        return pc.query_spheres(g, out_sdf, centre, radius, slices,
-                                handle=h)
-
-    # The timed steps time the composite kernel alone (a timed kernel
-    # costs the stream a few microseconds before it); the planes and
-    # queries are timed over as many steps right after.
-    h.profile(True, only=[_native.KERNEL_COMPOSITE])
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    h.profile_reset()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    comp_ms, comp_n = h.profile_read(_native.KERNEL_COMPOSITE)
-
-    h.profile(True, only=[_native.KERNEL_PLANES, _native.KERNEL_QUERY])
-    h.profile_reset()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    pl_ms, pl_n = h.profile_read(_native.KERNEL_PLANES)
-    qy_ms, qy_n = h.profile_read(_native.KERNEL_QUERY)
-    h.profile(True)
-    comp_avg_s = comp_ms / comp_n / 1e3
-    # compulsory bytes of one composite launch: read the static field once
-    # (4 B/voxel) and write both outputs (8 B/voxel-slice)
-    alg_bytes = (8.0 + 4.0 / n) * V * n
-    achieved = alg_bytes / comp_avg_s / 1e9
-    traffic = load_traffic(V, n)
+    make = {"room512": scenegen.room512, "room256": scenegen.room256}
+    sc = make[args.workload]()
+    head = measure_workload(pc, autotune, torch, dev, sc, args.workload,
+                            args.steps, args.warmup)
 
     line = {
         "metric": METRIC,
-        "value": V * n / (ms_per_step / 1e3),
+        "value": head.pop("value"),
         "unit": "voxel-slices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {
-            "workload": "256x256x128 grid at 0.02 m, 40 seeded "
-                        "boxes, 3 constant-velocity cylinder humans, 20 "
-                        "slices at dt=0.1 s, 10k exact sphere queries",
-            "grid": [g.nx, g.ny, g.nz], "voxel_m": g.h, "n_slices": n,
-            "n_humans": K, "n_queries": Q, "seed": sc.seed},
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_composite",
-            "kernel_ms": comp_avg_s * 1e3,
-            "bytes_per_voxel_slice": 8.0 + 4.0 / n,
-            "frac_12B_basis": 12.0 * V * n / comp_avg_s / 1e9 / HBM_PEAK_GBS,
-        },
-        "kernels_ms": {"composite": comp_avg_s * 1e3,
-                       "planes": pl_ms / max(pl_n, 1),
-                       "query": qy_ms / max(qy_n, 1),
-                       "static_build_once": static_ms},
-        "static_build_gbs_9B_basis": 9.0 * V / (static_ms * 1e-3) / 1e9,
-        "queries_per_s_exact_kernel": Q / (qy_ms / max(qy_n, 1) / 1e3)
-        if qy_ms > 0 else None,
-        "tuning": tuning,
+        "config": head.pop("config"),
+        "roofline": head.pop("roofline"),
     }
-    if not args.no_recompute:
-        line["fig6_recompute"] = recompute_section(
-            pc, torch, sc, occ, ssq_s, out_ssq, out_sdf, h)
-        line["template_composite"] = template_section(
-            pc, torch, sc, ssq_s, out_ssq, out_sdf, h)
-        line["next_rows"] = next_rows_section(pc, torch, sc, occ, ssq_s,
-                                              out_ssq, out_sdf, h)
-    del out_ssq, out_sdf
+    line.update(head)
+    if args.workload != "room256" and not args.no_room256:
+        sc2 = scenegen.room256()
+
+        def sections(h, occ, ssq_s, out_ssq, out_sdf):
+            if args.no_recompute:
+                return {}
+            return {"fig6_recompute": recompute_section(
+                        pc, torch, sc2, occ, ssq_s, out_ssq, out_sdf, h),
+                    "template_composite": template_section(
+                        pc, torch, sc2, ssq_s, out_ssq, out_sdf, h),
+                    "next_rows": next_rows_section(
+                        pc, torch, sc2, occ, ssq_s, out_ssq, out_sdf, h)}
+        line["room256"] = measure_workload(
+            pc, autotune, torch, dev, sc2, "room256", args.steps,
+            args.warmup, sections)
     if not args.no_surrogate:
         line["surrogate"] = surrogate_section(pc, torch, dev, args.weights)
     if not args.no_batch:
         line["batch64"] = batch_section(pc, autotune, scenegen, torch,
-                                              dev)
-    if not args.no_room512:
-        line["room512"] = room512_section(pc, autotune, scenegen, torch, dev)
+                                        dev)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_slices)
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_slices,
+                                            args.cpu_omp_slices)
     print(json.dumps(line), flush=True)
 
 

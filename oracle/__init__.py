@@ -4,8 +4,10 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
 baseline leg of the benchmark may import this package.  The GPU library
 (``paper_2201_05058_amd``) never imports it and shares no code with it.
 
-The arithmetic lives in ``pcsdf_oracle.c`` (plain single-threaded C, built
-with gcc by :func:`build`); this module only marshals numpy arrays.  Every
+The arithmetic lives in ``pcsdf_oracle.c`` (plain C, built with gcc by
+:func:`build` single-threaded, and once more with OpenMP for the CPU
+baseline's all-core timing: ``omp=True`` on the calls that take it);
+this module only marshals numpy arrays.  Every
 function cites the passage of Finean et al. (2022) it restates in the C
 source.  Parity status: every function here is pinned by the CPU tests in
 ``tests/test_oracle_pins.py`` (brute force, closed forms, invariants).
@@ -21,7 +23,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcsdf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_libs = {}
 
 INF32 = np.iinfo(np.int32).max
 INF64 = np.iinfo(np.int64).max
@@ -30,30 +33,43 @@ OOR_X, OOR_Y, OOR_Z = 1, 2, 4
 SLICE_CLAMPED, INF_CORNER, SLICE_NEG = 8, 16, 32
 
 
+def _compile(out: str, omp: bool):
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall",
+           "-fopenmp" if omp else "-Wno-unknown-pragmas", "-o", tmp, _SRC,
+           "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, no FMA
-    contraction) into ``oracle/liboracle.so``."""
-    global _lib
-    if not force and os.path.exists(_LIB) and \
-            os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    _lib = None
+    contraction) into ``oracle/liboracle.so`` (single-threaded) and
+    ``oracle/liboracle_omp.so`` (the same source with OpenMP)."""
+    for path, omp in ((_LIB, False), (_LIB_OMP, True)):
+        if force or not os.path.exists(path) or \
+                os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _compile(path, omp)
+    _libs.clear()
     return _LIB
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB) or \
-            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = C.CDLL(_LIB)
+def threads(omp: bool = True) -> int:
+    """Threads the OpenMP build's loops use (OMP_NUM_THREADS, else every
+    core the process may run on); 1 for the plain build."""
+    return int(_load(omp).or_threads())
+
+
+def _load(omp: bool = False):
+    key = bool(omp)
+    if key in _libs:
+        return _libs[key]
+    path = _LIB_OMP if omp else _LIB
+    if not os.path.exists(path) or \
+            os.path.getmtime(path) < os.path.getmtime(_SRC):
+        _compile(path, omp)
+    lib = C.CDLL(path)
     P = C.c_void_p
     i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
     lib.or_edt_sq.argtypes = [P, i32, i32, i32, P]
@@ -85,7 +101,9 @@ def _load():
     lib.or_query.argtypes = [P, i32, i32, i32, i32, f64, f64, f64, f64, i32,
                              P, P, P, f64, P, P, P, P]
     lib.or_query.restype = None
-    _lib = lib
+    lib.or_threads.argtypes = []
+    lib.or_threads.restype = C.c_int
+    _libs[key] = lib
     return lib
 
 
@@ -168,19 +186,19 @@ def composite(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     return out
 
 
-def build_static(grid, occ: np.ndarray):
+def build_static(grid, occ: np.ndarray, omp: bool = False):
     """(SSQ_s int32, F(SSQ_s) fp32) of the static occupancy."""
     m = _u8(occ)
     ssq = np.empty(grid.shape_zyx, dtype=np.int32)
     sdf = np.empty(grid.shape_zyx, dtype=np.float32)
-    if _load().or_build_static(_p(m), grid.nx, grid.ny, grid.nz, grid.h,
+    if _load(omp).or_build_static(_p(m), grid.nx, grid.ny, grid.nz, grid.h,
                                _p(ssq), _p(sdf)):
         raise MemoryError("oracle build_static")
     return ssq, sdf
 
 
 def predicted_composite(grid, static_ssq: np.ndarray, human_xy: np.ndarray,
-                        radius: float, height: float):
+                        radius: float, height: float, omp: bool = False):
     """Per-slice composite (int32 SSQ [n, nz, ny, nx], fp32 [n, ...])."""
     s = np.ascontiguousarray(static_ssq, dtype=np.int32)
     xy = np.ascontiguousarray(human_xy, dtype=np.float64)
@@ -189,7 +207,7 @@ def predicted_composite(grid, static_ssq: np.ndarray, human_xy: np.ndarray,
     ssq = np.empty(shp, dtype=np.int32)
     sdf = np.empty(shp, dtype=np.float32)
     ox, oy, oz = grid.origin
-    rc = _load().or_predicted_composite(_p(s), grid.nx, grid.ny, grid.nz,
+    rc = _load(omp).or_predicted_composite(_p(s), grid.nx, grid.ny, grid.nz,
                                         grid.h, ox, oy, oz, n, K, _p(xy),
                                         radius, height, _p(ssq), _p(sdf))
     if rc:

@@ -1,11 +1,14 @@
 /*
  * CPU oracle for predicted composite signed distance fields.
  *
- * TEST INFRASTRUCTURE ONLY.  This file is plain, slow, single-threaded C
- * that restates what the method computes so that the GPU library can be
- * checked against it.  Only the test suite, the smoke check and the CPU
- * baseline leg of the benchmark load it; the GPU library never does, and
- * the two share no code, header or table.
+ * TEST INFRASTRUCTURE ONLY.  This file is plain, slow C that restates
+ * what the method computes so that the GPU library can be checked against
+ * it.  Only the test suite, the smoke check and the CPU baseline leg of the
+ * benchmark load it; the GPU library never does, and the two share no
+ * code, header or table.  Built plainly it is single-threaded; built with
+ * -fopenmp (a separate library, for the CPU baseline's all-core timing) the
+ * independent lines of each pass and the voxel loops run on all threads,
+ * computing the same values in the same order per element.
  *
  * What is computed (Finean et al. 2022, section "Mapping - Predicted
  * Composite Distance Fields", and the RHAP-GPMP2 section):
@@ -96,24 +99,42 @@ static void or_envelope(const int64_t *f, int n, int64_t *d, int *v,
   }
 }
 
-/* One 1-D pass along `axis` (0 = x, 1 = y, 2 = z) of a full grid. */
-static void or_pass(int64_t *a, int nx, int ny, int nz, int axis,
-                    int64_t *fbuf, int64_t *dbuf, int *vbuf, double *zbuf) {
+/* One 1-D pass along `axis` (0 = x, 1 = y, 2 = z) of a full grid.  The
+ * lines are independent; each thread has its own envelope buffers.
+ * Returns -1 if they cannot be allocated. */
+static int or_pass(int64_t *a, int nx, int ny, int nz, int axis) {
   int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
   int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx : (int64_t)nx * ny);
   int n1 = axis == 0 ? ny : nx;
   int n2 = axis == 2 ? ny : nz;
-  for (int b = 0; b < n2; b++) {
-    for (int c = 0; c < n1; c++) {
-      int64_t base;
-      if (axis == 0) base = ((int64_t)b * ny + c) * nx;
-      else if (axis == 1) base = (int64_t)b * nx * ny + c;
-      else base = (int64_t)b * nx + c;
-      for (int q = 0; q < n; q++) fbuf[q] = a[base + q * stride];
-      or_envelope(fbuf, n, dbuf, vbuf, zbuf);
-      for (int q = 0; q < n; q++) a[base + q * stride] = dbuf[q];
+  int failed = 0;
+#pragma omp parallel
+  {
+    int64_t *fbuf = malloc(sizeof(int64_t) * n);
+    int64_t *dbuf = malloc(sizeof(int64_t) * n);
+    int *vbuf = malloc(sizeof(int) * n);
+    double *zbuf = malloc(sizeof(double) * (n + 1));
+    int ok = fbuf && dbuf && vbuf && zbuf;
+    if (!ok) {
+#pragma omp atomic write
+      failed = 1;
     }
+#pragma omp for collapse(2) schedule(static)
+    for (int b = 0; b < n2; b++) {
+      for (int c = 0; c < n1; c++) {
+        if (!ok) continue;
+        int64_t base;
+        if (axis == 0) base = ((int64_t)b * ny + c) * nx;
+        else if (axis == 1) base = (int64_t)b * nx * ny + c;
+        else base = (int64_t)b * nx + c;
+        for (int q = 0; q < n; q++) fbuf[q] = a[base + q * stride];
+        or_envelope(fbuf, n, dbuf, vbuf, zbuf);
+        for (int q = 0; q < n; q++) a[base + q * stride] = dbuf[q];
+      }
+    }
+    free(fbuf); free(dbuf); free(vbuf); free(zbuf);
   }
+  return failed ? -1 : 0;
 }
 
 /* E_S for the set of voxels where set[v] != 0 (want = 1) or == 0
@@ -121,22 +142,11 @@ static void or_pass(int64_t *a, int nx, int ny, int nz, int axis,
 static int or_edt_sq_sel(const uint8_t *set, int want, int nx, int ny,
                          int nz, int64_t *out) {
   int64_t V = (int64_t)nx * ny * nz;
-  int nmax = nx > ny ? nx : ny;
-  nmax = nmax > nz ? nmax : nz;
-  int64_t *fbuf = malloc(sizeof(int64_t) * nmax);
-  int64_t *dbuf = malloc(sizeof(int64_t) * nmax);
-  int *vbuf = malloc(sizeof(int) * nmax);
-  double *zbuf = malloc(sizeof(double) * (nmax + 1));
-  if (!fbuf || !dbuf || !vbuf || !zbuf) {
-    free(fbuf); free(dbuf); free(vbuf); free(zbuf);
-    return -1;
-  }
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < V; i++)
     out[i] = ((set[i] != 0) == (want != 0)) ? 0 : OR_INF64;
-  or_pass(out, nx, ny, nz, 0, fbuf, dbuf, vbuf, zbuf);
-  or_pass(out, nx, ny, nz, 1, fbuf, dbuf, vbuf, zbuf);
-  or_pass(out, nx, ny, nz, 2, fbuf, dbuf, vbuf, zbuf);
-  free(fbuf); free(dbuf); free(vbuf); free(zbuf);
+  for (int axis = 0; axis < 3; axis++)
+    if (or_pass(out, nx, ny, nz, axis)) return -1;
   return 0;
 }
 
@@ -149,20 +159,9 @@ int or_edt_sq(const uint8_t *set, int nx, int ny, int nz, int64_t *out) {
 int or_edt_sq_order(const uint8_t *set, int nx, int ny, int nz,
                     const int *order, int64_t *out) {
   int64_t V = (int64_t)nx * ny * nz;
-  int nmax = nx > ny ? nx : ny;
-  nmax = nmax > nz ? nmax : nz;
-  int64_t *fbuf = malloc(sizeof(int64_t) * nmax);
-  int64_t *dbuf = malloc(sizeof(int64_t) * nmax);
-  int *vbuf = malloc(sizeof(int) * nmax);
-  double *zbuf = malloc(sizeof(double) * (nmax + 1));
-  if (!fbuf || !dbuf || !vbuf || !zbuf) {
-    free(fbuf); free(dbuf); free(vbuf); free(zbuf);
-    return -1;
-  }
   for (int64_t i = 0; i < V; i++) out[i] = set[i] ? 0 : OR_INF64;
   for (int p = 0; p < 3; p++)
-    or_pass(out, nx, ny, nz, order[p], fbuf, dbuf, vbuf, zbuf);
-  free(fbuf); free(dbuf); free(vbuf); free(zbuf);
+    if (or_pass(out, nx, ny, nz, order[p])) return -1;
   return 0;
 }
 
@@ -189,6 +188,7 @@ int or_signed_sq(const uint8_t *set, int nx, int ny, int nz, int32_t *out) {
     free(eo); free(ef);
     return -1;
   }
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < V; i++) {
     if (set[i]) {
       out[i] = ef[i] == OR_INF64 ? -OR_INF32 : -(int32_t)ef[i];
@@ -213,8 +213,17 @@ float or_F(int32_t x, double h) {
 }
 
 void or_to_float(const int32_t *x, int64_t n, double h, float *out) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) out[i] = or_F(x[i], h);
 }
+
+/* Threads the loops above may use (1 unless built with OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_threads(void) { return omp_get_max_threads(); }
+#else
+int or_threads(void) { return 1; }
+#endif
 
 /* ---------------------------------------------------------------------
  * Voxelised vertical cylinders (the human primitive of the mapping
@@ -257,6 +266,7 @@ int or_human_occupancy(int nx, int ny, int nz, double h, double ox,
   }
   const int64_t half = 32768;
   __int128 R2 = (__int128)R * R;
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < nz; k++) {
     int zin = half * (2 * (int64_t)k + 1) <= Hq;
     for (int j = 0; j < ny; j++) {
@@ -284,6 +294,7 @@ int or_human_occupancy(int nx, int ny, int nz, double h, double ox,
  * ------------------------------------------------------------------- */
 void or_composite(const int32_t *a, const int32_t *b, int64_t n,
                   int32_t *out) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) out[i] = a[i] < b[i] ? a[i] : b[i];
 }
 
