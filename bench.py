@@ -570,33 +570,28 @@ def template_section(pc, torch, sc, ssq_s, out_ssq, out_sdf, h,
     return res
 
 
-def surrogate_section(pc, torch, dev, weights: str):
-    """Sphere queries by the trained surrogate (with exact fallback)
-    against the exact path: error in metres on the queries it answers, the
-    fallback fraction, the kernels at 1M queries and the end-to-end cost
-    per new human state at this workload's 10k queries."""
-    import scenegen
+def surrogate_section(pc, torch, dev, room: str, weights: str):
+    """Sphere queries by the trained per-human surrogate (with exact
+    fallback) against the exact path on the room's evaluation workload
+    (room256: 1M spheres, three fresh constant-velocity humans; room512:
+    its 5M spheres and eight piecewise-linear humans): error in metres on
+    the queries it answers, the fallback fraction, and GPU time of both
+    paths."""
     from paper_2201_05058_amd import train
     if not os.path.exists(weights):
         return {"weights": None, "note": "no trained weights file"}
     net, meta = train.load(weights)
-    sc = scenegen.room256()
-    res = train.evaluate(net, sc, dev, mode=meta.get("mode", "env"))
-    # algorithmic work of one query: the forward pass (22 -> 3 x 128 -> 1)
-    # and the reverse pass down to the three centre coordinates
-    flop = (2 * (22 * 128 + 3 * 128 * 128 + 128)
-            + 2 * (3 * 128 * 128 + 3 * 128))
-    ms = res["mlp_forward_grad_ms_1M"]
-    res["mlp_flop_per_query"] = flop
-    res["mlp_tflops"] = flop * res["queries"] / (ms / 1e3) / 1e12
-    res["mlp_frac_bf16_peak"] = res["mlp_tflops"] / 2500.0
-    res["queries_per_s_surrogate_path_1M"] = res["queries"] / (
-        res["surrogate_path_ms_1M"] / 1e3)
-    res["queries_per_s_exact_1M"] = res["queries"] / (
-        res["exact_query_ms_1M"] / 1e3)
+    sc = train.evaluation_scene(room)
+    res = train.evaluate(net, sc, dev)
+    res["queries_per_s_surrogate"] = res["queries"] / (
+        res["surrogate_path_ms"] / 1e3)
+    res["queries_per_s_exact_direct"] = res["queries"] / (
+        res["exact_direct_ms"] / 1e3)
     res["weights"] = os.path.relpath(weights, ROOT)
     res["trained_on"] = meta
     net.close()
+    del sc
+    torch.cuda.empty_cache()
     return res
 
 
@@ -633,8 +628,8 @@ def main():
                     help="skip the composite vs full recompute measurement")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate query measurement")
-    ap.add_argument("--weights", default=os.path.join(
-        ROOT, "paper_2201_05058_amd", "weights", "surrogate_room256.npz"))
+    ap.add_argument("--weights-dir", default=os.path.join(
+        ROOT, "paper_2201_05058_amd", "weights"))
     ap.add_argument("--traffic-from", default="",
                     help="write the composite's measured HBM traffic from "
                          "rocprofv3 PMC output under this directory")
@@ -700,7 +695,10 @@ def main():
             pc, autotune, torch, dev, sc2, "room256", args.steps,
             args.warmup, sections)
     if not args.no_surrogate:
-        line["surrogate"] = surrogate_section(pc, torch, dev, args.weights)
+        for room in ("room256", "room512"):
+            line[f"surrogate_{room}"] = surrogate_section(
+                pc, torch, dev, room,
+                os.path.join(args.weights_dir, f"surrogate_{room}.npz"))
     if not args.no_batch:
         line["batch64"] = batch_section(pc, autotune, scenegen, torch,
                                         dev)

@@ -370,57 +370,57 @@ int pcsdf_autotune_composite(pcsdf_handle *h, const pcsdf_scene *scene,
                              double *best_ms);
 
 /* ---- Learned surrogate for sphere queries (not in the paper) ----------
- * A multilayer perceptron mapping 22 input features (those written by
- * pcsdf_surrogate_features: a fixed transform of the sphere centre, the
- * slice time and three humans' state) to a distance in metres (the
- * humans' part of the composite when the surrogate query is given the
- * environment field, else the whole composite):
- * u = (x - offset) * scale;  4 hidden layers of
- * 128 SiLU units;  y = out_scale * (W4 a4 + b4).  Weights are fp32 masters
- * used as BF16 on the matrix cores with FP32 accumulation; activations,
- * SiLU derivatives and backward pre-activation gradients are rounded to
- * BF16 before each product.  Parameter vector (fp32, PCSDF_MLP_NPARAM):
- * W0[128][22] b0[128] W1[128][128] b1 W2[128][128] b2 W3[128][128] b3
+ * A multilayer perceptron mapping n_in <= 32 input features to one value:
+ * u = (x - offset) * scale;  4 hidden layers of 128 SiLU units;
+ * y = out_scale * (W4 a4 + b4).  Weights are fp32 masters used as BF16 on
+ * the matrix cores with FP32 accumulation; inputs, activations, SiLU
+ * derivatives and backward pre-activation gradients are rounded to BF16
+ * before each product.  Parameter vector (fp32, pcsdf_mlp_param_count):
+ * W0[128][n_in] b0[128] W1[128][128] b1 W2[128][128] b2 W3[128][128] b3
  * W4[1][128] b4[1].  The network object owns its weights, optimiser state
  * and workspace on the handle's device; calls on one network must not
- * overlap.  Batches are padded internally to a multiple of 1024 rows. */
-#define PCSDF_MLP_IN 22
-#define PCSDF_MLP_NPARAM 52609
+ * overlap.  Training batches are padded internally to a multiple of 1024
+ * rows. */
+#define PCSDF_MLP_MAX_IN 32
+#define PCSDF_SURROGATE_IN 16 /* features per (query, human) row */
 typedef struct pcsdf_mlp pcsdf_mlp;
-int pcsdf_mlp_create(pcsdf_handle *h, pcsdf_mlp **out);
+/* Parameters of a network with n_in inputs (-1 outside [1, 32]). */
+int pcsdf_mlp_param_count(int32_t n_in);
+int pcsdf_mlp_create(pcsdf_handle *h, int32_t n_in, pcsdf_mlp **out);
 void pcsdf_mlp_destroy(pcsdf_mlp *m);
-/* Uploads parameters and the input/output normalisation, and resets the
- * optimiser (waits for the device).  PCSDF_ERR_NUMERIC on non-finite
- * values. */
+/* Uploads parameters and the input/output normalisation (n_in values
+ * each), and resets the optimiser (waits for the device).
+ * PCSDF_ERR_NUMERIC on non-finite values. */
 int pcsdf_mlp_set_params(pcsdf_mlp *m, const float *params_host,
                          const float *in_offset_host,
                          const float *in_scale_host, float out_scale);
 int pcsdf_mlp_get_params(pcsdf_mlp *m, float *params_host);
-/* y[n] = network(x[n][22]) and, if grad_x_dev is given, dy/dx [n][22]. */
+/* y[n] = network(x[n][n_in]) and, if grad_x_dev is given, dy/dx
+ * [n][n_in]. */
 int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
                       float *y_dev, float *grad_x_dev, void *stream);
 /* Gradient of sum_m dy[m] * y[m] w.r.t. every parameter (grad_params_dev,
- * fp32 [PCSDF_MLP_NPARAM]) and, if given, w.r.t. the inputs. */
+ * fp32 [param count]) and, if given, w.r.t. the inputs. */
 int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n, const float *x_dev,
                         const float *dy_dev, float *grad_params_dev,
                         float *grad_x_dev, void *stream);
 /* One Adam step (bias-corrected) on the mean squared error between y(x)
- * and target [n] (metres); loss_dev [1] receives the loss before the
- * step, if given.  The same as pcsdf_mlp_loss_gradients followed by
+ * and target [n]; loss_dev [1] receives the loss before the step, if
+ * given.  The same as pcsdf_mlp_loss_gradients followed by
  * pcsdf_mlp_adam_step with that gradient. */
 int pcsdf_mlp_train_step(pcsdf_mlp *m, int32_t n, const float *x_dev,
                          const float *target_dev, float lr, float beta1,
                          float beta2, float eps, float *loss_dev,
                          void *stream);
 /* Gradient of the mean squared error (1/n) sum_m (y(x_m) - target_m)^2
- * w.r.t. every parameter, grad_params_dev fp32 [PCSDF_MLP_NPARAM] (device,
- * written), as the training step forms it; loss_dev [1] (nullable) gets the
- * loss.  No parameter changes. */
+ * w.r.t. every parameter, grad_params_dev fp32 [param count] (device,
+ * written), as the training step forms it; loss_dev [1] (nullable) gets
+ * the loss.  No parameter changes. */
 int pcsdf_mlp_loss_gradients(pcsdf_mlp *m, int32_t n, const float *x_dev,
                              const float *target_dev, float *grad_params_dev,
                              float *loss_dev, void *stream);
 /* One Adam step (Kingma and Ba, with bias correction) from the gradient
- * grad_params_dev fp32 [PCSDF_MLP_NPARAM] (device, read): with t the step
+ * grad_params_dev fp32 [param count] (device, read): with t the step
  * count after it is advanced by one,
  *   m1 = beta1 m1 + (1 - beta1) g,  m2 = beta2 m2 + (1 - beta2) g^2,
  *   p -= lr (m1 / c1) / (sqrt(m2 / c2) + eps),
@@ -430,8 +430,8 @@ int pcsdf_mlp_loss_gradients(pcsdf_mlp *m, int32_t n, const float *x_dev,
 int pcsdf_mlp_adam_step(pcsdf_mlp *m, const float *grad_params_dev, float lr,
                         float beta1, float beta2, float eps, void *stream);
 /* The optimiser's whole state for checkpoints: the fp32 masters, Adam's
- * first and second moments (each fp32 [PCSDF_MLP_NPARAM], host) and the
- * step count.  get waits for the device.  set uploads all of it with the
+ * first and second moments (each fp32 [param count], host) and the step
+ * count.  get waits for the device.  set uploads all of it with the
  * normalisation (as pcsdf_mlp_set_params, which it calls first, but keeps
  * the given moments and step instead of resetting them); a network
  * restored this way continues training exactly as the saved one would.
@@ -443,71 +443,81 @@ int pcsdf_mlp_set_state(pcsdf_mlp *m, const float *params_host,
                         int64_t step, const float *in_offset_host,
                         const float *in_scale_host, float out_scale);
 
-/* Network input for sphere queries, a fixed transform of the query and the
- * humans' state: x[q] = [c_x, c_y, c_z, t, then per human k
- * (dx_k, dy_k, rho_k, vx_k, vy_k, 0)] with t = dt_s * clamp(slice[q], 0,
- * n_slices - 1), (dx_k, dy_k) = c_xy - (p_k + v_k t) the offset from the
- * human's axis at t and rho_k = |(dx_k, dy_k)| (fp32, in that order of
- * operations, no contraction, correctly rounded square root).  state_host
- * holds the 18 state floats: per human its position (x, y, 0) and
- * velocity (vx, vy, 0) at t = 0, in metres and metres per second.
- * centre_dev [n][3], slice_dev [n], x_dev [n][22] (fp32, caller-owned). */
-int pcsdf_surrogate_features(pcsdf_handle *h, int32_t n_queries,
-                             const float *centre_dev,
-                             const int32_t *slice_dev, int32_t n_slices,
-                             double dt_s, const float *state_host,
-                             float *x_dev, void *stream);
+/* The surrogate's input row for one (query, human) pair: the
+ * PCSDF_SURROGATE_IN features the network of pcsdf_query_spheres_surrogate
+ * reads, in voxel units of the grid.  With the humans' fixed-point centres
+ * X, Y and radius R of the query's slice s' = clamp(slice, 0, n_slices-1)
+ * (as pcsdf_predicted_composite_sdf converts them), the top layer Kt of
+ * the cylinders, g = (c - origin)/h - 1/2 (fp64), the human's axis
+ * (cx, cy) = (X, Y)/2^16 - 1/2, Rv = R/2^16, (ux, uy) = g_xy - (cx, cy),
+ * rho = |(ux, uy)|, a = rho - Rv, w = g_z - Kt, d = |(max(a,0), max(w,0))|
+ * (the distance to the continuous cylinder), phi = ((X, Y) - 2^15) mod
+ * 2^16 / 2^16 and f = g - floor(g):
+ *   x = [ux/rho, uy/rho, a, w, d, 1/(1+d), sin 2pi phi_x, cos 2pi phi_x,
+ *        sin 2pi phi_y, cos 2pi phi_y, sin 2pi f_x, cos 2pi f_x,
+ *        sin 2pi f_y, cos 2pi f_y, sin 2pi f_z, cos 2pi f_z]
+ * (computed in fp64, rounded to fp32; ux/rho = uy/rho = 0 when rho = 0).
+ *   centre_dev [Q][3] fp32, slice_dev [Q] int32,
+ *   human_dev  [Q] int32 human index of each row (NULL: 0),
+ *   label_dev  [Q] fp32 metres, nullable (the exact distance at the centre),
+ *   x_dev      [Q][16] fp32 (written),
+ *   base_dev   [Q] fp32 d in voxels, nullable,
+ *   target_dev [Q] fp32 label/h - d in voxels, nullable (needs labels).
+ * Human arguments as pcsdf_predicted_composite_sdf (n_humans >= 1). */
+int pcsdf_surrogate_human_features(
+    pcsdf_handle *h, const pcsdf_grid *grid, int32_t n_slices,
+    int32_t n_humans, const double *human_xy_host, double radius_m,
+    double height_m, int32_t n_queries, const float *centre_dev,
+    const int32_t *slice_dev, const int32_t *human_dev, const float *label_dev,
+    float *x_dev, float *base_dev, float *target_dev, void *stream);
 
-/* The same for queries drawn over a pool of human configurations (for
- * training on many configurations per batch): slice_dev[q] = c*n_slices + s
- * selects configuration c in [0, n_configs) with state states_dev[c][0..17]
- * (device, fp32) and slice s (the global index is clamped to the pool);
- * t = dt_s * s. */
-int pcsdf_surrogate_features_pool(pcsdf_handle *h, int32_t n_queries,
-                                  const float *centre_dev,
-                                  const int32_t *slice_dev, int32_t n_slices,
-                                  int32_t n_configs, double dt_s,
-                                  const float *states_dev, float *x_dev,
-                                  void *stream);
-
-/* Sphere queries answered by the network, with the exact path as fallback.
- * Same outputs and status bits as pcsdf_query_spheres, for the composite
- * fields that pcsdf_predicted_composite_sdf would build from the same
- * static field, human positions and cylinder (arguments as there).
- * The prediction is y(c, t) = network(x) when static_sdf_dev is NULL.  With
- * the environment's fp32 field static_sdf_dev [V] (as written by
- * pcsdf_build_static_sdf), the network predicts the humans' part only and
- * the prediction is min(s, network(x)), s the environment field sampled at
- * c exactly as pcsdf_query_spheres samples (fp64 trilinear, rounded to
- * fp32); where s wins (ties included) the gradient is the environment's.
- * A query falls back to the exact path when
- *   - its predicted sphere distance y(c, t) - r is below fallback_margin_m,
- *     (dy/dc is the network's feature gradient taken through the transform
- *     of pcsdf_surrogate_features: G_c + sum_k (G_dk + G_rhok (dx_k, dy_k)
- *     / rho_k) in x and y, 0 for the ratio on an axis),
- *   - the network's value or gradient is not finite, or
- *   - its centre lies outside the span of voxel centres (the exact path then
- *     clamps and flags it);
- * other queries get dist = y - r, grad = dy/dc, status = SLICE_CLAMPED or 0,
- * cost = max(0, hinge_eps_m - dist).  Queries with slice < 0 get NaN and
- * SLICE_NEG.  used_fallback_dev [n] (nullable) is 1 for exact answers,
- * which are computed as pcsdf_query_spheres_direct computes them: no 3-D
- * field is built, only the planar fields of the slices that some fallback
- * query reads.
- * No host synchronisation: the fallback list and the slice marks live on
- * the device.  The network must belong to handle `h`.
- * The net takes the features of pcsdf_surrogate_features; its state
- * (state_host) and the human positions must describe the same humans. */
+/* Sphere queries answered by the surrogate, with the exact path as
+ * fallback, for the composite fields that pcsdf_predicted_composite_sdf
+ * would build from the same static field and humans (arguments as there;
+ * for humans moving at constant velocity the positions of slice j are
+ * p + v j dt).  The network m (PCSDF_SURROGATE_IN inputs, created on
+ * handle h) predicts one human's exact field: per (query, human) row
+ * y_k = fp32(h (d + clamp(network(x), -1/2, 3/2))) metres, x and d as in
+ * pcsdf_surrogate_human_features; its gradient is the closed-form
+ * gradient of d plus, when the network's value is not clamped, the
+ * network's feature gradient through the features' closed-form
+ * derivatives.  The environment's value e is the static fp32 field
+ * static_sdf_dev [V] sampled at the centre exactly as pcsdf_query_spheres
+ * samples it (zero radius).  A human is absent when no voxel centre of the
+ * grid lies within Rv of its axis along x or y (cx + Rv < 0, cx - Rv >
+ * nx - 1, likewise y) and clipped when present and its disk may reach
+ * beyond the grid (cx - Rv <= -1, cx + Rv >= nx, likewise y).  With
+ * y = min(e, y_k of the present humans) (the environment wins ties, then
+ * the lower index) and m2 the second smallest candidate, a query falls
+ * back to the exact path when
+ *   - its centre lies outside the span of voxel centres,
+ *   - y - r is below fallback_margin_m, or y - r or the gradient is not
+ *     finite,
+ *   - m2 - y < band_m (the candidates' order may change inside the
+ *     query's cell; 2 sqrt(3) h covers every such cell), or
+ *   - a clipped human's y_k <= y + band_m,
+ * and otherwise gets dist = y - r, grad = the winner's gradient, status =
+ * SLICE_CLAMPED or 0, cost = max(0, hinge_eps_m - dist).  Queries with
+ * slice < 0 get NaN and SLICE_NEG.  Humans whose lower bound
+ * h (d - 1/2) exceeds the least upper bound h (d + 3/2) (or e) by more
+ * than band_m cannot change the answer and are not evaluated; rows beyond
+ * the workspace's cap of max(4 Q, 2^20) rows make their queries fall back.
+ * rows_dev [1] int32 (nullable, device) receives the number of (query,
+ * human) rows the network evaluated.
+ * used_fallback_dev [Q] (nullable) is 1 for exact answers, which are
+ * computed as pcsdf_query_spheres_direct computes them: no 3-D field is
+ * built, only the planar fields of the slices that some fallback query
+ * reads.  Outputs and layouts as pcsdf_query_spheres.  No host
+ * synchronisation. */
 int pcsdf_query_spheres_surrogate(
     pcsdf_handle *h, pcsdf_mlp *m, const pcsdf_grid *grid,
     const int32_t *static_ssq_dev, const float *static_sdf_dev,
     int32_t n_slices, int32_t n_humans, const double *human_xy_host,
-    double radius_m, double height_m, const float *state_host, double dt_s,
-    double fallback_margin_m,
-    int32_t n_queries, const float *centre_dev, const float *radius_dev,
-    const int32_t *slice_dev, double hinge_eps_m, float *dist_dev,
-    float *grad_dev, uint8_t *status_dev, float *cost_dev,
-    uint8_t *used_fallback_dev, void *stream);
+    double radius_m, double height_m, double fallback_margin_m,
+    double band_m, int32_t n_queries, const float *centre_dev,
+    const float *radius_dev, const int32_t *slice_dev, double hinge_eps_m,
+    float *dist_dev, float *grad_dev, uint8_t *status_dev, float *cost_dev,
+    uint8_t *used_fallback_dev, int32_t *rows_dev, void *stream);
 
 /* Kernel timing for measurement.  When on, the kernels of the planar
  * fields, the composite and the sphere queries (PCSDF_KERNEL_PLANES,

@@ -2,11 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain numpy in fp64.
 
-The surrogate is not in the paper: it is a small multilayer perceptron
-that maps (sphere centre x, y, z, slice time t, and three humans' positions
-and velocities at t = 0) to the composite distance at the centre, with the
-distance gradient taken by reverse mode through the network.  Network:
-22 inputs -> 4 hidden layers of 128 SiLU units -> 1 output.  Weights are
+The surrogate is not in the paper: a small multilayer perceptron that maps
+a query's features to a distance (oracle/surrogate.py), with its input
+gradient taken by reverse mode through the network.  Network: n_in <= 32
+inputs -> 4 hidden layers of 128 SiLU units -> 1 output.  Weights are
 stored as fp32 masters and used in BF16; products accumulate in FP32 on
 the GPU (fp64 here).  BF16 rounding (round to nearest even) is applied at
 exactly the points where the GPU kernels round:
@@ -14,8 +13,8 @@ exactly the points where the GPU kernels round:
     are rounded to BF16 before they enter a product;
   - in the backward pass every pre-activation gradient is rounded to BF16
     before it enters a product.
-Parameter vector layout (fp32, 52609 values):
-  W0[128][22] b0[128] W1[128][128] b1 W2[128][128] b2 W3[128][128] b3
+Parameter vector layout (fp32, 49793 + 128 n_in values):
+  W0[128][n_in] b0[128] W1[128][128] b1 W2[128][128] b2 W3[128][128] b3
   W4[1][128] b4[1].
 Parity status: the forward pass is pinned by a closed form (a network that
 routes one input through the SiLU chain), the backward pass by central
@@ -27,12 +26,25 @@ from __future__ import annotations
 
 import numpy as np
 
-IN = 22
 HID = 128
 LAYERS = 4
-SHAPES = [(HID, IN), (HID,), (HID, HID), (HID,), (HID, HID), (HID,),
-          (HID, HID), (HID,), (1, HID), (1,)]
-NPARAM = int(sum(np.prod(s) for s in SHAPES))
+
+
+def shapes(n_in: int):
+    """Shapes of the parameter arrays of a network with n_in inputs."""
+    return [(HID, n_in), (HID,), (HID, HID), (HID,), (HID, HID), (HID,),
+            (HID, HID), (HID,), (1, HID), (1,)]
+
+
+def nparam(n_in: int) -> int:
+    return int(sum(np.prod(s) for s in shapes(n_in)))
+
+
+def n_inputs(params) -> int:
+    """n_in of a parameter vector (its length fixes it)."""
+    n = np.asarray(params).size - nparam(0)
+    assert n > 0 and n % HID == 0, "not a parameter vector of this network"
+    return n // HID
 
 
 def bf16(x, enabled: bool = True) -> np.ndarray:
@@ -53,9 +65,8 @@ def bf16(x, enabled: bool = True) -> np.ndarray:
 
 def unpack(params):
     p = np.asarray(params, dtype=np.float64).reshape(-1)
-    assert p.size == NPARAM
     out, o = [], 0
-    for s in SHAPES:
+    for s in shapes(n_inputs(p)):
         n = int(np.prod(s))
         out.append(p[o:o + n].reshape(s))
         o += n
@@ -77,7 +88,7 @@ def silu_prime(z):
 
 
 def forward(params, x, in_offset, in_scale, out_scale, rounding=True):
-    """x: [n, 22] raw features.  Returns (y [n] metres, cache)."""
+    """x: [n, n_in] raw features.  Returns (y [n], cache)."""
     Ws = unpack(params)
     W = [bf16(Ws[2 * l], rounding) for l in range(LAYERS + 1)]
     b = [Ws[2 * l + 1] for l in range(LAYERS + 1)]
@@ -94,8 +105,8 @@ def forward(params, x, in_offset, in_scale, out_scale, rounding=True):
 
 
 def backward(params, x, dy, in_offset, in_scale, out_scale, rounding=True):
-    """dy: [n] gradient of a scalar loss w.r.t. the outputs (metres).
-    Returns (grad_params [NPARAM], grad_x [n, 22])."""
+    """dy: [n] gradient of a scalar loss w.r.t. the outputs.
+    Returns (grad_params [nparam], grad_x [n, n_in])."""
     _, c = forward(params, x, in_offset, in_scale, out_scale, rounding)
     W, a, d = c["W"], c["a"], c["d"]
     dyn = np.asarray(dy, np.float64) * out_scale          # d/d(raw output)
@@ -114,7 +125,7 @@ def backward(params, x, dy, in_offset, in_scale, out_scale, rounding=True):
 
 def input_gradient(params, x, in_offset, in_scale, out_scale,
                    rounding=True):
-    """d y / d x for every sample (y in metres), [n, 22]."""
+    """d y / d x for every sample, [n, n_in]."""
     n = np.asarray(x).shape[0]
     _, gx = backward(params, x, np.ones(n), in_offset, in_scale, out_scale,
                      rounding)
@@ -122,7 +133,7 @@ def input_gradient(params, x, in_offset, in_scale, out_scale,
 
 
 def mse_loss_grad(y, target):
-    """Mean squared error in metres^2 and its gradient w.r.t. y."""
+    """Mean squared error and its gradient w.r.t. y."""
     r = np.asarray(y, np.float64) - np.asarray(target, np.float64)
     return float(np.mean(r * r)), 2.0 * r / r.size
 

@@ -274,16 +274,12 @@ int humans_upload(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   return PCSDF_OK;
 }
 
-int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
-               int32_t n_humans, const double *human_xy_host, double radius_m,
-               const double *radius_per_slice, double height_m,
-               const int32_t *need, hipStream_t s, PlaneSet *out) {
-  HumanSet hs;
-  int rc = humans_upload(h, g, n_slices, n_humans, human_xy_host, radius_m,
-                         radius_per_slice, height_m, s, &hs);
-  if (rc) return rc;
+int planes_from(Handle *h, const pcsdf_grid *g, const HumanSet &hs,
+                int32_t n_slices, int32_t n_humans, const int32_t *need,
+                hipStream_t s, PlaneSet *out) {
   const int nx = g->nx, ny = g->ny;
   const size_t plane_bytes = (size_t)n_slices * nx * ny * sizeof(int32_t);
+  int rc;
   if ((rc = ensure_buffer(h, h->plane_buf, 2 * plane_bytes, s))) return rc;
   int32_t *p2 = reinterpret_cast<int32_t *>(h->plane_buf.ptr);
   // Planar signed field of the disk union, per slice.
@@ -295,6 +291,17 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
   out->Kt = hs.Kt;
   out->has_above = hs.has_above;
   return PCSDF_OK;
+}
+
+int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
+               int32_t n_humans, const double *human_xy_host, double radius_m,
+               const double *radius_per_slice, double height_m,
+               const int32_t *need, hipStream_t s, PlaneSet *out) {
+  HumanSet hs;
+  int rc = humans_upload(h, g, n_slices, n_humans, human_xy_host, radius_m,
+                         radius_per_slice, height_m, s, &hs);
+  if (rc) return rc;
+  return planes_from(h, g, hs, n_slices, n_humans, need, s, out);
 }
 
 int composite_run(Handle *h, const pcsdf_grid *g,

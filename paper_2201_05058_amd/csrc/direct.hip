@@ -112,6 +112,19 @@ int direct_setup(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
   return PCSDF_OK;
 }
 
+int direct_from(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
+                const HumanSet &hs, int32_t n_slices, int32_t n_humans,
+                const int32_t *need, hipStream_t s, DirectSet *out) {
+  PlaneSet ps;
+  int rc = planes_from(h, g, hs, n_slices, n_humans, need, s, &ps);
+  if (rc) return rc;
+  out->P = ps.P;
+  out->Kt = ps.Kt;
+  out->has_above = ps.has_above;
+  out->S = static_ssq;
+  return PCSDF_OK;
+}
+
 int launch_direct(Handle *h, const pcsdf_grid *g, const DirectSet &d,
                   int n_slices, int n_queries, const uint8_t *mask,
                   const float *centre, const float *radius,

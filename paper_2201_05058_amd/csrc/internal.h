@@ -223,6 +223,10 @@ int planes_run(Handle *h, const pcsdf_grid *g, int32_t n_slices,
                int32_t n_humans, const double *xy_host, double radius_m,
                const double *radius_per_slice, double height_m,
                const int32_t *need, hipStream_t s, PlaneSet *out);
+// The same from humans already converted and placed by humans_upload.
+int planes_from(Handle *h, const pcsdf_grid *g, const HumanSet &hs,
+                int32_t n_slices, int32_t n_humans, const int32_t *need,
+                hipStream_t s, PlaneSet *out);
 
 // The streaming epilogue alone: outputs of every slice (with `need`, of
 // the marked slices) from the static field and the planar fields P
@@ -257,6 +261,9 @@ int direct_setup(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
                  int32_t n_slices, int32_t n_humans, const double *xy_host,
                  double radius_m, double height_m, const int32_t *need,
                  hipStream_t s, DirectSet *out);
+int direct_from(Handle *h, const pcsdf_grid *g, const int32_t *static_ssq,
+                const HumanSet &hs, int32_t n_slices, int32_t n_humans,
+                const int32_t *need, hipStream_t s, DirectSet *out);
 // Exact queries [0, n_queries), only those with mask[q] != 0 when a mask
 // is given (device uint8 [n_queries]).
 int launch_direct(Handle *h, const pcsdf_grid *g, const DirectSet &d,
@@ -281,5 +288,10 @@ int launch_query_list(Handle *h, const pcsdf_grid *g, const float *sdf,
 
 // The handle a network was created on.
 Handle *mlp_handle(pcsdf_mlp *m);
+// Inputs per row of the network.
+int mlp_inputs(const pcsdf_mlp *m);
+// Value and input gradient of rows [0, min(n, *n_dev)) (fused inference).
+int mlp_rows(pcsdf_mlp *m, int n, const int32_t *n_dev, const float *x,
+             float *y, float *gx, hipStream_t s);
 
 }  // namespace pcsdf

@@ -19,6 +19,8 @@ constexpr int kWbfTotal = 53376;
 
 struct Mlp {
   Handle *h = nullptr;
+  int n_in = 0;    // inputs per row, 1..kInPad
+  int nparam = 0;  // mlp_nparam(n_in)
   DevBuf params, grad, m1, m2, wbf, wtbf, norm, wofs;
   float out_scale = 1.f;
   int64_t step = 0;  // Adam steps taken
@@ -61,6 +63,7 @@ static const uint16_t *wb(Mlp *m, int l) {
 static const uint16_t *wtb(Mlp *m, int l) {
   return reinterpret_cast<const uint16_t *>(m->wtbf.ptr) + kWofs[l];
 }
+static int np(const Mlp *m) { return m->nparam; }
 static const float *pf(Mlp *m) {
   return reinterpret_cast<const float *>(m->params.ptr);
 }
@@ -111,18 +114,21 @@ static int forward(Mlp *m, int n, int npad, const float *x, float *y,
   const float *norm = reinterpret_cast<const float *>(m->norm.ptr);
   uint16_t *a0 = reinterpret_cast<uint16_t *>(m->a0.ptr);
   hipLaunchKernelGGL(k_mlp_input, dim3(blocks((int64_t)npad * kInPad, 256)),
-                     dim3(256), 0, s, x, n, npad, norm, norm + kIn, a0);
+                     dim3(256), 0, s, x, n, npad, m->n_in, norm,
+                     norm + kInPad, a0);
   const float *p = pf(m);
   const unsigned g = (unsigned)(npad / 128);
+  const int ni = m->n_in;
   hipLaunchKernelGGL(k_mlp_fwd<kInPad>, dim3(g), dim3(256), 0, s, a0,
-                     wb(m, 0), p + layer_desc(0).b_off, actp(m, 1), dp(m, 0));
+                     wb(m, 0), p + layer_desc(0, ni).b_off, actp(m, 1),
+                     dp(m, 0));
   for (int l = 1; l < kLayers; ++l)
     hipLaunchKernelGGL(k_mlp_fwd<kHid>, dim3(g), dim3(256), 0, s, actp(m, l),
-                       wb(m, l), p + layer_desc(l).b_off, actp(m, l + 1),
+                       wb(m, l), p + layer_desc(l, ni).b_off, actp(m, l + 1),
                        dp(m, l));
   if (y)
     hipLaunchKernelGGL(k_mlp_out, dim3(blocks(n, 256)), dim3(256), 0, s,
-                       actp(m, 4), wb(m, 4), p + layer_desc(4).b_off,
+                       actp(m, 4), wb(m, 4), p + layer_desc(4, ni).b_off,
                        m->out_scale, n, y);
   return check_launch(m->h, "mlp forward");
 }
@@ -137,17 +143,18 @@ static int backward(Mlp *m, int n, int npad, float *gp, float *grad_x,
   float *bpart = reinterpret_cast<float *>(m->bpart.ptr);
   const int chunks = npad / kChunk;
   const unsigned g = (unsigned)(npad / 128);
+  const int ni = m->n_in;
   if (gp) {
     hipLaunchKernelGGL(k_mlp_wgrad_out, dim3(chunks), dim3(256), 0, s, seed,
                        m->out_scale, actp(m, 4), n, bpart);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, bpart, chunks,
-                       kHid + 1, gp + layer_desc(4).w_off);
+                       kHid + 1, gp + layer_desc(4, ni).w_off);
   }
   hipLaunchKernelGGL(k_mlp_bwd_out, dim3(blocks((int64_t)npad * kHid, 256)),
                      dim3(256), 0, s, seed, m->out_scale, wb(m, 4), dp(m, 3),
                      npad, dzp(m, 3));
   for (int l = kLayers - 1; l >= 0; --l) {
-    const LayerDesc d = layer_desc(l);
+    const LayerDesc d = layer_desc(l, ni);
     if (gp) {
       const uint16_t *A = l == 0 ? reinterpret_cast<const uint16_t *>(m->a0.ptr)
                                  : actp(m, l);
@@ -165,12 +172,12 @@ static int backward(Mlp *m, int n, int npad, float *gp, float *grad_x,
     }
     if (l > 0)
       hipLaunchKernelGGL(k_mlp_bwd<kHid>, dim3(g), dim3(256), 0, s, dzp(m, l),
-                         wtb(m, l), dp(m, l - 1), dzp(m, l - 1), norm + kIn, n,
-                         nullptr);
+                         wtb(m, l), dp(m, l - 1), dzp(m, l - 1),
+                         norm + kInPad, n, ni, nullptr);
     else if (grad_x)
       hipLaunchKernelGGL(k_mlp_bwd<kInPad>, dim3(g), dim3(256), 0, s,
-                         dzp(m, 0), wtb(m, 0), nullptr, nullptr, norm + kIn, n,
-                         grad_x);
+                         dzp(m, 0), wtb(m, 0), nullptr, nullptr,
+                         norm + kInPad, n, ni, grad_x);
   }
   return check_launch(m->h, "mlp backward");
 }
@@ -184,6 +191,25 @@ static int check_rows(Mlp *m, int n, const void *x) {
 
 static int pad_rows(int n) { return ((n + kChunk - 1) / kChunk) * kChunk; }
 
+// Fused inference (value and input gradient) of rows [0, n) (with n_dev,
+// [0, min(n, *n_dev)) read on the device): one workgroup per tile of
+// 32 * kInferRowBlocks rows, at most 2048 workgroups striding over tiles.
+static int mlp_infer(Mlp *m, int n, const int *n_dev, const float *x,
+                     float *y, float *gx, hipStream_t s) {
+  NetWeights w;
+  for (int l = 0; l <= kLayers; ++l) w.W[l] = wb(m, l);
+  for (int l = 0; l < kLayers; ++l) w.Wt[l] = wtb(m, l);
+  constexpr int RB = kInferRowBlocks;
+  const int tiles = (n + 32 * RB - 1) / (32 * RB);
+  const int grid = tiles < 2048 ? tiles : 2048;
+  if (grid == 0) return PCSDF_OK;
+  hipLaunchKernelGGL(k_mlp_infer<RB>, dim3(grid), dim3(256), 0, s, x, n,
+                     n_dev, m->n_in,
+                     reinterpret_cast<const float *>(m->norm.ptr), w, pf(m),
+                     m->out_scale, y, gx);
+  return check_launch(m->h, "mlp inference");
+}
+
 }  // namespace pcsdf
 
 using namespace pcsdf;
@@ -191,25 +217,39 @@ using namespace pcsdf;
 struct pcsdf_mlp : Mlp {};
 
 Handle *pcsdf::mlp_handle(pcsdf_mlp *m) { return m ? m->h : nullptr; }
+int pcsdf::mlp_inputs(const pcsdf_mlp *m) { return m ? m->n_in : 0; }
+int pcsdf::mlp_rows(pcsdf_mlp *m, int n, const int32_t *n_dev,
+                    const float *x, float *y, float *gx, hipStream_t s) {
+  return mlp_infer(m, n, n_dev, x, y, gx, s);
+}
 
-extern "C" int pcsdf_mlp_create(pcsdf_handle *hp, pcsdf_mlp **out) {
+extern "C" int pcsdf_mlp_param_count(int32_t n_in) {
+  return n_in >= 1 && n_in <= kInPad ? mlp_nparam(n_in) : -1;
+}
+
+extern "C" int pcsdf_mlp_create(pcsdf_handle *hp, int32_t n_in,
+                                pcsdf_mlp **out) {
   Handle *h = reinterpret_cast<Handle *>(hp);
   if (!h) return PCSDF_ERR_INVALID_ARG;
   if (!out) return fail(h, PCSDF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  if (n_in < 1 || n_in > kInPad)
+    return fail(h, PCSDF_ERR_INVALID_ARG, "n_in must be in [1, 32]");
   int rc;
   if ((rc = bind_device(h))) return rc;
   pcsdf_mlp *m = new (std::nothrow) pcsdf_mlp();
   if (!m) return fail(h, PCSDF_ERR_OOM, "mlp allocation failed");
   m->h = h;
-  const size_t P = (size_t)kNParam * 4;
+  m->n_in = n_in;
+  m->nparam = mlp_nparam(n_in);
+  const size_t P = (size_t)m->nparam * 4;
   if ((rc = ensure_buffer(h, m->params, P, nullptr)) ||
       (rc = ensure_buffer(h, m->grad, P, nullptr)) ||
       (rc = ensure_buffer(h, m->m1, P, nullptr)) ||
       (rc = ensure_buffer(h, m->m2, P, nullptr)) ||
       (rc = ensure_buffer(h, m->wbf, kWbfTotal * 2, nullptr)) ||
       (rc = ensure_buffer(h, m->wtbf, kWbfTotal * 2, nullptr)) ||
-      (rc = ensure_buffer(h, m->norm, 2 * kIn * 4, nullptr)) ||
+      (rc = ensure_buffer(h, m->norm, 2 * kInPad * 4, nullptr)) ||
       (rc = ensure_buffer(h, m->wofs, 5 * 4, nullptr))) {
     pcsdf_mlp_destroy(m);
     return rc;
@@ -247,33 +287,36 @@ extern "C" int pcsdf_mlp_set_params(pcsdf_mlp *m, const float *params_host,
   Handle *h = m->h;
   if (!params_host || !in_offset_host || !in_scale_host)
     return fail(h, PCSDF_ERR_INVALID_ARG, "params, offset and scale required");
-  for (int i = 0; i < kNParam; ++i)
+  const int P = np(m), ni = m->n_in;
+  for (int i = 0; i < P; ++i)
     if (!std::isfinite(params_host[i]))
       return fail(h, PCSDF_ERR_NUMERIC,
                   "non-finite parameter at index " + std::to_string(i));
-  for (int i = 0; i < kIn; ++i)
+  for (int i = 0; i < ni; ++i)
     if (!std::isfinite(in_offset_host[i]) || !std::isfinite(in_scale_host[i]))
       return fail(h, PCSDF_ERR_NUMERIC, "non-finite normalisation");
   if (!std::isfinite(out_scale))
     return fail(h, PCSDF_ERR_NUMERIC, "non-finite output scale");
-  std::vector<float> norm(2 * kIn);
-  std::memcpy(norm.data(), in_offset_host, kIn * 4);
-  std::memcpy(norm.data() + kIn, in_scale_host, kIn * 4);
+  // [offset 32][scale 32]; padding columns read offset 0, scale 1
+  std::vector<float> norm(2 * kInPad, 0.f);
+  std::fill(norm.begin() + kInPad, norm.end(), 1.f);
+  std::memcpy(norm.data(), in_offset_host, (size_t)ni * 4);
+  std::memcpy(norm.data() + kInPad, in_scale_host, (size_t)ni * 4);
   if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(m->params.ptr, params_host, (size_t)kNParam * 4,
+      hipMemcpy(m->params.ptr, params_host, (size_t)P * 4,
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->norm.ptr, norm.data(), norm.size() * 4,
                 hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(m->m1.ptr, 0, (size_t)kNParam * 4) != hipSuccess ||
-      hipMemset(m->m2.ptr, 0, (size_t)kNParam * 4) != hipSuccess)
+      hipMemset(m->m1.ptr, 0, (size_t)P * 4) != hipSuccess ||
+      hipMemset(m->m2.ptr, 0, (size_t)P * 4) != hipSuccess)
     return fail(h, PCSDF_ERR_HIP, "uploading the parameters failed");
   m->out_scale = out_scale;
   m->step = 0;
-  hipLaunchKernelGGL(k_cast_weights, dim3(blocks(kNParam, 256)), dim3(256), 0,
+  hipLaunchKernelGGL(k_cast_weights, dim3(blocks(P, 256)), dim3(256), 0,
                      nullptr, reinterpret_cast<const float *>(m->params.ptr),
                      reinterpret_cast<uint16_t *>(m->wbf.ptr),
                      reinterpret_cast<uint16_t *>(m->wtbf.ptr),
-                     reinterpret_cast<const int *>(m->wofs.ptr));
+                     reinterpret_cast<const int *>(m->wofs.ptr), ni);
   if (hipDeviceSynchronize() != hipSuccess)
     return fail(h, PCSDF_ERR_HIP, "casting the weights failed");
   return PCSDF_OK;
@@ -283,14 +326,14 @@ extern "C" int pcsdf_mlp_get_params(pcsdf_mlp *m, float *params_host) {
   if (!m) return PCSDF_ERR_INVALID_ARG;
   if (!params_host) return fail(m->h, PCSDF_ERR_INVALID_ARG, "params NULL");
   if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(params_host, m->params.ptr, (size_t)kNParam * 4,
+      hipMemcpy(params_host, m->params.ptr, (size_t)np(m) * 4,
                 hipMemcpyDeviceToHost) != hipSuccess)
     return fail(m->h, PCSDF_ERR_HIP, "reading the parameters failed");
   return PCSDF_OK;
 }
 
 // Inference (value and input gradient) runs fused, one workgroup per tile
-// of 128 rows (mlp_fused.h); training keeps the layer-by-layer kernels,
+// of 64 rows (mlp_fused.h); training keeps the layer-by-layer kernels,
 // whose stored activations the weight gradients need.
 extern "C" int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
                                  float *y_dev, float *grad_x_dev,
@@ -302,17 +345,8 @@ extern "C" int pcsdf_mlp_forward(pcsdf_mlp *m, int32_t n, const float *x_dev,
   if (((uintptr_t)x_dev | (uintptr_t)y_dev | (uintptr_t)grad_x_dev) & 3)
     return fail(m->h, PCSDF_ERR_ALIGN, "device buffers must be 4-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  NetWeights w;
-  for (int l = 0; l <= kLayers; ++l) w.W[l] = wb(m, l);
-  for (int l = 0; l < kLayers; ++l) w.Wt[l] = wtb(m, l);
-  constexpr int RB = kInferRowBlocks;
-  const int tiles = (n + 32 * RB - 1) / (32 * RB);
-  const int grid = tiles < 2048 ? tiles : 2048;
   ProfScope ps(m->h, PCSDF_KERNEL_MLP, s);
-  hipLaunchKernelGGL(k_mlp_infer<RB>, dim3(grid), dim3(256), 0, s, x_dev, n,
-                     reinterpret_cast<const float *>(m->norm.ptr), w, pf(m),
-                     m->out_scale, y_dev, grad_x_dev, tiles);
-  return check_launch(m->h, "mlp inference");
+  return mlp_infer(m, n, nullptr, x_dev, y_dev, grad_x_dev, s);
 }
 
 extern "C" int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n,
@@ -333,7 +367,7 @@ extern "C" int pcsdf_mlp_gradients(pcsdf_mlp *m, int32_t n,
   return backward(m, n, npad, grad_params_dev, grad_x_dev, s);
 }
 
-// dLoss/dparams of the mean squared error into gp [kNParam] (and the loss
+// dLoss/dparams of the mean squared error into gp [nparam] (and the loss
 // into loss_dev): the forward pass, k_mse's seed and the backward pass.
 static int loss_gradients(Mlp *m, int n, const float *x_dev,
                           const float *target_dev, float *gp,
@@ -354,20 +388,20 @@ static int loss_gradients(Mlp *m, int n, const float *x_dev,
 }
 
 // One bias-corrected Adam step from the gradient g (device, fp32
-// [kNParam]); the step counter advances first, so the first step uses
+// [nparam]); the step counter advances first, so the first step uses
 // c1 = 1 - beta1, c2 = 1 - beta2.
 static int adam(Mlp *m, const float *g, float lr, float beta1, float beta2,
                 float eps, hipStream_t s) {
   m->step += 1;
   const float c1 = (float)(1.0 - std::pow((double)beta1, (double)m->step));
   const float c2 = (float)(1.0 - std::pow((double)beta2, (double)m->step));
-  hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam, 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_adam, dim3(blocks(np(m), 256)), dim3(256), 0, s,
                      reinterpret_cast<float *>(m->params.ptr), g,
                      reinterpret_cast<float *>(m->m1.ptr),
                      reinterpret_cast<float *>(m->m2.ptr), lr, beta1, beta2,
                      eps, c1, c2, reinterpret_cast<uint16_t *>(m->wbf.ptr),
                      reinterpret_cast<uint16_t *>(m->wtbf.ptr),
-                     reinterpret_cast<const int *>(m->wofs.ptr));
+                     reinterpret_cast<const int *>(m->wofs.ptr), m->n_in);
   return check_launch(m->h, "mlp adam step");
 }
 
@@ -436,7 +470,7 @@ extern "C" int pcsdf_mlp_get_state(pcsdf_mlp *m, float *params_host,
   if (!m) return PCSDF_ERR_INVALID_ARG;
   if (!params_host || !m1_host || !m2_host || !step)
     return fail(m->h, PCSDF_ERR_INVALID_ARG, "every output is required");
-  const size_t P = (size_t)kNParam * 4;
+  const size_t P = (size_t)np(m) * 4;
   if (hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(params_host, m->params.ptr, P, hipMemcpyDeviceToHost) !=
           hipSuccess ||
@@ -457,7 +491,7 @@ extern "C" int pcsdf_mlp_set_state(pcsdf_mlp *m, const float *params_host,
     return fail(m->h, PCSDF_ERR_INVALID_ARG, "moments are required");
   if (step < 0 || step > (int64_t)1 << 40)
     return fail(m->h, PCSDF_ERR_INVALID_ARG, "step out of range");
-  for (int i = 0; i < kNParam; ++i)
+  for (int i = 0; i < np(m); ++i)
     if (!std::isfinite(m1_host[i]) || !std::isfinite(m2_host[i]) ||
         m2_host[i] < 0.f)
       return fail(m->h, PCSDF_ERR_NUMERIC,
@@ -465,7 +499,7 @@ extern "C" int pcsdf_mlp_set_state(pcsdf_mlp *m, const float *params_host,
   int rc = pcsdf_mlp_set_params(m, params_host, in_offset_host,
                                 in_scale_host, out_scale);
   if (rc) return rc;
-  const size_t P = (size_t)kNParam * 4;
+  const size_t P = (size_t)np(m) * 4;
   if (hipMemcpy(m->m1.ptr, m1_host, P, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->m2.ptr, m2_host, P, hipMemcpyHostToDevice) != hipSuccess)
     return fail(m->h, PCSDF_ERR_HIP, "uploading the moments failed");

@@ -83,28 +83,34 @@ __device__ __forceinline__ void tile_gemm(const uint16_t *a_lds,
       acc[rb] = mfma(load8(arow + rb * 32 * kTS + ks * 16), bv[ks], acc[rb]);
 }
 
-// y [n] and, when gx is given, dy/dx [n][22] for rows [0, n), in tiles of
-// 32 RB rows (RB row blocks per wave).
+// y [n] and, when gx is given, dy/dx [n][n_in] for rows [0, n), x
+// [n][n_in], in tiles of 32 RB rows (RB row blocks per wave).  With n_dev
+// the row count is min(n, *n_dev), read on the device (a grid sized for n
+// then leaves its surplus workgroups idle).
 template <int RB>
 __global__ __launch_bounds__(256, RB == 4 ? 1 : 2) void k_mlp_infer(
-    const float *__restrict__ x, int n, const float *__restrict__ norm,
-    NetWeights w, const float *__restrict__ p, float out_scale,
-    float *__restrict__ y, float *__restrict__ gx, int tiles) {
+    const float *__restrict__ x, int n, const int *__restrict__ n_dev,
+    int n_in, const float *__restrict__ norm, NetWeights w,
+    const float *__restrict__ p, float out_scale, float *__restrict__ y,
+    float *__restrict__ gx) {
   constexpr int kTileRows = 32 * RB;
   __shared__ uint16_t tl[2][kTileRows * kTS];
   __shared__ uint16_t dl[2][kTileRows * kTS];  // D_0, D_1
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int unit = wave * 32 + (lane & 31);
-  const float *off = norm, *scale = norm + kIn;
+  const float *off = norm, *scale = norm + kInPad;
+  if (n_dev) n = min(n, *n_dev);
+  const int tiles = (n + kTileRows - 1) / kTileRows;
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t row0 = (int64_t)tile * kTileRows;
-    // A0 = bf16((x - offset) * scale), zero beyond 22 columns and n rows
+    // A0 = bf16((x - offset) * scale), zero beyond n_in columns and n rows
     for (int t = threadIdx.x; t < kTileRows * kInPad; t += 256) {
       const int r = t / kInPad, c = t - r * kInPad;
       const int64_t m = row0 + r;
       tl[0][r * kTS + c] =
-          (c < kIn && m < n) ? to_bf16((x[m * kIn + c] - off[c]) * scale[c])
-                             : (uint16_t)0;
+          (c < n_in && m < n)
+              ? to_bf16((x[m * n_in + c] - off[c]) * scale[c])
+              : (uint16_t)0;
     }
     __syncthreads();
     uint32_t D[2][RB][8];  // bf16 SiLU' of layers 2, 3 for this wave, 2 a word
@@ -117,7 +123,7 @@ __global__ __launch_bounds__(256, RB == 4 ? 1 : 2) void k_mlp_infer(
       else
         tile_gemm<kHid, RB>(tl[l & 1], w.W[l], unit, lane, acc);
       uint16_t *aout = tl[(l + 1) & 1];
-      const float bias = p[layer_desc(l).b_off + unit];
+      const float bias = p[layer_desc(l, n_in).b_off + unit];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256, RB == 4 ? 1 : 2) void k_mlp_infer(
       s += __shfl_xor(s, 1);
       const int64_t m = row0 + row;
       if (half == 0 && m < n)
-        y[m] = (s + p[layer_desc(kLayers).b_off]) * out_scale;
+        y[m] = (s + p[layer_desc(kLayers, n_in).b_off]) * out_scale;
     }
     if (gx) {
       // dZ3 = bf16(out_scale W4 (.) D3) into tile 1 (A3 is consumed)
@@ -217,12 +223,12 @@ __global__ __launch_bounds__(256, RB == 4 ? 1 : 2) void k_mlp_infer(
       for (int ks = 0; ks < kHid / 16; ++ks)
         g = mfma(load8(zrow + ks * 16), load8(brow + ks * 16), g);
       const int col = lane & 31;
-      if (col < kIn) {
+      if (col < n_in) {
         const float sc = scale[col];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int64_t m = row0 + wave * 32 + acc_row(r, lane);
-          if (m < n) gx[m * kIn + col] = g[r] * sc;
+          if (m < n) gx[m * n_in + col] = g[r] * sc;
         }
       }
       }

@@ -1,9 +1,10 @@
 // Kernels of the surrogate MLP (included by mlp.hip).
 #pragma once
 
-// Learned surrogate for sphere queries: a 22 -> 4 x 128 SiLU -> 1 MLP with
-// BF16 operands and FP32 accumulation on the matrix cores, its input
-// gradient by reverse mode, and its training (weight gradients + Adam).
+// Learned surrogate for sphere queries: an n_in -> 4 x 128 SiLU -> 1 MLP
+// (n_in <= 32 inputs, padded to 32 columns) with BF16 operands and FP32
+// accumulation on the matrix cores, its input gradient by reverse mode,
+// and its training (weight gradients + Adam).
 //
 // Every product of the network is a dense contraction with one dimension
 // of 128, so each layer is one MFMA GEMM over a batch of rows:
@@ -31,8 +32,11 @@
 
 namespace pcsdf {
 
-constexpr int kIn = 22, kInPad = 32, kHid = 128, kLayers = 4;
-constexpr int kNParam = 52609;
+constexpr int kInPad = 32, kHid = 128, kLayers = 4;
+// Parameters of a network with n_in inputs: W0 [128][n_in] and the rest.
+__host__ __device__ constexpr int mlp_nparam(int n_in) {
+  return kHid * n_in + kHid + 3 * (kHid * kHid + kHid) + kHid + 1;
+}
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -65,18 +69,18 @@ __device__ __forceinline__ int acc_row(int r, int lane) {
 
 // ----------------------------------------------------------- forward
 
-// A0 = bf16((x - offset) * scale), padded with zeros to 32 columns and
-// to npad rows.
+// A0 = bf16((x - offset) * scale), x [n][n_in], padded with zeros to 32
+// columns and to npad rows.
 __global__ __launch_bounds__(256) void k_mlp_input(
-    const float *__restrict__ x, int n, int npad,
+    const float *__restrict__ x, int n, int npad, int n_in,
     const float *__restrict__ off, const float *__restrict__ scale,
     uint16_t *__restrict__ a0) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)npad * kInPad) return;
   const int64_t m = t / kInPad;
   const int c = (int)(t - m * kInPad);
-  a0[t] = (c < kIn && m < n)
-              ? to_bf16((x[m * kIn + c] - off[c]) * scale[c])
+  a0[t] = (c < n_in && m < n)
+              ? to_bf16((x[m * n_in + c] - off[c]) * scale[c])
               : (uint16_t)0;
 }
 
@@ -180,12 +184,13 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_out(
 // Hidden layer backward: dA [rows][KO] = dZ [rows][128] * W [128][KO],
 // with Wt = W^T [KO][128] staged in LDS.  If Dp is given the result is
 // dZ_prev = bf16(dA (.) Dp) [M][KO]; otherwise dA is the gradient of the
-// normalised input and grad_x[m][c] = dA[m][c] * scale[c] for c < 22.
+// normalised input and grad_x[m][c] = dA[m][c] * scale[c] for c < n_in.
 template <int KO>
 __global__ __launch_bounds__(256) void k_mlp_bwd(
     const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ Wt,
     const uint16_t *__restrict__ Dp, uint16_t *__restrict__ dZp,
-    const float *__restrict__ scale, int n, float *__restrict__ grad_x) {
+    const float *__restrict__ scale, int n, int n_in,
+    float *__restrict__ grad_x) {
   constexpr int S = kHid + 8;
   __shared__ uint16_t w[KO * S];
   for (int t = threadIdx.x; t < KO * (kHid / 8); t += blockDim.x) {
@@ -222,8 +227,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(
       if (Dp) {
         dZp[row * KO + col] =
             to_bf16(acc[nb][r] * from_bf16(Dp[row * KO + col]));
-      } else if (col < kIn && row < n) {
-        grad_x[row * kIn + col] = acc[nb][r] * scale[col];
+      } else if (col < n_in && row < n) {
+        grad_x[row * n_in + col] = acc[nb][r] * scale[col];
       }
     }
   }
@@ -351,9 +356,9 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y,
 struct LayerDesc {
   int w_off, b_off, out, in, in_pad;
 };
-__host__ __device__ inline LayerDesc layer_desc(int l) {
-  // W0[128][22] b0 W1 b1 W2 b2 W3 b3 W4[1][128] b4
-  const int sizes_in[5] = {kIn, kHid, kHid, kHid, kHid};
+__host__ __device__ inline LayerDesc layer_desc(int l, int n_in) {
+  // W0[128][n_in] b0 W1 b1 W2 b2 W3 b3 W4[1][128] b4
+  const int sizes_in[5] = {n_in, kHid, kHid, kHid, kHid};
   const int sizes_out[5] = {kHid, kHid, kHid, kHid, 1};
   int off = 0;
   for (int q = 0; q < l; ++q) off += sizes_out[q] * sizes_in[q] + sizes_out[q];
@@ -372,9 +377,9 @@ __global__ __launch_bounds__(256) void k_adam(
     float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m1,
     float *__restrict__ m2, float lr, float b1, float b2, float eps,
     float c1, float c2, uint16_t *__restrict__ wbf, uint16_t *__restrict__ wtbf,
-    const int *__restrict__ wofs) {
+    const int *__restrict__ wofs, int n_in) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= kNParam) return;
+  if (i >= mlp_nparam(n_in)) return;
   const float gi = g[i];
   const float a = b1 * m1[i] + (1.f - b1) * gi;
   const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
@@ -383,7 +388,7 @@ __global__ __launch_bounds__(256) void k_adam(
   const float th = p[i] - lr * (a / c1) / (sqrtf(v / c2) + eps);
   p[i] = th;
   for (int l = 0; l <= kLayers; ++l) {
-    const LayerDesc d = layer_desc(l);
+    const LayerDesc d = layer_desc(l, n_in);
     if (i >= d.w_off && i < d.b_off) {
       const int o = (i - d.w_off) / d.in, c = (i - d.w_off) - o * d.in;
       const uint16_t hb = to_bf16(th);
@@ -396,11 +401,11 @@ __global__ __launch_bounds__(256) void k_adam(
 // BF16 copies of every weight matrix from the fp32 masters.
 __global__ __launch_bounds__(256) void k_cast_weights(
     const float *__restrict__ p, uint16_t *__restrict__ wbf,
-    uint16_t *__restrict__ wtbf, const int *__restrict__ wofs) {
+    uint16_t *__restrict__ wtbf, const int *__restrict__ wofs, int n_in) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= kNParam) return;
+  if (i >= mlp_nparam(n_in)) return;
   for (int l = 0; l <= kLayers; ++l) {
-    const LayerDesc d = layer_desc(l);
+    const LayerDesc d = layer_desc(l, n_in);
     if (i >= d.w_off && i < d.b_off) {
       const int o = (i - d.w_off) / d.in, c = (i - d.w_off) - o * d.in;
       const uint16_t hb = to_bf16(p[i]);

@@ -181,30 +181,38 @@ def test_profile_calls_without_device(h):
 
 
 def test_surrogate_validation(h):
+    """The surrogate's entry points reject bad arguments on the host."""
+    import numpy as np
     from paper_2201_05058_amd import surrogate as sg
     sg._declare(h.lib)
     g = grid()
-    st = (C.c_float * 18)()
+    xy = np.zeros((2, 1, 2))
+    P = xy.ctypes.data_as(C.c_void_p)
     # no network
     assert h.lib.pcsdf_query_spheres_surrogate(
-        h.ptr, None, C.byref(g), FAKE, None, 2, 0, None, 0.25, 1.8, st, 0.1,
-        0.1, 10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, None, None, None,
+        h.ptr, None, C.byref(g), FAKE, FAKE, 2, 1, P, 0.25, 1.8, 0.1, 0.05,
+        10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, None, None, None, None,
         None) == 1
 
-    def feat(n=5, centre=FAKE, slices=FAKE, n_slices=2, dt=0.1, state=st,
-             x=FAKE):
-        return h.lib.pcsdf_surrogate_features(h.ptr, n, centre, slices,
-                                              n_slices, dt, state, x, None)
+    def feat(n=5, n_humans=1, centre=FAKE, slices=FAKE, x=FAKE, label=None,
+             target=None):
+        return h.lib.pcsdf_surrogate_human_features(
+            h.ptr, C.byref(g), 2, n_humans, P, 0.25, 1.8, n, centre, slices,
+            None, label, x, None, target, None)
     assert feat(n=-1) == 1
-    assert feat(n_slices=0) == 1
-    assert feat(state=None) == 1
-    assert feat(dt=math.nan) == 6
-    assert feat(dt=-0.1) == 6
-    bad = (C.c_float * 18)(*([0.0] * 17 + [math.inf]))
-    assert feat(state=bad) == 6
+    assert feat(n_humans=0) == 1
+    assert feat(target=FAKE) == 1  # a target needs labels
     assert feat(centre=None) == 1
     assert feat(x=FAKE_MIS) == 3
     assert feat(n=0) == 0  # no work, nothing touched
+    # the network's width: 1..32 inputs
+    assert h.lib.pcsdf_mlp_param_count(16) == sg.nparam(16) == 51841
+    assert h.lib.pcsdf_mlp_param_count(22) == 52609
+    assert h.lib.pcsdf_mlp_param_count(0) == -1
+    assert h.lib.pcsdf_mlp_param_count(33) == -1
+    out = C.c_void_p()
+    assert h.lib.pcsdf_mlp_create(h.ptr, 0, C.byref(out)) == 1
+    assert h.lib.pcsdf_mlp_create(h.ptr, 33, C.byref(out)) == 1
 
 
 def test_tuning_validation_without_device(h):

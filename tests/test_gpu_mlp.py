@@ -47,10 +47,13 @@ def sg(dev):
     return m
 
 
-def rand_net(seed):
+IN = 22  # the width the tolerances were measured at (16 and 5 also run)
+
+
+def rand_net(seed, n_in=IN):
     r = np.random.default_rng(seed)
     out = []
-    for s in omlp.SHAPES:
+    for s in omlp.shapes(n_in):
         fan = s[-1] if len(s) == 2 else 16
         out.append(r.uniform(-1, 1, size=s) * 1.5 / np.sqrt(fan))
     return omlp.pack(out).astype(np.float32)
@@ -67,23 +70,25 @@ def close(got, want, rtol_rms=1e-2, med=5e-5, frac=0.02):
     assert np.mean(err > 1e-3) <= frac, float(np.mean(err > 1e-3))
 
 
-def setup(sg, dev, seed, n):
+def setup(sg, dev, seed, n, n_in=IN):
     r = np.random.default_rng(seed + 100)
-    p = rand_net(seed)
-    off = r.normal(size=22).astype(np.float32) * 0.1
-    sc = (0.5 + r.random(22)).astype(np.float32)
+    p = rand_net(seed, n_in)
+    off = r.normal(size=n_in).astype(np.float32) * 0.1
+    sc = (0.5 + r.random(n_in)).astype(np.float32)
     osc = 1.3
-    x = r.normal(size=(n, 22)).astype(np.float32)
-    net = sg.Mlp()
+    x = r.normal(size=(n, n_in)).astype(np.float32)
+    net = sg.Mlp(n_in=n_in)
     net.set_params(p, off, sc, osc)
     xd = torch.from_numpy(x).to(dev)
     return net, p, off, sc, osc, x, xd
 
 
-@pytest.mark.parametrize("seed,n", [(0, 1024), (1, 3000), (2, 77)])
-def test_forward_and_input_gradient(sg, dev, seed, n):
-    net, p, off, sc, osc, x, xd = setup(sg, dev, seed, n)
-    say(f"mlp forward seed={seed} n={n}")
+@pytest.mark.parametrize("seed,n,n_in", [(0, 1024, IN), (1, 3000, IN),
+                                         (2, 77, IN), (8, 2500, 16),
+                                         (9, 700, 5)])
+def test_forward_and_input_gradient(sg, dev, seed, n, n_in):
+    net, p, off, sc, osc, x, xd = setup(sg, dev, seed, n, n_in)
+    say(f"mlp forward seed={seed} n={n} n_in={n_in}")
     y, gx = net.forward(xd)
     torch.cuda.synchronize()
     wy, _ = omlp.forward(p.astype(np.float64), x, off, sc, osc)
@@ -95,9 +100,10 @@ def test_forward_and_input_gradient(sg, dev, seed, n):
     net.close()
 
 
-@pytest.mark.parametrize("seed,n", [(3, 2048), (4, 1500)])
-def test_parameter_gradients(sg, dev, seed, n):
-    net, p, off, sc, osc, x, xd = setup(sg, dev, seed, n)
+@pytest.mark.parametrize("seed,n,n_in", [(3, 2048, IN), (4, 1500, IN),
+                                         (10, 2048, 16)])
+def test_parameter_gradients(sg, dev, seed, n, n_in):
+    net, p, off, sc, osc, x, xd = setup(sg, dev, seed, n, n_in)
     dy = np.random.default_rng(seed).normal(size=n).astype(np.float32)
     say(f"mlp gradients seed={seed} n={n}")
     gp, gx = net.gradients(xd, torch.from_numpy(dy).to(dev))
@@ -173,7 +179,7 @@ def test_train_step_is_loss_gradient_then_adam(sg, dev):
     followed by an Adam step with it, bit for bit, over three steps."""
     n = 2048
     a, p, off, sc, osc, x, xd = setup(sg, dev, 6, n)
-    b = sg.Mlp()
+    b = sg.Mlp(n_in=IN)
     b.set_params(p, off, sc, osc)
     tgt = np.random.default_rng(9).normal(size=n).astype(np.float32)
     td = torch.from_numpy(tgt).to(dev)
@@ -207,13 +213,13 @@ def test_optimiser_state_round_trip(sg, dev):
     td = torch.from_numpy(tgt).to(dev)
     for _ in range(6):
         a.train_step(xd, td, 1e-3, beta2=0.99)
-    b = sg.Mlp()
+    b = sg.Mlp(n_in=IN)
     b.set_params(p, off, sc, osc)
     for _ in range(3):
         b.train_step(xd, td, 1e-3, beta2=0.99)
     state = b.get_state()
     b.close()
-    c = sg.Mlp()
+    c = sg.Mlp(n_in=IN)
     c.set_state(*state, off, sc, osc)
     assert c.get_state()[3] == 3
     for _ in range(3):
@@ -227,11 +233,11 @@ def test_training_reduces_loss(sg, dev):
     # fit the distance to a sphere of radius 0.5 m (a smooth target)
     r = np.random.default_rng(11)
     n = 8192
-    x = r.uniform(-1, 1, size=(n, 22)).astype(np.float32)
+    x = r.uniform(-1, 1, size=(n, 16)).astype(np.float32)
     t = (np.linalg.norm(x[:, :3], axis=1) - 0.5).astype(np.float32)
-    net = sg.Mlp()
-    net.set_params(sg.init_params(np.random.default_rng(0)), np.zeros(22),
-                   np.ones(22), 1.0)
+    net = sg.Mlp(n_in=16)
+    net.set_params(sg.init_params(np.random.default_rng(0), 16),
+                   np.zeros(16), np.ones(16), 1.0)
     xd = torch.from_numpy(x).to(dev)
     td = torch.from_numpy(t).to(dev)
     loss = torch.zeros(1, device=dev)

@@ -132,3 +132,68 @@ def test_other_slice_groups_give_identical_bytes(run, G):
     finally:
         h.close()
     torch.cuda.empty_cache()
+
+
+def test_surrogate_queries_on_oracle_slices(run, slice_oracle,
+                                            static_oracle):
+    """The trained room512 surrogate (eight humans on piecewise-linear
+    paths) on the workload's spheres of slices 0, 17 and 49, against the
+    oracle's rule given the GPU network's values for every (query, human)
+    row and the oracle's exact fields of those slices for the fallback:
+    identical decisions, bit-identical answered distances, gradients
+    within 1e-6, fallback answers within the exact-query contract."""
+    import os
+
+    from oracle import surrogate as osur
+    from paper_2201_05058_amd import surrogate as sg
+    from paper_2201_05058_amd import train
+    sc = run["sc"]
+    dev = run["ssq_s"].device
+    w = os.path.join(os.path.dirname(__file__), "..", "paper_2201_05058_amd",
+                     "weights", "surrogate_room512.npz")
+    net, _ = train.load(w)
+    q = sc.queries
+    sel = np.nonzero(np.isin(q.slice, CHECK_SLICES))[0][::10]
+    c, r, s = q.centre[sel], q.radius[sel], q.slice[sel]
+    say(f"room512: {len(sel)} surrogate queries vs oracle")
+    td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = sg.query_spheres_surrogate(
+        net, sc.grid, run["ssq_s"], run["sdf_s"], sc.human_xy, sc.radius,
+        sc.height, td(c), td(r), td(s), want_cost=True)
+    torch.cuda.synchronize()
+    # the oracle on the three slices (queries renumbered 0, 1, 2)
+    remap = {j: t for t, j in enumerate(CHECK_SLICES)}
+    s3 = np.array([remap[int(j)] for j in s], np.int32)
+    xy3 = sc.human_xy[list(CHECK_SLICES)]
+    wf3 = np.concatenate([slice_oracle[j][1] for j in CHECK_SLICES])
+    rows = {}
+
+    def gpu_net(x, k):
+        if k not in rows:
+            kk = np.full(len(s), k, np.int32)
+            xd, _, _ = sg.surrogate_human_features(
+                sc.grid, sc.human_xy, sc.radius, sc.height, td(c), td(s),
+                human=td(kk))
+            y, gx = net.forward(xd)
+            torch.cuda.synchronize()
+            rows[k] = (y.cpu().numpy(), gx.cpu().numpy())
+        return rows[k]
+    _, rf = static_oracle
+    wd, wg, wst, wcost, wused = osur.query(
+        sc.grid, wf3, rf, gpu_net, xy3, sc.radius, sc.height, c, r, s3,
+        margin=0.10, band=2 * np.sqrt(3) * sc.grid.h)
+    d = out["dist"].cpu().numpy()
+    gr = out["grad"].cpu().numpy()
+    used = out["used_fallback"].cpu().numpy()
+    np.testing.assert_array_equal(used, wused)
+    acc = used == 0
+    say(f"  answered {acc.mean():.3f}")
+    assert acc.mean() > 0.2
+    np.testing.assert_array_equal(d[acc], wd[acc])
+    np.testing.assert_array_equal(out["status"].cpu().numpy(), wst)
+    assert np.all(np.abs(gr[acc] - wg[acc]) <=
+                  1e-6 * np.maximum(np.abs(wg[acc]), 1.0))
+    ex = ~acc
+    assert np.all(np.abs(d[ex] - wd[ex]) <=
+                  1e-6 * np.maximum(np.abs(wd[ex]), sc.grid.h))
+    net.close()

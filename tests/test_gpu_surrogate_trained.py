@@ -1,14 +1,21 @@
-"""What the trained surrogate gains over the method without it.
+"""The trained per-human surrogate against the method without it.
 
-The committed network (trained on the GPU by the library's own kernels on
-the 256x256x128 room) answers sphere queries on a fresh draw of three
-constant-velocity humans, with the exact path as its fallback inside the
-0.10 m margin.  The same pipeline with the network as training starts
-(its initialisation, same input normalisation) stands for the method
-without the learned part.  Distances are judged against the oracle's
-composite fields of three slices (first, middle, last), computed on the
-CPU; every answer the network gives is compared, every fallback answer
-is the exact one by the parity tests.
+The committed networks (trained on the GPU by the library's own kernels,
+paper_2201_05058_amd/train.py: 0.02 m voxels for the 256x256x128 room,
+0.01 m for 512x512x256) answer sphere queries of the rooms' evaluation
+workloads (room256: three fresh constant-velocity humans; room512: its
+eight piecewise-linear humans), with the exact path as fallback.  Every
+answer is judged against the exact path on the same GPU
+(pcsdf_query_spheres_direct, bit-identical to sampling the composite
+fields, which the parity tests hold to the oracle).
+
+The method without the learned part is the same call with a network whose
+residual is zero (the distance to the continuous cylinder alone) and with
+a constant residual (the middle of the exact field's range): the trained
+network must be far more accurate than both, and within the 1 cm target
+on every query it answers.  Time is reported for both paths (the exact
+queries need no network; the surrogate buys accuracy per evaluated row,
+not speed, on this GPU).
 """
 import os
 import sys
@@ -16,15 +23,12 @@ import sys
 import numpy as np
 import pytest
 
-import oracle
-import scenegen
-
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2201_05058_amd",
-                       "weights", "surrogate_room256.npz")
-SLICES = (0, 9, 19)
+WDIR = os.path.join(os.path.dirname(__file__), "..", "paper_2201_05058_amd",
+                    "weights")
+TARGET_M = 0.010
 
 
 def say(*a):
@@ -32,77 +36,49 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def case(dev):
-    import paper_2201_05058_amd as pc
-    sc = scenegen.room256()
-    g = sc.grid
-    rng = np.random.Generator(np.random.PCG64(123))
-    start, vel = scenegen._cv_humans(rng, g, 3, scenegen.HUMAN_RADIUS)
-    xy = scenegen.cv_positions(start, vel, sc.n_slices, sc.dt)
-    state = scenegen.human_state(start, vel)
-    say("trained surrogate: oracle fields of 3 slices")
-    rs, _ = oracle.build_static(g, sc.occ)
-    _, wf = oracle.predicted_composite(g, rs, xy[list(SLICES)],
-                                       scenegen.HUMAN_RADIUS,
-                                       scenegen.HUMAN_HEIGHT)
-    Q = 30000
-    lo = np.array(g.origin) + g.h / 2
-    span = np.array(g.extent) - g.h
-    c = (rng.random((Q, 3)) * span + lo).astype(np.float32)
-    pick = rng.integers(0, len(SLICES), Q)
-    s = np.array(SLICES, np.int32)[pick]
-    r = (rng.random(Q) * 0.10 + 0.05).astype(np.float32)
-    want, _, _, _ = oracle.query(g, wf, c, r, pick.astype(np.int32))
-    occ = torch.from_numpy(sc.occ).to(dev)
-    ssq_s, sdf_s = pc.build_static_sdf(g, occ)
-    return {"sc": sc, "xy": xy, "state": state, "c": c, "r": r, "s": s,
-            "want": want, "ssq": ssq_s, "sdf": sdf_s}
+def subset(sc, n, seed):
+    """n of the room's queries, drawn without replacement."""
+    import scenegen
+    q = sc.queries
+    idx = np.sort(np.random.default_rng(seed).choice(len(q.radius), n,
+                                                     replace=False))
+    sc.queries = scenegen.Queries(centre=q.centre[idx], radius=q.radius[idx],
+                                  slice=q.slice[idx])
+    return sc
 
 
-def answers(dev, case, net):
-    from paper_2201_05058_amd.surrogate import query_spheres_surrogate
-    sc = case["sc"]
-    out = query_spheres_surrogate(
-        net, sc.grid, case["ssq"], case["xy"], scenegen.HUMAN_RADIUS,
-        scenegen.HUMAN_HEIGHT, case["state"], sc.dt,
-        torch.from_numpy(case["c"]).to(dev), torch.from_numpy(case["r"]).to(dev),
-        torch.from_numpy(case["s"]).to(dev), fallback_margin=0.10,
-        want_status=False, static_sdf=case["sdf"])
-    torch.cuda.synchronize()
-    used = out["used_fallback"].cpu().numpy().astype(bool)
-    err = np.abs(out["dist"].cpu().numpy().astype(np.float64) -
-                 case["want"].astype(np.float64))
-    return used, err
+def fixed_net(sg, value):
+    """A network whose output is `value` everywhere (zero weights)."""
+    net = sg.Mlp(n_in=sg.NIN)
+    p = np.zeros(sg.nparam(sg.NIN), np.float32)
+    p[-1] = value
+    net.set_params(p, np.zeros(sg.NIN), np.ones(sg.NIN), 1.0)
+    return net
 
 
-def test_trained_network_gains_over_its_initialisation(dev, case):
+@pytest.mark.parametrize("room,n", [("room256", 200_000),
+                                    ("room512", 200_000)])
+def test_trained_network_meets_target_and_beats_fixed_residuals(dev, room,
+                                                                  n):
+    from paper_2201_05058_amd import surrogate as sg
     from paper_2201_05058_amd import train
-    from paper_2201_05058_amd.surrogate import Mlp, init_params
-    net, meta = train.load(WEIGHTS)
-    used, err = answers(dev, case, net)
+    path = os.path.join(WDIR, f"surrogate_{room}.npz")
+    net, meta = train.load(path)
+    sc = subset(train.evaluation_scene(room), n, 11)
+    say(f"trained surrogate {room}: {n} queries, trained on "
+        f"{meta.get('samples')} samples")
+    res = train.evaluate(net, sc, dev, e2e_queries=10_000)
+    say({k: res[k] for k in ("err_max_m", "err_p99_m", "err_mean_m",
+                             "fallback_fraction", "rows_per_query",
+                             "surrogate_path_ms", "exact_direct_ms")})
+    assert res["fallback_fraction"] < 0.9
+    assert res["err_max_m"] <= TARGET_M
+    for v in (0.0, 0.5):
+        base = fixed_net(sg, v)
+        b = train.evaluate(base, sc, dev, e2e_queries=10_000)
+        say(f"  residual fixed at {v}: max {b['err_max_m']:.4f} "
+            f"p99 {b['err_p99_m']:.4f} mean {b['err_mean_m']:.5f}")
+        assert res["err_p99_m"] < 0.5 * b["err_p99_m"]
+        assert res["err_mean_m"] < 0.5 * b["err_mean_m"]
+        base.close()
     net.close()
-    a = ~used
-    say(f"trained: answers {a.mean():.3f}, error max {err[a].max():.4f} m, "
-        f"p99 {np.percentile(err[a], 99):.4f} m, mean {err[a].mean():.5f} m")
-    # fallback answers are the exact ones (to fp32 rounding)
-    assert err[used].max() <= 1e-5
-    assert a.mean() >= 0.6
-    assert err[a].max() <= 0.035 and np.percentile(err[a], 99) <= 0.015
-    assert err[a].mean() <= 0.002
-
-    untrained = Mlp()
-    off, scl = train.normalisation(case["sc"].grid)
-    untrained.set_params(init_params(np.random.Generator(np.random.PCG64(0))),
-                         off, scl, 1.0)
-    used0, err0 = answers(dev, case, untrained)
-    untrained.close()
-    a0 = ~used0
-    say(f"untrained: answers {a0.mean():.3f}, error max "
-        f"{err0[a0].max() if a0.any() else float('nan'):.4f} m")
-    # without training the humans are not seen: the initial network
-    # answers few queries, or is wrong by decimetres where it answers
-    assert a0.mean() < 0.2 or err0[a0].max() > 0.2
-    if a0.sum() >= 100:
-        assert (err0[a0] > 0.015).mean() > 10 * max(
-            (err[a] > 0.015).mean(), 1e-4)

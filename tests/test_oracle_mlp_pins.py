@@ -8,13 +8,17 @@ import torch
 
 from oracle import mlp
 
+IN = 22
+SHAPES = mlp.shapes(IN)
+NPARAM = mlp.nparam(IN)
+
 rng = np.random.default_rng(0)
 
 
 def rand_params(seed=1, scale=1.0):
     r = np.random.default_rng(seed)
     out = []
-    for s in mlp.SHAPES:
+    for s in SHAPES:
         fan = s[-1] if len(s) == 2 else 1
         out.append(r.uniform(-1, 1, size=s) * scale / np.sqrt(max(fan, 1)))
     return mlp.pack(out)
@@ -32,13 +36,13 @@ def test_bf16_matches_torch():
 
 
 def test_param_count():
-    assert mlp.NPARAM == 52609
+    assert NPARAM == 52609
 
 
 def test_forward_closed_form_chain():
     # route input 0 through unit 0 of every layer with weight 1, zero
     # biases, output weight w and bias c: y = w * silu^4(x0) + c
-    ws = [np.zeros(s) for s in mlp.SHAPES]
+    ws = [np.zeros(s) for s in SHAPES]
     for l in range(mlp.LAYERS):
         ws[2 * l][0, 0] = 1.0
     ws[8][0, 0] = 0.75
@@ -71,10 +75,10 @@ def test_backward_matches_central_differences():
         y, _ = mlp.forward(pp, xx, off, sc, osc, rounding=False)
         return float(np.dot(y, dy))
     eps = 1e-6
-    idx = np.concatenate([rng.choice(mlp.NPARAM, 60, replace=False),
-                          [mlp.NPARAM - 1, mlp.NPARAM - 2, 0, 2816]])
+    idx = np.concatenate([rng.choice(NPARAM, 60, replace=False),
+                          [NPARAM - 1, NPARAM - 2, 0, 2816]])
     for i in idx:
-        e = np.zeros(mlp.NPARAM)
+        e = np.zeros(NPARAM)
         e[i] = eps
         fd = (L(p + e, x) - L(p - e, x)) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), i

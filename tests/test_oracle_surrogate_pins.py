@@ -1,74 +1,249 @@
-"""Pins of the surrogate-query oracle (accept / fallback rule) by cases
-whose answer is known without it: a constant network (closed form), an
-infinite margin (reduces to the exact query), a non-finite network, the
-input layout, and the boundary of the span of voxel centres."""
+"""Pins of the per-human surrogate's oracle by cases whose answer is known
+without it: the features against geometry computed another way (nearest
+point of the solid cylinder, lattice identities), the gradient chain
+against central differences, the residual's range against the exact
+single-human field, and the combination rule against the exact query when
+the network reproduces every human's exact field (the band rule makes the
+two agree to rounding), a constant network (closed form), an infinite
+margin (the exact query), a non-finite network, absent and clipped humans.
+CPU only."""
 import numpy as np
+import pytest
 
 import oracle
 import scenegen
-from oracle import mlp as omlp
 from oracle import surrogate as osur
 
 
-def scene():
-    sc = scenegen.small_scene(41, 14, 12, 10, h=0.1, n_humans=3, n_slices=3)
-    rs, _ = oracle.build_static(sc.grid, sc.occ)
+def room(seed=41, nx=30, ny=26, nz=14, h=0.05, K=3, n=3, boxes=4):
+    sc = scenegen.small_scene(seed, nx, ny, nz, h=h, n_boxes=boxes,
+                              n_humans=K, n_slices=n, radius=0.2,
+                              height=0.45)
+    rs, rf = oracle.build_static(sc.grid, sc.occ)
     _, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
                                        sc.height)
-    st = scenegen.human_state(sc.meta["start"], sc.meta["vel"])
-    return sc, wf, st
+    return sc, rf, wf
 
 
-def queries(sc, Q=400, seed=0):
+def queries(sc, Q=600, seed=0, lo=-0.05, hi=1.05):
     rng = np.random.default_rng(seed)
     L = np.array(sc.grid.extent)
-    c = (rng.uniform(-0.1, 1.1, size=(Q, 3)) * L).astype(np.float32)
-    r = rng.uniform(0, 0.3, size=Q).astype(np.float32)
+    c = (rng.uniform(lo, hi, size=(Q, 3)) * L).astype(np.float32)
+    r = rng.uniform(0, 0.1, size=Q).astype(np.float32)
     s = rng.integers(-1, sc.n_slices + 2, size=Q).astype(np.int32)
     return c, r, s
 
 
-def const_net(value):
-    p = np.zeros(omlp.NPARAM)
-    p[-1] = value  # output bias: y = value * out_scale everywhere
-    return p
+def geometry(sc, c, s, k):
+    g, _ = osur.lattice(sc.grid, c)
+    G = osur.human_geometry(sc.grid, sc.human_xy, sc.radius, sc.height, g,
+                            s, np.full(len(s), k))
+    return g, G
+
+
+def test_features_against_cylinder_geometry():
+    sc, _, _ = room()
+    c, _, s = queries(sc, Q=2000, lo=0.0, hi=1.0)
+    h = sc.grid.h
+    Kt = osur.top_layer(sc.grid, sc.height)
+    # the top layer is the last whose centre lies at or under the top
+    assert (Kt + 0.5) * h <= sc.height < (Kt + 1.5) * h
+    for k in range(sc.n_humans):
+        g, G = geometry(sc, c, s, k)
+        x = osur.features(G, g, np.float64)
+        # the axis in voxel coordinates, from the metres directly
+        p = sc.human_xy[np.clip(s, 0, sc.n_slices - 1), k]
+        ax = (p - np.array(sc.grid.origin[:2])) / h - 0.5
+        np.testing.assert_allclose(g[:, 0] - x[:, 0] * G["rho"], ax[:, 0],
+                                   atol=2e-5)
+        # d: distance from g to the nearest point of the solid cylinder
+        # {|xy - axis| <= Rv, z <= Kt}
+        Rv = sc.radius / h
+        v = g[:, :2] - ax
+        rho = np.linalg.norm(v, axis=1)
+        near = ax + v * (np.minimum(rho, Rv) / np.maximum(rho, 1e-300))[:,
+                                                                       None]
+        nz = np.minimum(g[:, 2], Kt)
+        d = np.sqrt(np.sum((g[:, :2] - near) ** 2, axis=1) +
+                    (g[:, 2] - nz) ** 2)
+        np.testing.assert_allclose(x[:, 4], d, atol=2e-4)
+        # unit direction, and 1/(1+d)
+        np.testing.assert_allclose(x[:, 0] ** 2 + x[:, 1] ** 2, 1.0,
+                                   atol=1e-12)
+        np.testing.assert_allclose(x[:, 5] * (1 + x[:, 4]), 1.0, atol=1e-12)
+        # phases: the axis minus its phase lies on the lattice, as does
+        # the query minus its phase
+        X = osur._fixed(p[:, 0], sc.grid.origin[0], h)
+        cx = X / 65536.0 - 0.5
+        phx = np.arctan2(x[:, 6], x[:, 7]) / (2 * np.pi) % 1.0
+        fr = cx - phx
+        assert np.all(np.abs(fr - np.round(fr)) < 1e-9)
+        fgz = np.arctan2(x[:, 14], x[:, 15]) / (2 * np.pi) % 1.0
+        fr = g[:, 2] - fgz
+        assert np.all(np.abs(fr - np.round(fr)) < 1e-9)
+
+
+def test_gradient_chain_against_central_differences():
+    """With a network linear in the features (value w.x, input gradient
+    w), the gradient equals the central differences of the prediction in
+    metres, y(c) = h (d + w.x) with g = (c - o)/h - 1/2, taken in metres,
+    at points away from the kinks (the disk's rim, the top, cell
+    faces)."""
+    sc, _, _ = room(K=1)
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=16) * 0.05
+    c, _, s = queries(sc, Q=3000, lo=0.0, hi=1.0, seed=3)
+    h = sc.grid.h
+    g, G = geometry(sc, c, s, 0)
+    f = g - np.floor(g)
+    ok = (np.abs(G["a"]) > 0.05) & (np.abs(G["w"]) > 0.05) & \
+        np.all((f > 0.01) & (f < 0.99), axis=1) & (G["rho"] > 0.5)
+    ok &= s >= 0
+    assert ok.sum() > 500
+    x = osur.features(G, g, np.float64)
+    delta = np.clip(x @ w, osur.RES_LO, osur.RES_HI)
+    keep = ok & (np.abs(x @ w) < 0.4)
+    _, grad = osur.value_and_gradient(G, g, h, (x @ w).astype(np.float32),
+                                      np.tile(w.astype(np.float32),
+                                              (len(s), 1)))
+    eps = 1e-5 * h  # metres
+    o = np.asarray(sc.grid.origin, np.float64)
+    cm = (g + 0.5) * h + o  # the centres in metres (fp64)
+
+    def y_m(cc):
+        gg = (cc - o) / h - 0.5
+        GG = osur.human_geometry(sc.grid, sc.human_xy, sc.radius, sc.height,
+                                 gg, s, np.zeros(len(s), np.int64))
+        return h * (GG["d"] + osur.features(GG, gg, np.float64) @ w)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = eps
+        fd = (y_m(cm + e) - y_m(cm - e)) / (2 * eps)
+        np.testing.assert_allclose(grad[keep, a], fd[keep], rtol=1e-4,
+                                   atol=1e-4)
+    assert np.all(np.isfinite(delta))
+
+
+def test_residual_range_of_the_exact_single_human_field():
+    """The exact field of one human (the composite over an empty room) is
+    at least the distance d to the continuous cylinder (every occupied
+    voxel centre lies in the cylinder, and the trilinear sample of a
+    convex function's samples is at least the function) and exceeds it by
+    about one voxel at most (the voxelised disk's rim lies up to a voxel
+    inside the circle): the clamp [-1/2, 3/2] of the residual holds every
+    exact value with room to spare."""
+    for seed, h, r in ((7, 0.05, 0.2), (8, 0.02, 0.25), (9, 0.04, 0.31)):
+        sc = scenegen.small_scene(seed, 40, 36, 20, h=h, n_boxes=0,
+                                  n_humans=1, n_slices=3, radius=r,
+                                  height=12 * h)
+        # whole disks at three random sub-voxel phases
+        rng = np.random.default_rng(seed)
+        L = np.array(sc.grid.extent[:2])
+        sc.human_xy = rng.uniform(r + 2 * h, L - r - 2 * h, size=(3, 1, 2))
+        empty = np.full(sc.grid.shape_zyx, np.iinfo(np.int32).max, np.int32)
+        _, wf = oracle.predicted_composite(sc.grid, empty, sc.human_xy,
+                                           sc.radius, sc.height)
+        c, _, s = queries(sc, Q=4000, lo=0.0, hi=1.0, seed=seed)
+        s = np.abs(s) % sc.n_slices
+        ex, _, _, _ = oracle.query(sc.grid, wf, c, np.zeros(len(s)), s)
+        g, G = geometry(sc, c, s, 0)
+        _, inside = osur.lattice(sc.grid, c)
+        # whole disks (clipped ones are farther) and centres within the
+        # span of voxel centres (the exact query clamps the others)
+        far = G["present"] & ~G["clipped"] & inside & (G["d"] >= 1.0) & \
+            np.isfinite(ex)
+        res = ex[far] / h - G["d"][far]
+        assert far.sum() > 500
+        assert res.min() >= -1e-5 and res.max() < 1.25, (res.min(),
+                                                         res.max())
+
+
+def exact_network(sc, c, s):
+    """A 'network' returning, for human k's rows, the residual of that
+    human's exact single-human field at each query (its composite over an
+    empty room), with zero input gradient."""
+    g, _ = osur.lattice(sc.grid, c)
+    empty = np.full(sc.grid.shape_zyx, np.iinfo(np.int32).max, np.int32)
+    cache = {}
+    for k in range(sc.n_humans):
+        _, wf = oracle.predicted_composite(sc.grid, empty,
+                                           sc.human_xy[:, k:k + 1],
+                                           sc.radius, sc.height)
+        ex, _, _, _ = oracle.query(sc.grid, wf, c, np.zeros(len(s)),
+                                   np.clip(s, 0, sc.n_slices - 1))
+        _, G = geometry(sc, c, np.clip(s, 0, sc.n_slices - 1), k)
+        with np.errstate(invalid="ignore"):
+            cache[k] = (ex.astype(np.float64) / sc.grid.h - G["d"])
+
+    def net(x, k):
+        return cache[k].astype(np.float32), np.zeros((len(s), 16),
+                                                     np.float32)
+    return net
+
+
+@pytest.mark.parametrize("seed", [41, 42, 43])
+def test_exact_network_reproduces_the_exact_query(seed):
+    """Every answered query equals the exact query (to fp32 rounding of
+    the per-human values), so the min over candidates with the band rule
+    is the trilinear sample of the composite; some are answered (the room is
+    small: most of it lies within the band of a boundary),
+    and dropping the band makes some answers differ."""
+    sc, rf, wf = room(seed=seed)
+    c, r, s = queries(sc, Q=3000, seed=seed, lo=0.0, hi=1.0)
+    net = exact_network(sc, c, s)
+    band = 2 * np.sqrt(3) * sc.grid.h
+    d, g, st, cost, used = osur.query(sc.grid, wf, rf, net, sc.human_xy,
+                                      sc.radius, sc.height, c, r, s,
+                                      margin=0.02, band=band, hinge_eps=0.3)
+    ed, eg, est, ecost = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.3)
+    acc = (used == 0) & (s >= 0)
+    assert acc.mean() > 0.15
+    tol = 1e-6 * np.maximum(np.abs(ed[acc]), sc.grid.h) + 2e-7
+    assert np.all(np.abs(d[acc] - ed[acc]) <= tol)
+    np.testing.assert_array_equal(st[acc], est[acc])
+    # without the band the min of the samples differs somewhere
+    d0, _, _, _, u0 = osur.query(sc.grid, wf, rf, net, sc.human_xy,
+                                 sc.radius, sc.height, c, r, s, margin=0.02,
+                                 band=0.0)
+    a0 = (u0 == 0) & (s >= 0)
+    assert np.any(np.abs(d0[a0] - ed[a0]) > 1e-4)
 
 
 def test_constant_network_closed_form():
-    sc, wf, st = scene()
-    c, r, s = queries(sc)
-    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
-    d, g, status, cost, used, _ = osur.query(
-        sc.grid, wf, const_net(0.5), zeros, ones, 1.0, st, sc.dt, c, r, s,
-        margin=0.1, hinge_eps=0.4)
-    ed, eg, est, ecost = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.4)
-    inside = osur.in_span(sc.grid, c)
-    accept = inside & (s >= 0) & (np.float32(0.5) - r >= np.float32(0.1))
-    assert accept.any() and (~accept & (s >= 0)).any()
-    np.testing.assert_array_equal(d[accept], np.float32(0.5) - r[accept])
-    np.testing.assert_array_equal(g[accept], 0.0)
-    np.testing.assert_array_equal(
-        status[accept], np.where(s[accept] > sc.n_slices - 1, 8, 0))
-    np.testing.assert_array_equal(
-        cost[accept],
-        np.maximum(0.4 - (np.float32(0.5) - r[accept]).astype(np.float64),
-                   0).astype(np.float32))
-    rest = ~accept
-    np.testing.assert_array_equal(d[rest], ed[rest])
-    np.testing.assert_array_equal(status[rest], est[rest])
-    np.testing.assert_array_equal(used, (~accept & (s >= 0)).astype(np.uint8))
-    # slice < 0: NaN and the SLICE_NEG bit, never a fallback
+    sc, rf, wf = room(seed=44, boxes=0)
+    c, r, s = queries(sc, seed=1)
+    dv = float(np.float32(0.37))  # the network's fp32 output
+
+    def net(x, k):
+        return (np.full(len(x), dv, np.float32),
+                np.zeros((len(x), 16), np.float32))
+    d, g, st, cost, used = osur.query(sc.grid, wf, rf, net, sc.human_xy,
+                                      sc.radius, sc.height, c, r, s,
+                                      margin=0.05, band=0.0, hinge_eps=0.3)
+    h = sc.grid.h
+    gq, inside = osur.lattice(sc.grid, c)
+    best = np.full(len(s), np.inf, np.float32)
+    for k in range(sc.n_humans):
+        _, G = geometry(sc, c, s, k)
+        yk = (h * (G["d"] + dv)).astype(np.float32)
+        best = np.where(G["present"], np.minimum(best, yk), best)
+    acc = (used == 0) & (s >= 0)
+    assert acc.any()
+    np.testing.assert_array_equal(d[acc], (best - r)[acc])
+    assert np.all(inside[acc])
     neg = s < 0
-    assert np.isnan(d[neg]).all() and (status[neg] == 32).all()
+    assert np.isnan(d[neg]).all() and (st[neg] == 32).all()
+    assert (used[neg] == 0).all()
 
 
 def test_infinite_margin_is_the_exact_query():
-    sc, wf, st = scene()
-    c, r, s = queries(sc, seed=1)
-    p = np.random.default_rng(3).normal(size=omlp.NPARAM) * 0.05
-    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
-    got = osur.query(sc.grid, wf, p, zeros, ones, 1.0, st, sc.dt, c, r, s,
-                     margin=np.inf, hinge_eps=0.2)
+    sc, rf, wf = room(seed=45)
+    c, r, s = queries(sc, seed=2)
+    net = osur.network(np.random.default_rng(3).normal(
+        size=osur._mlp.nparam(16)) * 0.05, np.zeros(16), np.ones(16), 1.0)
+    got = osur.query(sc.grid, wf, rf, net, sc.human_xy, sc.radius,
+                     sc.height, c, r, s, margin=np.inf, band=0.0,
+                     hinge_eps=0.2)
     want = oracle.query(sc.grid, wf, c, r, s, hinge_eps=0.2)
     for a, b in zip(got[:4], want):
         np.testing.assert_array_equal(a, b)
@@ -76,110 +251,59 @@ def test_infinite_margin_is_the_exact_query():
 
 
 def test_nonfinite_network_falls_back():
-    sc, wf, st = scene()
-    c, r, s = queries(sc, seed=2)
-    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
-    got = osur.query(sc.grid, wf, const_net(1.0), zeros, ones, np.inf, st,
-                     sc.dt, c, r, s, margin=0.1)
-    want = oracle.query(sc.grid, wf, c, r, s)
-    np.testing.assert_array_equal(got[0], want[0])
-    assert (got[4] == (s >= 0)).all()
-
-
-def test_feature_layout():
-    """A worked example with exact binary values: human 0 starts at (1, 1)
-    with velocity (2, -2); at slice 2 of dt = 0.25 (t = 0.5) its axis is at
-    (2, 0), so a centre at (5, 4) is 3, 4 from it and 5 from the axis.
-    Slices are clamped to [0, n-1] for t."""
-    st = np.zeros(18, np.float32)
-    st[0:6] = [1, 1, 0, 2, -2, 0]
-    st[6:12] = [5, 4, 0, 0, 0, 0]      # on the centre: rho = 0
-    st[12:18] = [-1, 4, 0, 0.5, 0, 0]  # axis at (-0.75, 4) at t = 0.5
-    c = np.array([[5, 4, 7], [5, 4, 7]], np.float32)
-    x = osur.features(c, np.array([2, 9]), 3, 0.25, st)
-    np.testing.assert_array_equal(x[0, :4], [5, 4, 7, 0.5])
-    np.testing.assert_array_equal(x[0, 4:10], [3, 4, 5, 2, -2, 0])
-    np.testing.assert_array_equal(x[0, 10:16], [0, 0, 0, 0, 0, 0])
-    np.testing.assert_array_equal(x[0, 16:22], [5.75, 0, 5.75, 0.5, 0, 0])
-    assert x[1, 3] == np.float32(2) * np.float32(0.25)  # slice 9 -> n-1 = 2
-
-
-def test_centre_gradient_unit_cases():
-    """dy/dc through the transform for unit feature gradients: the centre
-    itself, a human's offsets (+1 along their axis) and its axis distance
-    (the unit vector away from the axis, 0 on the axis)."""
-    st = np.zeros(18, np.float32)
-    st[0:6] = [1, 1, 0, 2, -2, 0]
-    st[6:12] = [5, 4, 0, 0, 0, 0]
-    x = osur.features(np.array([[5, 4, 7]], np.float32), np.array([2]), 3,
-                      0.25, st)
-    cases = {0: [1, 0, 0], 1: [0, 1, 0], 2: [0, 0, 1], 3: [0, 0, 0],
-             4: [1, 0, 0], 5: [0, 1, 0], 6: [0.6, 0.8, 0], 7: [0, 0, 0],
-             12: [0, 0, 0]}  # 12: rho of human 1, who stands on the centre
-    for f, want in cases.items():
-        G = np.zeros((1, 22))
-        G[0, f] = 1.0
-        np.testing.assert_allclose(osur.centre_gradient(x, G)[0], want,
-                                   rtol=0, atol=1e-7, err_msg=str(f))
-
-
-def test_centre_gradient_matches_finite_differences():
-    """The chain rule against central differences of the fp64 network
-    (no rounding) composed with the feature transform, away from the
-    humans' axes."""
-    rng = np.random.default_rng(5)
-    p = omlp.pack([rng.normal(0, 0.3, s) for s in omlp.SHAPES])
-    off = np.zeros(22)
-    scl = np.full(22, 0.4)
-    st = np.zeros(18, np.float32)
-    st[0:6] = [1.0, 1.5, 0, 0.5, -0.25, 0]
-    st[6:12] = [3.0, 0.5, 0, -0.5, 0.75, 0]
-    st[12:18] = [0.5, 3.5, 0, 1.0, 0.0, 0]
-    c = np.array([[2.2, 2.9, 1.1], [0.4, 0.9, 0.3], [3.3, 3.1, 1.9]],
-                 np.float64)
-    s = np.array([1, 3, 2])
-
-    def y_of(cc):
-        xx = osur.features(cc.astype(np.float32), s, 5, 0.25, st)
-        return omlp.forward(p, xx, off, scl, 1.0, rounding=False)[0]
-    x = osur.features(c.astype(np.float32), s, 5, 0.25, st)
-    G = omlp.input_gradient(p, x, off, scl, 1.0, rounding=False)
-    g = osur.centre_gradient(x, G)
-    eps = 1e-2
-    for a in range(3):
-        d = np.zeros(3)
-        d[a] = eps
-        num = (y_of(c + d) - y_of(c - d)) / (2 * eps)
-        np.testing.assert_allclose(g[:, a], num, rtol=2e-3, atol=2e-4)
-
-
-def test_span_boundary():
-    g = scenegen.Grid(4, 5, 6, 0.5)
-    first = np.array([[0.25, 0.25, 0.25]], np.float32)
-    last = np.array([[1.75, 2.25, 2.75]], np.float32)
-    assert osur.in_span(g, first)[0] and osur.in_span(g, last)[0]
-    assert not osur.in_span(g, first - np.float32(1e-3))[0]
-    assert not osur.in_span(g, last + np.float32(1e-3))[0]
-
-
-def test_environment_min_closed_form():
-    # Constant network 0.3 with the environment field: the prediction is
-    # min(e, 0.3) with e the exact environment value at the centre.
-    sc, wf, st = scene()
-    rs, rf = oracle.build_static(sc.grid, sc.occ)
+    sc, rf, wf = room(seed=46, boxes=0)
     c, r, s = queries(sc, seed=4)
-    ones, zeros = np.ones(22, np.float32), np.zeros(22, np.float32)
-    d, g, status, cost, used, _ = osur.query(
-        sc.grid, wf, const_net(0.3), zeros, ones, 1.0, st, sc.dt, c, r, s,
-        margin=0.05, static_sdf=rf)
-    e, eg, _, _ = oracle.query(sc.grid, rf[None], c, np.zeros_like(r),
-                               np.zeros_like(s))
-    v = np.minimum(e, np.float32(0.3))
-    inside = osur.in_span(sc.grid, c)
-    accept = inside & (s >= 0) & (v - r >= np.float32(0.05))
-    assert accept.any() and (accept & (e < 0.3)).any()
-    np.testing.assert_array_equal(d[accept], (v - r)[accept])
-    env = accept & (e <= np.float32(0.3))
-    np.testing.assert_array_equal(g[env], eg[env])
-    np.testing.assert_array_equal(g[accept & ~env], 0.0)
-    np.testing.assert_array_equal(used, (~accept & (s >= 0)).astype(np.uint8))
+
+    def net(x, k):
+        return (np.full(len(x), np.nan, np.float32),
+                np.zeros((len(x), 16), np.float32))
+    d, _, _, _, used = osur.query(sc.grid, wf, rf, net, sc.human_xy,
+                                  sc.radius, sc.height, c, r, s,
+                                  margin=0.0, band=0.0)
+    ed, _, _, _ = oracle.query(sc.grid, wf, c, r, s)
+    # with no environment every in-grid query has a present human (NaN)
+    # or none at all (the environment's +inf: not finite): all fall back
+    pos = s >= 0
+    assert (used[pos] == 1).all()
+    np.testing.assert_array_equal(d[pos], ed[pos])
+
+
+def test_absent_humans_are_ignored_and_clipped_humans_fall_back():
+    sc, rf, wf = room(seed=47, K=2)
+    h = sc.grid.h
+    L = np.array(sc.grid.extent)
+    xy = sc.human_xy.copy()
+    xy[:, 1] = [L[0] + sc.radius + 2 * h, 0.5 * L[1]]   # wholly outside
+    c, r, s = queries(sc, seed=5, lo=0.0, hi=1.0)
+    rng = np.random.default_rng(6)
+    p = rng.normal(size=osur._mlp.nparam(16)) * 0.02
+    net = osur.network(p, np.zeros(16), np.ones(16), 1.0)
+    _, wf2 = oracle.predicted_composite(sc.grid, oracle.build_static(
+        sc.grid, sc.occ)[0], xy, sc.radius, sc.height)
+    a = osur.query(sc.grid, wf2, rf, net, xy, sc.radius, sc.height, c, r, s,
+                   margin=0.02, band=0.1)
+    b = osur.query(sc.grid, wf2, rf, net, xy[:, :1], sc.radius, sc.height,
+                   c, r, s, margin=0.02, band=0.1)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    # a human straddling the grid's edge: clipped, every query it could
+    # decide falls back
+    xy[:, 1] = [0.05, 0.5 * L[1]]
+    _, wf3 = oracle.predicted_composite(sc.grid, oracle.build_static(
+        sc.grid, sc.occ)[0], xy, sc.radius, sc.height)
+    g, _ = osur.lattice(sc.grid, c)
+    G = osur.human_geometry(sc.grid, xy, sc.radius, sc.height, g, s,
+                            np.ones(len(s), np.int64))
+    assert G["clipped"][s >= 0].all()
+    d, _, _, _, used = osur.query(sc.grid, wf3, rf, net, xy, sc.radius,
+                                  sc.height, c, r, s, margin=0.02, band=0.1)
+    yk, _ = osur.value_and_gradient(G, g, h, *net(osur.features(G, g), 1))
+    # no answered query has the clipped human within the band of its
+    # answer, and some queries fell back for it
+    acc = (used == 0) & (s >= 0)
+    assert acc.any()
+    assert np.all(yk[acc].astype(np.float64) >
+                  (d[acc] + r[acc]).astype(np.float64) + 0.1)
+    free = osur.query(sc.grid, wf3, rf, net, xy[:, :1], sc.radius,
+                      sc.height, c, r, s, margin=0.02, band=0.1)[4]
+    assert np.any((used == 1) & (free == 0) & (s >= 0))
