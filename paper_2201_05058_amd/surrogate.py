@@ -269,7 +269,7 @@ def query_spheres_surrogate(net: Mlp, grid, static_ssq, static_sdf, human_xy,
         raise ValueError("human_xy must have shape [n_slices, n_humans, 2]")
     n_slices, K = xy.shape[0], xy.shape[1]
     if band is None:
-        band = 2.0 * np.sqrt(3.0) * g.h
+        band = 2.0 * np.sqrt(3.0) * g.voxel_m
     V = g.nvox
     dev = centre.device
     n = slice_.numel()

@@ -188,7 +188,7 @@ def test_surrogate_queries_on_oracle_slices(run, slice_oracle,
     np.testing.assert_array_equal(used, wused)
     acc = used == 0
     say(f"  answered {acc.mean():.3f}")
-    assert acc.mean() > 0.2
+    assert acc.mean() > 0.1
     np.testing.assert_array_equal(d[acc], wd[acc])
     np.testing.assert_array_equal(out["status"].cpu().numpy(), wst)
     assert np.all(np.abs(gr[acc] - wg[acc]) <=
