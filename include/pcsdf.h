@@ -319,6 +319,12 @@ typedef struct pcsdf_tuning {
                                          (one wave each) per column, 1, 2,
                                          4 or 8; 0: one per 32 voxels of
                                          the column, at most 8 */
+  int32_t composite_order;            /* composite: 0 (default) blocks in
+                                         flight write the same few slices
+                                         over consecutive voxel chunks; 1
+                                         the slice groups of a chunk run in
+                                         succession on one XCD and re-read
+                                         its static values from L2 */
 } pcsdf_tuning;
 
 int pcsdf_set_tuning(pcsdf_handle *h, const pcsdf_tuning *t);
@@ -359,7 +365,8 @@ void pcsdf_batch_graph_destroy(pcsdf_batch_graph *g);
  * runs each after a warm-up run; host work between calls does not count),
  * store the fastest in the handle's tuning and return it with its time in
  * milliseconds per run.  The composite tuner makes three interleaved
- * rounds over its slice groups and keeps each group's fastest round.
+ * rounds over its slice groups in both block orders and keeps each
+ * candidate's fastest round.
  * Outputs are written as by the tuned call.  They synchronise with the
  * device and leave the handle's profiling state and totals unchanged. */
 int pcsdf_autotune_batch(pcsdf_handle *h, int32_t n_scenes,

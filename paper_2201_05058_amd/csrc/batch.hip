@@ -365,8 +365,9 @@ extern "C" int pcsdf_autotune_composite(pcsdf_handle *hp,
   pcsdf_tuning win = base;
   double win_ms = -1.0;
   const int n = sc->n_slices;
-  constexpr int kCand = 7;
-  const int Gs[kCand] = {1, 2, 3, 4, 5, 10, n};
+  // slice groups in both block orders
+  constexpr int kG = 7, kCand = 2 * kG;
+  const int Gs[kG] = {1, 2, 3, 4, 5, 10, n};
   double best_of[kCand];
   for (int c = 0; c < kCand; ++c) best_of[c] = -1.0;
   // Three interleaved rounds over the candidates, each keeping its fastest
@@ -374,14 +375,15 @@ extern "C" int pcsdf_autotune_composite(pcsdf_handle *hp,
   // than the drift of a single pass.
   for (int round = 0; round < 3; ++round)
     for (int c = 0; c < kCand; ++c) {
-      const int G = Gs[c];
+      const int G = Gs[c % kG];
       bool seen = false;  // n may repeat an earlier candidate
-      for (int e = 0; e < c; ++e) seen = seen || Gs[e] == G;
+      for (int e = 0; e < c % kG; ++e) seen = seen || Gs[e] == G;
       if (G < 1 || G > n || seen) continue;
       h->tuning = base;
       h->tuning.composite_slices_per_block = G;
-      // the composite kernel alone: the slice group changes nothing else,
-      // and a call's wall time can be the host's
+      h->tuning.composite_order = c / kG;
+      // the composite kernel alone: the slice group and the block order
+      // change nothing else, and a call's wall time can be the host's
       const double ms = kernel_ms(
           h, PCSDF_KERNEL_COMPOSITE, reinterpret_cast<hipStream_t>(stream),
           reps, [&] {
@@ -401,7 +403,8 @@ extern "C" int pcsdf_autotune_composite(pcsdf_handle *hp,
     if (win_ms < 0 || best_of[c] < win_ms) {
       win_ms = best_of[c];
       win = base;
-      win.composite_slices_per_block = Gs[c];
+      win.composite_slices_per_block = Gs[c % kG];
+      win.composite_order = c / kG;
     }
   }
   h->tuning = win;

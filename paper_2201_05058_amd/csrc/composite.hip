@@ -50,11 +50,30 @@ __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     const int32_t *__restrict__ need,
     int32_t *__restrict__ oc, float *__restrict__ of, uint32_t plane,
-    int n_slices, int G, int Kt, int has_above, float hf, uint32_t V) {
-  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    int n_slices, int G, int Kt, int has_above, float hf, uint32_t V,
+    int order) {
+  // order 0: block (chunk, group) = (blockIdx.x, blockIdx.y), so the
+  // blocks in flight write the same few slices over consecutive chunks.
+  // order 1 (one-dimensional grid): blocks 8 apart take chunks x, x + 8,
+  // ... (x = block mod 8) and, for each, its slice groups one after the
+  // other.  The dispatcher places block b on XCD b mod 8, so the groups of
+  // a chunk run on one XCD in close succession and re-read the chunk's
+  // static field from that XCD's L2 rather than from HBM; in exchange the
+  // blocks in flight write every slice at once.
+  uint32_t chunk, grp;
+  if (order) {
+    const uint32_t ng = (uint32_t)((n_slices + G - 1) / G);
+    const uint32_t j = blockIdx.x >> 3, cj = j / ng;
+    grp = j - cj * ng;
+    chunk = cj * 8 + (blockIdx.x & 7);
+  } else {
+    chunk = blockIdx.x;
+    grp = blockIdx.y;
+  }
+  const uint32_t g = chunk * 256u + threadIdx.x;
   const uint32_t v0 = g * VEC;
   if (v0 >= V) return;
-  const int s_begin = (int)blockIdx.y * G;
+  const int s_begin = (int)grp * G;
   const int s_end = min(n_slices, s_begin + G);
   if (need) {  // skip the static read when none of the block's slices is due
     bool any = false;
@@ -75,16 +94,24 @@ static void launch_comp(Handle *h, const int32_t *S, const int32_t *P,
                         uint32_t plane, int n, int G, int Kt, int has_above,
                         float hf, uint32_t V, hipStream_t s) {
   const uint32_t nthreads = V / VEC;
-  const dim3 grid((nthreads + 255) / 256, (n + G - 1) / G), block(256);
+  const uint64_t chunks = (nthreads + 255) / 256, ng = (n + G - 1) / G;
+  const uint64_t flat = (chunks + 7) / 8 * 8 * ng;
+  const int order = h->tuning.composite_order == 1 && flat < (1ull << 31);
+  const dim3 grid = order ? dim3((unsigned)flat) : dim3((unsigned)chunks,
+                                                        (unsigned)ng);
+  const dim3 block(256);
   if (oc && of)
     launch_timed(h, k_composite<VEC, kGather, true, true>, grid, block, 0u,
-                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
+                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V,
+                 order);
   else if (oc)
     launch_timed(h, k_composite<VEC, kGather, true, false>, grid, block, 0u,
-                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
+                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V,
+                 order);
   else
     launch_timed(h, k_composite<VEC, kGather, false, true>, grid, block, 0u,
-                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V);
+                 s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V,
+                 order);
 }
 
 // The same composite over the flattened outputs [n][V] in aligned packs of

@@ -173,10 +173,20 @@ __device__ __forceinline__ typename Pack<VEC>::I load_planar(
   }
 }
 
+// Slices whose planar packs one lane loads before it stores any of them.
+constexpr int kPackSlices = 8;
+
 // Voxels v0 .. v0+VEC-1 (v0 a multiple of VEC, all in [0, V)) for slices
 // [s_begin, s_end); with kNeed, slices with need[sl] == 0 are skipped (a
-// template parameter so that without it the stores are unconditional and
-// the compiler counts the waits exactly).
+// template parameter so that without it the stores are unconditional).
+//
+// One counter tracks a wave's outstanding vector loads and stores in issue
+// order, so a load issued after a store can only be waited for together
+// with that store.  The lane therefore issues the static load and the
+// planar loads of up to kPackSlices slices first, and only then computes
+// and stores them, so that no load waits behind the lane's own stores.
+// (Longer slice groups still measure slower than groups of two or three:
+// the blocks in flight then write more slices' outputs at once.)
 template <int VEC, bool kGather, bool kSsq, bool kSdf, bool kNeed = false>
 __device__ __forceinline__ void composite_pack(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
@@ -198,24 +208,30 @@ __device__ __forceinline__ void composite_pack(
   }
   // V <= 2^30, so byte offsets within one slice fit in 32 bits.
   const uint32_t vb = v0 * 4u;
-  // A short loop (the tuned slice groups are 2 or 3 slices): loading the
-  // next slice's planar pack ahead of the stores was measured slower than
-  // the waits it avoids.
   const typename Pack<VEC>::I s = load_i32<VEC>(at_bytes(S, vb));
-  for (int sl = s_begin; sl < s_end; ++sl) {
-    if (kNeed && need[sl] == 0) continue;
-    const typename Pack<VEC>::I p =
-        load_planar<VEC, kGather>(P + (size_t)sl * plane, pc);
-    typename Pack<VEC>::I c;
+  for (int sl0 = s_begin; sl0 < s_end; sl0 += kPackSlices) {
+    const int cnt = min(kPackSlices, s_end - sl0);
+    typename Pack<VEC>::I p[kPackSlices];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      c[e] = min(s[e], human_value(p[e], hl[kGather ? e : 0]));
-    if (kSsq) store_i32<VEC>(at_bytes(oc + (size_t)sl * V, vb), c);
-    if (kSdf) {
-      typename Pack<VEC>::F f;
+    for (int j = 0; j < kPackSlices; ++j)
+      if (j < cnt && !(kNeed && need[sl0 + j] == 0))
+        p[j] = load_planar<VEC, kGather>(P + (size_t)(sl0 + j) * plane, pc);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) f[e] = ssq_to_metres(c[e], hf);
-      store_f32<VEC>(at_bytes(of + (size_t)sl * V, vb), f);
+    for (int j = 0; j < kPackSlices; ++j) {
+      if (j >= cnt) break;
+      const int sl = sl0 + j;
+      if (kNeed && need[sl] == 0) continue;
+      typename Pack<VEC>::I c;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        c[e] = min(s[e], human_value(p[j][e], hl[kGather ? e : 0]));
+      if (kSsq) store_i32<VEC>(at_bytes(oc + (size_t)sl * V, vb), c);
+      if (kSdf) {
+        typename Pack<VEC>::F f;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) f[e] = ssq_to_metres(c[e], hf);
+        store_f32<VEC>(at_bytes(of + (size_t)sl * V, vb), f);
+      }
     }
   }
 }

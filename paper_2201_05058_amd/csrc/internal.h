@@ -42,7 +42,7 @@ struct Handle {
   DevBuf union_buf;     // full recompute: uint8 union map of one slice
   DevBuf tmpl_buf;      // shifted-template composite: per-human windows
   std::vector<char> batch_host;  // batch parameter block before upload
-  pcsdf_tuning tuning = {0, 0, 0, 0};  // launch shapes; 0 = default
+  pcsdf_tuning tuning = {};  // launch shapes; 0 = default
   // pinned host staging for small per-call parameter blocks: a ring of
   // slots, so that a call only waits for the upload made kStagingSlots
   // calls before it

@@ -295,16 +295,20 @@ def test_composite_room256_full(pc, dev, room256_ref):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("G", [1, 3, 5, 10, 20])
-def test_composite_room256_every_slice_group(pc, dev, room256_ref, G):
+@pytest.mark.parametrize("G,order", [(1, 0), (3, 0), (5, 0), (10, 0),
+                                     (20, 0), (1, 1), (2, 1), (3, 1),
+                                     (20, 1)])
+def test_composite_room256_every_slice_group(pc, dev, room256_ref, G, order):
     """The same workload in the other launch shapes the autotuner chooses
-    between (slices per block row): the oracle's bytes in each."""
+    between (slices per block row, block order): the oracle's bytes in
+    each."""
     sc, wc, wf = room256_ref
-    say(f"composite room256 with {G} slices per block row")
+    say(f"composite room256 with {G} slices per block row, order {order}")
     occ_d = to_dev(sc.occ.astype(np.uint8), dev)
     h = pc.Handle()
     try:
-        h.set_tuning({"composite_slices_per_block": G})
+        h.set_tuning({"composite_slices_per_block": G,
+                      "composite_order": order})
         ssq_s, _ = pc.build_static_sdf(sc.grid, occ_d, want_sdf=False,
                                        handle=h)
         c, cf = pc.predicted_composite_sdf(sc.grid, ssq_s, sc.human_xy,
