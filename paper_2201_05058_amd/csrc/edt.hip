@@ -276,16 +276,22 @@ __global__ __launch_bounds__(64) void k_pass_col(
 // Column values read per batch of loads in the segmented pass.
 constexpr int kSegBatch = 16;
 
-template <int S, bool kWriteSdf>
+//
+// With kOutside, every lane runs the occupied set's channel (64 adjacent
+// columns per wave) and the free set's channel, which only the occupied
+// voxels need, is left to k_pass_col_search: a column's LDS then serves
+// twice the columns.
+template <int S, bool kWriteSdf, bool kOutside>
 __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     const int32_t *__restrict__ in, int32_t *__restrict__ out,
     float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
     int64_t outer_stride, int64_t nblocks, int tiles) {
   extern __shared__ uint32_t lds_seg[];
+  constexpr int kCols = kOutside ? 64 : 32;  // columns per wave
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int col = lane & 31;
-  const bool inside_ch = lane >= 32;  // channel of the free set
+  const int col = kOutside ? lane : lane & 31;
+  const bool inside_ch = !kOutside && lane >= 32;  // the free set's channel
   const int L = (m + S - 1) / S;
   uint32_t *const stacks = lds_seg;                       // [S][L][64]
   int *const tops = reinterpret_cast<int *>(lds_seg + (size_t)S * L * 64);
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
   for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
     const int64_t o = b / tiles;
     const int tile = (int)(b - o * tiles);
-    const int i = tile * 32 + col;
+    const int i = tile * kCols + col;
     const bool active = i < nfast;
     const int32_t *src = in + o * outer_stride + (active ? i : 0);
     int32_t *dst = out + o * outer_stride + (active ? i : 0);
@@ -418,20 +424,27 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
 // searching p = q -+ d for d = 1, 2, ... until d^2 >= the best value so
 // far (no farther p can be smaller, f >= 0).  Exact, like the envelope;
 // its work grows with the distance found, so it is kept to small passes.
-template <bool kWriteSdf>
+//
+// With kInsideOnly only the occupied voxels are computed (the free set's
+// channel, beside k_pass_col_seg's occupied-set channel); the distances
+// found there are bounded by the obstacles' half-widths.  Grid: (voxels
+// of one outer index / 256, outer indices).
+constexpr int kSearchBatch = 4;
+
+template <bool kWriteSdf, bool kInsideOnly>
 __global__ __launch_bounds__(256) void k_pass_col_search(
     const int32_t *__restrict__ in, int32_t *__restrict__ out,
     float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
-    int64_t outer_stride, int64_t total) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= total) return;
-  const int i = (int)(t % nfast);
-  const int64_t rest = t / nfast;
-  const int q = (int)(rest % m);
-  const int64_t o = rest / m;
+    int64_t outer_stride) {
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (uint32_t)nfast * (uint32_t)m) return;
+  const int q = (int)(t / (uint32_t)nfast);
+  const int i = (int)(t - (uint32_t)q * (uint32_t)nfast);
+  const int64_t o = blockIdx.y;
   const int32_t *src = in + o * outer_stride + i;
   const int32_t x = src[(int64_t)q * stride];
   const bool inside = x < 0;  // occupied: the free set's channel
+  if (kInsideOnly && !inside) return;
   // value of row p in this voxel's channel (kInf: no site in that row)
   auto f_of = [&](int32_t v) -> int32_t {
     if (!inside) return v == kInf ? kInf : (v > 0 ? v : 0);
@@ -439,16 +452,26 @@ __global__ __launch_bounds__(256) void k_pass_col_search(
   };
   int32_t best = f_of(x);
   const int dmax = max(q, m - 1 - q);
-  for (int d = 1; d <= dmax; ++d) {
-    const int32_t d2 = d * d;
-    if (d2 >= best) break;
-    if (q - d >= 0) {
-      const int32_t f = f_of(src[(int64_t)(q - d) * stride]);
-      if (f != kInf) best = min(best, d2 + f);
+  // kSearchBatch distances per step: their loads are issued together, so
+  // a step costs one memory latency (rows past the stopping distance are
+  // read and cannot lower the value: d^2 >= best there).
+  for (int d0 = 1; d0 <= dmax; d0 += kSearchBatch) {
+    if (d0 * d0 >= best) break;
+    int32_t lo[kSearchBatch], hi[kSearchBatch];
+#pragma unroll
+    for (int u = 0; u < kSearchBatch; ++u) {
+      const int d = d0 + u;
+      lo[u] = q - d >= 0 ? src[(int64_t)(q - d) * stride] : kInf;
+      hi[u] = q + d < m ? src[(int64_t)(q + d) * stride] : kInf;
     }
-    if (q + d < m) {
-      const int32_t f = f_of(src[(int64_t)(q + d) * stride]);
-      if (f != kInf) best = min(best, d2 + f);
+#pragma unroll
+    for (int u = 0; u < kSearchBatch; ++u) {
+      const int d = d0 + u;
+      const int32_t d2 = d * d;
+      const int32_t fl = q - d >= 0 ? f_of(lo[u]) : kInf;
+      const int32_t fh = q + d < m ? f_of(hi[u]) : kInf;
+      if (fl != kInf) best = min(best, d2 + fl);
+      if (fh != kInf) best = min(best, d2 + fh);
     }
   }
   const int32_t v = inside ? (best == kInf ? -kInf : -best) : best;
@@ -481,18 +504,20 @@ static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
       (unsigned)(nblocks < (1LL << 30) ? nblocks : (1LL << 30));
   if (sdf_out) {
     const hipError_t e =
-        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, true>),
+        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, true, true>),
                   lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, true>), dim3(grid), dim3(64 * S),
+    hipLaunchKernelGGL((k_pass_col_seg<S, true, true>), dim3(grid),
+                       dim3(64 * S),
                        lds, s, in, out, sdf_out, h_f, nfast, m, stride,
                        outer_stride, nblocks, tiles);
   } else {
     const hipError_t e =
-        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, false>),
+        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, false, true>),
                   lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, false>), dim3(grid), dim3(64 * S),
+    hipLaunchKernelGGL((k_pass_col_seg<S, false, true>), dim3(grid),
+                       dim3(64 * S),
                        lds, s, in, out, sdf_out, h_f, nfast, m, stride,
                        outer_stride, nblocks, tiles);
   }
@@ -513,17 +538,18 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   if (nfast <= 0 || nouter <= 0 || m <= 0) return PCSDF_OK;
   const int tiles = (nfast + 31) / 32;
   const int64_t nblocks = (int64_t)tiles * nouter;
+  // the search kernel's grid: (nfast m / 256, nouter); nfast, m <= 1024
+  const dim3 sgrid((unsigned)(((int64_t)nfast * m + 255) / 256),
+                   (unsigned)nouter);
   if (nblocks < kSearchTiles && h->tuning.static_segments == 0) {
-    const int64_t total = (int64_t)nfast * m * nouter;
-    const unsigned grid = (unsigned)((total + 255) / 256);
     if (sdf_out)
-      hipLaunchKernelGGL((k_pass_col_search<true>), dim3(grid), dim3(256), 0,
-                         s, in, out, sdf_out, h_f, nfast, m, stride,
-                         outer_stride, total);
-    else
-      hipLaunchKernelGGL((k_pass_col_search<false>), dim3(grid), dim3(256),
+      hipLaunchKernelGGL((k_pass_col_search<true, false>), sgrid, dim3(256),
                          0, s, in, out, sdf_out, h_f, nfast, m, stride,
-                         outer_stride, total);
+                         outer_stride);
+    else
+      hipLaunchKernelGGL((k_pass_col_search<false, false>), sgrid,
+                         dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
+                         stride, outer_stride);
     return check_launch(h, "pass_col_search");
   }
   int S = column_segments(h, m);
@@ -532,26 +558,40 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
     const int L = (m + S - 1) / S;
     const size_t lds_seg = ((size_t)S * L * 64 + (size_t)S * 64) * 4;
     if ((int64_t)lds_seg <= h->max_lds) {
+      // the occupied set's channel by envelopes, 64 columns per wave; then
+      // the free set's channel of the occupied voxels by search
+      const int tiles64 = (nfast + 63) / 64;
+      const int64_t nblocks64 = (int64_t)tiles64 * nouter;
       hipError_t e;
       switch (S) {
         case 2:
           e = launch_seg<2>(in, out, sdf_out, h_f, nfast, m, stride,
-                            outer_stride, nblocks, tiles, lds_seg, s);
+                            outer_stride, nblocks64, tiles64, lds_seg, s);
           break;
         case 4:
           e = launch_seg<4>(in, out, sdf_out, h_f, nfast, m, stride,
-                            outer_stride, nblocks, tiles, lds_seg, s);
+                            outer_stride, nblocks64, tiles64, lds_seg, s);
           break;
         default:
           e = launch_seg<8>(in, out, sdf_out, h_f, nfast, m, stride,
-                            outer_stride, nblocks, tiles, lds_seg, s);
+                            outer_stride, nblocks64, tiles64, lds_seg, s);
           break;
       }
       if (e != hipSuccess)
         return fail(h, PCSDF_ERR_HIP,
                     std::string("raising the LDS limit of pass_col_seg: ") +
                         hipGetErrorString(e));
-      return check_launch(h, "pass_col_seg");
+      int rc = check_launch(h, "pass_col_seg");
+      if (rc) return rc;
+      if (sdf_out)
+        hipLaunchKernelGGL((k_pass_col_search<true, true>), sgrid, dim3(256),
+                           0, s, in, out, sdf_out, h_f, nfast, m, stride,
+                           outer_stride);
+      else
+        hipLaunchKernelGGL((k_pass_col_search<false, true>), sgrid,
+                           dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
+                           stride, outer_stride);
+      return check_launch(h, "pass_col_inside");
     }
   }
   const size_t lds = (size_t)m * 64 * sizeof(uint32_t);
