@@ -66,21 +66,10 @@ def source_hash(path: str) -> str:
 
 
 def composite_outputs(torch, n, shape_zyx, dev):
-    """The int32 and fp32 fields [n, nz, ny, nx] in one allocation, the fp32
-    field starting 4 KiB past the end of the int32 one.  Two output streams
-    whose starts differ by a multiple of 8 KiB (as two separate large
-    allocations do) write measurably more slowly on this GPU; the layout is
-    the caller's choice.  The fp32 field keeps the alignment the library's
-    pack width for these dimensions asks for (16 B when V is a multiple of
-    4, 8 B when it is even)."""
-    cnt = n
-    for d in shape_zyx:
-        cnt *= d
-    pad = 1024  # int32 elements: 4 KiB
-    buf = torch.empty(2 * cnt + pad, dtype=torch.int32, device=dev)
-    oc = buf[:cnt].view((n,) + tuple(shape_zyx))
-    of = buf[cnt + pad:].view(torch.float32).view((n,) + tuple(shape_zyx))
-    return oc, of
+    """The composite calls' default output layout (the package's
+    composite_outputs: both fields in one allocation, 4 KiB apart)."""
+    import paper_2201_05058_amd as pc
+    return pc.composite_outputs(n, shape_zyx, dev)
 
 
 def traffic_from(prof_dir: str, V: int, n: int) -> dict:
@@ -595,6 +584,65 @@ def surrogate_section(pc, torch, dev, room: str, weights: str):
     return res
 
 
+def hbm_ceilings(mib: int = 1024, reps: int = 20):
+    """Plain torch kernels on buffers of `mib` MiB: fill (write only), sum
+    (read only) and copy, best of `reps` timed with CUDA events: the
+    bandwidths a streaming kernel can reach on this GPU."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    out = {"buffer_bytes": n * 4}
+    cases = {"write_fill": (lambda: a.fill_(1.0), n * 4),
+             "read_sum": (lambda: a.sum(), n * 4),
+             "copy": (lambda: b.copy_(a), 2 * n * 4)}
+    for name, (fn, nbytes) in cases.items():
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name + "_gbs"] = nbytes / (best / 1e3) / 1e9
+    print(json.dumps(out))
+
+
+def mlp_rows(n: int, weights: str, reps: int = 10):
+    """The fused surrogate network (value and input gradient) on n seeded
+    rows of its 16 features, kernel time by the library's HIP events."""
+    import numpy as np
+    import torch
+    from paper_2201_05058_amd import _native, train
+    torch.cuda.set_device(0)
+    net, _ = train.load(weights)
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(
+        (rng.normal(size=(n, net.n_in)) * 3).astype(np.float32)).cuda()
+    net.forward(x)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(3):
+        net.h.profile(True, only=[_native.KERNEL_MLP])
+        net.h.profile_reset()
+        for _ in range(reps):
+            net.forward(x)
+        torch.cuda.synchronize()
+        ms = net.h.profile_read(_native.KERNEL_MLP)[0] / reps
+        best = ms if best is None else min(best, ms)
+    net.h.profile(False)
+    flop = 205056 * n
+    print(json.dumps({"mlp_rows": n, "kernel": "k_mlp_infer", "ms": best,
+                      "tflops": flop / (best / 1e3) / 1e12,
+                      "frac_bf16_dense": flop / (best / 1e3) / 2.5e15}))
+    net.close()
+
+
 def calibrate_copy(mib: int, reps: int):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -620,6 +668,11 @@ def main():
     ap.add_argument("--cpu-omp-slices", type=int, default=4,
                     help="slices of the all-core oracle sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
+    ap.add_argument("--hbm-ceilings", action="store_true",
+                    help="measure fill, sum and copy bandwidths and exit")
+    ap.add_argument("--mlp-rows", type=int, default=0,
+                    help="time the fused surrogate network on this many "
+                         "rows and exit")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-scene batch measurement")
     ap.add_argument("--no-room256", action="store_true",
@@ -640,6 +693,13 @@ def main():
               f"supported (slices shard across GPUs by design, but the "
               f"library has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
+    if args.hbm_ceilings:
+        hbm_ceilings()
+        return
+    if args.mlp_rows:
+        mlp_rows(args.mlp_rows, os.path.join(args.weights_dir,
+                                             "surrogate_room256.npz"))
+        return
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib, max(1, args.steps))
         return

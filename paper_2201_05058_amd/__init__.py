@@ -96,6 +96,32 @@ def build_floor_sdf(grid, occ, z_lo=0, z_hi=None, want_sdf=True,
     return ssq, sdf
 
 
+def composite_outputs(n, shape_zyx, device, want_ssq=True, want_sdf=True):
+    """Output fields [n, nz, ny, nx] (int32 squared voxel distance, fp32
+    metres) as the composite calls allocate them by default: both in one
+    allocation, the fp32 field starting 4 KiB past the end of the int32
+    one.  Two output streams whose starts differ by a multiple of 8 KiB (as
+    two separate large allocations do) write measurably more slowly on
+    this GPU (256x256x128 x 20 slices: 0.239 against 0.231 ms).  The fp32
+    field keeps the 16-byte alignment the widest packs need."""
+    torch = _torch()
+    cnt = int(n)
+    for d in shape_zyx:
+        cnt *= int(d)
+    shp = (int(n),) + tuple(int(d) for d in shape_zyx)
+    if not (want_ssq and want_sdf):
+        oc = torch.empty(shp, dtype=torch.int32, device=device) \
+            if want_ssq else None
+        of = torch.empty(shp, dtype=torch.float32, device=device) \
+            if want_sdf else None
+        return oc, of
+    pad = 1024  # int32 elements: 4 KiB
+    buf = torch.empty(2 * cnt + pad, dtype=torch.int32, device=device)
+    oc = buf[:cnt].view(shp)
+    of = buf[cnt + pad:].view(torch.float32).view(shp)
+    return oc, of
+
+
 def predicted_composite_sdf(grid, static_ssq, human_xy, radius, height,
                             out_ssq=None, out_sdf=None, want_ssq=True,
                             want_sdf=True, handle: Handle | None = None):
@@ -113,6 +139,9 @@ def predicted_composite_sdf(grid, static_ssq, human_xy, radius, height,
     n, K = xy.shape[0], xy.shape[1]
     V = g.nvox
     dev = static_ssq.device
+    if out_ssq is None and out_sdf is None:
+        out_ssq, out_sdf = composite_outputs(n, g.shape_zyx, dev, want_ssq,
+                                             want_sdf)
     shp = (n,) + g.shape_zyx
     if out_ssq is None and want_ssq:
         out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
@@ -173,6 +202,9 @@ def predicted_composite_sdf_growing(grid, static_ssq, human_xy,
         raise ValueError("radius_per_slice must have n_slices entries")
     V = g.nvox
     dev = static_ssq.device
+    if out_ssq is None and out_sdf is None:
+        out_ssq, out_sdf = composite_outputs(n, g.shape_zyx, dev, want_ssq,
+                                             want_sdf)
     shp = (n,) + g.shape_zyx
     if out_ssq is None and want_ssq:
         out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
@@ -267,6 +299,9 @@ def template_composite_sdf(grid, static_ssq, human_xy, radius, height,
     n, K = xy.shape[0], xy.shape[1]
     V = g.nvox
     dev = static_ssq.device
+    if out_ssq is None and out_sdf is None:
+        out_ssq, out_sdf = composite_outputs(n, g.shape_zyx, dev, want_ssq,
+                                             want_sdf)
     shp = (n,) + g.shape_zyx
     if out_ssq is None and want_ssq:
         out_ssq = torch.empty(shp, dtype=torch.int32, device=dev)
