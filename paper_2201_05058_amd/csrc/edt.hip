@@ -276,12 +276,48 @@ __global__ __launch_bounds__(64) void k_pass_col(
 // Column values read per batch of loads in the segmented pass.
 constexpr int kSegBatch = 16;
 
+// LDS home of the segments' envelopes, [S][L][64] entries.  Registers hold
+// an entry as above (site << 22 | value).  With kRoot the pass's inputs
+// are squares of integers below 1024 (the x pass's squared distances), and
+// an entry is stored in 16 bits: the site's offset within its segment (L
+// <= 64: 6 bits) and the square root of its value (10 bits), which halves
+// the LDS of a column.
+template <bool kRoot>
+struct EnvLds {
+  void *base;
+  int L;
+  __device__ __forceinline__ uint32_t get(int s, int idx, int lane) const {
+    const size_t at = ((size_t)s * L + idx) * 64 + lane;
+    if (kRoot) {
+      const uint32_t e = static_cast<const uint16_t *>(base)[at];
+      const uint32_t site = (uint32_t)(s * L) + (e >> 10), r = e & 1023u;
+      return (site << 22) | (r * r);
+    }
+    return static_cast<const uint32_t *>(base)[at];
+  }
+  __device__ __forceinline__ void put(int s, int idx, int lane,
+                                      uint32_t e) const {
+    const size_t at = ((size_t)s * L + idx) * 64 + lane;
+    if (kRoot) {
+      const uint32_t f = e & 0x3FFFFFu;
+      uint32_t r = (uint32_t)__builtin_sqrtf((float)f);  // exact: f < 2^20
+      r -= r * r > f ? 1u : 0u;
+      r += (r + 1) * (r + 1) <= f ? 1u : 0u;
+      static_cast<uint16_t *>(base)[at] =
+          (uint16_t)((((e >> 22) - (uint32_t)(s * L)) << 10) | r);
+    } else {
+      static_cast<uint32_t *>(base)[at] = e;
+    }
+  }
+  static constexpr int bytes() { return kRoot ? 2 : 4; }
+};
+
 //
 // With kOutside, every lane runs the occupied set's channel (64 adjacent
 // columns per wave) and the free set's channel, which only the occupied
 // voxels need, is left to k_pass_col_search: a column's LDS then serves
 // twice the columns.
-template <int S, bool kWriteSdf, bool kOutside>
+template <int S, bool kWriteSdf, bool kOutside, bool kRoot>
 __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     const int32_t *__restrict__ in, int32_t *__restrict__ out,
     float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
@@ -293,9 +329,10 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
   const int col = kOutside ? lane : lane & 31;
   const bool inside_ch = !kOutside && lane >= 32;  // the free set's channel
   const int L = (m + S - 1) / S;
-  uint32_t *const stacks = lds_seg;                       // [S][L][64]
-  int *const tops = reinterpret_cast<int *>(lds_seg + (size_t)S * L * 64);
-  uint32_t *const stk = stacks + (size_t)w * L * 64;
+  const EnvLds<kRoot> env{lds_seg, L};  // [S][L][64]
+  int *const tops = reinterpret_cast<int *>(
+      reinterpret_cast<char *>(lds_seg) +
+      (size_t)S * L * 64 * EnvLds<kRoot>::bytes());
   const int q0 = w * L;
   const int q1 = min(m, q0 + L);
 
@@ -336,7 +373,7 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
         if (site) {
           const int fq = f + q * q;
           while (top >= 1) {
-            const uint32_t eb = stk[(top - 1) * 64 + lane];
+            const uint32_t eb = env.get(w, top - 1, lane);
             const int sa = site_of(etop), fa = val_of(etop);
             const int sb = site_of(eb), fb = val_of(eb);
             const int64_t lhs = (int64_t)(fq - fa - sa * sa) * (sa - sb);
@@ -351,7 +388,7 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
           }
           ++top;
           etop = ((uint32_t)q << 22) | (uint32_t)f;
-          stk[top * 64 + lane] = etop;
+          env.put(w, top, lane, etop);
         }
       }
     }
@@ -363,18 +400,16 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     uint32_t ek[S], ek1[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const uint32_t *st = stacks + (size_t)s * L * 64;
       tp[s] = tops[s * 64 + lane];
       k[s] = 0;
-      ek[s] = tp[s] >= 0 ? st[lane] : 0;
-      ek1[s] = tp[s] >= 1 ? st[64 + lane] : 0;
+      ek[s] = tp[s] >= 0 ? env.get(s, 0, lane) : 0;
+      ek1[s] = tp[s] >= 1 ? env.get(s, 1, lane) : 0;
     }
     for (int q = q0; q < q1; ++q) {
       {
         // Value of envelope s at q (its walk pointer moves right only; an
         // envelope skipped for some q catches up when next evaluated).
         auto eval = [&](int s) -> int32_t {
-          const uint32_t *st = stacks + (size_t)s * L * 64;
           while (k[s] < tp[s]) {
             const int dk = q - site_of(ek[s]), dk1 = q - site_of(ek1[s]);
             const int vk = dk * dk + val_of(ek[s]);
@@ -382,7 +417,7 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
             if (vk1 <= vk) {
               ++k[s];
               ek[s] = ek1[s];
-              ek1[s] = k[s] < tp[s] ? st[(k[s] + 1) * 64 + lane] : 0;
+              ek1[s] = k[s] < tp[s] ? env.get(s, k[s] + 1, lane) : 0;
             } else {
               break;
             }
@@ -495,7 +530,7 @@ static hipError_t allow_lds(const void *kernel, size_t bytes) {
                              (int)bytes);
 }
 
-template <int S>
+template <int S, bool kRoot>
 static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
                              float h_f, int nfast, int m, int64_t stride,
                              int64_t outer_stride, int64_t nblocks, int tiles,
@@ -503,25 +538,42 @@ static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
   const unsigned grid =
       (unsigned)(nblocks < (1LL << 30) ? nblocks : (1LL << 30));
   if (sdf_out) {
-    const hipError_t e =
-        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, true, true>),
-                  lds);
+    const hipError_t e = allow_lds(
+        reinterpret_cast<const void *>(&k_pass_col_seg<S, true, true, kRoot>),
+        lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, true, true>), dim3(grid),
-                       dim3(64 * S),
-                       lds, s, in, out, sdf_out, h_f, nfast, m, stride,
-                       outer_stride, nblocks, tiles);
+    hipLaunchKernelGGL((k_pass_col_seg<S, true, true, kRoot>), dim3(grid),
+                       dim3(64 * S), lds, s, in, out, sdf_out, h_f, nfast, m,
+                       stride, outer_stride, nblocks, tiles);
   } else {
-    const hipError_t e =
-        allow_lds(reinterpret_cast<const void *>(&k_pass_col_seg<S, false, true>),
-                  lds);
+    const hipError_t e = allow_lds(
+        reinterpret_cast<const void *>(&k_pass_col_seg<S, false, true, kRoot>),
+        lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, false, true>), dim3(grid),
-                       dim3(64 * S),
-                       lds, s, in, out, sdf_out, h_f, nfast, m, stride,
-                       outer_stride, nblocks, tiles);
+    hipLaunchKernelGGL((k_pass_col_seg<S, false, true, kRoot>), dim3(grid),
+                       dim3(64 * S), lds, s, in, out, sdf_out, h_f, nfast, m,
+                       stride, outer_stride, nblocks, tiles);
   }
   return hipSuccess;
+}
+
+template <bool kRoot>
+static hipError_t launch_seg_any(int S, const int32_t *in, int32_t *out,
+                                 float *sdf_out, float h_f, int nfast, int m,
+                                 int64_t stride, int64_t outer_stride,
+                                 int64_t nblocks, int tiles, size_t lds,
+                                 hipStream_t s) {
+  switch (S) {
+    case 2:
+      return launch_seg<2, kRoot>(in, out, sdf_out, h_f, nfast, m, stride,
+                                  outer_stride, nblocks, tiles, lds, s);
+    case 4:
+      return launch_seg<4, kRoot>(in, out, sdf_out, h_f, nfast, m, stride,
+                                  outer_stride, nblocks, tiles, lds, s);
+    default:
+      return launch_seg<8, kRoot>(in, out, sdf_out, h_f, nfast, m, stride,
+                                  outer_stride, nblocks, tiles, lds, s);
+  }
 }
 
 // Segments per column: the tuning's, else one per 32 voxels of the column
@@ -534,7 +586,8 @@ static int column_segments(const Handle *h, int m) {
 
 int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                     float *sdf_out, float h_f, int nfast, int nouter, int m,
-                    int64_t stride, int64_t outer_stride, hipStream_t s) {
+                    int64_t stride, int64_t outer_stride, bool square_input,
+                    hipStream_t s) {
   if (nfast <= 0 || nouter <= 0 || m <= 0) return PCSDF_OK;
   const int tiles = (nfast + 31) / 32;
   const int64_t nblocks = (int64_t)tiles * nouter;
@@ -556,27 +609,23 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   while (S > 1 && S > m) S >>= 1;  // a power of two, at most m
   if (S > 1) {
     const int L = (m + S - 1) / S;
-    const size_t lds_seg = ((size_t)S * L * 64 + (size_t)S * 64) * 4;
+    // 16-bit envelope entries when the inputs are squares and a segment's
+    // site offsets fit in 6 bits
+    const bool root = square_input && L <= 64;
+    const size_t lds_seg =
+        (size_t)S * L * 64 * (root ? 2 : 4) + (size_t)S * 64 * 4;
     if ((int64_t)lds_seg <= h->max_lds) {
       // the occupied set's channel by envelopes, 64 columns per wave; then
       // the free set's channel of the occupied voxels by search
       const int tiles64 = (nfast + 63) / 64;
       const int64_t nblocks64 = (int64_t)tiles64 * nouter;
-      hipError_t e;
-      switch (S) {
-        case 2:
-          e = launch_seg<2>(in, out, sdf_out, h_f, nfast, m, stride,
-                            outer_stride, nblocks64, tiles64, lds_seg, s);
-          break;
-        case 4:
-          e = launch_seg<4>(in, out, sdf_out, h_f, nfast, m, stride,
-                            outer_stride, nblocks64, tiles64, lds_seg, s);
-          break;
-        default:
-          e = launch_seg<8>(in, out, sdf_out, h_f, nfast, m, stride,
-                            outer_stride, nblocks64, tiles64, lds_seg, s);
-          break;
-      }
+      const hipError_t e =
+          root ? launch_seg_any<true>(S, in, out, sdf_out, h_f, nfast, m,
+                                      stride, outer_stride, nblocks64,
+                                      tiles64, lds_seg, s)
+               : launch_seg_any<false>(S, in, out, sdf_out, h_f, nfast, m,
+                                       stride, outer_stride, nblocks64,
+                                       tiles64, lds_seg, s);
       if (e != hipSuccess)
         return fail(h, PCSDF_ERR_HIP,
                     std::string("raising the LDS limit of pass_col_seg: ") +
@@ -663,9 +712,10 @@ extern "C" int pcsdf_build_static_sdf(pcsdf_handle *hp, const pcsdf_grid *g,
   ProfScope ps(h, PCSDF_KERNEL_STATIC, s);
   if ((rc = launch_pass_x_u8(h, occ_dev, ssq_dev, nx, (int64_t)ny * nz, s)))
     return rc;
+  // the y pass reads the x pass's squared distances (perfect squares)
   if ((rc = launch_pass_col(h, ssq_dev, tmp, nullptr, hf, nx, nz, ny, nx,
-                            (int64_t)nx * ny, s)))
+                            (int64_t)nx * ny, true, s)))
     return rc;
   return launch_pass_col(h, tmp, ssq_dev, sdf_dev, hf, nx, ny, nz,
-                         (int64_t)nx * ny, nx, s);
+                         (int64_t)nx * ny, nx, false, s);
 }

@@ -155,7 +155,8 @@ int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
 // When sdf_out is non-null the pass also writes F(out) with voxel size h.
 int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                     float *sdf_out, float h_f, int nfast, int nouter, int m,
-                    int64_t stride, int64_t outer_stride, hipStream_t s);
+                    int64_t stride, int64_t outer_stride, bool square_input,
+                    hipStream_t s);
 
 // ---- implemented in planes.hip -----------------------------------------
 
