@@ -475,9 +475,17 @@ __global__ __launch_bounds__(256) void k_pass_col_search(
   if (t >= (uint32_t)nfast * (uint32_t)m) return;
   const int q = (int)(t / (uint32_t)nfast);
   const int i = (int)(t - (uint32_t)q * (uint32_t)nfast);
+  // The outer index's slab is uniform across the block, so each access is
+  // a uniform base plus a 32-bit lane byte offset (a slab holds at most
+  // 2^30 elements).
   const int64_t o = blockIdx.y;
-  const int32_t *src = in + o * outer_stride + i;
-  const int32_t x = src[(int64_t)q * stride];
+  const char *base = reinterpret_cast<const char *>(in + o * outer_stride);
+  const uint32_t st = (uint32_t)stride * 4u;  // bytes
+  const uint32_t at = (uint32_t)i * 4u + (uint32_t)q * st;
+  auto ld = [&](uint32_t off) -> int32_t {
+    return *reinterpret_cast<const int32_t *>(base + off);
+  };
+  const int32_t x = ld(at);
   const bool inside = x < 0;  // occupied: the free set's channel
   if (kInsideOnly && !inside) return;
   // value of row p in this voxel's channel (kInf: no site in that row)
@@ -496,8 +504,8 @@ __global__ __launch_bounds__(256) void k_pass_col_search(
 #pragma unroll
     for (int u = 0; u < kSearchBatch; ++u) {
       const int d = d0 + u;
-      lo[u] = q - d >= 0 ? src[(int64_t)(q - d) * stride] : kInf;
-      hi[u] = q + d < m ? src[(int64_t)(q + d) * stride] : kInf;
+      lo[u] = q - d >= 0 ? ld(at - (uint32_t)d * st) : kInf;
+      hi[u] = q + d < m ? ld(at + (uint32_t)d * st) : kInf;
     }
 #pragma unroll
     for (int u = 0; u < kSearchBatch; ++u) {
@@ -510,10 +518,11 @@ __global__ __launch_bounds__(256) void k_pass_col_search(
     }
   }
   const int32_t v = inside ? (best == kInf ? -kInf : -best) : best;
-  int32_t *dst = out + o * outer_stride + i;
-  dst[(int64_t)q * stride] = v;
+  *reinterpret_cast<int32_t *>(
+      reinterpret_cast<char *>(out + o * outer_stride) + at) = v;
   if (kWriteSdf)
-    sdf[o * outer_stride + i + (int64_t)q * stride] = ssq_to_metres(v, hf);
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(sdf + o * outer_stride) +
+                               at) = ssq_to_metres(v, hf);
 }
 
 // Column tiles below which a pass runs one lane per voxel.
