@@ -21,17 +21,22 @@
 //     count-leading / trailing-zeros of the masked ballot with a carry
 //     across chunks.  No LDS.
 //   - y and z passes: lanes run along x, so every step of a column sweep is
-//     one coalesced 128-byte load shared by both halves of the wave:
-//     lanes 0..31 run the occupied-set channel of 32 adjacent columns and
-//     lanes 32..63 the free-set channel of the same columns.  No transpose
-//     is needed because x is the contiguous axis.  Each lane keeps its
-//     envelope stack in LDS, one packed 32-bit entry per site (site index
-//     in 10 bits, value in 22 bits: values stay below 2*1023^2 < 2^22
-//     before the last pass), laid out [depth][lane] so a wave's accesses
-//     spread over all banks.  Intersections are compared by
-//     cross-multiplication in int64, so the envelope has no division.
+//     one coalesced load of adjacent columns, and no transpose is needed
+//     because x is the contiguous axis.  On the static build the occupied
+//     set's channel (every free voxel's value) is a lower envelope per
+//     column, split into segments with one wave each (k_pass_col_seg), and
+//     the free set's channel, needed only at the occupied voxels, is a
+//     bounded search over groups of rows (k_pass_col_inside).  Envelope
+//     stacks live in LDS laid out [depth][lane] so a wave's accesses spread
+//     over all banks, and intersections are compared by cross-multiplication,
+//     so the envelope has no division.  Columns too long for the segmented
+//     kernel's LDS run both channels in one wave per 32 columns
+//     (k_pass_col), and passes with few columns one lane per voxel
+//     (k_pass_col_search).
 #include "device_common.h"
 #include "internal.h"
+
+#include <type_traits>
 
 namespace pcsdf {
 
@@ -261,73 +266,97 @@ __global__ __launch_bounds__(64) void k_pass_col(
 }
 
 // The same pass with each column split into S segments, one wave per
-// segment (workgroup = S waves, 32 columns x 2 channels per wave as
-// above).  Wave w builds the lower envelope of the sites in its segment;
-// after a barrier it fills its segment's voxels with the minimum over the
-// S envelopes, walking each one as the fill sweep above walks its single
-// envelope (the minimizing parabola of an envelope moves right as q
+// segment (workgroup = S waves), for the occupied set's channel only:
+// every lane runs one column (64 adjacent columns per wave), and the free
+// set's channel, which only the occupied voxels need, is left to
+// k_pass_col_search.  Wave w builds the lower envelope of the sites in its
+// segment; after a barrier it fills its segment's voxels with the minimum
+// over the S envelopes, walking each one as the fill sweep above walks its
+// single envelope (the minimizing parabola of an envelope moves right as q
 // grows).  The envelope of the whole column is the lower envelope of the
 // segments' envelopes, so the result is exact.  Its own segment is
-// evaluated first and another segment only while it could still lower
-// the value (its nearest voxel is closer than the square root of the
-// value so far), so a fill usually reads one or two envelopes.  The
-// workgroup's LDS is the same as one wave's above (S segments of m/S
-// entries), so S times as many waves share a CU.
-// Column values read per batch of loads in the segmented pass.
+// evaluated first, then the other segments of each side nearest first; a
+// side ends at the first segment that no lane of the wave can use (its
+// nearest voxel is no closer than the square root of the value so far,
+// and farther segments are farther still).
+//
+// Arithmetic.  A parabola of site p and value f is held as (p, h) with
+// h = f + p^2, so its value at q is q^2 - 2 q p + h.  Every operand fits in
+// 24 bits (p, q < 1024 and h < 2^22 for grids of at most 1024 voxels per
+// axis: f < 2 * 1023^2 before the last pass), so every product runs on the
+// full-rate 24-bit multiplier, including the 48-bit cross-products of the
+// stack test.
 constexpr int kSegBatch = 16;
 
-// LDS home of the segments' envelopes, [S][L][64] entries.  Registers hold
-// an entry as above (site << 22 | value).  With kRoot the pass's inputs
-// are squares of integers below 1024 (the x pass's squared distances), and
-// an entry is stored in 16 bits: the site's offset within its segment (L
-// <= 64: 6 bits) and the square root of its value (10 bits), which halves
-// the LDS of a column.
+// The low 24 bits, sign-extended: marks a value as fitting the 24-bit
+// multiplier, which reads only those bits (the extension costs nothing).
+// mul24 is the product of two such values on that multiplier, mul48 its
+// full 48-bit product.
+__device__ __forceinline__ int32_t i24(int32_t v) { return (v << 8) >> 8; }
+__device__ __forceinline__ int32_t mul24(int32_t a, int32_t b) {
+  return __mul24(a, b);
+}
+__device__ __forceinline__ int64_t mul48(int32_t a, int32_t b) {
+  return (int64_t)i24(a) * (int64_t)i24(b);
+}
+
+// LDS home of the segments' envelopes, [S][L][64] entries.  An entry is
+// p << 22 | h in 32 bits.  With kRoot the pass's inputs are squares of
+// integers below 1024 (the x pass's squared distances), and an entry is
+// stored in 16 bits: p's offset within its segment (L <= 64: 6 bits) and
+// the square root of f (10 bits), which halves the LDS of a column.
 template <bool kRoot>
 struct EnvLds {
   void *base;
   int L;
-  __device__ __forceinline__ uint32_t get(int s, int idx, int lane) const {
-    const size_t at = ((size_t)s * L + idx) * 64 + lane;
-    if (kRoot) {
-      const uint32_t e = static_cast<const uint16_t *>(base)[at];
-      const uint32_t site = (uint32_t)(s * L) + (e >> 10), r = e & 1023u;
-      return (site << 22) | (r * r);
-    }
-    return static_cast<const uint32_t *>(base)[at];
+  typedef typename std::conditional<kRoot, uint16_t, uint32_t>::type Raw;
+  __device__ __forceinline__ uint32_t raw(int s, int idx, int lane) const {
+    return static_cast<const Raw *>(base)[(uint32_t)(s * L + idx) * 64u +
+                                          (uint32_t)lane];
   }
-  __device__ __forceinline__ void put(int s, int idx, int lane,
-                                      uint32_t e) const {
-    const size_t at = ((size_t)s * L + idx) * 64 + lane;
+  __device__ __forceinline__ void decode(int s, uint32_t e, int *p,
+                                         int *h) const {
     if (kRoot) {
-      const uint32_t f = e & 0x3FFFFFu;
-      uint32_t r = (uint32_t)__builtin_sqrtf((float)f);  // exact: f < 2^20
-      r -= r * r > f ? 1u : 0u;
-      r += (r + 1) * (r + 1) <= f ? 1u : 0u;
-      static_cast<uint16_t *>(base)[at] =
-          (uint16_t)((((e >> 22) - (uint32_t)(s * L)) << 10) | r);
+      const int pp = s * L + (int)(e >> 10), r = (int)(e & 1023u);
+      *p = pp;
+      *h = mul24(r, r) + mul24(pp, pp);
     } else {
-      static_cast<uint32_t *>(base)[at] = e;
+      *p = (int)(e >> 22);
+      *h = (int)(e & 0x3FFFFFu);
     }
+  }
+  __device__ __forceinline__ void get(int s, int idx, int lane, int *p,
+                                      int *h) const {
+    decode(s, raw(s, idx, lane), p, h);
+  }
+  // r: the square root of the site's value (kRoot only)
+  __device__ __forceinline__ void put(int s, int idx, int lane, int p, int h,
+                                      int r) const {
+    const uint32_t at = (uint32_t)(s * L + idx) * 64u + (uint32_t)lane;
+    if (kRoot)
+      static_cast<uint16_t *>(base)[at] =
+          (uint16_t)(((uint32_t)(p - s * L) << 10) | (uint32_t)r);
+    else
+      static_cast<uint32_t *>(base)[at] = ((uint32_t)p << 22) | (uint32_t)h;
   }
   static constexpr int bytes() { return kRoot ? 2 : 4; }
 };
 
-//
-// With kOutside, every lane runs the occupied set's channel (64 adjacent
-// columns per wave) and the free set's channel, which only the occupied
-// voxels need, is left to k_pass_col_search: a column's LDS then serves
-// twice the columns.
-template <int S, bool kWriteSdf, bool kOutside, bool kRoot>
+// Square root of a perfect square below 2^20: the hardware's approximate
+// root is within an ulp (2^-13 here) of the integer, so rounding to
+// nearest recovers it exactly.
+__device__ __forceinline__ int root_of_square(int f) {
+  return (int)(__builtin_amdgcn_sqrtf((float)f) + 0.5f);
+}
+
+template <int S, bool kWriteSdf, bool kRoot>
 __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     const int32_t *__restrict__ in, int32_t *__restrict__ out,
     float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
     int64_t outer_stride, int64_t nblocks, int tiles) {
   extern __shared__ uint32_t lds_seg[];
-  constexpr int kCols = kOutside ? 64 : 32;  // columns per wave
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int col = kOutside ? lane : lane & 31;
-  const bool inside_ch = !kOutside && lane >= 32;  // the free set's channel
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int L = (m + S - 1) / S;
   const EnvLds<kRoot> env{lds_seg, L};  // [S][L][64]
   int *const tops = reinterpret_cast<int *>(
@@ -339,115 +368,111 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
   for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
     const int64_t o = b / tiles;
     const int tile = (int)(b - o * tiles);
-    const int i = tile * kCols + col;
+    const int i = tile * 64 + lane;
     const bool active = i < nfast;
-    const int32_t *src = in + o * outer_stride + (active ? i : 0);
-    int32_t *dst = out + o * outer_stride + (active ? i : 0);
-    float *dsdf = kWriteSdf ? sdf + o * outer_stride + (active ? i : 0)
-                            : nullptr;
+    const int64_t at0 = o * outer_stride + (active ? i : 0) + q0 * stride;
+    const int32_t *src = in + at0;  // row q0 of this lane's column
+    int32_t *dst = out + at0;
+    float *dsdf = kWriteSdf ? sdf + at0 : nullptr;
 
-    // Envelope of this segment's sites.
+    // Envelope of this segment's sites; its top two entries in registers.
     int top = -1;
-    uint32_t etop = 0;  // stk[top] cached in a register
+    int pa = 0, ha = 0;  // entry top
+    int pb = 0, hb = 0;  // entry top - 1
     for (int qb = q0; qb < q1; qb += kSegBatch) {
       int32_t xb[kSegBatch];
 #pragma unroll
-      for (int t = 0; t < kSegBatch; ++t) {
-        const int q = qb + t;
-        xb[t] = (active && q < q1) ? src[(int64_t)q * stride] : 0;
-      }
+      for (int t = 0; t < kSegBatch; ++t)
+        xb[t] = (active && qb + t < q1)
+                    ? src[(int64_t)(qb - q0 + t) * stride]
+                    : kInf;
 #pragma unroll
       for (int t = 0; t < kSegBatch; ++t) {
         const int q = qb + t;
         const int32_t x = xb[t];
-        bool site;
-        int f;
-        if (!inside_ch) {
-          site = x != kInf;
-          f = x > 0 ? x : 0;
-        } else {
-          site = x != -kInf;
-          f = x < 0 ? -x : 0;
+        if (x == kInf) continue;  // no site in this row (or past the end)
+        const int f = x > 0 ? x : 0;
+        const int hq = f + mul24(q, q);
+        while (top >= 1) {
+          // entry top - 2, read before the test so that a pop finds it
+          const uint32_t ec = env.raw(w, max(top - 2, 0), lane);
+          // The top stays if the new parabola overtakes it to the right
+          // of where it overtakes the entry below (cross-multiplied).
+          if (mul48(hq - ha, pa - pb) > mul48(ha - hb, q - pa)) break;
+          --top;
+          pa = pb;
+          ha = hb;
+          env.decode(w, ec, &pb, &hb);
         }
-        site = site && active && q < q1;
-        if (site) {
-          const int fq = f + q * q;
-          while (top >= 1) {
-            const uint32_t eb = env.get(w, top - 1, lane);
-            const int sa = site_of(etop), fa = val_of(etop);
-            const int sb = site_of(eb), fb = val_of(eb);
-            const int64_t lhs = (int64_t)(fq - fa - sa * sa) * (sa - sb);
-            const int64_t rhs =
-                (int64_t)(fa + sa * sa - fb - sb * sb) * (q - sa);
-            if (lhs <= rhs) {
-              --top;
-              etop = eb;
-            } else {
-              break;
-            }
-          }
-          ++top;
-          etop = ((uint32_t)q << 22) | (uint32_t)f;
-          env.put(w, top, lane, etop);
-        }
+        pb = pa;
+        hb = ha;
+        pa = q;
+        ha = hq;
+        ++top;
+        env.put(w, top, lane, q, hq, kRoot ? root_of_square(f) : 0);
       }
     }
     tops[w * 64 + lane] = top;
     __syncthreads();
 
-    // Fill this segment from all S envelopes.
-    int tp[S], k[S];
-    uint32_t ek[S], ek1[S];
+    // Fill this segment from the S envelopes: per envelope its walk
+    // position k and entries k, k + 1.
+    int tp[S], k[S], p0[S], h0[S], p1[S], h1[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       tp[s] = tops[s * 64 + lane];
       k[s] = 0;
-      ek[s] = tp[s] >= 0 ? env.get(s, 0, lane) : 0;
-      ek1[s] = tp[s] >= 1 ? env.get(s, 1, lane) : 0;
+      p0[s] = h0[s] = p1[s] = h1[s] = 0;
+      if (tp[s] >= 0) env.get(s, 0, lane, &p0[s], &h0[s]);
+      if (tp[s] >= 1) env.get(s, 1, lane, &p1[s], &h1[s]);
     }
+    int32_t *dq = dst;
+    float *fq = dsdf;
     for (int q = q0; q < q1; ++q) {
-      {
-        // Value of envelope s at q (its walk pointer moves right only; an
-        // envelope skipped for some q catches up when next evaluated).
-        auto eval = [&](int s) -> int32_t {
-          while (k[s] < tp[s]) {
-            const int dk = q - site_of(ek[s]), dk1 = q - site_of(ek1[s]);
-            const int vk = dk * dk + val_of(ek[s]);
-            const int vk1 = dk1 * dk1 + val_of(ek1[s]);
-            if (vk1 <= vk) {
-              ++k[s];
-              ek[s] = ek1[s];
-              ek1[s] = k[s] < tp[s] ? env.get(s, k[s] + 1, lane) : 0;
-            } else {
-              break;
-            }
-          }
-          const int d = q - site_of(ek[s]);
-          return d * d + val_of(ek[s]);
-        };
-        // Own segment first; another segment s is gap voxels away at
-        // least, so it cannot lower a value already <= gap^2.
-        int32_t val = kInf;
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-          if (s == w && tp[s] >= 0) val = eval(s);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          if (s == w || tp[s] < 0) continue;
-          const int gap = s < w ? q - ((s + 1) * L - 1) : s * L - q;
-          if (gap * gap >= val) continue;
-          val = min(val, eval(s));
+      const int q2 = 2 * q, qq = mul24(q, q);
+      // value of envelope s at q (its walk position moves right only; an
+      // envelope skipped for some q catches up when next evaluated)
+      auto eval = [&](int s) -> int32_t {
+        while (k[s] < tp[s]) {
+          // entry k + 1 is no higher at q: h1 - h0 <= 2 q (p1 - p0)
+          if (h1[s] - h0[s] > mul24(q2, p1[s] - p0[s])) break;
+          ++k[s];
+          p0[s] = p1[s];
+          h0[s] = h1[s];
+          if (k[s] < tp[s]) env.get(s, k[s] + 1, lane, &p1[s], &h1[s]);
         }
-        // A voxel of this channel's own set (free for the outside
-        // channel, occupied for the inside one) is a site of the other
-        // channel at distance 0, so each channel's value is positive
-        // exactly on the voxels it owns: no second read of the input.
-        if (val > 0 && active) {
-          const int32_t v = inside_ch ? -val : val;
-          dst[(int64_t)q * stride] = v;
-          if (kWriteSdf) dsdf[(int64_t)q * stride] = ssq_to_metres(v, hf);
-        }
+        return qq + h0[s] - mul24(q2, p0[s]);
+      };
+      int32_t val = kInf;
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        if (s == w && tp[s] >= 0) val = eval(s);
+      // segments below, nearest first
+#pragma unroll
+      for (int s = S - 1; s >= 0; --s) {
+        if (s >= w) continue;
+        const int gap = q - ((s + 1) * L - 1);
+        const bool reach = mul24(gap, gap) < val;
+        if (__ballot(reach) == 0) break;
+        if (reach && tp[s] >= 0) val = min(val, eval(s));
       }
+      // segments above, nearest first
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s <= w) continue;
+        const int gap = s * L - q;
+        const bool reach = mul24(gap, gap) < val;
+        if (__ballot(reach) == 0) break;
+        if (reach && tp[s] >= 0) val = min(val, eval(s));
+      }
+      // The free voxels get their value; an occupied voxel is a site of
+      // value 0 (left to the free set's channel).
+      if (val > 0 && active) {
+        *dq = val;
+        if (kWriteSdf) *fq = ssq_to_metres(val, hf);
+      }
+      dq += stride;
+      if (kWriteSdf) fq += stride;
     }
     __syncthreads();  // the stacks are reused by the next column tile
   }
@@ -459,25 +484,86 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
 // searching p = q -+ d for d = 1, 2, ... until d^2 >= the best value so
 // far (no farther p can be smaller, f >= 0).  Exact, like the envelope;
 // its work grows with the distance found, so it is kept to small passes.
-//
-// With kInsideOnly only the occupied voxels are computed (the free set's
-// channel, beside k_pass_col_seg's occupied-set channel); the distances
-// found there are bounded by the obstacles' half-widths.  Grid: (voxels
-// of one outer index / 256, outer indices).
+// Grid: (voxels of one outer index / 256, outer indices).
 constexpr int kSearchBatch = 4;
 
-template <bool kWriteSdf, bool kInsideOnly, int kSearchRows>
+template <bool kWriteSdf>
 __global__ __launch_bounds__(256) void k_pass_col_search(
     const int32_t *__restrict__ in, int32_t *__restrict__ out,
     float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
     int64_t outer_stride) {
-  // Lane t takes column i = t mod nfast and rows q = kSearchRows (t /
-  // nfast) + 0 .. kSearchRows-1: their values are loaded together, and
-  // only the voxels that need a value are searched (with kInsideOnly most
-  // are free and cost one load; several rows per lane save launching a
-  // wave per load on large passes, one row per lane keeps the searches of
-  // small passes parallel).
-  const uint32_t mg = (uint32_t)(m + kSearchRows - 1) / kSearchRows;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (uint32_t)nfast * (uint32_t)m) return;
+  const int q = (int)(t / (uint32_t)nfast);
+  const int i = (int)(t - (uint32_t)q * (uint32_t)nfast);
+  // The outer index's slab is uniform across the block, so each access is
+  // a uniform base plus a 32-bit lane byte offset (a slab holds at most
+  // 2^30 elements).
+  const int64_t o = blockIdx.y;
+  const char *base = reinterpret_cast<const char *>(in + o * outer_stride);
+  char *obase = reinterpret_cast<char *>(out + o * outer_stride);
+  char *fbase = kWriteSdf ? reinterpret_cast<char *>(sdf + o * outer_stride)
+                          : nullptr;
+  const uint32_t st = (uint32_t)stride * 4u;  // bytes
+  auto ld = [&](uint32_t off) -> int32_t {
+    return *reinterpret_cast<const int32_t *>(base + off);
+  };
+  const uint32_t at = (uint32_t)i * 4u + (uint32_t)q * st;
+  const int32_t x = ld(at);
+  const bool inside = x < 0;  // occupied: the free set's channel
+  // value of row p in this voxel's channel (kInf: no site in that row)
+  auto f_of = [&](int32_t v) -> int32_t {
+    if (!inside) return v == kInf ? kInf : (v > 0 ? v : 0);
+    return v == -kInf ? kInf : (v < 0 ? -v : 0);
+  };
+  int32_t best = f_of(x);
+  const int dmax = max(q, m - 1 - q);
+  // kSearchBatch distances per step: their loads are issued together, so a
+  // step costs one memory latency (rows past the stopping distance are read
+  // and cannot lower the value: d^2 >= best there).
+  for (int d0 = 1; d0 <= dmax; d0 += kSearchBatch) {
+    if (d0 * d0 >= best) break;
+    int32_t lo[kSearchBatch], hi[kSearchBatch];
+#pragma unroll
+    for (int u = 0; u < kSearchBatch; ++u) {
+      const int d = d0 + u;
+      lo[u] = q - d >= 0 ? ld(at - (uint32_t)d * st) : kInf;
+      hi[u] = q + d < m ? ld(at + (uint32_t)d * st) : kInf;
+    }
+#pragma unroll
+    for (int u = 0; u < kSearchBatch; ++u) {
+      const int d = d0 + u;
+      const int32_t d2 = d * d;
+      const int32_t fl = q - d >= 0 ? f_of(lo[u]) : kInf;
+      const int32_t fh = q + d < m ? f_of(hi[u]) : kInf;
+      if (fl != kInf) best = min(best, d2 + fl);
+      if (fh != kInf) best = min(best, d2 + fh);
+    }
+  }
+  const int32_t v = inside ? (best == kInf ? -kInf : -best) : best;
+  *reinterpret_cast<int32_t *>(obase + at) = v;
+  if (kWriteSdf)
+    *reinterpret_cast<float *>(fbase + at) = ssq_to_metres(v, hf);
+}
+
+// The free set's channel of the occupied voxels, beside k_pass_col_seg's
+// occupied-set channel (the distances found there are bounded by the
+// obstacles' half-widths).  Lane t takes column i = t mod nfast and the G
+// consecutive rows qa = G (t / nfast) .. qa + G - 1 of it.  It loads those
+// rows and, if any of them is occupied, searches outward from the group:
+// kSearchBatch rows below and above per step (their loads issued
+// together), each row read once and offered to every row of the group.  A
+// side ends when no occupied row of the group can still be lowered from
+// it (the next row's distance squared is at least that row's value so far;
+// farther rows are farther still).  Neighbouring rows share their
+// neighbours, so a group costs about one search instead of G.  Exact, like
+// the envelope.  Grid: (lanes of one outer index / 256, outer indices).
+template <bool kWriteSdf, int G>
+__global__ __launch_bounds__(256) void k_pass_col_inside(
+    const int32_t *__restrict__ in, int32_t *__restrict__ out,
+    float *__restrict__ sdf, float hf, int nfast, int m, int64_t stride,
+    int64_t outer_stride) {
+  const uint32_t mg = (uint32_t)(m + G - 1) / G;
   const uint32_t t = blockIdx.x * 256u + threadIdx.x;
   if (t >= (uint32_t)nfast * mg) return;
   const int qg = (int)(t / (uint32_t)nfast);
@@ -494,54 +580,82 @@ __global__ __launch_bounds__(256) void k_pass_col_search(
   auto ld = [&](uint32_t off) -> int32_t {
     return *reinterpret_cast<const int32_t *>(base + off);
   };
-  int32_t xs[kSearchRows];
+  // value of a row in the free set's channel: 0 on a free voxel, f_F on an
+  // occupied one, kInf where the row has no free voxel (rows outside the
+  // column are passed as -kInf)
+  auto f_free = [](int32_t v) -> int32_t {
+    return v == -kInf ? kInf : (v < 0 ? -v : 0);
+  };
+  const int qa = qg * G;
+  const int n = min(G, m - qa);  // rows of the group inside the column
+  const uint32_t at0 = (uint32_t)i * 4u + (uint32_t)qa * st;
+  int32_t x[G];
 #pragma unroll
-  for (int r = 0; r < kSearchRows; ++r) {
-    const int q = qg * kSearchRows + r;
-    xs[r] = q < m ? ld((uint32_t)i * 4u + (uint32_t)q * st) : 0;
+  for (int r = 0; r < G; ++r) x[r] = r < n ? ld(at0 + (uint32_t)r * st) : -kInf;
+  bool need[G];  // occupied rows: the ones this channel writes
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    need[r] = r < n && x[r] < 0;
+    any = any || need[r];
   }
-#pragma unroll 1
-  for (int r = 0; r < kSearchRows; ++r) {
-    const int q = qg * kSearchRows + r;
-    const int32_t x = xs[r];
-    const bool inside = x < 0;  // occupied: the free set's channel
-    if (q >= m || (kInsideOnly && !inside)) continue;
-    const uint32_t at = (uint32_t)i * 4u + (uint32_t)q * st;
-    // value of row p in this voxel's channel (kInf: no site in that row)
-    auto f_of = [&](int32_t v) -> int32_t {
-      if (!inside) return v == kInf ? kInf : (v > 0 ? v : 0);
-      return v == -kInf ? kInf : (v < 0 ? -v : 0);
-    };
-    int32_t best = f_of(x);
-    const int dmax = max(q, m - 1 - q);
-    // kSearchBatch distances per step: their loads are issued together,
-    // so a step costs one memory latency (rows past the stopping distance
-    // are read and cannot lower the value: d^2 >= best there).
-    for (int d0 = 1; d0 <= dmax; d0 += kSearchBatch) {
-      if (d0 * d0 >= best) break;
-      int32_t lo[kSearchBatch], hi[kSearchBatch];
+  if (!any) return;
+  int32_t best[G];
 #pragma unroll
-      for (int u = 0; u < kSearchBatch; ++u) {
-        const int d = d0 + u;
-        lo[u] = q - d >= 0 ? ld(at - (uint32_t)d * st) : kInf;
-        hi[u] = q + d < m ? ld(at + (uint32_t)d * st) : kInf;
-      }
+  for (int r = 0; r < G; ++r) best[r] = kInf;
 #pragma unroll
-      for (int u = 0; u < kSearchBatch; ++u) {
-        const int d = d0 + u;
-        const int32_t d2 = d * d;
-        const int32_t fl = q - d >= 0 ? f_of(lo[u]) : kInf;
-        const int32_t fh = q + d < m ? f_of(hi[u]) : kInf;
-        if (fl != kInf) best = min(best, d2 + fl);
-        if (fh != kInf) best = min(best, d2 + fh);
+  for (int p = 0; p < G; ++p) {
+    const int32_t fp = f_free(x[p]);
+    if (fp == kInf) continue;
+#pragma unroll
+    for (int r = 0; r < G; ++r) best[r] = min(best[r], fp + (r - p) * (r - p));
+  }
+  for (int d0 = 1;; d0 += kSearchBatch) {
+    bool lo = false, hi = false;
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      if (!need[r]) continue;
+      const int dl = r + d0, dh = n - 1 - r + d0;
+      lo = lo || mul24(dl, dl) < best[r];
+      hi = hi || mul24(dh, dh) < best[r];
+    }
+    lo = lo && qa - d0 >= 0;
+    hi = hi && qa + n - 1 + d0 < m;
+    if (!lo && !hi) break;
+    int32_t vl[kSearchBatch], vh[kSearchBatch];
+#pragma unroll
+    for (int u = 0; u < kSearchBatch; ++u) {
+      const int d = d0 + u;
+      vl[u] = lo && qa - d >= 0 ? ld(at0 - (uint32_t)d * st) : -kInf;
+      vh[u] = hi && qa + n - 1 + d < m
+                  ? ld(at0 + (uint32_t)(n - 1 + d) * st)
+                  : -kInf;
+    }
+#pragma unroll
+    for (int u = 0; u < kSearchBatch; ++u) {
+      const int d = d0 + u;
+      const int32_t fl = f_free(vl[u]), fh = f_free(vh[u]);
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int dl = r + d, dh = n - 1 - r + d;
+        if (fl != kInf) best[r] = min(best[r], fl + mul24(dl, dl));
+        if (fh != kInf) best[r] = min(best[r], fh + mul24(dh, dh));
       }
     }
-    const int32_t v = inside ? (best == kInf ? -kInf : -best) : best;
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    if (!need[r]) continue;
+    const int32_t v = best[r] == kInf ? -kInf : -best[r];
+    const uint32_t at = at0 + (uint32_t)r * st;
     *reinterpret_cast<int32_t *>(obase + at) = v;
     if (kWriteSdf)
       *reinterpret_cast<float *>(fbase + at) = ssq_to_metres(v, hf);
   }
 }
+
+// Rows per lane of the free set's channel.
+constexpr int kInsideRows = 4;
 
 // Column tiles below which a pass runs one lane per voxel.
 constexpr int64_t kSearchTiles = 64;
@@ -566,18 +680,18 @@ static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
       (unsigned)(nblocks < (1LL << 30) ? nblocks : (1LL << 30));
   if (sdf_out) {
     const hipError_t e = allow_lds(
-        reinterpret_cast<const void *>(&k_pass_col_seg<S, true, true, kRoot>),
+        reinterpret_cast<const void *>(&k_pass_col_seg<S, true, kRoot>),
         lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, true, true, kRoot>), dim3(grid),
+    hipLaunchKernelGGL((k_pass_col_seg<S, true, kRoot>), dim3(grid),
                        dim3(64 * S), lds, s, in, out, sdf_out, h_f, nfast, m,
                        stride, outer_stride, nblocks, tiles);
   } else {
     const hipError_t e = allow_lds(
-        reinterpret_cast<const void *>(&k_pass_col_seg<S, false, true, kRoot>),
+        reinterpret_cast<const void *>(&k_pass_col_seg<S, false, kRoot>),
         lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, false, true, kRoot>), dim3(grid),
+    hipLaunchKernelGGL((k_pass_col_seg<S, false, kRoot>), dim3(grid),
                        dim3(64 * S), lds, s, in, out, sdf_out, h_f, nfast, m,
                        stride, outer_stride, nblocks, tiles);
   }
@@ -626,11 +740,11 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   };
   if (nblocks < kSearchTiles && h->tuning.static_segments == 0) {
     if (sdf_out)
-      hipLaunchKernelGGL((k_pass_col_search<true, false, 1>), sgrid(1),
+      hipLaunchKernelGGL((k_pass_col_search<true>), sgrid(1),
                          dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
                          stride, outer_stride);
     else
-      hipLaunchKernelGGL((k_pass_col_search<false, false, 1>), sgrid(1),
+      hipLaunchKernelGGL((k_pass_col_search<false>), sgrid(1),
                          dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
                          stride, outer_stride);
     return check_launch(h, "pass_col_search");
@@ -662,25 +776,15 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                         hipGetErrorString(e));
       int rc = check_launch(h, "pass_col_seg");
       if (rc) return rc;
-      // four rows per lane from 2^25 voxels on (512^2 x 128: 3 % faster
-      // than one; 256^2 x 128: 7 % slower)
-      const bool big = (int64_t)nfast * m * nouter >= (1LL << 25);
-      if (sdf_out && big)
-        hipLaunchKernelGGL((k_pass_col_search<true, true, 4>), sgrid(4),
-                           dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
-                           stride, outer_stride);
-      else if (sdf_out)
-        hipLaunchKernelGGL((k_pass_col_search<true, true, 1>), sgrid(1),
-                           dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
-                           stride, outer_stride);
-      else if (big)
-        hipLaunchKernelGGL((k_pass_col_search<false, true, 4>), sgrid(4),
-                           dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
-                           stride, outer_stride);
+      // the free set's channel: groups of 8 rows per lane
+      if (sdf_out)
+        hipLaunchKernelGGL((k_pass_col_inside<true, kInsideRows>),
+                           sgrid(kInsideRows), dim3(256), 0, s, in, out,
+                           sdf_out, h_f, nfast, m, stride, outer_stride);
       else
-        hipLaunchKernelGGL((k_pass_col_search<false, true, 1>), sgrid(1),
-                           dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
-                           stride, outer_stride);
+        hipLaunchKernelGGL((k_pass_col_inside<false, kInsideRows>),
+                           sgrid(kInsideRows), dim3(256), 0, s, in, out,
+                           sdf_out, h_f, nfast, m, stride, outer_stride);
       return check_launch(h, "pass_col_inside");
     }
   }
