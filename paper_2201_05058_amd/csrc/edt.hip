@@ -375,10 +375,13 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     int32_t *dst = out + at0;
     float *dsdf = kWriteSdf ? sdf + at0 : nullptr;
 
-    // Envelope of this segment's sites; its top two entries in registers.
+    // Envelope of this segment's sites; its top three entries in registers,
+    // so that a pop reads the LDS only for the entry that a second pop
+    // would need.
     int top = -1;
     int pa = 0, ha = 0;  // entry top
     int pb = 0, hb = 0;  // entry top - 1
+    int pc = 0, hc = 0;  // entry top - 2
     for (int qb = q0; qb < q1; qb += kSegBatch) {
       int32_t xb[kSegBatch];
 #pragma unroll
@@ -394,16 +397,18 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
         const int f = x > 0 ? x : 0;
         const int hq = f + mul24(q, q);
         while (top >= 1) {
-          // entry top - 2, read before the test so that a pop finds it
-          const uint32_t ec = env.raw(w, max(top - 2, 0), lane);
           // The top stays if the new parabola overtakes it to the right
           // of where it overtakes the entry below (cross-multiplied).
           if (mul48(hq - ha, pa - pb) > mul48(ha - hb, q - pa)) break;
           --top;
           pa = pb;
           ha = hb;
-          env.decode(w, ec, &pb, &hb);
+          pb = pc;
+          hb = hc;
+          if (top >= 2) env.get(w, top - 2, lane, &pc, &hc);
         }
+        pc = pb;
+        hc = hb;
         pb = pa;
         hb = ha;
         pa = q;
@@ -415,61 +420,78 @@ __global__ __launch_bounds__(64 * S) void k_pass_col_seg(
     tops[w * 64 + lane] = top;
     __syncthreads();
 
-    // Fill this segment from the S envelopes: per envelope its walk
-    // position k and entries k, k + 1.
+    // Fill this segment from the S envelopes.  Envelope j is that of
+    // segment (w + j) mod S: j = 0 is this wave's own, j = 1 .. S-1-w the
+    // segments above, the rest those below.  Per envelope: its walk
+    // position k, entries k and k + 1 decoded and entry k + 2 as read
+    // ahead.  An empty envelope holds one entry of value kFar at every q
+    // (above every real value), so no lane tests for emptiness.
+    constexpr int kFar = 1 << 30;
     int tp[S], k[S], p0[S], h0[S], p1[S], h1[S];
+    uint32_t e2[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      tp[s] = tops[s * 64 + lane];
-      k[s] = 0;
-      p0[s] = h0[s] = p1[s] = h1[s] = 0;
-      if (tp[s] >= 0) env.get(s, 0, lane, &p0[s], &h0[s]);
-      if (tp[s] >= 1) env.get(s, 1, lane, &p1[s], &h1[s]);
+    for (int j = 0; j < S; ++j) {
+      const int s = w + j < S ? w + j : w + j - S;
+      tp[j] = tops[s * 64 + lane];
+      k[j] = 0;
+      p1[j] = h1[j] = 0;
+      e2[j] = 0;
+      if (tp[j] >= 0) {
+        env.get(s, 0, lane, &p0[j], &h0[j]);
+      } else {
+        p0[j] = 0;
+        h0[j] = kFar;
+        tp[j] = 0;
+      }
+      if (tp[j] >= 1) env.get(s, 1, lane, &p1[j], &h1[j]);
+      if (tp[j] >= 2) e2[j] = env.raw(s, 2, lane);
     }
     int32_t *dq = dst;
     float *fq = dsdf;
     for (int q = q0; q < q1; ++q) {
       const int q2 = 2 * q, qq = mul24(q, q);
-      // value of envelope s at q (its walk position moves right only; an
+      // value of envelope j at q (its walk position moves right only; an
       // envelope skipped for some q catches up when next evaluated)
-      auto eval = [&](int s) -> int32_t {
-        while (k[s] < tp[s]) {
+      auto eval = [&](int j) -> int32_t {
+        const int s = w + j < S ? w + j : w + j - S;
+        while (k[j] < tp[j]) {
           // entry k + 1 is no higher at q: h1 - h0 <= 2 q (p1 - p0)
-          if (h1[s] - h0[s] > mul24(q2, p1[s] - p0[s])) break;
-          ++k[s];
-          p0[s] = p1[s];
-          h0[s] = h1[s];
-          if (k[s] < tp[s]) env.get(s, k[s] + 1, lane, &p1[s], &h1[s]);
+          if (h1[j] - h0[j] > mul24(q2, p1[j] - p0[j])) break;
+          ++k[j];
+          p0[j] = p1[j];
+          h0[j] = h1[j];
+          if (k[j] < tp[j]) {
+            env.decode(s, e2[j], &p1[j], &h1[j]);
+            e2[j] = env.raw(s, min(k[j] + 2, tp[j]), lane);
+          }
         }
-        return qq + h0[s] - mul24(q2, p0[s]);
+        return qq + h0[j] - mul24(q2, p0[j]);
       };
-      int32_t val = kInf;
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-        if (s == w && tp[s] >= 0) val = eval(s);
-      // segments below, nearest first
-#pragma unroll
-      for (int s = S - 1; s >= 0; --s) {
-        if (s >= w) continue;
-        const int gap = q - ((s + 1) * L - 1);
-        const bool reach = mul24(gap, gap) < val;
-        if (__ballot(reach) == 0) break;
-        if (reach && tp[s] >= 0) val = min(val, eval(s));
-      }
+      int32_t val = eval(0);
       // segments above, nearest first
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (s <= w) continue;
-        const int gap = s * L - q;
+      for (int j = 1; j < S; ++j) {
+        if (j >= S - w) break;
+        const int gap = (w + j) * L - q;
         const bool reach = mul24(gap, gap) < val;
         if (__ballot(reach) == 0) break;
-        if (reach && tp[s] >= 0) val = min(val, eval(s));
+        if (reach) val = min(val, eval(j));
+      }
+      // segments below, nearest first
+#pragma unroll
+      for (int j = S - 1; j >= 1; --j) {
+        if (j < S - w) break;
+        const int gap = q - ((w + j - S + 1) * L - 1);
+        const bool reach = mul24(gap, gap) < val;
+        if (__ballot(reach) == 0) break;
+        if (reach) val = min(val, eval(j));
       }
       // The free voxels get their value; an occupied voxel is a site of
       // value 0 (left to the free set's channel).
       if (val > 0 && active) {
-        *dq = val;
-        if (kWriteSdf) *fq = ssq_to_metres(val, hf);
+        const int32_t v = val >= kFar ? kInf : val;
+        *dq = v;
+        if (kWriteSdf) *fq = ssq_to_metres(v, hf);
       }
       dq += stride;
       if (kWriteSdf) fq += stride;
