@@ -116,6 +116,108 @@ __global__ __launch_bounds__(256) void k_pass_x(Occ occ, int32_t *out,
   }
 }
 
+// The same pass with VPL adjacent voxels per lane (nx a multiple of VPL,
+// at most 64 VPL): the row's occupancy is one load of VPL bytes per lane
+// and its values VPL / 4 stores of 16 bytes.  Each lane finds the last and
+// first voxel of either type among its own; the nearest lane to the left
+// (right) holding a voxel of a type is a masked ballot's highest (lowest)
+// bit, and that lane's last (first) voxel is read across lanes; a sweep
+// over the lane's voxels then gives each voxel its nearest voxel of the
+// other type on either side.
+template <int VPL>
+struct BytePack;
+template <>
+struct BytePack<4> {
+  typedef uint32_t T;
+};
+template <>
+struct BytePack<8> {
+  typedef uint2 T;
+};
+template <>
+struct BytePack<16> {
+  typedef uint4 T;
+};
+
+template <int VPL>
+__global__ __launch_bounds__(256) void k_pass_x_vec(const uint8_t *occ,
+                                                    int32_t *out, int nx,
+                                                    int64_t rows) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;  // uniform across the wave
+  constexpr int kNone = 0x40000000;
+  const int i0 = lane * VPL;
+  const bool valid = i0 < nx;  // the whole pack: nx is a multiple of VPL
+  typename BytePack<VPL>::T raw{};
+  if (valid)
+    raw = *reinterpret_cast<const typename BytePack<VPL>::T *>(
+        occ + row * nx + i0);
+  const uint8_t *bytes = reinterpret_cast<const uint8_t *>(&raw);
+  uint32_t mo = 0;  // bit j: voxel i0 + j is occupied
+#pragma unroll
+  for (int j = 0; j < VPL; ++j) mo |= (bytes[j] != 0 ? 1u : 0u) << j;
+  const uint32_t mf = valid ? ~mo & ((1u << VPL) - 1u) : 0u;
+  // last / first voxel of each type in this lane
+  const int lastO = mo ? i0 + 31 - __builtin_clz(mo) : -kNone;
+  const int lastF = mf ? i0 + 31 - __builtin_clz(mf) : -kNone;
+  const int firstO = mo ? i0 + __builtin_ctz(mo) : kNone;
+  const int firstF = mf ? i0 + __builtin_ctz(mf) : kNone;
+  const uint64_t anyO = __ballot(mo != 0), anyF = __ballot(mf != 0);
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint64_t above = lane == 63 ? 0ull : ~0ull << (lane + 1);
+  const uint64_t bO = anyO & below, bF = anyF & below;
+  const uint64_t aO = anyO & above, aF = anyF & above;
+  // source lanes (this lane where there is none; its value is not used)
+  const int sbO = bO ? 63 - __builtin_clzll(bO) : lane;
+  const int sbF = bF ? 63 - __builtin_clzll(bF) : lane;
+  const int saO = aO ? __builtin_ctzll(aO) : lane;
+  const int saF = aF ? __builtin_ctzll(aF) : lane;
+  const int pO = __shfl(lastO, sbO), pF = __shfl(lastF, sbF);
+  const int nO = __shfl(firstO, saO), nF = __shfl(firstF, saF);
+  int lO = bO ? pO : -kNone, lF = bF ? pF : -kNone;  // nearest at or left
+  int rO = aO ? nO : kNone, rF = aF ? nF : kNone;    // nearest at or right
+  int left[VPL];  // nearest voxel of the other type to the left
+#pragma unroll
+  for (int j = 0; j < VPL; ++j) {
+    const bool o = (mo >> j) & 1u;
+    left[j] = o ? lF : lO;
+    if (o)
+      lO = i0 + j;
+    else
+      lF = i0 + j;
+  }
+  int32_t v[VPL];
+#pragma unroll
+  for (int j = VPL - 1; j >= 0; --j) {
+    const bool o = (mo >> j) & 1u;
+    const int i = i0 + j;
+    const int r = o ? rF : rO;
+    if (o)
+      rO = i;
+    else
+      rF = i;
+    const int l = left[j];
+    const bool none_l = l < 0, none_r = r >= nx;
+    int32_t d2;
+    if (none_l && none_r) {
+      d2 = kInf;
+    } else {
+      const int dl = none_l ? kNone : i - l;
+      const int dr = none_r ? kNone : r - i;
+      const int d = dl < dr ? dl : dr;
+      d2 = d * d;
+    }
+    v[j] = o ? -d2 : d2;
+  }
+  if (valid) {
+    int4 *dst = reinterpret_cast<int4 *>(out + row * nx + i0);
+#pragma unroll
+    for (int c = 0; c < VPL / 4; ++c)
+      dst[c] = make_int4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+  }
+}
+
 template <class Occ>
 static int launch_x(Handle *h, const Occ &occ, int32_t *out, int nx,
                     int64_t rows, hipStream_t s, const char *what) {
@@ -142,7 +244,28 @@ static int launch_x(Handle *h, const Occ &occ, int32_t *out, int nx,
 
 int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
                      int64_t rows, hipStream_t s) {
-  return launch_x(h, OccU8{occ, nx}, out, nx, rows, s, "pass_x_u8");
+  // VPL voxels per lane where the row fits one wave and every pack is
+  // aligned (occupancy to VPL bytes, values to 16)
+  int vpl = 0;
+  for (int c : {4, 8, 16})
+    if (nx <= 64 * c && nx % c == 0 && !((uintptr_t)occ % c) &&
+        !((uintptr_t)out % 16)) {
+      vpl = c;
+      break;
+    }
+  if (vpl == 0 || rows <= 0)
+    return launch_x(h, OccU8{occ, nx}, out, nx, rows, s, "pass_x_u8");
+  const dim3 grid((unsigned)((rows + 3) / 4)), block(256);
+  if (vpl == 4)
+    hipLaunchKernelGGL((k_pass_x_vec<4>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  else if (vpl == 8)
+    hipLaunchKernelGGL((k_pass_x_vec<8>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  else
+    hipLaunchKernelGGL((k_pass_x_vec<16>), grid, block, 0, s, occ, out, nx,
+                       rows);
+  return check_launch(h, "pass_x_vec");
 }
 
 // ------------------------------------------------------- y / z column pass
@@ -798,7 +921,7 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                         hipGetErrorString(e));
       int rc = check_launch(h, "pass_col_seg");
       if (rc) return rc;
-      // the free set's channel: groups of 8 rows per lane
+      // the free set's channel, kInsideRows rows per lane
       if (sdf_out)
         hipLaunchKernelGGL((k_pass_col_inside<true, kInsideRows>),
                            sgrid(kInsideRows), dim3(256), 0, s, in, out,

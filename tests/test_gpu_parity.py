@@ -59,7 +59,7 @@ def gpu_static(pc, grid, occ, dev):
 STATIC_SHAPES = [  # (nz, ny, nx)
     (1, 1, 1), (1, 1, 9), (1, 7, 1), (5, 1, 1), (4, 5, 6), (12, 12, 12),
     (29, 131, 67), (33, 70, 130), (3, 2, 200), (7, 64, 64), (2, 3, 1024),
-    (1, 300, 257), (1, 256, 256),
+    (1, 300, 257), (1, 256, 256), (5, 9, 264), (3, 4, 512), (2, 4, 528),
 ]
 
 
@@ -72,6 +72,33 @@ def test_static_build_matches_oracle(pc, dev, shape):
         say(f"static shape={shape} p={p}")
         ssq, sdf = gpu_static(pc, grid, occ, dev)
         rs, rf = oracle.build_static(grid, occ)
+        np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
+        assert_f32_close(sdf.cpu().numpy(), rf)
+
+
+@pytest.mark.parametrize("shape", [(6, 9, 64), (4, 5, 264)])
+def test_static_build_unaligned_buffers(pc, dev, shape):
+    """The x pass reads a row's occupancy as one 4-, 8- or 16-byte pack per
+    lane and writes 16-byte packs when the buffers are aligned to them;
+    an occupancy map starting at an odd byte and an output starting 4 bytes
+    past a 16-byte boundary take the voxel-per-lane path: both give the
+    oracle's bytes."""
+    rng = np.random.default_rng(3)
+    grid = scenegen.Grid(shape[2], shape[1], shape[0], 0.05)
+    occ = (rng.random(shape) < 0.05).astype(np.uint8)
+    rs, rf = oracle.build_static(grid, occ)
+    V = occ.size
+    flat = torch.zeros(V + 1, dtype=torch.uint8, device=dev)
+    flat[1:] = to_dev(occ.reshape(-1), dev)
+    occ_odd = flat[1:].view(shape)
+    out = torch.empty(V + 1, dtype=torch.int32, device=dev)
+    ssq_off = out[1:].view(shape)
+    for o, q in ((occ_odd, None), (to_dev(occ, dev), ssq_off),
+                 (occ_odd, ssq_off)):
+        say(f"static unaligned shape={shape} occ+{o.data_ptr() % 16} "
+            f"ssq+{(q.data_ptr() % 16) if q is not None else 0}")
+        ssq, sdf = pc.build_static_sdf(grid, o, ssq=q)
+        torch.cuda.synchronize()
         np.testing.assert_array_equal(ssq.cpu().numpy(), rs)
         assert_f32_close(sdf.cpu().numpy(), rf)
 
