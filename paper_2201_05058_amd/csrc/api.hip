@@ -288,6 +288,9 @@ extern "C" void pcsdf_destroy(pcsdf_handle *hp) {
     h->prof_pool.push_back(p.b);
   }
   for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   delete h;
 }
 

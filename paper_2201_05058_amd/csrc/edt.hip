@@ -862,6 +862,22 @@ static hipError_t launch_seg_any(int S, const int32_t *in, int32_t *out,
   }
 }
 
+// The handle's side stream and its fork and join events, created on first
+// use.
+static int ensure_side_stream(Handle *h) {
+  hipError_t e = hipSuccess;
+  if (!h->side) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !h->fork_ev)
+    e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess && !h->join_ev)
+    e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+  if (e != hipSuccess)
+    return fail(h, PCSDF_ERR_HIP,
+                std::string("creating the side stream: ") +
+                    hipGetErrorString(e));
+  return PCSDF_OK;
+}
+
 // Segments per column: the tuning's, else one per 32 voxels of the column
 // (at most 8: 16 waves of this kernel exceed the registers of a CU's
 // share and were measured slower).
@@ -904,33 +920,54 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
     const size_t lds_seg =
         (size_t)S * L * 64 * (root ? 2 : 4) + (size_t)S * 64 * 4;
     if ((int64_t)lds_seg <= h->max_lds) {
-      // the occupied set's channel by envelopes, 64 columns per wave; then
-      // the free set's channel of the occupied voxels by search
-      const int tiles64 = (nfast + 63) / 64;
-      const int64_t nblocks64 = (int64_t)tiles64 * nouter;
-      const hipError_t e =
-          root ? launch_seg_any<true>(S, in, out, sdf_out, h_f, nfast, m,
-                                      stride, outer_stride, nblocks64,
-                                      tiles64, lds_seg, s)
-               : launch_seg_any<false>(S, in, out, sdf_out, h_f, nfast, m,
-                                       stride, outer_stride, nblocks64,
-                                       tiles64, lds_seg, s);
+      // The free set's channel of the occupied voxels by search, on the
+      // side stream, beside the occupied set's channel by envelopes (64
+      // columns per wave) on the caller's: they read the same input and
+      // write disjoint voxels, and the search's memory waits fill the
+      // envelope kernel's issue gaps.
+      int rc = ensure_side_stream(h);
+      if (rc) return rc;
+      hipError_t e = hipEventRecord(h->fork_ev, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork_ev, 0);
       if (e != hipSuccess)
         return fail(h, PCSDF_ERR_HIP,
-                    std::string("raising the LDS limit of pass_col_seg: ") +
+                    std::string("forking the side stream: ") +
                         hipGetErrorString(e));
-      int rc = check_launch(h, "pass_col_seg");
-      if (rc) return rc;
-      // the free set's channel, kInsideRows rows per lane
       if (sdf_out)
         hipLaunchKernelGGL((k_pass_col_inside<true, kInsideRows>),
-                           sgrid(kInsideRows), dim3(256), 0, s, in, out,
+                           sgrid(kInsideRows), dim3(256), 0, h->side, in, out,
                            sdf_out, h_f, nfast, m, stride, outer_stride);
       else
         hipLaunchKernelGGL((k_pass_col_inside<false, kInsideRows>),
-                           sgrid(kInsideRows), dim3(256), 0, s, in, out,
+                           sgrid(kInsideRows), dim3(256), 0, h->side, in, out,
                            sdf_out, h_f, nfast, m, stride, outer_stride);
-      return check_launch(h, "pass_col_inside");
+      rc = check_launch(h, "pass_col_inside");
+      if (!rc) {
+        const int tiles64 = (nfast + 63) / 64;
+        const int64_t nblocks64 = (int64_t)tiles64 * nouter;
+        e = root ? launch_seg_any<true>(S, in, out, sdf_out, h_f, nfast, m,
+                                        stride, outer_stride, nblocks64,
+                                        tiles64, lds_seg, s)
+                 : launch_seg_any<false>(S, in, out, sdf_out, h_f, nfast, m,
+                                         stride, outer_stride, nblocks64,
+                                         tiles64, lds_seg, s);
+        if (e != hipSuccess)
+          rc = fail(h, PCSDF_ERR_HIP,
+                    std::string("raising the LDS limit of pass_col_seg: ") +
+                        hipGetErrorString(e));
+        else
+          rc = check_launch(h, "pass_col_seg");
+      }
+      // join in every case, so that no work of this call outlives it on
+      // the side stream
+      e = hipEventRecord(h->join_ev, h->side);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, h->join_ev, 0);
+      if (rc) return rc;
+      if (e != hipSuccess)
+        return fail(h, PCSDF_ERR_HIP,
+                    std::string("joining the side stream: ") +
+                        hipGetErrorString(e));
+      return PCSDF_OK;
     }
   }
   const size_t lds = (size_t)m * 64 * sizeof(uint32_t);

@@ -42,6 +42,11 @@ struct Handle {
   DevBuf union_buf;     // full recompute: uint8 union map of one slice
   DevBuf tmpl_buf;      // shifted-template composite: per-human windows
   std::vector<char> batch_host;  // batch parameter block before upload
+  // A second stream on the handle's device, forked from and joined back to
+  // the caller's stream with the two events: the static build runs the
+  // free set's channel of a column pass on it, beside the envelope kernel.
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   pcsdf_tuning tuning = {};  // launch shapes; 0 = default
   // pinned host staging for small per-call parameter blocks: a ring of
   // slots, so that a call only waits for the upload made kStagingSlots
