@@ -643,6 +643,42 @@ def mlp_rows(n: int, weights: str, reps: int = 10):
     net.close()
 
 
+def static_builds(workloads, reps: int):
+    """The static build (pcsdf_build_static_sdf) of each workload's map,
+    `reps` builds per round, three rounds: the best round's mean build
+    time by the library's HIP events (kernel-trace and counter runs use
+    this mode)."""
+    import torch
+
+    import paper_2201_05058_amd as pc
+    import scenegen
+    from paper_2201_05058_amd import _native
+    torch.cuda.set_device(0)
+    out = {}
+    for name in workloads:
+        sc = (scenegen.room256() if name == "room256"
+              else scenegen.room512(with_queries=False))
+        occ = torch.from_numpy(sc.occ).cuda()
+        h = pc.Handle()
+        pc.build_static_sdf(sc.grid, occ, handle=h)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            h.profile(True, only=[_native.KERNEL_STATIC])
+            h.profile_reset()
+            for _ in range(reps):
+                pc.build_static_sdf(sc.grid, occ, handle=h)
+            torch.cuda.synchronize()
+            ms = h.profile_read(_native.KERNEL_STATIC)[0] / reps
+            best = ms if best is None else min(best, ms)
+        h.profile(False)
+        h.close()
+        out[name + "_static_build_ms"] = best
+        del occ
+        torch.cuda.empty_cache()
+    print(json.dumps(out))
+
+
 def calibrate_copy(mib: int, reps: int):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -673,6 +709,9 @@ def main():
     ap.add_argument("--mlp-rows", type=int, default=0,
                     help="time the fused surrogate network on this many "
                          "rows and exit")
+    ap.add_argument("--static-builds", type=int, default=0,
+                    help="time this many static builds per round of the "
+                         "256x256x128 and 512x512x256 maps and exit")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-scene batch measurement")
     ap.add_argument("--no-room256", action="store_true",
@@ -699,6 +738,9 @@ def main():
     if args.mlp_rows:
         mlp_rows(args.mlp_rows, os.path.join(args.weights_dir,
                                              "surrogate_room256.npz"))
+        return
+    if args.static_builds:
+        static_builds(["room256", "room512"], args.static_builds)
         return
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib, max(1, args.steps))
