@@ -66,6 +66,9 @@ __device__ __forceinline__ int4 disk_box(int64_t X, int64_t Y, int64_t R,
   return b;
 }
 
+// v^2 on the full-rate 24-bit multiplier: pixel offsets are below 2^11.
+__device__ __forceinline__ int32_t sq24(int v) { return __mul24(v, v); }
+
 __device__ __forceinline__ bool covers(int2 c, int i) {
   return c.x <= i && i <= c.y;
 }
@@ -100,7 +103,7 @@ __device__ __forceinline__ int32_t row_free_dist(const Tab &ch, int K, int ny,
   const int dl = lo >= 1 ? i - lo + 1 : kInfP;
   const int dr = hi <= nx - 2 ? hi + 1 - i : kInfP;
   const int d = dl < dr ? dl : dr;
-  return d == kInfP ? kInfP : d * d;
+  return d == kInfP ? kInfP : sq24(d);
 }
 
 // Chord table views: LDS (ds_read) or global memory through the cache.
@@ -124,7 +127,7 @@ __device__ __forceinline__ int32_t scan_rows(const Tab &ch, int base, int i,
     const int dy0 = jj - j;
     // every remaining row is at least this far: (dy)^2 plus the squared
     // distance to the disk's x extent
-    if (dy0 * dy0 + dxb2 >= best) break;
+    if (sq24(dy0) + dxb2 >= best) break;
     int2 c[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -137,7 +140,7 @@ __device__ __forceinline__ int32_t scan_rows(const Tab &ch, int base, int i,
       const int dy = dy0 + u * dir;
       if (c[u].x > c[u].y) continue;
       const int dx = i < c[u].x ? c[u].x - i : (i > c[u].y ? i - c[u].y : 0);
-      best = min(best, dy * dy + dx * dx);
+      best = min(best, sq24(dy) + sq24(dx));
     }
   }
   return best;
@@ -152,8 +155,8 @@ __device__ __forceinline__ int32_t scan_disk(const Tab &ch, int4 b, int k,
   if (b.x > b.y || b.z > b.w) return best;
   const int dxb = max(0, max(b.x - i, i - b.y));
   const int dyb = max(0, max(b.z - j, j - b.w));
-  const int dxb2 = dxb * dxb;
-  if (dxb2 + dyb * dyb >= best) return best;
+  const int dxb2 = sq24(dxb);
+  if (dxb2 + sq24(dyb) >= best) return best;
   const int j0 = min(max(j, b.z), b.w);
   best = scan_rows(ch, k * ny, i, j, j0, b.w, +1, dxb2, best);
   return scan_rows(ch, k * ny, i, j, j0 - 1, b.z, -1, dxb2, best);
@@ -165,7 +168,7 @@ struct RowFreeTable {
   const int32_t *f1;
   int nx;
   __device__ __forceinline__ int32_t operator()(int jr) const {
-    return f1[(int64_t)jr * nx];
+    return f1[__mul24(jr, nx)];  // jr nx < 2^20
   }
 };
 template <class Tab>
@@ -200,7 +203,7 @@ __device__ __forceinline__ int32_t plane_value_rf(const Tab &ch,
       if (b.x > b.y || b.z > b.w) continue;
       const int dxb = max(0, max(b.x - i, i - b.y));
       const int dyb = max(0, max(b.z - j, j - b.w));
-      const int lb = dxb * dxb + dyb * dyb;
+      const int lb = sq24(dxb) + sq24(dyb);
       if (lb < lbmin) {
         lbmin = lb;
         kbest = k;
@@ -217,7 +220,7 @@ __device__ __forceinline__ int32_t plane_value_rf(const Tab &ch,
     int32_t best = rf(j);
     const int dmax = max(j, ny - 1 - j);
     for (int d0 = 1; d0 <= dmax; d0 += 4) {
-      if (d0 * d0 >= best) break;
+      if (sq24(d0) >= best) break;
       int32_t v[8];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -227,7 +230,7 @@ __device__ __forceinline__ int32_t plane_value_rf(const Tab &ch,
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int d2 = (d0 + u) * (d0 + u);
+        const int d2 = sq24(d0 + u);
         if (v[2 * u] != kInfP) best = min(best, d2 + v[2 * u]);
         if (v[2 * u + 1] != kInfP) best = min(best, d2 + v[2 * u + 1]);
       }

@@ -51,25 +51,29 @@ __global__ __launch_bounds__(256) void k_chords(Centres C, int K, int nx,
 // Row pass of the free-set channel for every pixel of every slice:
 // F1[s][j][i] = squared distance along row j to the nearest uncovered
 // pixel (0 when (i, j) is uncovered, kInf when the whole row is covered).
+// Block b takes pixels 256 (b mod bpr) + 0..255 of row b / bpr of all
+// slices' rows: the row, and so its chords, is uniform over the block.
 __global__ __launch_bounds__(256) void k_rowfree(
-    const int2 *__restrict__ chords, int K, int nx, int ny, int64_t total,
+    const int2 *__restrict__ chords, int K, int nx, int ny, int bpr,
     const int32_t *__restrict__ need, int32_t *__restrict__ F1) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= total) return;
-  const int64_t row = t / nx;  // s*ny + j
-  const int i = (int)(t - row * nx);
-  const int64_t s = row / ny;
-  if (need && need[s] == 0) return;
-  const int j = (int)(row - s * ny);
-  const GlobalTab ch{chords + s * K * ny};
-  F1[t] = row_free_dist(ch, K, ny, nx, j, i);
+  const int row = (int)(blockIdx.x / (unsigned)bpr);  // s*ny + j
+  const int i = (int)(blockIdx.x - (unsigned)row * bpr) * 256 + threadIdx.x;
+  const int s = row / ny;
+  if (i >= nx || (need && need[s] == 0)) return;
+  const int j = row - s * ny;
+  const GlobalTab ch{chords + (int64_t)s * K * ny};
+  F1[(int64_t)row * nx + i] = row_free_dist(ch, K, ny, nx, j, i);
 }
 
 // One block per (tile, slice).  The slice's chords (K*ny pairs) are staged
 // in LDS when they fit (kLds), else read through the cache from global
-// memory; the disks' bounding boxes always live in LDS.
+// memory; the disks' bounding boxes always live in LDS.  Blocks of 16
+// waves: two share a CU's waves at 33 KB of LDS each for 8 humans x 512
+// rows (blocks of 4 waves would be limited to 16 waves per CU by LDS),
+// and the per-pixel row scans are chains of LDS round trips.
+constexpr int kPlaneThreads = 1024;
 template <bool kLds>
-__global__ __launch_bounds__(256) void k_planes(
+__global__ __launch_bounds__(kPlaneThreads) void k_planes(
     const int2 *__restrict__ chords, Centres C, int K, int nx, int ny,
     int tiles, const int32_t *__restrict__ F1,
     const int32_t *__restrict__ need, int32_t *__restrict__ P) {
@@ -82,8 +86,8 @@ __global__ __launch_bounds__(256) void k_planes(
   int4 *box = sh4;                                   // K boxes
   int2 *lch = reinterpret_cast<int2 *>(sh4 + K);     // K*ny chords
   if (kLds)
-    for (int t = threadIdx.x; t < K * ny; t += 256) lch[t] = gch[t];
-  for (int k = threadIdx.x; k < K; k += 256) {
+    for (int t = threadIdx.x; t < K * ny; t += kPlaneThreads) lch[t] = gch[t];
+  for (int k = threadIdx.x; k < K; k += kPlaneThreads) {
     const int64_t X = centre_word(C, 2 * ((int64_t)s * K + k));
     const int64_t Y = centre_word(C, 2 * ((int64_t)s * K + k) + 1);
     const int4 b = disk_box(X, Y, R, nx, ny);
@@ -94,7 +98,8 @@ __global__ __launch_bounds__(256) void k_planes(
                                                                    : gch};
 
   const int npx = nx * ny;
-  for (int p = tile * 256 + threadIdx.x; p < npx; p += tiles * 256) {
+  for (int p = tile * kPlaneThreads + threadIdx.x; p < npx;
+       p += tiles * kPlaneThreads) {
     const int j = p / nx;
     const int i = p - j * nx;
     const int32_t out = plane_value(ch, box, F1 + (int64_t)s * npx + i, K, nx,
@@ -122,19 +127,21 @@ int launch_planes(Handle *h, const Centres &C, int K, bool empty,
   int32_t *F1 = P + (int64_t)n_slices * npx;
   const int64_t npix = (int64_t)n_slices * npx;
   if (Keff > 0) {
-    launch_timed(h, k_rowfree, dim3((unsigned)((npix + 255) / 256)),
-                 dim3(256), 0, s, chords, Keff, nx, ny, npix, need, F1);
+    const int bpr = (nx + 255) / 256;
+    launch_timed(h, k_rowfree, dim3((unsigned)(npix / nx * bpr)), dim3(256),
+                 0, s, chords, Keff, nx, ny, bpr, need, F1);
     int rc = check_launch(h, "rowfree");
     if (rc) return rc;
   }
-  int tiles = (2048 + n_slices - 1) / n_slices;
-  const int maxt = (npx + 255) / 256;
+  int tiles = (512 + n_slices - 1) / n_slices;
+  const int maxt = (npx + kPlaneThreads - 1) / kPlaneThreads;
   if (tiles > maxt) tiles = maxt;
   if (tiles < 1) tiles = 1;
   const size_t box_bytes = (size_t)Keff * sizeof(int4);
   const size_t ch_bytes = (size_t)Keff * ny * sizeof(int2);
   const bool use_lds = box_bytes + ch_bytes <= 48 * 1024;
-  const dim3 grid((unsigned)((int64_t)tiles * n_slices)), block(256);
+  const dim3 grid((unsigned)((int64_t)tiles * n_slices)),
+      block(kPlaneThreads);
   if (use_lds)
     launch_timed(h, k_planes<true>, grid, block,
                  (uint32_t)(box_bytes + ch_bytes), s, chords, C, Keff, nx, ny,
