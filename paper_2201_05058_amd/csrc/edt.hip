@@ -225,19 +225,19 @@ static int launch_x(Handle *h, const Occ &occ, int32_t *out, int nx,
   const int nch = (nx + 63) / 64;
   const dim3 grid((unsigned)((rows + 3) / 4)), block(256);
   if (nch <= 1)
-    hipLaunchKernelGGL((k_pass_x<1, Occ>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x<1, Occ>, grid, block, 0, s, occ, out, nx,
                        rows);
   else if (nch <= 2)
-    hipLaunchKernelGGL((k_pass_x<2, Occ>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x<2, Occ>, grid, block, 0, s, occ, out, nx,
                        rows);
   else if (nch <= 4)
-    hipLaunchKernelGGL((k_pass_x<4, Occ>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x<4, Occ>, grid, block, 0, s, occ, out, nx,
                        rows);
   else if (nch <= 8)
-    hipLaunchKernelGGL((k_pass_x<8, Occ>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x<8, Occ>, grid, block, 0, s, occ, out, nx,
                        rows);
   else
-    hipLaunchKernelGGL((k_pass_x<16, Occ>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x<16, Occ>, grid, block, 0, s, occ, out, nx,
                        rows);
   return check_launch(h, what);
 }
@@ -257,13 +257,13 @@ int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
     return launch_x(h, OccU8{occ, nx}, out, nx, rows, s, "pass_x_u8");
   const dim3 grid((unsigned)((rows + 3) / 4)), block(256);
   if (vpl == 4)
-    hipLaunchKernelGGL((k_pass_x_vec<4>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x_vec<4>, grid, block, 0, s, occ, out, nx,
                        rows);
   else if (vpl == 8)
-    hipLaunchKernelGGL((k_pass_x_vec<8>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x_vec<8>, grid, block, 0, s, occ, out, nx,
                        rows);
   else
-    hipLaunchKernelGGL((k_pass_x_vec<16>), grid, block, 0, s, occ, out, nx,
+    launch_timed(h, k_pass_x_vec<16>, grid, block, 0, s, occ, out, nx,
                        rows);
   return check_launch(h, "pass_x_vec");
 }
@@ -817,7 +817,8 @@ static hipError_t allow_lds(const void *kernel, size_t bytes) {
 }
 
 template <int S, bool kRoot>
-static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
+static hipError_t launch_seg(Handle *h, const int32_t *in, int32_t *out,
+                             float *sdf_out,
                              float h_f, int nfast, int m, int64_t stride,
                              int64_t outer_stride, int64_t nblocks, int tiles,
                              size_t lds, hipStream_t s) {
@@ -828,7 +829,7 @@ static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
         reinterpret_cast<const void *>(&k_pass_col_seg<S, true, kRoot>),
         lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, true, kRoot>), dim3(grid),
+    launch_timed(h, k_pass_col_seg<S, true, kRoot>, dim3(grid),
                        dim3(64 * S), lds, s, in, out, sdf_out, h_f, nfast, m,
                        stride, outer_stride, nblocks, tiles);
   } else {
@@ -836,7 +837,7 @@ static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
         reinterpret_cast<const void *>(&k_pass_col_seg<S, false, kRoot>),
         lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pass_col_seg<S, false, kRoot>), dim3(grid),
+    launch_timed(h, k_pass_col_seg<S, false, kRoot>, dim3(grid),
                        dim3(64 * S), lds, s, in, out, sdf_out, h_f, nfast, m,
                        stride, outer_stride, nblocks, tiles);
   }
@@ -844,20 +845,21 @@ static hipError_t launch_seg(const int32_t *in, int32_t *out, float *sdf_out,
 }
 
 template <bool kRoot>
-static hipError_t launch_seg_any(int S, const int32_t *in, int32_t *out,
+static hipError_t launch_seg_any(Handle *h, int S, const int32_t *in,
+                                 int32_t *out,
                                  float *sdf_out, float h_f, int nfast, int m,
                                  int64_t stride, int64_t outer_stride,
                                  int64_t nblocks, int tiles, size_t lds,
                                  hipStream_t s) {
   switch (S) {
     case 2:
-      return launch_seg<2, kRoot>(in, out, sdf_out, h_f, nfast, m, stride,
+      return launch_seg<2, kRoot>(h, in, out, sdf_out, h_f, nfast, m, stride,
                                   outer_stride, nblocks, tiles, lds, s);
     case 4:
-      return launch_seg<4, kRoot>(in, out, sdf_out, h_f, nfast, m, stride,
+      return launch_seg<4, kRoot>(h, in, out, sdf_out, h_f, nfast, m, stride,
                                   outer_stride, nblocks, tiles, lds, s);
     default:
-      return launch_seg<8, kRoot>(in, out, sdf_out, h_f, nfast, m, stride,
+      return launch_seg<8, kRoot>(h, in, out, sdf_out, h_f, nfast, m, stride,
                                   outer_stride, nblocks, tiles, lds, s);
   }
 }
@@ -889,7 +891,7 @@ static int column_segments(const Handle *h, int m) {
 int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                     float *sdf_out, float h_f, int nfast, int nouter, int m,
                     int64_t stride, int64_t outer_stride, bool square_input,
-                    hipStream_t s) {
+                    bool use_side, hipStream_t s) {
   if (nfast <= 0 || nouter <= 0 || m <= 0) return PCSDF_OK;
   const int tiles = (nfast + 31) / 32;
   const int64_t nblocks = (int64_t)tiles * nouter;
@@ -901,11 +903,11 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   };
   if (nblocks < kSearchTiles && h->tuning.static_segments == 0) {
     if (sdf_out)
-      hipLaunchKernelGGL((k_pass_col_search<true>), sgrid(1),
+      launch_timed(h, k_pass_col_search<true>, sgrid(1),
                          dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
                          stride, outer_stride);
     else
-      hipLaunchKernelGGL((k_pass_col_search<false>), sgrid(1),
+      launch_timed(h, k_pass_col_search<false>, sgrid(1),
                          dim3(256), 0, s, in, out, sdf_out, h_f, nfast, m,
                          stride, outer_stride);
     return check_launch(h, "pass_col_search");
@@ -921,34 +923,40 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
         (size_t)S * L * 64 * (root ? 2 : 4) + (size_t)S * 64 * 4;
     if ((int64_t)lds_seg <= h->max_lds) {
       // The free set's channel of the occupied voxels by search, on the
-      // side stream, beside the occupied set's channel by envelopes (64
-      // columns per wave) on the caller's: they read the same input and
-      // write disjoint voxels, and the search's memory waits fill the
-      // envelope kernel's issue gaps.
-      int rc = ensure_side_stream(h);
-      if (rc) return rc;
-      hipError_t e = hipEventRecord(h->fork_ev, s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork_ev, 0);
-      if (e != hipSuccess)
-        return fail(h, PCSDF_ERR_HIP,
-                    std::string("forking the side stream: ") +
-                        hipGetErrorString(e));
+      // side stream (use_side), beside the occupied set's channel by
+      // envelopes (64 columns per wave) on the caller's: they read the same
+      // input and write disjoint voxels, and the search's memory waits
+      // fill the envelope kernel's issue gaps.  Without use_side both run
+      // on the caller's stream, one after the other.
+      hipStream_t ss = s;
+      int rc = PCSDF_OK;
+      hipError_t e = hipSuccess;
+      if (use_side) {
+        if ((rc = ensure_side_stream(h))) return rc;
+        e = hipEventRecord(h->fork_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork_ev, 0);
+        if (e != hipSuccess)
+          return fail(h, PCSDF_ERR_HIP,
+                      std::string("forking the side stream: ") +
+                          hipGetErrorString(e));
+        ss = h->side;
+      }
       if (sdf_out)
-        hipLaunchKernelGGL((k_pass_col_inside<true, kInsideRows>),
-                           sgrid(kInsideRows), dim3(256), 0, h->side, in, out,
-                           sdf_out, h_f, nfast, m, stride, outer_stride);
+        launch_timed(h, k_pass_col_inside<true, kInsideRows>,
+                     sgrid(kInsideRows), dim3(256), 0, ss, in, out, sdf_out,
+                     h_f, nfast, m, stride, outer_stride);
       else
-        hipLaunchKernelGGL((k_pass_col_inside<false, kInsideRows>),
-                           sgrid(kInsideRows), dim3(256), 0, h->side, in, out,
-                           sdf_out, h_f, nfast, m, stride, outer_stride);
+        launch_timed(h, k_pass_col_inside<false, kInsideRows>,
+                     sgrid(kInsideRows), dim3(256), 0, ss, in, out, sdf_out,
+                     h_f, nfast, m, stride, outer_stride);
       rc = check_launch(h, "pass_col_inside");
       if (!rc) {
         const int tiles64 = (nfast + 63) / 64;
         const int64_t nblocks64 = (int64_t)tiles64 * nouter;
-        e = root ? launch_seg_any<true>(S, in, out, sdf_out, h_f, nfast, m,
+        e = root ? launch_seg_any<true>(h, S, in, out, sdf_out, h_f, nfast, m,
                                         stride, outer_stride, nblocks64,
                                         tiles64, lds_seg, s)
-                 : launch_seg_any<false>(S, in, out, sdf_out, h_f, nfast, m,
+                 : launch_seg_any<false>(h, S, in, out, sdf_out, h_f, nfast, m,
                                          stride, outer_stride, nblocks64,
                                          tiles64, lds_seg, s);
         if (e != hipSuccess)
@@ -958,6 +966,7 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
         else
           rc = check_launch(h, "pass_col_seg");
       }
+      if (!use_side) return rc;
       // join in every case, so that no work of this call outlives it on
       // the side stream
       e = hipEventRecord(h->join_ev, h->side);
@@ -984,11 +993,11 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                   std::string("raising the LDS limit of pass_col: ") +
                       hipGetErrorString(e));
     if (sdf_out)
-      hipLaunchKernelGGL((k_pass_col<false, true>), dim3(grid), block, lds,
+      launch_timed(h, k_pass_col<false, true>, dim3(grid), block, lds,
                          s, in, out, sdf_out, h_f, nfast, m, stride,
                          outer_stride, nblocks, tiles, nullptr);
     else
-      hipLaunchKernelGGL((k_pass_col<false, false>), dim3(grid), block, lds,
+      launch_timed(h, k_pass_col<false, false>, dim3(grid), block, lds,
                          s, in, out, sdf_out, h_f, nfast, m, stride,
                          outer_stride, nblocks, tiles, nullptr);
     return check_launch(h, "pass_col");
@@ -1000,11 +1009,11 @@ int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
   if (rc) return rc;
   uint32_t *gstack = reinterpret_cast<uint32_t *>(h->stack_buf.ptr);
   if (sdf_out)
-    hipLaunchKernelGGL((k_pass_col<true, true>), dim3((unsigned)gblocks),
+    launch_timed(h, k_pass_col<true, true>, dim3((unsigned)gblocks),
                        block, 0, s, in, out, sdf_out, h_f, nfast, m, stride,
                        outer_stride, nblocks, tiles, gstack);
   else
-    hipLaunchKernelGGL((k_pass_col<true, false>), dim3((unsigned)gblocks),
+    launch_timed(h, k_pass_col<true, false>, dim3((unsigned)gblocks),
                        block, 0, s, in, out, sdf_out, h_f, nfast, m, stride,
                        outer_stride, nblocks, tiles, gstack);
   return check_launch(h, "pass_col_global_stack");
@@ -1041,8 +1050,8 @@ extern "C" int pcsdf_build_static_sdf(pcsdf_handle *hp, const pcsdf_grid *g,
     return rc;
   // the y pass reads the x pass's squared distances (perfect squares)
   if ((rc = launch_pass_col(h, ssq_dev, tmp, nullptr, hf, nx, nz, ny, nx,
-                            (int64_t)nx * ny, true, s)))
+                            (int64_t)nx * ny, true, true, s)))
     return rc;
   return launch_pass_col(h, tmp, ssq_dev, sdf_dev, hf, nx, ny, nz,
-                         (int64_t)nx * ny, nx, false, s);
+                         (int64_t)nx * ny, nx, false, true, s);
 }

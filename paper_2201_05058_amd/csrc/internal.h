@@ -158,10 +158,13 @@ int launch_pass_x_u8(Handle *h, const uint8_t *occ, int32_t *out, int nx,
 // element q of column (i, o) is at o*outer_stride + i + q*stride, q < m.
 // Input and output are signed-squared partial fields (see edt.hip).
 // When sdf_out is non-null the pass also writes F(out) with voxel size h.
+// square_input: the inputs are perfect squares (an x pass's output).
+// use_side: the free set's channel may run on the handle's side stream
+// (created on first use), joined back before the call returns.
 int launch_pass_col(Handle *h, const int32_t *in, int32_t *out,
                     float *sdf_out, float h_f, int nfast, int nouter, int m,
                     int64_t stride, int64_t outer_stride, bool square_input,
-                    hipStream_t s);
+                    bool use_side, hipStream_t s);
 
 // ---- implemented in planes.hip -----------------------------------------
 

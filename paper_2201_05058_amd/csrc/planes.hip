@@ -65,6 +65,23 @@ __global__ __launch_bounds__(256) void k_rowfree(
   F1[(int64_t)row * nx + i] = row_free_dist(ch, K, ny, nx, j, i);
 }
 
+// Coverage of every pixel of every slice by the disks, one byte per pixel
+// (1: covered): the map whose 2-D signed EDT is the planar field.  Block b
+// takes pixels 256 (b mod bpr) + 0..255 of row b / bpr of all slices'
+// rows: the row's chords are uniform over the block.
+__global__ __launch_bounds__(256) void k_cover(
+    const int2 *__restrict__ chords, int K, int nx, int ny, int bpr,
+    uint8_t *__restrict__ cov) {
+  const int row = (int)(blockIdx.x / (unsigned)bpr);  // s*ny + j
+  const int i = (int)(blockIdx.x - (unsigned)row * bpr) * 256 + threadIdx.x;
+  if (i >= nx) return;
+  const int s = row / ny, j = row - s * ny;
+  const int2 *ch = chords + (int64_t)s * K * ny + j;
+  bool c = false;
+  for (int k = 0; k < K; ++k) c = c || covers(ch[k * ny], i);
+  cov[(int64_t)row * nx + i] = c ? 1 : 0;
+}
+
 // One block per (tile, slice).  The slice's chords (K*ny pairs) are staged
 // in LDS when they fit (kLds), else read through the cache from global
 // memory; the disks' bounding boxes always live in LDS.  Blocks of 16
@@ -126,6 +143,29 @@ int launch_planes(Handle *h, const Centres &C, int K, bool empty,
   const int npx = nx * ny;
   int32_t *F1 = P + (int64_t)n_slices * npx;
   const int64_t npix = (int64_t)n_slices * npx;
+  if (!need && Keff > 0 && ny <= 512 &&
+      (int64_t)((nx + 63) / 64) * n_slices >= 256) {
+    // Every slice of a large stack: the planar field is the 2-D signed EDT
+    // of the disks' coverage, by the static build's row pass and y column
+    // pass over the stack of slices (each slice a z layer of an
+    // nx x ny x n grid).  The coverage bytes use the front of P, the row
+    // pass's output the back.  Columns of at most 512 pixels keep the
+    // column pass's envelopes in LDS (16-bit entries), so that no
+    // workspace is allocated; below one workgroup of column segments per
+    // CU (64 columns of a slice each) the per-pixel kernel below is faster
+    // (512 x 512 x 50 slices: 0.27 ms against 0.47; 256 x 256 x 20: 0.076
+    // against 0.035).
+    uint8_t *cov = reinterpret_cast<uint8_t *>(P);
+    const int bpr = (nx + 255) / 256;
+    launch_timed(h, k_cover, dim3((unsigned)(npix / nx * bpr)), dim3(256),
+                 0u, s, chords, Keff, nx, ny, bpr, cov);
+    int rc = check_launch(h, "cover");
+    if (!rc) rc = launch_pass_x_u8(h, cov, F1, nx, (int64_t)n_slices * ny, s);
+    if (!rc)
+      rc = launch_pass_col(h, F1, P, nullptr, 1.0f, nx, n_slices, ny, nx,
+                           (int64_t)npx, true, false, s);
+    return rc;
+  }
   if (Keff > 0) {
     const int bpr = (nx + 255) / 256;
     launch_timed(h, k_rowfree, dim3((unsigned)(npix / nx * bpr)), dim3(256),

@@ -22,6 +22,12 @@ using std::max;
 struct Dim3 { unsigned x = 0, y = 0, z = 0; };
 extern thread_local Dim3 threadIdx, blockIdx, blockDim, gridDim;
 inline void __syncthreads() {}
+// the 24-bit multiplier: the low 24 bits of each operand, sign-extended
+inline int __mul24(int a, int b) {
+  return static_cast<int>(
+      static_cast<unsigned>(static_cast<int>(static_cast<unsigned>(a) << 8) >> 8) *
+      static_cast<unsigned>(static_cast<int>(static_cast<unsigned>(b) << 8) >> 8));
+}
 inline void __threadfence() { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
 #define __HIP_MEMORY_SCOPE_AGENT 0
 #define __hip_atomic_load(p, o, s) __atomic_load_n((p), (o))

@@ -1,9 +1,11 @@
 """The composite entry point that allocates nothing
 (pcsdf_predicted_composite_sdf_noalloc), called through the C-ABI, against
-pcsdf_predicted_composite_sdf: identical int32 and fp32 fields on two
-calls in a row, the second with a smaller grid, fewer slices and humans
-(the shared scratch keeps the first call's contents), and the oracle on
-the second."""
+pcsdf_predicted_composite_sdf: identical int32 and fp32 fields on calls in
+a row, each with a smaller grid, fewer slices and humans (the shared
+scratch keeps the previous call's contents), and the oracle on the first
+and the last.  The first call's stack of planes (16 slices of 1024 x 128)
+is large enough for the planar fields' separable path (coverage, row pass
+and column pass), the others take the per-pixel kernel."""
 import ctypes as C
 import sys
 
@@ -45,7 +47,9 @@ def noalloc(pc, h, sc, ssq_s, dev):
 def test_noalloc_matches_composite_twice(dev):
     import paper_2201_05058_amd as pc
     h = pc.Handle()
-    scenes = [scenegen.small_scene(31, 96, 80, 40, h=0.04, n_boxes=8,
+    scenes = [scenegen.small_scene(30, 1024, 128, 6, h=0.02, n_boxes=12,
+                                   n_humans=4, n_slices=16),
+              scenegen.small_scene(31, 96, 80, 40, h=0.04, n_boxes=8,
                                    n_humans=3, n_slices=6),
               scenegen.small_scene(32, 37, 29, 23, h=0.05, n_boxes=4,
                                    n_humans=2, n_slices=3)]
@@ -62,7 +66,8 @@ def test_noalloc_matches_composite_twice(dev):
         np.testing.assert_array_equal(c, wc.cpu().numpy())
         np.testing.assert_array_equal(cf.view(np.int32),
                                       wf.cpu().numpy().view(np.int32))
-        if q == 1:
+        if q in (0, len(scenes) - 1):
+            say("  against the oracle")
             rs, _ = oracle.build_static(sc.grid, sc.occ)
             oc, of = oracle.predicted_composite(sc.grid, rs, sc.human_xy,
                                                 sc.radius, sc.height)
