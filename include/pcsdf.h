@@ -61,7 +61,8 @@ enum pcsdf_status_code {
 
 /* Timed regions of pcsdf_profile_read. */
 #define PCSDF_KERNEL_COMPOSITE 0 /* streaming composite epilogue kernel */
-#define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (chords, row pass, planes) */
+#define PCSDF_KERNEL_PLANES 1    /* humans' planar EDT (chords, coverage or
+                                    row pass, then the planes) */
 #define PCSDF_KERNEL_QUERY 2     /* sphere query kernel */
 #define PCSDF_KERNEL_STATIC 3    /* the three passes of the static build */
 #define PCSDF_KERNEL_BATCH 4     /* a batch: both of its launches */
@@ -90,9 +91,9 @@ typedef struct pcsdf_grid {
  * NULL, PCSDF_ERR_OOM if the host allocation fails. */
 int pcsdf_create(pcsdf_handle **out);
 
-/* Waits for the handle's pending uploads, frees its workspace and the
- * handle.  NULL is ignored.  Device buffers passed to earlier calls are
- * not touched. */
+/* Waits for the handle's pending uploads, frees its workspace, its second
+ * stream and the handle.  NULL is ignored.  Device buffers passed to
+ * earlier calls are not touched. */
 void pcsdf_destroy(pcsdf_handle *h);
 
 /* Message of the last failed call on this handle ("" if none).  The
@@ -108,7 +109,12 @@ const char *pcsdf_status_string(int status);
  *   occ_dev  [V] uint8, nonzero = occupied.             (device, read)
  *   ssq_dev  [V] int32 SSQ of the occupied set.         (device, written)
  *   sdf_dev  [V] fp32 F(SSQ), may be NULL.              (device, written)
- * Uses a workspace of 4*V bytes.  Exact: the int32 result is unique. */
+ * Uses a workspace of 4*V bytes.  Exact: the int32 result is unique.
+ * Part of the work may run on a second stream the handle owns (created at
+ * the first call that needs it, destroyed with the handle), ordered after
+ * the work enqueued on `stream` before the call and joined back into
+ * `stream` before the call returns (with events, so a capture of `stream`
+ * into a HIP graph includes it). */
 int pcsdf_build_static_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                            const uint8_t *occ_dev, int32_t *ssq_dev,
                            float *sdf_dev, void *stream);
