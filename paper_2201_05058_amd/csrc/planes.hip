@@ -160,18 +160,19 @@ int launch_planes(Handle *h, const Centres &C, int K, bool empty,
   const int npx = nx * ny;
   int32_t *F1 = P + (int64_t)n_slices * npx;
   const int64_t npix = (int64_t)n_slices * npx;
-  if (!need && Keff > 0 && ny <= 512 &&
+  if (!need && Keff > 0 && ny <= 512 && h->tuning.static_segments == 0 &&
       (int64_t)((nx + 63) / 64) * n_slices >= 256) {
     // Every slice of a large stack: the planar field is the 2-D signed EDT
     // of the disks' coverage, by the static build's row pass and y column
     // pass over the stack of slices (each slice a z layer of an
     // nx x ny x n grid).  The coverage bytes use the front of P, the row
-    // pass's output the back.  Columns of at most 512 pixels keep the
-    // column pass's envelopes in LDS (16-bit entries), so that no
-    // workspace is allocated; below one workgroup of column segments per
-    // CU (64 columns of a slice each) the per-pixel kernel below is faster
-    // (512 x 512 x 50 slices: 0.27 ms against 0.47; 256 x 256 x 20: 0.076
-    // against 0.035).
+    // pass's output the back.  With the default segment counts (a static
+    // build tuning sends the planes to the per-pixel kernel) columns of at
+    // most 512 pixels keep the column pass's envelopes in LDS (16-bit
+    // entries), so no workspace is allocated.  Below one workgroup of
+    // column segments per CU (64 columns of a slice each) the per-pixel
+    // kernel is faster (512 x 512 x 50 slices: 0.20 ms against 0.47;
+    // 256 x 256 x 20: 0.076 against 0.035).
     uint8_t *cov = reinterpret_cast<uint8_t *>(P);
     launch_timed(h, k_cover, dim3((unsigned)(npix / nx)), dim3(256), 0u, s,
                  chords, Keff, nx, ny, cov);
