@@ -27,6 +27,9 @@
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
  *     asynchronous on that stream; no call waits for the device except
  *     where stated.  A handle is not reentrant: use one per host thread.
+ *     Calls on one handle share its workspace, so calls enqueued on
+ *     different streams must be ordered by the caller (events, or one
+ *     handle per stream).
  *   - Every call returns PCSDF_OK (0) or an error code.  On error nothing
  *     has been enqueued unless the code is PCSDF_ERR_HIP, and output
  *     buffers are unspecified.  pcsdf_last_error() describes the failure.
