@@ -50,13 +50,13 @@ COMPOSITE_SRC = os.path.join(ROOT, "paper_2201_05058_amd", "csrc",
 
 
 def source_hash(path: str) -> str:
-    """Hash of the composite kernel's own source text (the k_composite
-    template, the shared epilogue in composite_device.h and the helpers of
-    device_common.h), so host-side edits of composite.hip keep a
+    """Hash of the composite kernels' own source text (k_static16 and the
+    k_composite template, the shared epilogue in composite_device.h and the
+    helpers of device_common.h), so host-side edits of composite.hip keep a
     measurement valid."""
     with open(path) as f:
         src = f.read()
-    a = src.find("template <int VEC, bool kGather, bool kSsq, bool kSdf>")
+    a = src.find("// The 16-bit copy of the static field: S16[v]")
     b = src.find("template <int VEC, bool kGather>", a)
     text = src[a:b] if a >= 0 and b > a else src
     for dep in ("composite_device.h", "device_common.h"):
@@ -73,10 +73,12 @@ def composite_outputs(torch, n, shape_zyx, dev):
 
 
 def traffic_from(prof_dir: str, V: int, n: int) -> dict:
-    """HBM bytes per composite launch from two rocprofv3 --pmc runs
+    """HBM bytes per composite call from two rocprofv3 --pmc runs
     (FETCH_SIZE and WRITE_SIZE, KiB per dispatch) of this benchmark and of
     a 1 GiB device copy (--calibrate-copy-mib 1024), each counter scaled
-    by copy bytes / what it reads for the copy."""
+    by copy bytes / what it reads for the copy: the k_composite launch
+    and, when the call makes one, the k_static16 launch of its 16-bit
+    static copy."""
     import csv
     import statistics
 
@@ -93,9 +95,11 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
                 int(r["Grid_Size"]), []).append(float(r["Counter_Value"]))
         return d
 
-    def step_launches(d):
+    def step_launches(d, kernel="k_composite"):
         # the timed step's launch shape: the one dispatched most often
-        by_grid = d["k_composite"]
+        by_grid = d.get(kernel)
+        if not by_grid:
+            return None, [0.0]
         g = max(by_grid, key=lambda k: len(by_grid[k]))
         return g, by_grid[g]
     f, w = load("prof_fetch"), load("prof_write")
@@ -108,10 +112,15 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
     _, wv = step_launches(w)
     fb = statistics.mean(fv) * 1024 * fs
     wb = statistics.mean(wv) * 1024 * ws
+    _, f16 = step_launches(f, "k_static16")
+    _, w16 = step_launches(w, "k_static16")
+    fb16 = statistics.mean(f16) * 1024 * fs
+    wb16 = statistics.mean(w16) * 1024 * ws
     return {"kernel": "k_composite", "V": V, "n_slices": n,
             "grid_size": grid, "launches": len(fv),
             "fetch_bytes": fb, "write_bytes": wb,
-            "bytes_per_launch": fb + wb, "fetch_scale": fs,
+            "static16_fetch_bytes": fb16, "static16_write_bytes": wb16,
+            "bytes_per_launch": fb + wb + fb16 + wb16, "fetch_scale": fs,
             "write_scale": ws,
             "composite_hip_sha256_16": source_hash(COMPOSITE_SRC)}
 
@@ -334,10 +343,16 @@ def measure_workload(pc, autotune, torch, dev, sc, name: str, steps: int,
     qy_ms, qy_n = h.profile_read(_native.KERNEL_QUERY)
     h.profile(True)
     comp_avg_s = comp_ms / comp_n / 1e3
-    # compulsory bytes of one composite launch: read the static field once
-    # (4 B/voxel) and write both outputs (8 B/voxel-slice)
+    # compulsory bytes of one composite call: read the static field once
+    # (4 B/voxel) and write both outputs (8 B/voxel-slice).  The call's
+    # time is that of its kernels: k_composite and, when it makes the
+    # 16-bit static copy, k_static16 before it.
     alg_bytes = (8.0 + 4.0 / n) * V * n
     achieved = alg_bytes / comp_avg_s / 1e9
+    # the library's rule for the copy (pcsdf_tuning.composite_static16)
+    G = min(tuning.get("composite_slices_per_block") or 2, n)
+    c16 = tuning.get("composite_static16", 0)
+    copy16 = c16 == 2 or (c16 == 0 and V >= 1 << 25 and -(-n // G) >= 4)
     qy_avg = qy_ms / max(qy_n, 1)
     res = {
         "value": V * n / (ms_per_step / 1e3),
@@ -350,7 +365,8 @@ def measure_workload(pc, autotune, torch, dev, sc, name: str, steps: int,
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": load_traffic(name, V, n),
-            "kernel": "k_composite",
+            "kernel": ("k_static16 + k_composite" if copy16
+                       else "k_composite"),
             "kernel_ms": comp_avg_s * 1e3,
             "kernel_launches_timed": comp_n,
             "bytes_per_voxel_slice": 8.0 + 4.0 / n,

@@ -155,7 +155,9 @@ int pcsdf_build_floor_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
  * is min(static SSQ, SSQ of the humans' voxels), both signed, and its F.
  * Errors: PCSDF_ERR_NUMERIC for non-finite inputs or when a fixed-point
  * value reaches 2^62 in magnitude or R reaches 2^31.
- * Uses a workspace of 8*n_slices*nx*ny + 24*n_slices*n_humans*ny bytes. */
+ * Uses a workspace of 8*n_slices*nx*ny + 24*n_slices*n_humans*ny bytes,
+ * plus 2*V bytes for the 16-bit static copy (see pcsdf_tuning) when the
+ * outputs are written in per-slice packs of 4, 2 or 1 voxels. */
 int pcsdf_predicted_composite_sdf(pcsdf_handle *h, const pcsdf_grid *grid,
                                   const int32_t *static_ssq_dev,
                                   int32_t n_slices, int32_t n_humans,
@@ -334,6 +336,15 @@ typedef struct pcsdf_tuning {
                                          the slice groups of a chunk run in
                                          succession on one XCD and re-read
                                          its static values from L2 */
+  int32_t composite_static16;         /* composite: 1 the slice groups read
+                                         the static field; 2 a 16-bit copy
+                                         of it made first (half the bytes;
+                                         values beyond +-32767 are read
+                                         from the field), in the handle's
+                                         workspace (2 B per voxel); 0 the
+                                         copy for grids of at least 2^25
+                                         voxels with at least 4 slice
+                                         groups */
 } pcsdf_tuning;
 
 int pcsdf_set_tuning(pcsdf_handle *h, const pcsdf_tuning *t);

@@ -74,7 +74,8 @@ class Tuning(C.Structure):
                 ("batch_chunk_quads", C.c_int32),
                 ("batch_blocks_per_cu", C.c_int32),
                 ("static_segments", C.c_int32),
-                ("composite_order", C.c_int32)]
+                ("composite_order", C.c_int32),
+                ("composite_static16", C.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

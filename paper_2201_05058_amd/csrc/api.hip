@@ -308,11 +308,12 @@ extern "C" int pcsdf_set_tuning(pcsdf_handle *hp, const pcsdf_tuning *t) {
       t->batch_chunk_quads < 0 || t->batch_blocks_per_cu < 0 ||
       t->batch_blocks_per_cu > 32 || t->batch_chunk_quads % 256 != 0 ||
       !(sg == 0 || sg == 1 || sg == 2 || sg == 4 || sg == 8) ||
-      (t->composite_order != 0 && t->composite_order != 1))
+      (t->composite_order != 0 && t->composite_order != 1) ||
+      t->composite_static16 < 0 || t->composite_static16 > 2)
     return fail(h, PCSDF_ERR_INVALID_ARG,
                 "tuning values must be >= 0, blocks per CU <= 32, chunk "
-                "quads a multiple of 256, static segments 0, 1, 2, 4 or 8 "
-                "and composite order 0 or 1");
+                "quads a multiple of 256, static segments 0, 1, 2, 4 or 8, "
+                "composite order 0 or 1 and composite static16 0, 1 or 2");
   h->tuning = *t;
   return PCSDF_OK;
 }

@@ -45,13 +45,34 @@ namespace pcsdf {
 // Slices with need[sl] == 0 are skipped when `need` is non-null.  Thread g
 // handles voxels VEC g .. VEC g + VEC - 1 (VEC divides V); kGather reads
 // their planar values one by one (VEC does not divide nx ny).
+// The 16-bit copy of the static field: S16[v] = S[v] where |S[v]| <=
+// 32767, else kS16Far.  Thread t converts voxels 4t .. 4t+3 (S16 is
+// 256-byte aligned; S is read in 16-byte packs when it is so aligned).
+__global__ __launch_bounds__(256) void k_static16(
+    const int32_t *__restrict__ S, int16_t *__restrict__ S16, uint32_t V) {
+  const uint32_t v = (blockIdx.x * 256u + threadIdx.x) * 4u;
+  if (v >= V) return;
+  auto c16 = [](int32_t x) -> uint32_t {
+    return (uint32_t)(uint16_t)(x >= -32767 && x <= 32767 ? x : kS16Far);
+  };
+  if (v + 3 < V && !((uintptr_t)S & 15)) {
+    const pk_i32x4 x = ld_global(reinterpret_cast<const pk_i32x4 *>(S + v));
+    pk_i32x2 w;
+    w[0] = (int32_t)(c16(x[0]) | c16(x[1]) << 16);
+    w[1] = (int32_t)(c16(x[2]) | c16(x[3]) << 16);
+    *reinterpret_cast<pk_i32x2 *>(S16 + v) = w;
+  } else {
+    for (uint32_t e = v; e < V && e < v + 4; ++e) S16[e] = (int16_t)c16(S[e]);
+  }
+}
+
 template <int VEC, bool kGather, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     const int32_t *__restrict__ need,
     int32_t *__restrict__ oc, float *__restrict__ of, uint32_t plane,
     int n_slices, int G, int Kt, int has_above, float hf, uint32_t V,
-    int order) {
+    int order, const int16_t *__restrict__ S16) {
   // order 0: block (chunk, group) = (blockIdx.x, blockIdx.y), so the
   // blocks in flight write the same few slices over consecutive chunks.
   // order 1 (one-dimensional grid): blocks 8 apart take chunks x, x + 8,
@@ -85,14 +106,16 @@ __global__ __launch_bounds__(256) void k_composite(
         S, P, need, oc, of, plane, V, v0, s_begin, s_end, Kt, has_above, hf);
   else
     composite_pack<VEC, kGather, kSsq, kSdf, false>(
-        S, P, need, oc, of, plane, V, v0, s_begin, s_end, Kt, has_above, hf);
+        S, P, need, oc, of, plane, V, v0, s_begin, s_end, Kt, has_above, hf,
+        S16);
 }
 
 template <int VEC, bool kGather>
 static void launch_comp(Handle *h, const int32_t *S, const int32_t *P,
                         const int32_t *need, int32_t *oc, float *of,
                         uint32_t plane, int n, int G, int Kt, int has_above,
-                        float hf, uint32_t V, hipStream_t s) {
+                        float hf, uint32_t V, const int16_t *S16,
+                        hipStream_t s) {
   const uint32_t nthreads = V / VEC;
   const uint64_t chunks = (nthreads + 255) / 256, ng = (n + G - 1) / G;
   const uint64_t flat = (chunks + 7) / 8 * 8 * ng;
@@ -103,15 +126,15 @@ static void launch_comp(Handle *h, const int32_t *S, const int32_t *P,
   if (oc && of)
     launch_timed(h, k_composite<VEC, kGather, true, true>, grid, block, 0u,
                  s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V,
-                 order);
+                 order, S16);
   else if (oc)
     launch_timed(h, k_composite<VEC, kGather, true, false>, grid, block, 0u,
                  s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V,
-                 order);
+                 order, S16);
   else
     launch_timed(h, k_composite<VEC, kGather, false, true>, grid, block, 0u,
                  s, S, P, need, oc, of, plane, n, G, Kt, has_above, hf, V,
-                 order);
+                 order, S16);
 }
 
 // The same composite over the flattened outputs [n][V] in aligned packs of
@@ -354,14 +377,28 @@ int composite_run(Handle *h, const pcsdf_grid *g,
   ProfScope ps(h, PCSDF_KERNEL_COMPOSITE, s, true);
   return launch_composite(h, g, static_ssq_dev, ps_.P, need, ps_.Kt,
                           ps_.has_above, n_slices, out_ssq_dev, out_sdf_dev,
-                          s);
+                          s, true);
+}
+
+// Whether the per-slice packs read the 16-bit static copy: the tuning's
+// choice, else when they read a static field of at least kStatic16Voxels
+// voxels for at least kStatic16Groups slice groups (the copy costs 6 B per
+// voxel once and saves 2 B per voxel and group; a smaller field is
+// re-read from the caches, where the copy was measured to gain nothing:
+// 256x256x128 x 20 slices).
+constexpr int kStatic16Groups = 4;
+constexpr int64_t kStatic16Voxels = 1LL << 25;
+static bool use_static16(const Handle *h, int64_t V, int groups) {
+  const int t = h->tuning.composite_static16;
+  return t == 2 ||
+         (t == 0 && V >= kStatic16Voxels && groups >= kStatic16Groups);
 }
 
 int launch_composite(Handle *h, const pcsdf_grid *g,
                      const int32_t *static_ssq_dev, const int32_t *P,
                      const int32_t *need, int Kt, int has_above,
                      int32_t n_slices, int32_t *out_ssq_dev,
-                     float *out_sdf_dev, hipStream_t s) {
+                     float *out_sdf_dev, hipStream_t s, bool static_copy) {
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int64_t V = (int64_t)nx * ny * nz;
   // Streaming epilogue over all voxels and slices.
@@ -389,21 +426,38 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
                             plane, Vu, N, Kt, has_above, hf, s);
     return check_launch(h, "composite");
   }
+  const int16_t *S16 = nullptr;
+  if (static_copy && !need && use_static16(h, V, (n_slices + G - 1) / G)) {
+    // the copy lives in the static build's intermediate buffer, which is
+    // free between builds
+    int rc = ensure_buffer(h, h->tmp_buf, (size_t)V * 2, s);
+    if (rc) return rc;
+    int16_t *c = reinterpret_cast<int16_t *>(h->tmp_buf.ptr);
+    launch_timed(h, k_static16, dim3((unsigned)(((Vu + 3) / 4 + 255) / 256)),
+                 dim3(256), 0u, s, static_ssq_dev, c, Vu);
+    if ((rc = check_launch(h, "static16"))) return rc;
+    S16 = c;
+  }
   if (ps.vec == 4 && !ps.gather)
     launch_comp<4, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
-                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
+                          plane, n_slices, G, Kt, has_above, hf, Vu, S16,
+                          s);
   else if (ps.vec == 4)
     launch_comp<4, true>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
-                         plane, n_slices, G, Kt, has_above, hf, Vu, s);
+                         plane, n_slices, G, Kt, has_above, hf, Vu, S16,
+                          s);
   else if (ps.vec == 2 && !ps.gather)
     launch_comp<2, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
-                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
+                          plane, n_slices, G, Kt, has_above, hf, Vu, S16,
+                          s);
   else if (ps.vec == 2)
     launch_comp<2, true>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
-                         plane, n_slices, G, Kt, has_above, hf, Vu, s);
+                         plane, n_slices, G, Kt, has_above, hf, Vu, S16,
+                          s);
   else
     launch_comp<1, false>(h, static_ssq_dev, P, need, out_ssq_dev, out_sdf_dev,
-                          plane, n_slices, G, Kt, has_above, hf, Vu, s);
+                          plane, n_slices, G, Kt, has_above, hf, Vu, S16,
+                          s);
   return check_launch(h, "composite");
 }
 

@@ -176,6 +176,32 @@ __device__ __forceinline__ typename Pack<VEC>::I load_planar(
 // Slices whose planar packs one lane loads before it stores any of them.
 constexpr int kPackSlices = 8;
 
+// The 16-bit copy of the static field (k_static16): values in
+// [-32767, 32767] as they are, every other value as kS16Far, which sends
+// the reader to the int32 field.
+constexpr int32_t kS16Far = -32768;
+
+// The VEC static values of a pack from the 16-bit copy, sign-extended
+// (kS16Far where the int32 field must be read).
+template <int VEC>
+__device__ __forceinline__ typename Pack<VEC>::I load_s16(const int16_t *p) {
+  typename Pack<VEC>::I s;
+  if constexpr (VEC == 4) {
+    const pk_i32x2 w = ld_global(reinterpret_cast<const pk_i32x2 *>(p));
+    s[0] = (int32_t)(int16_t)(w[0] & 0xFFFF);
+    s[1] = w[0] >> 16;
+    s[2] = (int32_t)(int16_t)(w[1] & 0xFFFF);
+    s[3] = w[1] >> 16;
+  } else if constexpr (VEC == 2) {
+    const pk_i32x1 w = ld_global(reinterpret_cast<const pk_i32x1 *>(p));
+    s[0] = (int32_t)(int16_t)(w[0] & 0xFFFF);
+    s[1] = w[0] >> 16;
+  } else {
+    s[0] = p[0];
+  }
+  return s;
+}
+
 // Voxels v0 .. v0+VEC-1 (v0 a multiple of VEC, all in [0, V)) for slices
 // [s_begin, s_end); with kNeed, slices with need[sl] == 0 are skipped (a
 // template parameter so that without it the stores are unconditional).
@@ -187,12 +213,17 @@ constexpr int kPackSlices = 8;
 // and stores them, so that no load waits behind the lane's own stores.
 // (Longer slice groups still measure slower than groups of two or three:
 // the blocks in flight then write more slices' outputs at once.)
+//
+// With S16 (the 16-bit copy of the static field, k_static16) the static
+// values come from it and only the far ones from S: every slice group
+// reads the static values again, and the copy is half their bytes.
 template <int VEC, bool kGather, bool kSsq, bool kSdf, bool kNeed = false>
 __device__ __forceinline__ void composite_pack(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
     const int32_t *__restrict__ need, int32_t *__restrict__ oc,
     float *__restrict__ of, uint32_t plane, uint32_t V, uint32_t v0,
-    int s_begin, int s_end, int Kt, int has_above, float hf) {
+    int s_begin, int s_end, int Kt, int has_above, float hf,
+    const int16_t *__restrict__ S16 = nullptr) {
   const PackCoords<VEC, kGather> pc = pack_coords<VEC, kGather>(v0, plane);
   constexpr int NL = kGather ? VEC : 1;
   HumanLayer hl[NL];
@@ -208,7 +239,8 @@ __device__ __forceinline__ void composite_pack(
   }
   // V <= 2^30, so byte offsets within one slice fit in 32 bits.
   const uint32_t vb = v0 * 4u;
-  const typename Pack<VEC>::I s = load_i32<VEC>(at_bytes(S, vb));
+  typename Pack<VEC>::I s = S16 ? load_s16<VEC>(at_bytes(S16, v0 * 2u))
+                                : load_i32<VEC>(at_bytes(S, vb));
   for (int sl0 = s_begin; sl0 < s_end; sl0 += kPackSlices) {
     const int cnt = min(kPackSlices, s_end - sl0);
     typename Pack<VEC>::I p[kPackSlices];
@@ -216,6 +248,15 @@ __device__ __forceinline__ void composite_pack(
     for (int j = 0; j < kPackSlices; ++j)
       if (j < cnt && !(kNeed && need[sl0 + j] == 0))
         p[j] = load_planar<VEC, kGather>(P + (size_t)(sl0 + j) * plane, pc);
+    if (S16 && sl0 == s_begin) {
+      // the far values from the int32 field (after the planar loads are
+      // issued, so that only the static load is waited for)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        if (s[e] == kS16Far)
+          s[e] = ld_global(reinterpret_cast<const pk_i32x1 *>(
+              at_bytes(S, vb + 4u * e)))[0];
+    }
 #pragma unroll
     for (int j = 0; j < kPackSlices; ++j) {
       if (j >= cnt) break;

@@ -31,7 +31,8 @@ struct Handle {
   std::string err;
   int device = -1;
   int max_lds = 65536;  // bytes of LDS a workgroup may use on `device`
-  DevBuf tmp_buf;       // int32 [V] intermediate of the 3-D EDT
+  DevBuf tmp_buf;       // int32 [V] intermediate of the 3-D EDT; between
+                        // builds the composite's 16-bit static copy
   DevBuf plane_buf;     // int32 planar fields of the humans
   DevBuf chord_buf;     // int2 chords of the humans' disks per row
   DevBuf param_buf;     // per-call parameter blocks (fixed-point centres)
@@ -244,7 +245,8 @@ int launch_composite(Handle *h, const pcsdf_grid *g,
                      const int32_t *static_ssq_dev, const int32_t *P,
                      const int32_t *need, int Kt, int has_above,
                      int32_t n_slices, int32_t *out_ssq_dev,
-                     float *out_sdf_dev, hipStream_t s);
+                     float *out_sdf_dev, hipStream_t s,
+                     bool static_copy = false);
 
 // The whole predicted-composite call (validation, planes, streaming
 // epilogue).  With `need` (device int32 [n_slices]) only the slices whose

@@ -218,18 +218,21 @@ def test_surrogate_validation(h):
 def test_tuning_validation_without_device(h):
     """Launch shapes are checked on the host: negative values, more than 32
     workgroups per CU, chunk sizes off the 256-quad step, segment counts
-    other than 0, 1, 2, 4 or 8 and block orders other than 0 or 1 are
-    rejected; accepted values read back unchanged."""
+    other than 0, 1, 2, 4 or 8, block orders other than 0 or 1 and static
+    copy choices other than 0, 1 or 2 are rejected; accepted values read
+    back unchanged."""
     from paper_2201_05058_amd._native import Tuning
     good = {"composite_slices_per_block": 3, "batch_slices_per_item": 2,
             "batch_chunk_quads": 512, "batch_blocks_per_cu": 8,
-            "static_segments": 4, "composite_order": 1}
+            "static_segments": 4, "composite_order": 1,
+            "composite_static16": 2}
     h.set_tuning(good)
     assert h.get_tuning().as_dict() == good
     for bad in ({"composite_slices_per_block": -1}, {"batch_blocks_per_cu": 33},
                 {"batch_chunk_quads": 100}, {"static_segments": 3},
                 {"static_segments": 16}, {"static_segments": -2},
-                {"composite_order": 2}, {"composite_order": -1}):
+                {"composite_order": 2}, {"composite_order": -1},
+                {"composite_static16": 3}, {"composite_static16": -1}):
         t = Tuning.from_dict(bad)
         assert h.lib.pcsdf_set_tuning(h.ptr, C.byref(t)) == 1, bad
     assert h.get_tuning().as_dict() == good  # rejected calls change nothing

@@ -224,15 +224,17 @@ def width_case_scene(dims):
     (1, 1, 8), (3, 1, 4), (2, 1, 6),  # planes smaller than a pack
     (3, 1, 1), (1, 1, 7), (3, 1, 2)])  # V of 3, 7 and 6 voxels
 @pytest.mark.parametrize("offset", [0, 1, 2])
-def test_composite_vector_widths_and_alignment(pc, dev, dims, offset):
+@pytest.mark.parametrize("copy", [1, 2])
+def test_composite_vector_widths_and_alignment(pc, dev, dims, offset, copy):
     """The composite streams 4, 2 or 1 voxels per lane by V mod 4 and the
     alignment of its three buffers, reading the planar values as one
     vector when the pack width divides nx*ny and one by one otherwise
     (a pack may then cross layer boundaries).  Buffers offset by one or two
-    elements (4- and 8-byte aligned) take the narrower packs.  Every case
-    gives the oracle's bytes."""
+    elements (4- and 8-byte aligned) take the narrower packs.  Each pack
+    width reads the static values from the int32 field (copy 1) or from
+    the 16-bit copy (copy 2).  Every case gives the oracle's bytes."""
     sc = width_case_scene(dims)
-    say(f"composite widths grid={dims} offset={offset}")
+    say(f"composite widths grid={dims} offset={offset} static16={copy}")
     n, V = sc.n_slices, sc.grid.nvox
     shp = (n,) + sc.grid.shape_zyx
     ssq_s, _ = gpu_static(pc, sc.grid, sc.occ, dev)
@@ -241,16 +243,64 @@ def test_composite_vector_widths_and_alignment(pc, dev, dims, offset):
     bi = torch.empty(n * V + offset, dtype=torch.int32, device=dev)
     bf = torch.empty(n * V + offset, dtype=torch.float32, device=dev)
     oc, of = bi[offset:].view(shp), bf[offset:].view(shp)
-    pc.predicted_composite_sdf(sc.grid, bs[offset:].view(sc.grid.shape_zyx),
-                               sc.human_xy, sc.radius, sc.height,
-                               out_ssq=oc, out_sdf=of)
-    torch.cuda.synchronize()
+    h = pc.Handle()
+    try:
+        h.set_tuning({"composite_static16": copy})
+        pc.predicted_composite_sdf(sc.grid,
+                                   bs[offset:].view(sc.grid.shape_zyx),
+                                   sc.human_xy, sc.radius, sc.height,
+                                   out_ssq=oc, out_sdf=of, handle=h)
+        torch.cuda.synchronize()
+    finally:
+        h.close()
     rs, _ = oracle.build_static(sc.grid, sc.occ)
     wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
                                         sc.height)
     assert np.unique(wc).size > 2  # the case has structure to get wrong
     np.testing.assert_array_equal(oc.cpu().numpy(), wc)
     assert_f32_close(of.cpu().numpy(), wf)
+
+
+def far_scene(kind):
+    """Static fields beyond the 16-bit copy's range (|value| > 32767):
+    free voxels up to 399 voxels from the nearest obstacle, an empty map
+    (+inf everywhere) and a full one (-inf everywhere), 8 slices."""
+    sc = scenegen.small_scene(31, 400, 12, 10, h=0.05, n_boxes=1,
+                              n_humans=2, n_slices=8)
+    sc.occ[:] = 0
+    if kind == "far":
+        sc.occ[2:5, 3:6, 0:3] = 1   # obstacle at x = 0..2, z = 2..4
+    elif kind == "full":
+        sc.occ[:] = 1
+    return sc
+
+
+@pytest.mark.parametrize("kind", ["far", "empty", "full"])
+def test_composite_static16_far_values(pc, dev, kind):
+    """The 16-bit static copy holds values in [-32767, 32767] and sends
+    the composite to the int32 field for every other one: with the copy
+    forced, left to the library (not used on a grid this small) and off,
+    the oracle's bytes on fields whose values mostly lie beyond that
+    range."""
+    sc = far_scene(kind)
+    rs, _ = oracle.build_static(sc.grid, sc.occ)
+    if kind == "far":
+        assert (rs > 32767).sum() > sc.grid.nvox // 4
+    wc, wf = oracle.predicted_composite(sc.grid, rs, sc.human_xy, sc.radius,
+                                        sc.height)
+    ssq_s, _ = gpu_static(pc, sc.grid, sc.occ, dev)
+    for copy in (2, 0, 1):
+        say(f"composite static16={copy} {kind}")
+        h = pc.Handle()
+        try:
+            h.set_tuning({"composite_static16": copy})
+            c, cf = pc.predicted_composite_sdf(sc.grid, ssq_s, sc.human_xy,
+                                               sc.radius, sc.height, handle=h)
+            torch.cuda.synchronize()
+        finally:
+            h.close()
+        np.testing.assert_array_equal(c.cpu().numpy(), wc)
+        assert_f32_close(cf.cpu().numpy(), wf)
 
 
 @pytest.mark.parametrize("r,H", [(0.25, 1.8), (0.0, 1.8), (0.25, 0.01),
@@ -322,20 +372,25 @@ def test_composite_room256_full(pc, dev, room256_ref):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("G,order", [(1, 0), (3, 0), (5, 0), (10, 0),
-                                     (20, 0), (1, 1), (2, 1), (3, 1),
-                                     (20, 1)])
-def test_composite_room256_every_slice_group(pc, dev, room256_ref, G, order):
+@pytest.mark.parametrize("G,order,copy", [
+    (1, 0, 0), (3, 0, 0), (5, 0, 0), (10, 0, 0), (20, 0, 0), (1, 1, 0),
+    (2, 1, 0), (3, 1, 0), (20, 1, 0), (2, 0, 1), (1, 0, 2), (2, 0, 2),
+    (1, 1, 2), (10, 0, 2), (20, 1, 2)])
+def test_composite_room256_every_slice_group(pc, dev, room256_ref, G, order,
+                                             copy):
     """The same workload in the other launch shapes the autotuner chooses
-    between (slices per block row, block order): the oracle's bytes in
-    each."""
+    between (slices per block row, block order) and with the 16-bit static
+    copy left to the library (not used on this grid), off or forced: the
+    oracle's bytes in each."""
     sc, wc, wf = room256_ref
-    say(f"composite room256 with {G} slices per block row, order {order}")
+    say(f"composite room256 with {G} slices per block row, order {order}, "
+        f"static16 {copy}")
     occ_d = to_dev(sc.occ.astype(np.uint8), dev)
     h = pc.Handle()
     try:
         h.set_tuning({"composite_slices_per_block": G,
-                      "composite_order": order})
+                      "composite_order": order,
+                      "composite_static16": copy})
         ssq_s, _ = pc.build_static_sdf(sc.grid, occ_d, want_sdf=False,
                                        handle=h)
         c, cf = pc.predicted_composite_sdf(sc.grid, ssq_s, sc.human_xy,

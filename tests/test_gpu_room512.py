@@ -112,19 +112,22 @@ def test_queries_on_oracle_slices(run, slice_oracle):
     assert (err <= 1e-6 * np.maximum(np.abs(wg), 1.0)).all()
 
 
-@pytest.mark.parametrize("G,order", [(5, 0), (10, 0), (25, 0), (2, 1)])
-def test_other_slice_groups_give_identical_bytes(run, G, order):
+@pytest.mark.parametrize("G,order,copy", [(5, 0, 0), (10, 0, 0), (25, 0, 0),
+                                          (2, 1, 0), (2, 0, 1)])
+def test_other_slice_groups_give_identical_bytes(run, G, order, copy):
     """The composite in other launch shapes the autotuner may pick for
     this workload (slice groups of 5, 10 and 25 per block row; the XCD
-    block order): the same bytes as the default shape checked above, for
-    all 50 slices."""
+    block order) and without the 16-bit static copy: the same bytes as the
+    default shape checked above, for all 50 slices."""
     import paper_2201_05058_amd as pc
     sc = run["sc"]
-    say(f"room512: composite with {G} slices per block row, order {order}")
+    say(f"room512: composite with {G} slices per block row, order {order}, "
+        f"static16 {copy}")
     h = pc.Handle()
     try:
         h.set_tuning({"composite_slices_per_block": G,
-                      "composite_order": order})
+                      "composite_order": order,
+                      "composite_static16": copy})
         c, cf = pc.predicted_composite_sdf(sc.grid, run["ssq_s"], sc.human_xy,
                                            sc.radius, sc.height, handle=h)
         torch.cuda.synchronize()
