@@ -125,6 +125,20 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
             "composite_hip_sha256_16": source_hash(COMPOSITE_SRC)}
 
 
+def traffic_slice_groups(workload: str, V: int):
+    """Slice groups of the composite launch whose counters the traffic
+    record holds (its grid is 256-lane chunks of 4-voxel packs times the
+    groups, in either block order when the chunk count is a multiple of
+    8), or None."""
+    try:
+        with open(traffic_file(workload)) as f:
+            t = json.load(f)
+        chunks = -(-(V // 4) // 256)
+        return int(t["grid_size"]) // (chunks * 256)
+    except (OSError, ValueError, KeyError, TypeError):
+        return None
+
+
 def load_traffic(workload: str, V: int, n: int):
     """Measured HBM bytes per composite launch (rocprofv3 PMC FETCH_SIZE +
     WRITE_SIZE, scaled by a copy-kernel calibration), or None when absent
@@ -365,6 +379,10 @@ def measure_workload(pc, autotune, torch, dev, sc, name: str, steps: int,
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": load_traffic(name, V, n),
+            # the counters were taken in the autotuner's shape of the
+            # profiled run; the static re-reads scale with the groups
+            "traffic_slice_groups": traffic_slice_groups(name, V),
+            "slice_groups": -(-n // G),
             "kernel": ("k_static16 + k_composite" if copy16
                        else "k_composite"),
             "kernel_ms": comp_avg_s * 1e3,
