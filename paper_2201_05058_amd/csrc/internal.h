@@ -240,7 +240,9 @@ int planes_from(Handle *h, const pcsdf_grid *g, const HumanSet &hs,
 
 // The streaming epilogue alone: outputs of every slice (with `need`, of
 // the marked slices) from the static field and the planar fields P
-// [n_slices][ny][nx] of the humans (cylinder layers 0..Kt).
+// [n_slices][ny][nx] of the humans (cylinder layers 0..Kt).  With
+// static_copy (callers that may use the handle's workspace) it may first
+// make the 16-bit copy of the static field there and read that instead.
 int launch_composite(Handle *h, const pcsdf_grid *g,
                      const int32_t *static_ssq_dev, const int32_t *P,
                      const int32_t *need, int Kt, int has_above,
