@@ -125,34 +125,57 @@ def traffic_from(prof_dir: str, V: int, n: int) -> dict:
             "composite_hip_sha256_16": source_hash(COMPOSITE_SRC)}
 
 
-def traffic_slice_groups(workload: str, V: int):
-    """Slice groups of the composite launch whose counters the traffic
-    record holds (its grid is 256-lane chunks of 4-voxel packs times the
-    groups, in either block order when the chunk count is a multiple of
-    8), or None."""
-    try:
-        with open(traffic_file(workload)) as f:
-            t = json.load(f)
-        chunks = -(-(V // 4) // 256)
-        return int(t["grid_size"]) // (chunks * 256)
-    except (OSError, ValueError, KeyError, TypeError):
-        return None
-
-
-def load_traffic(workload: str, V: int, n: int):
-    """Measured HBM bytes per composite launch (rocprofv3 PMC FETCH_SIZE +
-    WRITE_SIZE, scaled by a copy-kernel calibration), or None when absent
-    or taken on a different version of the kernel source."""
+def traffic_records(workload: str) -> list:
+    """The traffic records of a workload: one per launch shape measured
+    (a file holding a single record is read as a list of one)."""
     try:
         with open(traffic_file(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
-    if t.get("composite_hip_sha256_16") != source_hash(COMPOSITE_SRC):
-        return None
-    if t.get("V") != V or t.get("n_slices") != n:
-        return None
-    return t.get("bytes_per_launch")
+        return []
+    if isinstance(t, dict) and isinstance(t.get("records"), list):
+        return [r for r in t["records"] if isinstance(r, dict)]
+    return [t] if isinstance(t, dict) else []
+
+
+def store_traffic(workload: str, rec: dict) -> None:
+    """Adds a record, replacing one of the same shape and dropping those
+    of other kernel sources."""
+    key = (rec.get("composite_slices_per_block"), rec.get("composite_order"))
+    recs = [r for r in traffic_records(workload)
+            if r.get("composite_hip_sha256_16") ==
+            rec["composite_hip_sha256_16"] and
+            (r.get("composite_slices_per_block"),
+             r.get("composite_order")) != key]
+    recs.append(rec)
+    recs.sort(key=lambda r: (r.get("composite_order") or 0,
+                             r.get("composite_slices_per_block") or 0))
+    with open(traffic_file(workload), "w") as fh:
+        json.dump({"records": recs}, fh, indent=1)
+
+
+def load_traffic(workload: str, V: int, n: int, G: int, order: int):
+    """Measured HBM bytes per composite call (rocprofv3 PMC FETCH_SIZE +
+    WRITE_SIZE, scaled by a copy-kernel calibration) in the launch shape
+    of this run (G slices per block row, block order), or None when that
+    shape was not measured or the counters were taken on a different
+    version of the kernel source."""
+    h = source_hash(COMPOSITE_SRC)
+    for t in traffic_records(workload):
+        if (t.get("composite_hip_sha256_16") == h and t.get("V") == V and
+                t.get("n_slices") == n and
+                t.get("composite_slices_per_block") == G and
+                t.get("composite_order") == order):
+            return t.get("bytes_per_launch")
+    return None
+
+
+def traffic_shapes(workload: str) -> list:
+    """[G, order] of every measured shape whose source hash matches."""
+    h = source_hash(COMPOSITE_SRC)
+    return [[t.get("composite_slices_per_block"), t.get("composite_order")]
+            for t in traffic_records(workload)
+            if t.get("composite_hip_sha256_16") == h]
 
 
 def cpu_model() -> str:
@@ -365,6 +388,7 @@ def measure_workload(pc, autotune, torch, dev, sc, name: str, steps: int,
     achieved = alg_bytes / comp_avg_s / 1e9
     # the library's rule for the copy (pcsdf_tuning.composite_static16)
     G = min(tuning.get("composite_slices_per_block") or 2, n)
+    order = int(tuning.get("composite_order") or 0)
     c16 = tuning.get("composite_static16", 0)
     copy16 = c16 == 2 or (c16 == 0 and V >= 1 << 25 and -(-n // G) >= 4)
     qy_avg = qy_ms / max(qy_n, 1)
@@ -378,11 +402,12 @@ def measure_workload(pc, autotune, torch, dev, sc, name: str, steps: int,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": load_traffic(name, V, n),
-            # the counters were taken in the autotuner's shape of the
-            # profiled run; the static re-reads scale with the groups
-            "traffic_slice_groups": traffic_slice_groups(name, V),
-            "slice_groups": -(-n // G),
+            # counters of this run's launch shape (the static re-reads
+            # scale with the slice groups), null for a shape not measured
+            "traffic": load_traffic(name, V, n, G, order),
+            "traffic_shapes_measured": traffic_shapes(name),
+            "composite_slices_per_block": G,
+            "composite_order": order,
             "kernel": ("k_static16 + k_composite" if copy16
                        else "k_composite"),
             "kernel_ms": comp_avg_s * 1e3,
@@ -756,6 +781,10 @@ def main():
                     help="skip the surrogate query measurement")
     ap.add_argument("--weights-dir", default=os.path.join(
         ROOT, "paper_2201_05058_amd", "weights"))
+    ap.add_argument("--traffic-shape", default="2,0",
+                    help="slices per block row and block order of the "
+                    "launches whose counters --traffic-from reads (the "
+                    "tuning the counted runs were given)")
     ap.add_argument("--traffic-from", default="",
                     help="write the composite's measured HBM traffic from "
                          "rocprofv3 PMC output under this directory")
@@ -783,8 +812,10 @@ def main():
         V, n = {"room512": (512 * 512 * 256, 50),
                 "room256": (256 * 256 * 128, 20)}[args.workload]
         t = traffic_from(args.traffic_from, V, n)
-        with open(traffic_file(args.workload), "w") as fh:
-            json.dump(t, fh, indent=1)
+        G, order = (int(x) for x in args.traffic_shape.split(","))
+        t["composite_slices_per_block"] = G
+        t["composite_order"] = order
+        store_traffic(args.workload, t)
         print(json.dumps(t))
         return
 
