@@ -42,9 +42,6 @@
 
 namespace pcsdf {
 
-// Slices with need[sl] == 0 are skipped when `need` is non-null.  Thread g
-// handles voxels VEC g .. VEC g + VEC - 1 (VEC divides V); kGather reads
-// their planar values one by one (VEC does not divide nx ny).
 // The 16-bit copy of the static field: S16[v] = S[v] where |S[v]| <=
 // 32767, else kS16Far.  Thread t converts voxels 4t .. 4t+3 (S16 is
 // 256-byte aligned; S is read in 16-byte packs when it is so aligned).
@@ -66,6 +63,10 @@ __global__ __launch_bounds__(256) void k_static16(
   }
 }
 
+// Slices with need[sl] == 0 are skipped when `need` is non-null.  Thread g
+// handles voxels VEC g .. VEC g + VEC - 1 (VEC divides V); kGather reads
+// their planar values one by one (VEC does not divide nx ny); with S16
+// the static values come from the 16-bit copy.
 template <int VEC, bool kGather, bool kSsq, bool kSdf>
 __global__ __launch_bounds__(256) void k_composite(
     const int32_t *__restrict__ S, const int32_t *__restrict__ P,
